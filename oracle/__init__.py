@@ -1,0 +1,301 @@
+"""FP64 CPU oracle for the Barnes-Hut gravity hot path (Iwasawa et al., FDPS).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's CPU-baseline
+leg may import this package; the GPU library never does, and nothing in the product path
+may fall back to it.  It shares no code with the GPU library.
+
+Two parts:
+  O-D  `direct`      softened FP64 direct summation (equation ParticleParticleNbody, G = 1),
+                     the exact quantity the tree approximates;
+  O-T  `build_tree`, `make_groups`, `walk`, `tree_force`
+                     a plain serial tree that fixes keys, order, cells, groups and lists
+                     (the readings are documented in oracle.c next to each step).
+Plus the leapfrog of the sample program (`kdk`), energy and error diagnostics and the
+interaction-list length model (equation nlist_long).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        _LIB = C.CDLL(_build.LIB)
+        _declare(_LIB)
+    return _LIB
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _declare(L):
+    vp, i64, i32, f64 = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+    L.or_direct.argtypes = [i64, i64, vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp]
+    L.or_keys.argtypes = [i64, vp, vp, vp, vp, vp, vp]
+    L.or_interleave.argtypes = [C.c_uint32] * 3
+    L.or_interleave.restype = C.c_uint64
+    L.or_deinterleave.argtypes = [i64, vp, vp]
+    L.or_sort.argtypes = [i64, vp, vp, vp]
+    L.or_build_cells.argtypes = [i64, vp, vp, i32]
+    L.or_build_cells.restype = vp
+    L.or_cells_count.argtypes = [vp]
+    L.or_cells_count.restype = i64
+    L.or_cells_system.argtypes = [vp, i64, vp]
+    L.or_cells_export.argtypes = [vp] + [vp] * 7
+    L.or_cells_free.argtypes = [vp]
+    L.or_moments.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp]
+    L.or_groups.argtypes = [vp, i64, i32]
+    L.or_groups.restype = vp
+    L.or_groups_count.argtypes = [vp]
+    L.or_groups_count.restype = i64
+    L.or_groups_export.argtypes = [vp, vp, vp, vp]
+    L.or_groups_free.argtypes = [vp]
+    L.or_group_geometry.argtypes = [i64] + [vp] * 11
+    L.or_walk.argtypes = [vp, i64, vp, vp, vp, vp, f64, vp]
+    L.or_walk.restype = vp
+    L.or_walk_export.argtypes = [vp, vp, vp]
+    L.or_walk_free.argtypes = [vp]
+    L.or_force.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp]
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+# ----------------------------------------------------------------------------------------
+# O-D
+def direct(ps, targets=None) -> np.ndarray:
+    """Direct-sum {ax, ay, az, phi} on the target particles (user indices), each against the
+    particles of its own system only.  Returns an array [len(targets), 4]."""
+    L = lib()
+    off = ps.offsets()
+    if targets is None:
+        targets = np.arange(ps.n, dtype=np.int64)
+    targets = _c(targets, np.int64)
+    out = np.zeros((targets.shape[0], 4))
+    sys_of = np.searchsorted(off, targets, side="right") - 1
+    x, y, z, m, e = (_c(getattr(ps, k), np.float64) for k in ("x", "y", "z", "m", "eps"))
+    for s in np.unique(sys_of):
+        sel = np.nonzero(sys_of == s)[0]
+        t = _c(targets[sel], np.int64)
+        ax, ay, az, pot = (np.zeros(t.shape[0]) for _ in range(4))
+        L.or_direct(int(off[s]), int(off[s + 1]), _p(x), _p(y), _p(z), _p(m), _p(e),
+                    t.shape[0], _p(t), _p(ax), _p(ay), _p(az), _p(pot))
+        out[sel, 0], out[sel, 1], out[sel, 2], out[sel, 3] = ax, ay, az, pot
+    return out
+
+
+# ----------------------------------------------------------------------------------------
+# O-T
+def interleave(qx: int, qy: int, qz: int) -> int:
+    return int(lib().or_interleave(qx, qy, qz))
+
+
+def deinterleave(keys: np.ndarray) -> np.ndarray:
+    keys = _c(keys, np.uint64)
+    q = np.zeros((keys.shape[0], 3), dtype=np.uint32)
+    lib().or_deinterleave(keys.shape[0], _p(keys), _p(q))
+    return q
+
+
+def keys(ps):
+    """Root cube {ox, oy, oz, Lr} per system and the 63-bit key of every particle."""
+    off = _c(ps.offsets(), np.int64)
+    S = off.shape[0] - 1
+    cube = np.zeros((S, 4))
+    key = np.zeros(ps.n, dtype=np.uint64)
+    x, y, z = (_c(getattr(ps, k), np.float64) for k in ("x", "y", "z"))
+    lib().or_keys(S, _p(off), _p(x), _p(y), _p(z), _p(cube), _p(key))
+    return cube, key
+
+
+def sort(ps, key) -> np.ndarray:
+    off = _c(ps.offsets(), np.int64)
+    perm = np.zeros(ps.n, dtype=np.uint32)
+    key = _c(key, np.uint64)
+    lib().or_sort(off.shape[0] - 1, _p(off), _p(key), _p(perm))
+    return perm
+
+
+class Tree:
+    """Keys, order, cells and moments of one particle set (all systems)."""
+
+    def __init__(self, ps, n_leaf: int = 8, moments: bool = True):
+        L = lib()
+        self.ps = ps
+        self.n_leaf = n_leaf
+        self.off = _c(ps.offsets(), np.int64)
+        self.n_sys = self.off.shape[0] - 1
+        self.cube, self.key = keys(ps)
+        self.perm = sort(ps, self.key)
+        p = self.perm.astype(np.int64)
+        self.skey = _c(self.key[p], np.uint64)
+        self.sx, self.sy, self.sz, self.sm, self.seps = (
+            _c(getattr(ps, k)[p], np.float64) for k in ("x", "y", "z", "m", "eps"))
+        h = L.or_build_cells(self.n_sys, _p(self.off), _p(self.skey), n_leaf)
+        try:
+            nc = L.or_cells_count(h)
+            self.level = np.zeros(nc, np.int32)
+            self.prefix = np.zeros(nc, np.uint64)
+            self.begin, self.count, self.first_child, self.nchild, self.parent, self.csys = (
+                np.zeros(nc, np.uint32) for _ in range(6))
+            L.or_cells_export(h, _p(self.level), _p(self.prefix), _p(self.begin),
+                              _p(self.count), _p(self.first_child), _p(self.nchild),
+                              _p(self.parent))
+            L.or_cells_system(h, self.n_sys, _p(self.csys))
+            self._h = h
+        except Exception:
+            L.or_cells_free(h)
+            raise
+        self.mom = None
+        if moments:
+            self.compute_moments()
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().or_cells_free(h)
+            self._h = None
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.level.shape[0])
+
+    def compute_moments(self):
+        self.mom = np.zeros((self.n_cells, 10))
+        lib().or_moments(self.n_cells, _p(self.begin), _p(self.count), _p(self.sx),
+                         _p(self.sy), _p(self.sz), _p(self.sm), _p(self.mom))
+        return self.mom
+
+
+def build_tree(ps, n_leaf: int = 8, moments: bool = True) -> Tree:
+    return Tree(ps, n_leaf, moments)
+
+
+class Groups:
+    def __init__(self, tree: Tree, n_group: int):
+        L = lib()
+        self.n_group = n_group
+        h = L.or_groups(tree._h, tree.n_sys, n_group)
+        ng = L.or_groups_count(h)
+        self.cell, self.begin, self.count = (np.zeros(ng, np.uint32) for _ in range(3))
+        L.or_groups_export(h, _p(self.cell), _p(self.begin), _p(self.count))
+        L.or_groups_free(h)
+        self.qmin = np.zeros((ng, 3), np.uint32)
+        self.qmax = np.zeros((ng, 3), np.uint32)
+        self.centre = np.zeros((ng, 3))
+        L.or_group_geometry(ng, _p(self.cell), _p(self.begin), _p(self.count), _p(tree.level),
+                            _p(tree.prefix), _p(tree.skey), _p(tree.csys), _p(tree.cube),
+                            _p(self.qmin), _p(self.qmax), _p(self.centre))
+        self.root = _c(tree.csys[self.cell], np.uint32)   # roots are cells 0..S-1
+
+    @property
+    def n(self) -> int:
+        return int(self.cell.shape[0])
+
+
+def make_groups(tree: Tree, n_group: int) -> Groups:
+    return Groups(tree, n_group)
+
+
+class Lists:
+    """Interaction lists of selected groups, CSR: EPJ (sorted particle positions) and SPJ
+    (cell ids), each in depth-first walk order."""
+
+    def __init__(self, tree: Tree, grp: Groups, theta: float, sel=None):
+        L = lib()
+        self.tree, self.grp = tree, grp
+        self.sel = _c(np.arange(grp.n) if sel is None else sel, np.int64)
+        k = self.sel.shape[0]
+        counts = np.zeros(2 * k, np.int64)
+        self._h = L.or_walk(tree._h, k, _p(self.sel), _p(grp.root), _p(grp.qmin),
+                            _p(grp.qmax), float(theta), _p(counts))
+        self.n_epj = counts[0::2].copy()
+        self.n_spj = counts[1::2].copy()
+        self.epj_off = np.concatenate([[0], np.cumsum(self.n_epj)]).astype(np.int64)
+        self.spj_off = np.concatenate([[0], np.cumsum(self.n_spj)]).astype(np.int64)
+        self.epj = np.zeros(int(self.epj_off[-1]), np.uint32)
+        self.spj = np.zeros(int(self.spj_off[-1]), np.uint32)
+        L.or_walk_export(self._h, _p(self.epj), _p(self.spj))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().or_walk_free(h)
+            self._h = None
+
+    def group_lists(self, k: int):
+        return (self.epj[self.epj_off[k]:self.epj_off[k + 1]],
+                self.spj[self.spj_off[k]:self.spj_off[k + 1]])
+
+    def force(self, quad: bool) -> np.ndarray:
+        """{ax, ay, az, phi} at every sorted position covered by the selected groups
+        (rows of unselected groups stay NaN)."""
+        t, g = self.tree, self.grp
+        if t.mom is None:
+            t.compute_moments()
+        acc = np.full((t.ps.n, 4), np.nan)
+        lib().or_force(self._h, _p(self.sel), _p(g.begin), _p(g.count), _p(t.sx), _p(t.sy),
+                       _p(t.sz), _p(t.sm), _p(t.seps), _p(t.mom), 1 if quad else 0, _p(acc))
+        return acc
+
+
+def walk(tree: Tree, grp: Groups, theta: float, sel=None) -> Lists:
+    return Lists(tree, grp, theta, sel)
+
+
+def tree_force(ps, theta: float, n_leaf: int = 8, n_group: int = 64, quad: bool = True):
+    """Whole O-T evaluation; returns {ax, ay, az, phi} in the user's original order."""
+    t = build_tree(ps, n_leaf)
+    g = make_groups(t, n_group)
+    lists = walk(t, g, theta)
+    acc_sorted = lists.force(quad)
+    acc = np.empty_like(acc_sorted)
+    acc[t.perm.astype(np.int64)] = acc_sorted
+    return acc
+
+
+# ----------------------------------------------------------------------------------------
+# Leapfrog (predict = half kick + drift, correct = half kick, as in the sample program),
+# energy and error diagnostics.
+def kick(v: np.ndarray, a: np.ndarray, dt: float):
+    v += (0.5 * dt) * a
+
+
+def drift(x: np.ndarray, v: np.ndarray, dt: float):
+    x += dt * v
+
+
+def energy(ps, pot: np.ndarray):
+    """Kinetic, potential (1/2 sum m phi, per-particle phi from `pot`) and total."""
+    K = 0.5 * float(np.sum(ps.m * (ps.vx ** 2 + ps.vy ** 2 + ps.vz ** 2)))
+    W = 0.5 * float(np.sum(ps.m * pot))
+    return K, W, K + W
+
+
+def rms_rel_error(a: np.ndarray, a_ref: np.ndarray) -> float:
+    """sqrt(mean_i |a_i - a_ref_i|^2 / |a_ref_i|^2) over the rows given (3 components)."""
+    d = np.sum((a[:, :3] - a_ref[:, :3]) ** 2, axis=1)
+    r = np.sum(a_ref[:, :3] ** 2, axis=1)
+    return float(math.sqrt(np.mean(d / r)))
+
+
+def nlist_model(n_grp: float, theta: float, n_total: float) -> float:
+    """Mean interaction-list length of the long-range tree walk, equation nlist_long of
+    section "Tree traverse and interaction calculation" (n n_p = total particle count)."""
+    return (n_grp + 14.0 * n_grp ** (2.0 / 3.0) / theta
+            + 21.0 * math.pi * n_grp ** (1.0 / 3.0) / theta ** 2
+            + 28.0 * math.pi / (3.0 * theta ** 3)
+            * math.log2(theta / 2.8 * (n_total ** (1.0 / 3.0) - n_grp ** (1.0 / 3.0))))
