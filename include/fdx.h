@@ -1,0 +1,174 @@
+/*
+ * fdx.h -- C ABI of the MI355X (gfx950) Barnes-Hut gravity library.
+ *
+ * The calls follow the way Iwasawa et al. ("Implementation and Performance of FDPS",
+ * section "An example -- gravitational N-body problem") state a gravitational N-body
+ * problem: initialise, hand over the particles, build the tree, compute the long-range
+ * force from particles (EPJ) and superparticles (SPJ) under an opening angle theta, and
+ * advance the particles with the leapfrog of the sample program; then finalise.  The
+ * interaction is fixed to softened Newtonian gravity with G = 1:
+ *   a_i   = sum_j m_j (r_j - r_i) / (|r_j - r_i|^2 + eps_i^2)^{3/2}      (j != i)
+ *   phi_i = -sum_j m_j / (|r_j - r_i|^2 + eps_i^2)^{1/2}                  (j != i)
+ * approximated by the tree (equations ParticleParticleNbody, ParticleSuperparticleNbody
+ * and geqL), with superparticles up to the quadrupole moment.
+ *
+ * Conventions for every call:
+ *   - returns FDX_OK (0) on success or a negative FDX_E* code; no C++ exception crosses
+ *     this boundary; fdx_last_error() then holds a message for that context;
+ *   - all GPU work is issued on the stream bound at fdx_create, in order, asynchronously;
+ *     calls that return data to host memory synchronise that stream first;
+ *   - the library owns its tree, list and scratch buffers (device memory it allocates);
+ *     the caller owns every pointer it passes;
+ *   - particle arrays are structure-of-arrays FP64 of length n; several independent systems
+ *     may be laid end to end (sys_off), and particles never interact across systems;
+ *   - results are deterministic: the same input gives bit-identical keys, cells, lists and
+ *     forces on every run;
+ *   - one context must not be used from two host threads at once.
+ */
+#ifndef FDX_H
+#define FDX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fdx_ctx fdx_ctx;
+
+/* status codes */
+#define FDX_OK 0
+#define FDX_EINVAL -1   /* an argument is out of range, null or non-finite */
+#define FDX_ENOMEM -2   /* a device allocation failed */
+#define FDX_EHIP -3     /* a HIP runtime call failed, or a kernel reported an error */
+#define FDX_ESTATE -4   /* calls made in the wrong order (e.g. force before particles) */
+
+/* where a pointer lives */
+#define FDX_MEM_HOST 0
+#define FDX_MEM_DEVICE 1
+
+/* fdx_calc_force / fdx_integrate flags (bitwise or) */
+#define FDX_QUAD 1        /* superparticles carry the quadrupole moment (else monopole) */
+#define FDX_FP32REL 2     /* FP32 force kernels on group-relative coordinates with
+                             compensated accumulation (else FP64 kernels) */
+#define FDX_PREDICTOR 4   /* size interaction lists from the learned list-length predictor
+                             (single walk; overflowing groups are re-walked exactly, so
+                             forces never depend on it) */
+#define FDX_PERSISTENT 8  /* one persistent force launch that pops groups from a
+                             cost-ordered global queue */
+#define FDX_GRAPH 16      /* fdx_integrate: capture one step as a HIP graph and replay it */
+#define FDX_TIMING 32     /* record per-phase times (fdx_get_stats) */
+
+/* Create a context on HIP device `device`, issuing work on `hip_stream` (a hipStream_t;
+ * NULL = the library creates its own stream).  Corresponds to FDPS's Initialize.
+ * *out receives the handle.  FDX_EINVAL if out is null or the device does not exist. */
+int fdx_create(fdx_ctx **out, int device, void *hip_stream);
+
+/* Free every buffer the library owns and the handle.  Corresponds to FDPS's Finalize.
+ * A null ctx is accepted and ignored. */
+int fdx_destroy(fdx_ctx *ctx);
+
+/* Hand over n particles (the ParticleSystem of the sample program): positions x,y,z,
+ * velocities vx,vy,vz and masses m, each an FP64 array of length n; eps = per-particle
+ * softening (length n, or null to use the eps argument of fdx_calc_force); sys_off = n_sys+1
+ * ascending int64 offsets that split [0, n) into independent systems (null with n_sys = 1
+ * for a single system).
+ * mem_kind FDX_MEM_HOST: the arrays are copied to device memory before the call returns.
+ * mem_kind FDX_MEM_DEVICE: the arrays are device pointers that the library borrows: it
+ *   reads them, and fdx_integrate updates x..vz in place; the caller keeps them alive and
+ *   unchanged by others until fdx_destroy or the next fdx_set_particles.  sys_off is always
+ *   a host pointer.
+ * Masses must be finite and >= 0, eps finite and > 0 (checked on the host for host memory
+ * and on the device, reported by the next fdx_calc_force, for device memory).
+ * FDX_EINVAL: n < 0, n >= 2^31, a null array, n_sys < 1, offsets not ascending from 0 to n,
+ * or an invalid value. */
+int fdx_set_particles(fdx_ctx *ctx, int64_t n, const double *x, const double *y,
+                      const double *z, const double *vx, const double *vy, const double *vz,
+                      const double *m, const double *eps, const int64_t *sys_off,
+                      int32_t n_sys, int32_t mem_kind);
+
+/* Build the tree of the current positions: root cube and 63-bit Morton keys per system,
+ * stable radix sort by (system, key), octree cells (split while a cell holds more than
+ * n_leaf particles, up to level 21), multipole moments up to the quadrupole, and i-particle
+ * groups (maximal cells of at most n_group particles; modified tree algorithm, section
+ * "Tree traverse and interaction calculation").  fdx_calc_force does this itself; this call
+ * exists to inspect or time the tree alone.  FDX_EINVAL: n_leaf < 1 or n_group < 1;
+ * FDX_ESTATE: no particles. */
+int fdx_build_tree(fdx_ctx *ctx, int32_t n_leaf, int32_t n_group);
+
+/* One force evaluation (calcForceAllAndWriteBack of the sample program): rebuilds the tree,
+ * walks each group from its system's root with opening angle theta (a cell of side S whose
+ * centre lies at distance D from the group's box is a superparticle iff S^2 < theta^2 D^2,
+ * otherwise it is opened; opened leaves give particles), and evaluates accelerations and
+ * potentials.  Results stay in device memory in the caller's original particle order
+ * (fdx_get_forces).  eps is the softening used when fdx_set_particles got no eps array.
+ * flags: FDX_QUAD, FDX_FP32REL, FDX_PREDICTOR, FDX_PERSISTENT, FDX_TIMING.
+ * FDX_EINVAL: theta not in (0, 1], n_leaf < 1, n_group < 1 or > 512, eps not finite > 0
+ * when it is used, or non-finite particle data; FDX_ESTATE: no particles. */
+int fdx_calc_force(fdx_ctx *ctx, double theta, int32_t n_leaf, int32_t n_group, double eps,
+                   int32_t flags);
+
+/* Advance n_steps leapfrog steps of size dt (predict: v += dt/2 a, x += dt v; force;
+ * correct: v += dt/2 a), with the tree parameters and flags of the last fdx_calc_force,
+ * which must have been called first (the sample program evaluates the force once before
+ * its loop).  flags may add FDX_GRAPH: the step is captured once as a HIP graph and
+ * replayed.  FDX_ESTATE: no prior force evaluation; FDX_EINVAL: dt not finite or
+ * n_steps < 0. */
+int fdx_integrate(fdx_ctx *ctx, double dt, int32_t n_steps, int32_t flags);
+
+/* Copy positions and velocities (caller's order) into x..vz (length n each, memory of
+ * kind mem_kind).  Any pointer may be null to skip that array. */
+int fdx_get_particles(fdx_ctx *ctx, double *x, double *y, double *z, double *vx, double *vy,
+                      double *vz, int32_t mem_kind);
+
+/* Copy the last forces (caller's order) into ax, ay, az, pot (length n each; null skips).
+ * FDX_ESTATE if no force has been evaluated. */
+int fdx_get_forces(fdx_ctx *ctx, double *ax, double *ay, double *az, double *pot,
+                   int32_t mem_kind);
+
+/* Sizes and counters of the last tree / force evaluation. */
+typedef struct {
+    int64_t n, n_sys;
+    int64_t n_cells, n_groups, depth;
+    int64_t n_epj, n_spj;              /* list entries summed over groups */
+    int64_t n_interactions_pp;         /* sum over groups of n_i * |EPJ| (self pairs included) */
+    int64_t n_interactions_pc;         /* sum over groups of n_i * |SPJ| */
+    int64_t overflow_groups;           /* predictor path: groups re-walked exactly */
+    int64_t list_capacity;             /* list entries allocated in the last walk */
+    int32_t n_leaf, n_group, flags;
+    double theta;
+    /* phase times in milliseconds (FDX_TIMING): keys, sort, tree, moments, groups, walk,
+       force, unsort, predict (feature + MLP), total */
+    double t_keys, t_sort, t_tree, t_moments, t_groups, t_walk, t_force, t_unsort, t_predict,
+        t_total;
+} fdx_stats;
+
+int fdx_get_stats(fdx_ctx *ctx, fdx_stats *out);
+
+/* Debug views for parity checks (host memory, sizes from fdx_get_stats; null skips).
+ * cube[4 s] = {origin x, y, z, side} of system s; key[r] and perm[r] = key and original
+ * index of the particle at sorted rank r; cell arrays in breadth-first order;
+ * mom[10 c] = {M, X, Y, Z, Qxx, Qyy, Qzz, Qxy, Qxz, Qyz}. */
+int fdx_get_tree(fdx_ctx *ctx, double *cube, uint64_t *key, uint32_t *perm, int32_t *level,
+                 uint64_t *prefix, uint32_t *begin, uint32_t *count, uint32_t *first_child,
+                 uint32_t *nchild, uint32_t *parent, double *mom);
+
+/* Groups in ascending order of their first sorted particle: cell, begin, count, integer
+ * box qmin[3 g], qmax[3 g] (grid units) and the geometric centre of the group's cell. */
+int fdx_get_groups(fdx_ctx *ctx, uint32_t *cell, uint32_t *begin, uint32_t *count,
+                   uint32_t *qmin, uint32_t *qmax, double *centre);
+
+/* Interaction lists of the last walk: n_epj[g], n_spj[g]; epj = the EPJ entries (sorted
+ * particle ranks) of all groups concatenated, spj = the SPJ entries (cell ids) likewise
+ * (each group's entries in the library's emission order). */
+int fdx_get_lists(fdx_ctx *ctx, uint32_t *n_epj, uint32_t *n_spj, uint32_t *epj,
+                  uint32_t *spj);
+
+/* Message of the last failed call on ctx (never null; "" when none). */
+const char *fdx_last_error(const fdx_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDX_H */

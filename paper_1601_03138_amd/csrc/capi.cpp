@@ -1,0 +1,583 @@
+// C ABI (include/fdx.h) and host orchestration of the gfx950 Barnes-Hut hot path.
+//
+// One force evaluation is one pass over: root cubes and keys -> radix sort -> sorted
+// particle gather -> level-by-level octree -> bottom-up moments -> groups -> walk (count,
+// scan, fill) -> force kernel -> return of forces to the caller's order.  Everything runs on
+// the bound stream; the host waits once per evaluation, after the counting walk, to size
+// the list buffer (and to read the device status: bad input, tree overflow).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ctx.h"
+
+using namespace fdx;
+
+namespace fdx {
+
+int fail(fdx_ctx *c, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+}  // namespace fdx
+
+namespace fdx {
+
+bool finite_all(const double *p, int64_t n) {
+    for (int64_t i = 0; i < n; i++)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+int ensure_tree_buffers(fdx_ctx *c, uint32_t cell_cap, uint32_t group_cap) {
+    const size_t n = (size_t)c->n, S = (size_t)c->nsys;
+    if (cell_cap > c->cell_cap || !c->c_level.p) {
+        HIPCHK(c, c->c_level.ensure(cell_cap));
+        HIPCHK(c, c->c_begin.ensure(cell_cap));
+        HIPCHK(c, c->c_count.ensure(cell_cap));
+        HIPCHK(c, c->c_first.ensure(cell_cap));
+        HIPCHK(c, c->c_nchild.ensure(cell_cap));
+        HIPCHK(c, c->c_parent.ensure(cell_cap));
+        HIPCHK(c, c->c_prefix.ensure(cell_cap));
+        HIPCHK(c, c->c_node.ensure(cell_cap));
+        HIPCHK(c, c->c_link.ensure(cell_cap));
+        HIPCHK(c, c->c_mom.ensure(10 * (size_t)cell_cap));
+        c->cell_cap = cell_cap;
+    }
+    HIPCHK(c, c->c_lvl.ensure(kLevels + 2));
+    HIPCHK(c, c->tmp_n.ensure(n + S + 1));
+    HIPCHK(c, c->tmp_off.ensure(n + S + 2));
+    if (group_cap > c->group_cap || !c->g_cell.p) {
+        HIPCHK(c, c->g_cell.ensure(group_cap));
+        HIPCHK(c, c->g_begin.ensure(group_cap));
+        HIPCHK(c, c->g_count.ensure(group_cap));
+        HIPCHK(c, c->g_sys.ensure(group_cap));
+        HIPCHK(c, c->g_box.ensure(6 * (size_t)group_cap));
+        HIPCHK(c, c->g_centre.ensure(3 * (size_t)group_cap));
+        HIPCHK(c, c->cnt_e.ensure(group_cap));
+        HIPCHK(c, c->cnt_s.ensure(group_cap));
+        HIPCHK(c, c->lcap.ensure(group_cap));
+        HIPCHK(c, c->seg.ensure((size_t)group_cap + 1));
+        HIPCHK(c, c->ovf_list.ensure(group_cap));
+        HIPCHK(c, c->order.ensure(group_cap));
+        c->group_cap = group_cap;
+    }
+    return FDX_OK;
+}
+
+Cells cells_view(fdx_ctx *c) {
+    Cells v;
+    v.level = c->c_level.p; v.begin = c->c_begin.p; v.count = c->c_count.p;
+    v.first = c->c_first.p; v.nchild = c->c_nchild.p; v.parent = c->c_parent.p;
+    v.prefix = c->c_prefix.p; v.node = c->c_node.p; v.link = c->c_link.p; v.mom = c->c_mom.p;
+    v.lvl = c->c_lvl.p; v.cap = c->cell_cap;
+    return v;
+}
+
+Groups groups_view(fdx_ctx *c) {
+    Groups g;
+    g.cell = c->g_cell.p; g.begin = c->g_begin.p; g.count = c->g_count.p; g.sys = c->g_sys.p;
+    g.box = c->g_box.p; g.centre = c->g_centre.p; g.cap = c->group_cap;
+    return g;
+}
+
+void mark(fdx_ctx *c, int k) {
+    if (c->flags & FDX_TIMING) (void)hipEventRecord(c->ev[k], c->stream);
+}
+
+int read_status(fdx_ctx *c) {
+    HIPCHK(c, hipMemcpyAsync(&c->hst->st, c->st, sizeof(DevStatus), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->hst->lvl, c->c_lvl.p, sizeof(uint32_t) * (kLevels + 2),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return FDX_OK;
+}
+
+// Tree part of one evaluation: keys, sort, gather, cells, moments, groups.  Retries with
+// larger cell / group capacity when the device reports an overflow.  Leaves the status
+// (group count, levels) in c->hst after its synchronisation when `sync` is true.
+int run_tree(fdx_ctx *c, bool sync) {
+    const size_t n = (size_t)c->n;
+    const int S = c->nsys;
+    hipStream_t s = c->stream;
+    HIPCHK(c, fill_u32((uint32_t *)c->st, 0u, sizeof(DevStatus) / 4, s));
+    if (c->borrowed || !c->eps_given)
+        HIPCHK(c, check_input(n, c->x, c->y, c->z, c->m, c->eps_given ? c->eps : nullptr, c->st, s));
+    mark(c, 0);
+    HIPCHK(c, bbox(n, c->x, c->y, c->z, c->sysid.p, S, c->bbox_u.p, s));
+    HIPCHK(c, root_cubes(S, c->bbox_u.p, c->cube.p, s));
+    HIPCHK(c, morton_keys(n, c->x, c->y, c->z, c->sysid.p, c->cube.p, c->key.p, c->perm.p, s));
+    mark(c, 1);
+    bool alt = false;
+    HIPCHK(c, radix_sort(n, c->key.p, c->key_alt.p, c->perm.p, c->perm_alt.p, c->sysid.p, S,
+                         c->rs_scratch.p, c->partial.p, &alt, s));
+    c->skey = alt ? c->key_alt.p : c->key.p;
+    c->sperm = alt ? c->perm_alt.p : c->perm.p;
+    HIPCHK(c, gather_sorted(n, c->sperm, c->x, c->y, c->z, c->m, c->eps_given ? c->eps : nullptr,
+                            c->eps_all, c->jp.p, c->seps.p, c->inv.p, s));
+    mark(c, 2);
+    for (int attempt = 0;; attempt++) {
+        HIPCHK(c, tree_build(n, S, c->sys_off.p, c->skey, c->n_leaf, cells_view(c), c->tmp_n.p,
+                             c->tmp_off.p, c->partial.p, c->st, s));
+        mark(c, 3);
+        HIPCHK(c, tree_moments(cells_view(c), c->jp.p, s));
+        mark(c, 4);
+        HIPCHK(c, make_groups(n, S, c->sys_off.p, cells_view(c), c->skey, c->cube.p, c->n_group,
+                              groups_view(c), c->flag.p, c->gcell_at.p, c->gpos.p, c->partial.p,
+                              c->st, s));
+        mark(c, 5);
+        if (!sync) return FDX_OK;
+        int r = read_status(c);
+        if (r) return r;
+        const DevStatus &h = c->hst->st;
+        if (h.bad_input)
+            return fail(c, FDX_EINVAL, "particle data has a non-finite value, a negative mass "
+                                       "or eps <= 0");
+        bool grow = false;
+        uint32_t ncap = c->cell_cap, gcap = c->group_cap;
+        if (h.cell_overflow) { ncap = (uint32_t)std::min<uint64_t>(2ull * c->cell_cap, 0xFFFFFFF0ull); grow = true; }
+        if (h.n_groups > c->group_cap) { gcap = h.n_groups + 1024; grow = true; }
+        if (!grow) return FDX_OK;
+        if (attempt > 8) return fail(c, FDX_EHIP, "tree capacity did not converge");
+        r = ensure_tree_buffers(c, ncap, gcap);
+        if (r) return r;
+        HIPCHK(c, fill_u32((uint32_t *)c->st, 0u, sizeof(DevStatus) / 4, s));
+    }
+}
+
+// Walk + force + return of forces.  Needs run_tree(sync=true) first.
+int run_force(fdx_ctx *c) {
+    hipStream_t s = c->stream;
+    const size_t n = (size_t)c->n;
+    const uint32_t G0 = c->hst->st.n_groups;
+    const double th2 = c->theta * c->theta;
+    Groups gv = groups_view(c);
+    Cells cv = cells_view(c);
+    uint32_t G = G0;
+    if (c->flags & FDX_PREDICTOR) {
+        int r = ext_predicted_walk(c, G);
+        if (r) return r;
+    } else {
+        HIPCHK(c, walk(false, G, gv, cv, th2, nullptr, nullptr, nullptr, c->cnt_e.p, c->cnt_s.p,
+                       c->ovf_list.p, c->st, s));
+        HIPCHK(c, list_caps(G, c->cnt_e.p, c->cnt_s.p, c->lcap.p, c->st, s));
+        HIPCHK(c, scan_u32_to_u64(c->lcap.p, c->seg.p, G, nullptr, nullptr, c->partial.p,
+                                  &c->st->list_total, s));
+        int r = read_status(c);
+        if (r) return r;
+        if (c->hst->st.walk_error) return fail(c, FDX_EHIP, "walk stack exhausted");
+        const uint64_t total = c->hst->st.list_total;
+        if (total > c->list_cap || !c->list.p) {
+            const uint64_t want = total + total / 8 + 1024;
+            HIPCHK(c, c->list.ensure(want));
+            c->list_cap = want;
+        }
+        HIPCHK(c, walk(true, G, gv, cv, th2, c->seg.p, c->lcap.p, c->list.p, c->cnt_e.p,
+                       c->cnt_s.p, c->ovf_list.p, c->st, s));
+        c->stats.list_capacity = (int64_t)total;
+    }
+    HIPCHK(c, list_stats(G, gv, c->cnt_e.p, c->cnt_s.p, c->st, s));
+    mark(c, 6);
+    ForceArgs fa;
+    fa.g = &gv; fa.jp = c->jp.p; fa.seps = c->seps.p; fa.mom = c->c_mom.p;
+    fa.seg = c->seg.p; fa.cap = c->lcap.p; fa.cnt_e = c->cnt_e.p; fa.cnt_s = c->cnt_s.p;
+    fa.list = c->list.p; fa.order = nullptr; fa.fs = c->fs.p; fa.st = c->st;
+    fa.quad = (c->flags & FDX_QUAD) != 0;
+    fa.fp32 = (c->flags & FDX_FP32REL) != 0;
+    fa.persistent = (c->flags & FDX_PERSISTENT) != 0;
+    fa.variant = ext_force_variant(c);
+    if (fa.persistent) {
+        fa.order = ext_queue_order(c, G);
+    }
+    HIPCHK(c, force(G, fa, s));
+    mark(c, 7);
+    HIPCHK(c, unsort_forces(n, c->fs.p, c->inv.p, c->ax.p, c->ay.p, c->az.p, c->pot.p, s));
+    mark(c, 8);
+    c->have_force = true;
+    return FDX_OK;
+}
+
+}  // namespace fdx
+
+namespace {
+
+int setup_eval(fdx_ctx *c, double theta, int n_leaf, int n_group, double eps, int flags) {
+    if (!c) return FDX_EINVAL;
+    if (!c->have_particles) return fail(c, FDX_ESTATE, "no particles: call fdx_set_particles first");
+    if (!(theta > 0.0 && theta <= 1.0)) return fail(c, FDX_EINVAL, "theta must be in (0, 1]");
+    if (n_leaf < 1) return fail(c, FDX_EINVAL, "n_leaf must be >= 1");
+    if (n_group < 1 || n_group > kMaxGroup) return fail(c, FDX_EINVAL, "n_group must be in [1, %d]", kMaxGroup);
+    if (!c->eps_given && !(std::isfinite(eps) && eps > 0.0))
+        return fail(c, FDX_EINVAL, "eps must be finite and > 0");
+    c->theta = theta; c->n_leaf = n_leaf; c->n_group = n_group; c->eps_all = eps;
+    c->flags = flags;
+    const size_t n = (size_t)c->n, S = (size_t)c->nsys;
+    uint32_t ccap = std::max<uint32_t>(c->cell_cap, (uint32_t)std::min<uint64_t>(n + S + 1024, 0xFFFFFFF0ull));
+    uint32_t gcap = std::max<uint32_t>(c->group_cap, (uint32_t)(n / 8 + S + 1024));
+    return ensure_tree_buffers(c, ccap, gcap);
+}
+
+void finish_stats(fdx_ctx *c) {
+    fdx_stats &o = c->stats;
+    const DevStatus &h = c->hst->st;
+    o.n = c->n; o.n_sys = c->nsys;
+    o.n_cells = c->hst->lvl[kLevels + 1];
+    o.n_groups = h.n_groups;
+    int depth = 0;
+    for (int l = 0; l <= kLevels; l++)
+        if (c->hst->lvl[l + 1] > c->hst->lvl[l]) depth = l;
+    o.depth = depth;
+    o.n_leaf = c->n_leaf; o.n_group = c->n_group; o.flags = c->flags; o.theta = c->theta;
+}
+
+int sync_timing(fdx_ctx *c) {
+    if (!(c->flags & FDX_TIMING)) return FDX_OK;
+    HIPCHK(c, hipEventSynchronize(c->ev[8]));
+    float t[9] = {};
+    for (int k = 0; k < 8; k++) hipEventElapsedTime(&t[k], c->ev[k], c->ev[k + 1]);
+    fdx_stats &o = c->stats;
+    o.t_keys = t[0]; o.t_sort = t[1]; o.t_tree = t[2]; o.t_moments = t[3]; o.t_groups = t[4];
+    o.t_walk = t[5]; o.t_force = t[6]; o.t_unsort = t[7];
+    float tot = 0;
+    hipEventElapsedTime(&tot, c->ev[0], c->ev[8]);
+    o.t_total = tot;
+    return FDX_OK;
+}
+
+int read_counters(fdx_ctx *c) {
+    HIPCHK(c, hipMemcpyAsync(&c->hst->st, c->st, sizeof(DevStatus), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const DevStatus &h = c->hst->st;
+    c->stats.n_epj = (int64_t)h.n_epj;
+    c->stats.n_spj = (int64_t)h.n_spj;
+    c->stats.n_interactions_pp = (int64_t)h.inter_pp;
+    c->stats.n_interactions_pc = (int64_t)h.inter_pc;
+    return FDX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fdx_create(fdx_ctx **out, int device, void *hip_stream) {
+    if (!out) return FDX_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return FDX_EINVAL;
+    fdx_ctx *c = new (std::nothrow) fdx_ctx();
+    if (!c) return FDX_ENOMEM;
+    c->device = device;
+    if (hipSetDevice(device) != hipSuccess) { delete c; return FDX_EHIP; }
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreate(&c->stream) != hipSuccess) { delete c; return FDX_EHIP; }
+        c->own_stream = true;
+    }
+    if (hipMalloc((void **)&c->st, sizeof(DevStatus)) != hipSuccess ||
+        hipHostMalloc((void **)&c->hst, sizeof(HostStatus), hipHostMallocDefault) != hipSuccess) {
+        fdx_destroy(c);
+        return FDX_ENOMEM;
+    }
+    memset(c->hst, 0, sizeof(HostStatus));
+    for (auto &e : c->ev)
+        if (hipEventCreate(&e) != hipSuccess) { fdx_destroy(c); return FDX_EHIP; }
+    if (c->partial.ensure(kScanBlocks + 1) != hipSuccess) { fdx_destroy(c); return FDX_ENOMEM; }
+    *out = c;
+    return FDX_OK;
+}
+
+int fdx_destroy(fdx_ctx *c) {
+    if (!c) return FDX_OK;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    ext_release(c);
+    for (auto *b : {&c->ox, &c->oy, &c->oz, &c->ovx, &c->ovy, &c->ovz, &c->om, &c->oeps, &c->cube,
+                    &c->seps, &c->c_mom, &c->g_centre, &c->ax, &c->ay, &c->az, &c->pot})
+        b->release();
+    for (auto *b : {&c->sysid, &c->perm, &c->perm_alt, &c->inv, &c->rs_scratch, &c->c_level,
+                    &c->c_begin, &c->c_count, &c->c_first, &c->c_nchild, &c->c_parent, &c->c_lvl,
+                    &c->tmp_n, &c->tmp_off, &c->g_cell, &c->g_begin, &c->g_count, &c->g_sys,
+                    &c->g_box, &c->flag, &c->gcell_at, &c->gpos, &c->cnt_e, &c->cnt_s, &c->lcap,
+                    &c->list, &c->ovf_list, &c->order})
+        b->release();
+    for (auto *b : {&c->bbox_u, &c->key, &c->key_alt, &c->partial, &c->c_prefix, &c->seg}) b->release();
+    c->sys_off.release();
+    c->jp.release();
+    c->fs.release();
+    c->c_node.release();
+    c->c_link.release();
+    if (c->st) (void)hipFree(c->st);
+    if (c->hst) (void)hipHostFree(c->hst);
+    for (auto &e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return FDX_OK;
+}
+
+int fdx_set_particles(fdx_ctx *c, int64_t n, const double *x, const double *y, const double *z,
+                      const double *vx, const double *vy, const double *vz, const double *m,
+                      const double *eps, const int64_t *sys_off, int32_t n_sys, int32_t mem_kind) {
+    if (!c) return FDX_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, FDX_EHIP, "hipSetDevice failed");
+    if (n < 0 || n >= (1ll << 31)) return fail(c, FDX_EINVAL, "n must be in [0, 2^31)");
+    if (mem_kind != FDX_MEM_HOST && mem_kind != FDX_MEM_DEVICE)
+        return fail(c, FDX_EINVAL, "mem_kind must be FDX_MEM_HOST or FDX_MEM_DEVICE");
+    if (n > 0 && (!x || !y || !z || !vx || !vy || !vz || !m))
+        return fail(c, FDX_EINVAL, "null particle array");
+    if (n_sys < 1) return fail(c, FDX_EINVAL, "n_sys must be >= 1");
+    std::vector<int64_t> off(n_sys + 1);
+    if (sys_off) {
+        for (int s = 0; s <= n_sys; s++) off[s] = sys_off[s];
+        if (off[0] != 0 || off[n_sys] != n) return fail(c, FDX_EINVAL, "sys_off must run from 0 to n");
+        for (int s = 0; s < n_sys; s++)
+            if (off[s + 1] < off[s]) return fail(c, FDX_EINVAL, "sys_off must be ascending");
+    } else {
+        if (n_sys != 1) return fail(c, FDX_EINVAL, "sys_off is null but n_sys != 1");
+        off[0] = 0; off[1] = n;
+    }
+    if (mem_kind == FDX_MEM_HOST && n > 0) {
+        for (const double *p : {x, y, z, vx, vy, vz, m})
+            if (!finite_all(p, n)) return fail(c, FDX_EINVAL, "non-finite particle data");
+        for (int64_t i = 0; i < n; i++)
+            if (m[i] < 0) return fail(c, FDX_EINVAL, "negative mass");
+        if (eps)
+            for (int64_t i = 0; i < n; i++)
+                if (!(eps[i] > 0.0) || !std::isfinite(eps[i]))
+                    return fail(c, FDX_EINVAL, "eps must be finite and > 0");
+    }
+    c->have_particles = false;
+    c->have_force = false;
+    c->n = n;
+    c->nsys = n_sys;
+    c->sys_off_h = off;
+    c->eps_given = eps != nullptr;
+    c->borrowed = mem_kind == FDX_MEM_DEVICE;
+    const size_t N = (size_t)n;
+    hipStream_t s = c->stream;
+    if (c->borrowed) {
+        c->x = (double *)x; c->y = (double *)y; c->z = (double *)z;
+        c->vx = (double *)vx; c->vy = (double *)vy; c->vz = (double *)vz;
+        c->m = (double *)m; c->eps = (double *)eps;
+    } else {
+        DBuf<double> *bufs[8] = {&c->ox, &c->oy, &c->oz, &c->ovx, &c->ovy, &c->ovz, &c->om, &c->oeps};
+        const double *src[8] = {x, y, z, vx, vy, vz, m, eps};
+        double **dst[8] = {&c->x, &c->y, &c->z, &c->vx, &c->vy, &c->vz, &c->m, &c->eps};
+        for (int k = 0; k < 8; k++) {
+            if (!src[k]) { *dst[k] = nullptr; continue; }
+            HIPCHK(c, bufs[k]->ensure(N));
+            *dst[k] = bufs[k]->p;
+            if (N) HIPCHK(c, hipMemcpyAsync(bufs[k]->p, src[k], N * sizeof(double),
+                                            hipMemcpyHostToDevice, s));
+        }
+    }
+    HIPCHK(c, c->sys_off.ensure(n_sys + 1));
+    HIPCHK(c, hipMemcpyAsync(c->sys_off.p, off.data(), sizeof(int64_t) * (n_sys + 1),
+                             hipMemcpyHostToDevice, s));
+    HIPCHK(c, c->sysid.ensure(N));
+    HIPCHK(c, sysid_fill(c->sys_off.p, n_sys, c->sysid.p, N, s));
+    HIPCHK(c, c->bbox_u.ensure(6 * (size_t)n_sys));
+    HIPCHK(c, c->cube.ensure(4 * (size_t)n_sys));
+    HIPCHK(c, c->key.ensure(N));
+    HIPCHK(c, c->key_alt.ensure(N));
+    HIPCHK(c, c->perm.ensure(N));
+    HIPCHK(c, c->perm_alt.ensure(N));
+    HIPCHK(c, c->inv.ensure(N));
+    HIPCHK(c, c->rs_scratch.ensure(radix_scratch_u32(N)));
+    HIPCHK(c, c->jp.ensure(N));
+    HIPCHK(c, c->seps.ensure(N));
+    HIPCHK(c, c->flag.ensure(N));
+    HIPCHK(c, c->gcell_at.ensure(N));
+    HIPCHK(c, c->gpos.ensure(N));
+    HIPCHK(c, c->fs.ensure(N));
+    HIPCHK(c, c->ax.ensure(N));
+    HIPCHK(c, c->ay.ensure(N));
+    HIPCHK(c, c->az.ensure(N));
+    HIPCHK(c, c->pot.ensure(N));
+    HIPCHK(c, hipStreamSynchronize(s));   // host arrays may be freed by the caller afterwards
+    c->have_particles = true;
+    c->stats = fdx_stats{};
+    return FDX_OK;
+}
+
+int fdx_build_tree(fdx_ctx *c, int32_t n_leaf, int32_t n_group) {
+    if (!c) return FDX_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, FDX_EHIP, "hipSetDevice failed");
+    double eps = c->eps_given ? 0.0 : (c->eps_all > 0 ? c->eps_all : 1.0);
+    int r = setup_eval(c, c->theta, n_leaf, n_group, eps, c->flags & ~FDX_TIMING);
+    if (r) return r;
+    r = run_tree(c, true);
+    if (r) return r;
+    finish_stats(c);
+    return FDX_OK;
+}
+
+int fdx_calc_force(fdx_ctx *c, double theta, int32_t n_leaf, int32_t n_group, double eps,
+                   int32_t flags) {
+    if (!c) return FDX_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, FDX_EHIP, "hipSetDevice failed");
+    int r = setup_eval(c, theta, n_leaf, n_group, eps, flags);
+    if (r) return r;
+    r = run_tree(c, true);
+    if (r) return r;
+    r = run_force(c);
+    if (r) return r;
+    finish_stats(c);
+    r = sync_timing(c);
+    if (r) return r;
+    return read_counters(c);
+}
+
+int fdx_integrate(fdx_ctx *c, double dt, int32_t n_steps, int32_t flags) {
+    if (!c) return FDX_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, FDX_EHIP, "hipSetDevice failed");
+    if (!c->have_force) return fail(c, FDX_ESTATE, "evaluate the force once before integrating");
+    if (!std::isfinite(dt) || n_steps < 0) return fail(c, FDX_EINVAL, "bad dt or n_steps");
+    if (flags & FDX_GRAPH) return ext_integrate_graph(c, dt, n_steps);
+    const size_t n = (size_t)c->n;
+    for (int k = 0; k < n_steps; k++) {
+        HIPCHK(c, kick_drift(n, c->x, c->y, c->z, c->vx, c->vy, c->vz, c->ax.p, c->ay.p, c->az.p,
+                             dt, c->stream));
+        int r = run_tree(c, true);
+        if (r) return r;
+        r = run_force(c);
+        if (r) return r;
+        HIPCHK(c, kick(n, c->vx, c->vy, c->vz, c->ax.p, c->ay.p, c->az.p, dt, nullptr, c->stream));
+    }
+    finish_stats(c);
+    return read_counters(c);
+}
+
+int fdx_get_particles(fdx_ctx *c, double *x, double *y, double *z, double *vx, double *vy,
+                      double *vz, int32_t mem_kind) {
+    if (!c) return FDX_EINVAL;
+    if (!c->have_particles) return fail(c, FDX_ESTATE, "no particles");
+    hipMemcpyKind k = mem_kind == FDX_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const size_t bytes = sizeof(double) * (size_t)c->n;
+    double *dst[6] = {x, y, z, vx, vy, vz};
+    double *src[6] = {c->x, c->y, c->z, c->vx, c->vy, c->vz};
+    for (int i = 0; i < 6; i++)
+        if (dst[i] && bytes) HIPCHK(c, hipMemcpyAsync(dst[i], src[i], bytes, k, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return FDX_OK;
+}
+
+int fdx_get_forces(fdx_ctx *c, double *ax, double *ay, double *az, double *pot, int32_t mem_kind) {
+    if (!c) return FDX_EINVAL;
+    if (!c->have_force) return fail(c, FDX_ESTATE, "no force evaluated");
+    hipMemcpyKind k = mem_kind == FDX_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const size_t bytes = sizeof(double) * (size_t)c->n;
+    double *dst[4] = {ax, ay, az, pot};
+    double *src[4] = {c->ax.p, c->ay.p, c->az.p, c->pot.p};
+    for (int i = 0; i < 4; i++)
+        if (dst[i] && bytes) HIPCHK(c, hipMemcpyAsync(dst[i], src[i], bytes, k, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return FDX_OK;
+}
+
+int fdx_get_stats(fdx_ctx *c, fdx_stats *out) {
+    if (!c || !out) return FDX_EINVAL;
+    *out = c->stats;
+    return FDX_OK;
+}
+
+int fdx_get_tree(fdx_ctx *c, double *cube, uint64_t *key, uint32_t *perm, int32_t *level,
+                 uint64_t *prefix, uint32_t *begin, uint32_t *count, uint32_t *first_child,
+                 uint32_t *nchild, uint32_t *parent, double *mom) {
+    if (!c) return FDX_EINVAL;
+    if (!c->skey) return fail(c, FDX_ESTATE, "no tree built");
+    hipStream_t s = c->stream;
+    const size_t n = (size_t)c->n, nc = (size_t)c->stats.n_cells;
+    auto cp = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
+        if (!dst || !bytes) return hipSuccess;
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s);
+    };
+    HIPCHK(c, cp(cube, c->cube.p, 4 * sizeof(double) * c->nsys));
+    HIPCHK(c, cp(key, c->skey, 8 * n));
+    HIPCHK(c, cp(perm, c->sperm, 4 * n));
+    HIPCHK(c, cp(level, c->c_level.p, 4 * nc));
+    HIPCHK(c, cp(prefix, c->c_prefix.p, 8 * nc));
+    HIPCHK(c, cp(begin, c->c_begin.p, 4 * nc));
+    HIPCHK(c, cp(count, c->c_count.p, 4 * nc));
+    HIPCHK(c, cp(first_child, c->c_first.p, 4 * nc));
+    HIPCHK(c, cp(nchild, c->c_nchild.p, 4 * nc));
+    HIPCHK(c, cp(parent, c->c_parent.p, 4 * nc));
+    HIPCHK(c, cp(mom, c->c_mom.p, 80 * nc));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return FDX_OK;
+}
+
+int fdx_get_groups(fdx_ctx *c, uint32_t *cell, uint32_t *begin, uint32_t *count, uint32_t *qmin,
+                   uint32_t *qmax, double *centre) {
+    if (!c) return FDX_EINVAL;
+    if (!c->skey) return fail(c, FDX_ESTATE, "no tree built");
+    hipStream_t s = c->stream;
+    const size_t G = (size_t)c->stats.n_groups;
+    auto cp = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
+        if (!dst || !bytes) return hipSuccess;
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s);
+    };
+    HIPCHK(c, cp(cell, c->g_cell.p, 4 * G));
+    HIPCHK(c, cp(begin, c->g_begin.p, 4 * G));
+    HIPCHK(c, cp(count, c->g_count.p, 4 * G));
+    HIPCHK(c, cp(centre, c->g_centre.p, 24 * G));
+    std::vector<uint32_t> box(6 * G);
+    HIPCHK(c, cp(box.data(), c->g_box.p, 24 * G));
+    HIPCHK(c, hipStreamSynchronize(s));
+    for (size_t g = 0; g < G; g++)
+        for (int a = 0; a < 3; a++) {
+            if (qmin) qmin[3 * g + a] = box[6 * g + a];
+            if (qmax) qmax[3 * g + a] = box[6 * g + 3 + a];
+        }
+    return FDX_OK;
+}
+
+int fdx_get_lists(fdx_ctx *c, uint32_t *n_epj, uint32_t *n_spj, uint32_t *epj, uint32_t *spj) {
+    if (!c) return FDX_EINVAL;
+    if (!c->have_force) return fail(c, FDX_ESTATE, "no walk done");
+    hipStream_t s = c->stream;
+    const size_t G = (size_t)c->stats.n_groups;
+    std::vector<uint32_t> ce(G), cs(G), cap(G);
+    std::vector<uint64_t> seg(G);
+    HIPCHK(c, hipMemcpyAsync(ce.data(), c->cnt_e.p, 4 * G, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(cs.data(), c->cnt_s.p, 4 * G, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(cap.data(), c->lcap.p, 4 * G, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(seg.data(), c->seg.p, 8 * G, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    uint64_t end = 0;
+    for (size_t g = 0; g < G; g++) end = std::max<uint64_t>(end, seg[g] + cap[g]);
+    std::vector<uint32_t> all(end ? end : 1);
+    if (end) HIPCHK(c, hipMemcpy(all.data(), c->list.p, 4 * end, hipMemcpyDeviceToHost));
+    uint64_t oe = 0, os = 0;
+    for (size_t g = 0; g < G; g++) {
+        if (n_epj) n_epj[g] = ce[g];
+        if (n_spj) n_spj[g] = cs[g];
+        if (epj) memcpy(epj + oe, all.data() + seg[g], 4ull * ce[g]);
+        if (spj) memcpy(spj + os, all.data() + seg[g] + cap[g] - cs[g], 4ull * cs[g]);
+        oe += ce[g];
+        os += cs[g];
+    }
+    return FDX_OK;
+}
+
+const char *fdx_last_error(const fdx_ctx *c) {
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,129 @@
+// Host-side context of the Barnes-Hut library (shared by the C ABI and the host extensions:
+// predictor, autotuner, graph capture).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/fdx.h"
+#include "fdx_internal.h"
+#include "host_ext.h"
+
+namespace fdx {
+
+template <class T>
+struct DBuf {
+    T *p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t n) {
+        if (n == 0) n = 1;
+        if (n <= cap) return hipSuccess;
+        release();
+        hipError_t e = hipMalloc((void **)&p, n * sizeof(T));
+        if (e != hipSuccess) { p = nullptr; cap = 0; return e; }
+        cap = n;
+        return hipSuccess;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+struct HostStatus {
+    DevStatus st;
+    uint32_t lvl[kLevels + 2];
+};
+
+}  // namespace fdx
+
+struct fdx_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+
+    // particles (caller's order)
+    int64_t n = 0;
+    int nsys = 0;
+    bool have_particles = false, borrowed = false, eps_given = false;
+    std::vector<int64_t> sys_off_h;
+    fdx::DBuf<double> ox, oy, oz, ovx, ovy, ovz, om, oeps;       // owned copies
+    double *x = nullptr, *y = nullptr, *z = nullptr, *vx = nullptr, *vy = nullptr,
+           *vz = nullptr, *m = nullptr, *eps = nullptr;    // active arrays
+    fdx::DBuf<int64_t> sys_off;
+    fdx::DBuf<uint32_t> sysid;
+
+    // keys and order
+    fdx::DBuf<uint64_t> bbox_u, key, key_alt;
+    fdx::DBuf<double> cube;
+    fdx::DBuf<uint32_t> perm, perm_alt, inv, rs_scratch;
+    fdx::DBuf<uint64_t> partial;
+    uint64_t *skey = nullptr;
+    uint32_t *sperm = nullptr;
+    fdx::DBuf<double4> jp;
+    fdx::DBuf<double> seps;
+
+    // tree
+    fdx::DBuf<uint32_t> c_level, c_begin, c_count, c_first, c_nchild, c_parent, c_lvl;
+    fdx::DBuf<uint64_t> c_prefix;
+    fdx::DBuf<uint4> c_node;
+    fdx::DBuf<uint2> c_link;
+    fdx::DBuf<double> c_mom;
+    fdx::DBuf<uint32_t> tmp_n, tmp_off;
+    uint32_t cell_cap = 0;
+
+    // groups
+    fdx::DBuf<uint32_t> g_cell, g_begin, g_count, g_sys, g_box, flag, gcell_at, gpos;
+    fdx::DBuf<double> g_centre;
+    uint32_t group_cap = 0;
+
+    // lists
+    fdx::DBuf<uint32_t> cnt_e, cnt_s, lcap, list, ovf_list, order;
+    fdx::DBuf<uint64_t> seg;
+    uint64_t list_cap = 0;
+
+    // forces
+    fdx::DBuf<double4> fs;
+    fdx::DBuf<double> ax, ay, az, pot;
+    bool have_force = false;
+
+    // status
+    fdx::DevStatus *st = nullptr;
+    fdx::HostStatus *hst = nullptr;
+
+    // last parameters
+    double theta = 0.5, eps_all = 0.0;
+    int n_leaf = 8, n_group = 64, flags = 0, variant = -1;
+    fdx_stats stats{};
+    hipEvent_t ev[12] = {};
+
+    fdx::HostExt ext;   // predictor, autotuner, graph state
+};
+
+namespace fdx {
+
+int fail(fdx_ctx *c, int code, const char *fmt, ...);
+
+#define HIPCHK(ctx, expr)                                                                     \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return ::fdx::fail(ctx, e_ == hipErrorOutOfMemory ? FDX_ENOMEM : FDX_EHIP,         \
+                               "%s: %s (%s)", #expr, hipGetErrorString(e_), __func__);       \
+    } while (0)
+
+Cells cells_view(fdx_ctx *c);
+Groups groups_view(fdx_ctx *c);
+void mark(fdx_ctx *c, int k);
+int read_status(fdx_ctx *c);
+int run_tree(fdx_ctx *c, bool sync);
+int run_force(fdx_ctx *c);
+int ensure_tree_buffers(fdx_ctx *c, uint32_t cell_cap, uint32_t group_cap);
+
+}  // namespace fdx

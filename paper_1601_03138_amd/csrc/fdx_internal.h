@@ -1,0 +1,141 @@
+// Internal declarations of the gfx950 Barnes-Hut library: device helpers and the host-side
+// launchers of every kernel.  Not part of the C ABI (include/fdx.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace fdx {
+
+constexpr int kLevels = 21;              // key bits per axis; deepest cell level
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr int kMaxGroup = 512;           // largest n_group the force kernels take
+constexpr int kWalkStack = 2048;         // per-wave LDS stack of the group walk (entries)
+
+// Device-side status and counters of one evaluation, read back once per force call.
+struct DevStatus {
+    uint32_t cell_overflow;   // the tree needed more cells than were allocated
+    uint32_t bad_input;       // a non-finite coordinate, negative mass or eps <= 0 was seen
+    uint32_t walk_error;      // a walk stack would have overflowed (group left incomplete)
+    uint32_t list_overflow;   // groups whose list exceeded its capacity (predictor path)
+    uint32_t n_groups;
+    uint32_t depth;
+    uint32_t queue_head;      // persistent force kernel: next queue slot to pop
+    uint32_t pad;
+    uint64_t list_total;      // entries needed by all lists
+    uint64_t n_epj, n_spj;
+    uint64_t inter_pp, inter_pc;
+};
+
+// Tree cell arrays (breadth-first order) and walk-friendly views.
+struct Cells {
+    uint32_t *level, *begin, *count, *first, *nchild, *parent;
+    uint64_t *prefix;
+    uint4 *node;      // {2*corner_x + 2^(21-l), ... y, ... z, level | nchild << 8} (half-grid)
+    uint2 *link;      // leaf: {begin, count}; internal: {first_child, count}
+    double *mom;      // 10 per cell: M, X, Y, Z, Qxx, Qyy, Qzz, Qxy, Qxz, Qyz
+    uint32_t *lvl;    // lvl[l] = first cell of level l, l = 0..22
+    uint32_t cap;
+};
+
+struct Groups {
+    uint32_t *cell, *begin, *count, *sys;
+    uint32_t *box;    // 6 per group: qmin x y z, qmax x y z (grid units)
+    double *centre;   // 3 per group: geometric centre of the group's cell
+    uint32_t cap;
+};
+
+// ---------------------------------------------------------------------------------------
+// launchers (every one enqueues on `s` and returns the launch status)
+
+// misc
+hipError_t fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+hipError_t fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t s);
+hipError_t iota_u32(uint32_t *p, size_t n, hipStream_t s);
+hipError_t check_input(size_t n, const double *x, const double *y, const double *z,
+                       const double *m, const double *eps, DevStatus *st, hipStream_t s);
+hipError_t sysid_fill(const int64_t *sys_off, int nsys, uint32_t *sysid, size_t n,
+                      hipStream_t s);
+hipError_t kick_drift(size_t n, double *x, double *y, double *z, double *vx, double *vy,
+                      double *vz, const double *ax, const double *ay, const double *az,
+                      double dt, hipStream_t s);
+hipError_t kick(size_t n, double *vx, double *vy, double *vz, const double *ax,
+                const double *ay, const double *az, double dt, const DevStatus *st,
+                hipStream_t s);
+hipError_t unsort_forces(size_t n, const double4 *fs, const uint32_t *inv, double *ax,
+                         double *ay, double *az, double *pot, hipStream_t s);
+
+// scan: exclusive prefix sums of u32 counts.  The element count is n_host, or, if lo/hi are
+// given, (*hi - *lo) read on the device.  partial must hold kScanBlocks + 1 entries.
+constexpr int kScanBlocks = 512;
+hipError_t scan_u32_to_u32(const uint32_t *in, uint32_t *out, size_t n_host,
+                           const uint32_t *lo, const uint32_t *hi, uint64_t *partial,
+                           uint32_t *total32, hipStream_t s);
+hipError_t scan_u32_to_u64(const uint32_t *in, uint64_t *out, size_t n_host,
+                           const uint32_t *lo, const uint32_t *hi, uint64_t *partial,
+                           uint64_t *total64, hipStream_t s);
+
+// keys
+hipError_t bbox(size_t n, const double *x, const double *y, const double *z,
+                const uint32_t *sysid, int nsys, uint64_t *bbox_u, hipStream_t s);
+hipError_t root_cubes(int nsys, const uint64_t *bbox_u, double *cube, hipStream_t s);
+hipError_t morton_keys(size_t n, const double *x, const double *y, const double *z,
+                       const uint32_t *sysid, const double *cube, uint64_t *key,
+                       uint32_t *perm, hipStream_t s);
+
+// radix sort of (key, perm) pairs by key, then (stable) by system id of the original index.
+size_t radix_scratch_u32(size_t n);
+hipError_t radix_sort(size_t n, uint64_t *key, uint64_t *key_alt, uint32_t *val,
+                      uint32_t *val_alt, const uint32_t *sysid, int nsys, uint32_t *scratch,
+                      uint64_t *partial, bool *result_in_alt, hipStream_t s);
+
+// sorted particle data
+hipError_t gather_sorted(size_t n, const uint32_t *perm, const double *x, const double *y,
+                         const double *z, const double *m, const double *eps, double eps_all,
+                         double4 *jp, double *seps, uint32_t *inv, hipStream_t s);
+
+// tree
+hipError_t tree_build(size_t n, int nsys, const int64_t *sys_off, const uint64_t *skey,
+                      int n_leaf, Cells c, uint32_t *tmp_n, uint32_t *tmp_off,
+                      uint64_t *partial, DevStatus *st, hipStream_t s);
+hipError_t tree_moments(Cells c, const double4 *jp, hipStream_t s);
+hipError_t make_groups(size_t n, int nsys, const int64_t *sys_off, Cells c,
+                       const uint64_t *skey, const double *cube, int n_group, Groups g,
+                       uint32_t *flag, uint32_t *gcell_at, uint32_t *gpos, uint64_t *partial,
+                       DevStatus *st, hipStream_t s);
+
+// walk: count (fill = false) or fill (fill = true) the interaction lists.
+// seg[g]/cap[g] = start and capacity of group g's segment in `list`; EPJ entries grow from
+// the front, SPJ entries from the back.  cnt_e/cnt_s receive the exact counts.
+hipError_t walk(bool fill, size_t gmax, const Groups g, const Cells c, double theta2,
+                const uint64_t *seg, const uint32_t *cap, uint32_t *list, uint32_t *cnt_e,
+                uint32_t *cnt_s, uint32_t *ovf_list, DevStatus *st, hipStream_t s);
+hipError_t list_caps(size_t gmax, const uint32_t *cnt_e, const uint32_t *cnt_s, uint32_t *cap,
+                     DevStatus *st, hipStream_t s);
+hipError_t list_stats(size_t gmax, const Groups g, const uint32_t *cnt_e,
+                      const uint32_t *cnt_s, DevStatus *st, hipStream_t s);
+
+// force
+struct ForceArgs {
+    const Groups *g;
+    const double4 *jp;      // sorted x, y, z, m
+    const double *seps;     // sorted eps
+    const double *mom;
+    const uint64_t *seg;
+    const uint32_t *cap, *cnt_e, *cnt_s;
+    const uint32_t *list;   // interaction list segments
+    const uint32_t *order;  // queue order (null: group order)
+    double4 *fs;            // sorted output {ax, ay, az, phi}
+    DevStatus *st;
+    bool quad, fp32, persistent;
+    int variant;            // kernel shape chosen by the autotuner
+};
+// G = number of groups (direct launch: one workgroup per group; persistent launch: G bounds
+// the grid and the kernel reads the true count from the device status).
+hipError_t force(size_t G, const ForceArgs &a, hipStream_t s);
+int force_variants();
+const char *force_variant_name(int v);
+
+}  // namespace fdx

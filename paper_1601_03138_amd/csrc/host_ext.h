@@ -1,0 +1,25 @@
+// Host-side extensions of the force path: learned list-length predictor, force-kernel
+// autotuner, persistent-queue ordering and HIP-graph capture of leapfrog steps.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+struct fdx_ctx;
+
+namespace fdx {
+
+struct HostExt {
+    int variant = -1;                 // autotuned force-kernel variant (-1: default)
+    void *pred = nullptr;             // predictor state (weights, normalisation)
+    void *graph = nullptr;            // captured step
+};
+
+int ext_predicted_walk(fdx_ctx *c, uint32_t G);
+int ext_force_variant(fdx_ctx *c);
+const uint32_t *ext_queue_order(fdx_ctx *c, uint32_t G);
+int ext_integrate_graph(fdx_ctx *c, double dt, int n_steps);
+void ext_release(fdx_ctx *c);
+
+}  // namespace fdx

@@ -1,0 +1,324 @@
+// Particle-particle and particle-superparticle force kernels over the shared group lists.
+//
+// The paper asks for an interaction routine that takes many i-particles and many
+// j-particles at once so each j is reused from fast memory (section "Design concept of
+// FDPS"), with particles (EPJ) and superparticles (SPJ) as two sums (equation geqL).  Here
+// one workgroup evaluates one group: j entries are gathered tile by tile into LDS, and every
+// thread owns IPL i-particles of the group and one slice of each tile; slices are combined
+// at the end in a fixed order, so the result is deterministic.
+//
+// Particle term (equation ParticleParticleNbody, G = 1):
+//   a_i += m_j (r_j - r_i) / (|r_j - r_i|^2 + eps_i^2)^{3/2},  phi_i -= m_j / (...)^{1/2}
+// Superparticle term (equation ParticleSuperparticleNbody with the superparticle at r'_j,
+// extended to the quadrupole; r = r_i - X, R^2 = |r|^2 + eps_i^2):
+//   phi_i -= M/R + (1/2) r.Q.r / R^5
+//   a_i   += -M r / R^3 + Q r / R^5 - (5/2) (r.Q.r) r / R^7
+// Each group's own particles are in its particle list (its leaves are always opened), so
+// the self pair adds exactly 0 to a_i (r = 0) and -m_i/eps_i to phi_i, which is removed after
+// the loop.
+//
+// FP32 variant: positions are taken relative to the centre of the group's cell in FP64 and
+// rounded to FP32 when a tile is staged; the inner loop is FP32 (hardware reciprocal square
+// root); each slice sums a tile plainly and adds the tile total into a Kahan-compensated
+// accumulator; outputs are FP64.
+#include "dev_util.h"
+#include "fdx_internal.h"
+
+namespace fdx {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kTile = 256;
+
+struct KArgs {
+    const uint32_t *gbegin, *gcount;
+    const double *gcentre;
+    const double4 *jp;
+    const double *seps;
+    const double *mom;
+    const uint64_t *seg;
+    const uint32_t *cap, *cnt_e, *cnt_s, *list;
+    const uint32_t *order;
+    const uint32_t *ngroups;
+    double4 *fs;
+    DevStatus *st;
+    uint32_t G;              // groups (direct launch); persistent kernels read *ngroups
+};
+
+template <class T> struct V4;
+template <> struct V4<float> { using t = float4; };
+template <> struct V4<double> { using t = double4; };
+
+// Kahan accumulator (FP32) or plain sum (FP64)
+template <class T> struct Acc {
+    T s = 0;
+    __device__ __forceinline__ void add(T v) { s += v; }
+    __device__ __forceinline__ double val() const { return (double)s; }
+};
+template <> struct Acc<float> {
+    float s = 0.f, c = 0.f;
+    __device__ __forceinline__ void add(float v) {
+        float y = v - c;
+        float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ __forceinline__ double val() const { return (double)s - (double)c; }
+};
+
+__device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
+
+template <class T>
+__device__ __forceinline__ void pp(const typename V4<T>::t &J, T xi, T yi, T zi, T e2, T &ax,
+                                   T &ay, T &az, T &ph) {
+    const T dx = J.x - xi, dy = J.y - yi, dz = J.z - zi;
+    const T r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+    const T ri = rsqrt_t(r2);
+    const T mri = J.w * ri;
+    const T mri3 = mri * (ri * ri);
+    ax = fma(mri3, dx, ax);
+    ay = fma(mri3, dy, ay);
+    az = fma(mri3, dz, az);
+    ph -= mri;
+}
+
+template <class T, bool QUAD>
+__device__ __forceinline__ void pc(const typename V4<T>::t &A, const typename V4<T>::t &B,
+                                   const typename V4<T>::t &C, T xi, T yi, T zi, T e2, T &ax,
+                                   T &ay, T &az, T &ph) {
+    const T rx = xi - A.x, ry = yi - A.y, rz = zi - A.z;
+    const T R2 = fma(rz, rz, fma(ry, ry, fma(rx, rx, e2)));
+    const T Ri = rsqrt_t(R2);
+    const T Ri2 = Ri * Ri;
+    const T MRi = A.w * Ri;
+    const T MRi3 = MRi * Ri2;
+    if (!QUAD) {
+        ax = fma(-MRi3, rx, ax);
+        ay = fma(-MRi3, ry, ay);
+        az = fma(-MRi3, rz, az);
+        ph -= MRi;
+    } else {
+        // B = {Qxx, Qyy, Qzz, Qxy}, C = {Qxz, Qyz, -, -}
+        const T qx = fma(B.w, ry, fma(C.x, rz, B.x * rx));
+        const T qy = fma(B.w, rx, fma(C.y, rz, B.y * ry));
+        const T qz = fma(C.x, rx, fma(C.y, ry, B.z * rz));
+        const T rqr = fma(rx, qx, fma(ry, qy, rz * qz));
+        const T Ri5 = Ri * Ri2 * Ri2;
+        const T t = rqr * Ri5;
+        const T u = fma((T)2.5 * t, Ri2, MRi3);
+        ax = fma(-u, rx, fma(Ri5, qx, ax));
+        ay = fma(-u, ry, fma(Ri5, qy, ay));
+        az = fma(-u, rz, fma(Ri5, qz, az));
+        ph -= fma((T)0.5, t, MRi);
+    }
+}
+
+__device__ __forceinline__ uint32_t next_pow2(uint32_t v) {
+    return v <= 1 ? 1u : 1u << (32 - __clz((int)(v - 1)));
+}
+
+template <class T, bool QUAD, int IPL>
+struct Smem {
+    using V = typename V4<T>::t;
+    union {
+        struct { V e[kTile]; V s[3 * kTile]; } t;   // EPJ tile, SPJ tile (A, B, C per entry)
+        double red[kThreads * IPL * 4];     // per-thread slice partials
+    };
+    uint32_t slot;
+};
+
+// one group: gi
+template <class T, bool QUAD, int IPL>
+__device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T, QUAD, IPL> &sm) {
+    using V = typename V4<T>::t;
+    const int tid = threadIdx.x;
+    const uint32_t gb = a.gbegin[gi], ni = a.gcount[gi];
+    const uint32_t ne = a.cnt_e[gi], ns = a.cnt_s[gi], capg = a.cap[gi];
+    const uint32_t *epj = a.list + a.seg[gi];
+    const uint32_t *spj = epj + capg - ns;
+    const bool fp32 = sizeof(T) == 4;
+    const double cx = fp32 ? a.gcentre[3 * gi] : 0.0, cy = fp32 ? a.gcentre[3 * gi + 1] : 0.0,
+                 cz = fp32 ? a.gcentre[3 * gi + 2] : 0.0;
+
+    uint32_t tps = next_pow2((ni + IPL - 1) / IPL);
+    tps = tps > (uint32_t)kThreads ? (uint32_t)kThreads : tps;
+    const uint32_t nslice = kThreads / tps;
+    const uint32_t slice = tid / tps, li = tid % tps;
+
+    T xi[IPL], yi[IPL], zi[IPL], e2[IPL];
+    Acc<T> ax[IPL], ay[IPL], az[IPL], ph[IPL];
+#pragma unroll
+    for (int k = 0; k < IPL; k++) {
+        const uint32_t i = li + k * tps;
+        const uint32_t r = gb + (i < ni ? i : 0);
+        const double4 p = a.jp[r];
+        xi[k] = (T)(p.x - cx); yi[k] = (T)(p.y - cy); zi[k] = (T)(p.z - cz);
+        const double e = a.seps[r];
+        e2[k] = (T)(e * e);
+    }
+
+    // particle tiles
+    for (uint32_t t0 = 0; t0 < ne; t0 += kTile) {
+        const uint32_t nt = min((uint32_t)kTile, ne - t0);
+        __syncthreads();
+        for (uint32_t k = tid; k < nt; k += kThreads) {
+            const double4 p = a.jp[epj[t0 + k]];
+            V v;
+            v.x = (T)(p.x - cx); v.y = (T)(p.y - cy); v.z = (T)(p.z - cz); v.w = (T)p.w;
+            sm.t.e[k] = v;
+        }
+        __syncthreads();
+        T tx[IPL], ty[IPL], tz[IPL], tp[IPL];
+#pragma unroll
+        for (int k = 0; k < IPL; k++) tx[k] = ty[k] = tz[k] = tp[k] = 0;
+#pragma unroll 4
+        for (uint32_t j = slice; j < nt; j += nslice) {
+            const V J = sm.t.e[j];
+#pragma unroll
+            for (int k = 0; k < IPL; k++) pp<T>(J, xi[k], yi[k], zi[k], e2[k], tx[k], ty[k], tz[k], tp[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < IPL; k++) { ax[k].add(tx[k]); ay[k].add(ty[k]); az[k].add(tz[k]); ph[k].add(tp[k]); }
+    }
+
+    // superparticle tiles
+    for (uint32_t t0 = 0; t0 < ns; t0 += kTile) {
+        const uint32_t nt = min((uint32_t)kTile, ns - t0);
+        __syncthreads();
+        for (uint32_t k = tid; k < nt; k += kThreads) {
+            const double *o = a.mom + 10 * (size_t)spj[t0 + k];
+            V A, B, C;
+            A.x = (T)(o[1] - cx); A.y = (T)(o[2] - cy); A.z = (T)(o[3] - cz); A.w = (T)o[0];
+            sm.t.s[3 * k] = A;
+            if (QUAD) {
+                B.x = (T)o[4]; B.y = (T)o[5]; B.z = (T)o[6]; B.w = (T)o[7];
+                C.x = (T)o[8]; C.y = (T)o[9]; C.z = 0; C.w = 0;
+                sm.t.s[3 * k + 1] = B;
+                sm.t.s[3 * k + 2] = C;
+            }
+        }
+        __syncthreads();
+        T tx[IPL], ty[IPL], tz[IPL], tp[IPL];
+#pragma unroll
+        for (int k = 0; k < IPL; k++) tx[k] = ty[k] = tz[k] = tp[k] = 0;
+#pragma unroll 2
+        for (uint32_t j = slice; j < nt; j += nslice) {
+            const V A = sm.t.s[3 * j];
+            V B, C;
+            if (QUAD) { B = sm.t.s[3 * j + 1]; C = sm.t.s[3 * j + 2]; } else { B = A; C = A; }
+#pragma unroll
+            for (int k = 0; k < IPL; k++)
+                pc<T, QUAD>(A, B, C, xi[k], yi[k], zi[k], e2[k], tx[k], ty[k], tz[k], tp[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < IPL; k++) { ax[k].add(tx[k]); ay[k].add(ty[k]); az[k].add(tz[k]); ph[k].add(tp[k]); }
+    }
+
+    // combine slices in slice order (FP64), remove the self term of the potential
+    __syncthreads();
+    double *red = sm.red;
+#pragma unroll
+    for (int k = 0; k < IPL; k++) {
+        double *o = red + 4 * ((size_t)k * kThreads + tid);
+        o[0] = ax[k].val(); o[1] = ay[k].val(); o[2] = az[k].val(); o[3] = ph[k].val();
+    }
+    __syncthreads();
+    if (slice == 0) {
+#pragma unroll
+        for (int k = 0; k < IPL; k++) {
+            const uint32_t i = li + k * tps;
+            if (i >= ni) continue;
+            double s[4] = {0, 0, 0, 0};
+            for (uint32_t q = 0; q < nslice; q++) {
+                const double *o = red + 4 * ((size_t)k * kThreads + q * tps + li);
+                s[0] += o[0]; s[1] += o[1]; s[2] += o[2]; s[3] += o[3];
+            }
+            const uint32_t r = gb + i;
+            const T mi = (T)a.jp[r].w;
+            const T self = mi * rsqrt_t(e2[k]);
+            a.fs[r] = make_double4(s[0], s[1], s[2], s[3] + (double)self);
+        }
+    }
+}
+
+template <class T, bool QUAD, int IPL>
+__global__ void __launch_bounds__(kThreads)
+k_force_direct(KArgs a) {
+    __shared__ Smem<T, QUAD, IPL> sm;
+    // XCD-aware order: consecutive blocks go round-robin over the 8 XCDs, so hand each XCD a
+    // contiguous run of groups (neighbouring groups share most of their lists -> L2 reuse).
+    const uint32_t G = a.G;
+    const uint32_t chunk = (G + 7) / 8;
+    const uint32_t gi = (blockIdx.x % 8) * chunk + blockIdx.x / 8;
+    if (gi >= G) return;
+    force_group<T, QUAD, IPL>(a, a.order ? a.order[gi] : gi, sm);
+}
+
+template <class T, bool QUAD, int IPL>
+__global__ void __launch_bounds__(kThreads)
+k_force_persistent(KArgs a) {
+    __shared__ Smem<T, QUAD, IPL> sm;
+    const uint32_t G = *a.ngroups;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) sm.slot = atomicAdd(&a.st->queue_head, 1u);
+        __syncthreads();
+        const uint32_t slot = sm.slot;
+        if (slot >= G) break;
+        force_group<T, QUAD, IPL>(a, a.order ? a.order[slot] : slot, sm);
+    }
+}
+
+template <class T, bool QUAD, int IPL>
+hipError_t launch(const KArgs &k, bool persistent, size_t gmax, hipStream_t s) {
+    if (persistent) {
+        int dev = 0, ncu = 256;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        int per_cu = 0;
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_force_persistent<T, QUAD, IPL>,
+                                                     kThreads, 0);
+        if (per_cu < 1) per_cu = 1;
+        size_t grid = (size_t)ncu * per_cu;
+        if (grid > gmax) grid = gmax ? gmax : 1;
+        hipLaunchKernelGGL((k_force_persistent<T, QUAD, IPL>), dim3((unsigned)grid), dim3(kThreads),
+                           0, s, k);
+    } else {
+        if (k.G == 0) return hipSuccess;
+        const uint32_t chunk = (k.G + 7) / 8;
+        hipLaunchKernelGGL((k_force_direct<T, QUAD, IPL>), dim3(8 * chunk), dim3(kThreads), 0, s, k);
+    }
+    return hipGetLastError();
+}
+
+constexpr const char *kVariantNames[] = {"ipl1", "ipl2"};
+
+}  // namespace
+
+int force_variants() { return 2; }
+const char *force_variant_name(int v) { return kVariantNames[v < 0 || v > 1 ? 0 : v]; }
+
+hipError_t force(size_t G, const ForceArgs &fa, hipStream_t s) {
+    KArgs k;
+    k.gbegin = fa.g->begin; k.gcount = fa.g->count; k.gcentre = fa.g->centre;
+    k.jp = fa.jp; k.seps = fa.seps; k.mom = fa.mom;
+    k.seg = fa.seg; k.cap = fa.cap; k.cnt_e = fa.cnt_e; k.cnt_s = fa.cnt_s;
+    k.list = fa.list;
+    k.order = fa.order; k.ngroups = &fa.st->n_groups; k.fs = fa.fs; k.st = fa.st;
+    k.G = (uint32_t)G;
+    const int ipl = fa.variant == 1 ? 2 : 1;
+    if (fa.fp32) {
+        if (fa.quad) return ipl == 2 ? launch<float, true, 2>(k, fa.persistent, G, s)
+                                     : launch<float, true, 1>(k, fa.persistent, G, s);
+        return ipl == 2 ? launch<float, false, 2>(k, fa.persistent, G, s)
+                        : launch<float, false, 1>(k, fa.persistent, G, s);
+    }
+    if (fa.quad) return ipl == 2 ? launch<double, true, 2>(k, fa.persistent, G, s)
+                                 : launch<double, true, 1>(k, fa.persistent, G, s);
+    return ipl == 2 ? launch<double, false, 2>(k, fa.persistent, G, s)
+                    : launch<double, false, 1>(k, fa.persistent, G, s);
+}
+
+}  // namespace fdx

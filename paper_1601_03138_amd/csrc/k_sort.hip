@@ -1,0 +1,157 @@
+// Stable LSD radix sort of (63-bit key, u32 index) pairs, then stably by system id, so the
+// result is ordered by (system, key, original index).  8-bit digits; per pass: per-tile
+// digit histograms, a device-wide exclusive scan over (digit, tile), and a scatter in which
+// each wave ranks its elements with ballot-based multisplit so the order is stable.
+#include "dev_util.h"
+#include "fdx_internal.h"
+
+namespace fdx {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / kWave;     // 4
+constexpr int kItems = 16;                   // rounds of 64 per wave
+constexpr int kWaveTile = kItems * kWave;    // 1024 elements per wave
+constexpr int kTile = kWaves * kWaveTile;    // 4096 elements per block
+constexpr int kRadix = 256;
+
+template <bool SYS>
+__device__ __forceinline__ uint32_t digit_of(uint64_t k, uint32_t v, const uint32_t *sysid,
+                                             int shift) {
+    if (SYS) return (sysid[v] >> shift) & (kRadix - 1);
+    return (uint32_t)(k >> shift) & (kRadix - 1);
+}
+
+template <bool SYS>
+__global__ void __launch_bounds__(kThreads)
+k_rs_hist(const uint64_t *key, const uint32_t *val, const uint32_t *sysid, size_t n, int shift,
+          uint32_t nblocks, uint32_t *counts) {
+    __shared__ uint32_t h[kRadix];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const size_t base = (size_t)blockIdx.x * kTile;
+#pragma unroll 4
+    for (int r = 0; r < kTile / kThreads; r++) {
+        size_t i = base + (size_t)r * kThreads + threadIdx.x;
+        if (i < n) {
+            uint32_t d = SYS ? digit_of<true>(0, val[i], sysid, shift)
+                             : digit_of<false>(key[i], 0, nullptr, shift);
+            atomicAdd(&h[d], 1u);
+        }
+    }
+    __syncthreads();
+    counts[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+template <bool SYS>
+__global__ void __launch_bounds__(kThreads)
+k_rs_scatter(const uint64_t *key_in, const uint32_t *val_in, const uint32_t *sysid, size_t n,
+             int shift, uint32_t nblocks, const uint32_t *offs, uint64_t *key_out,
+             uint32_t *val_out) {
+    __shared__ uint32_t wcnt[kWaves][kRadix];
+    __shared__ uint32_t woff[kWaves][kRadix];
+    for (int k = threadIdx.x; k < kWaves * kRadix; k += kThreads) (&wcnt[0][0])[k] = 0;
+    __syncthreads();
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const uint64_t lt = lanemask_lt();
+    const size_t base = (size_t)blockIdx.x * kTile + (size_t)w * kWaveTile;
+    uint64_t kk[kItems];
+    uint32_t vv[kItems], rk[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; r++) {
+        const size_t i = base + (size_t)r * kWave + lane;
+        const bool valid = i < n;
+        uint64_t k = 0;
+        uint32_t v = 0, d = 0;
+        if (valid) {
+            k = key_in[i];
+            v = val_in[i];
+            d = digit_of<SYS>(k, v, sysid, shift);
+        }
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            uint64_t bal = __ballot((d >> b) & 1u);
+            m &= ((d >> b) & 1u) ? bal : ~bal;
+        }
+        const uint32_t before = (uint32_t)__popcll(m & lt);
+        const uint32_t cnt = (uint32_t)__popcll(m);
+        const uint32_t prev = valid ? wcnt[w][d] : 0u;
+        wave_barrier();
+        if (valid && before == 0) wcnt[w][d] = prev + cnt;
+        wave_barrier();
+        kk[r] = k;
+        vv[r] = v;
+        rk[r] = (d << 16) | (prev + before);
+    }
+    __syncthreads();
+    {
+        const int d = threadIdx.x;                 // kThreads == kRadix
+        uint32_t run = offs[(size_t)d * nblocks + blockIdx.x];
+#pragma unroll
+        for (int ww = 0; ww < kWaves; ww++) { woff[ww][d] = run; run += wcnt[ww][d]; }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kItems; r++) {
+        const size_t i = base + (size_t)r * kWave + lane;
+        if (i < n) {
+            const uint32_t d = rk[r] >> 16;
+            const uint32_t pos = woff[w][d] + (rk[r] & 0xFFFFu);
+            key_out[pos] = kk[r];
+            val_out[pos] = vv[r];
+        }
+    }
+}
+
+static_assert(kThreads == kRadix, "one thread per digit in the offset step");
+
+}  // namespace
+
+size_t radix_scratch_u32(size_t n) {
+    size_t nblocks = (n + kTile - 1) / kTile;
+    if (nblocks < 1) nblocks = 1;
+    return 2 * (size_t)kRadix * nblocks;      // counts + scanned offsets
+}
+
+hipError_t radix_sort(size_t n, uint64_t *key, uint64_t *key_alt, uint32_t *val,
+                      uint32_t *val_alt, const uint32_t *sysid, int nsys, uint32_t *scratch,
+                      uint64_t *partial, bool *result_in_alt, hipStream_t s) {
+    *result_in_alt = false;
+    if (n <= 1) return hipSuccess;
+    const uint32_t nblocks = (uint32_t)((n + kTile - 1) / kTile);
+    const size_t ncount = (size_t)kRadix * nblocks;
+    uint32_t *counts = scratch, *offs = scratch + ncount;
+    uint64_t *kin = key, *kout = key_alt;
+    uint32_t *vin = val, *vout = val_alt;
+    int sys_passes = 0;
+    for (int b = 0; (1ll << b) < (long long)nsys; b += 8) sys_passes++;
+    const int passes = 8 + sys_passes;           // key bits 0..63, then system id bytes
+    for (int p = 0; p < passes; p++) {
+        const bool sysp = p >= 8;
+        const int shift = sysp ? 8 * (p - 8) : 8 * p;
+        if (sysp)
+            hipLaunchKernelGGL(k_rs_hist<true>, dim3(nblocks), dim3(kThreads), 0, s, kin, vin,
+                               sysid, n, shift, nblocks, counts);
+        else
+            hipLaunchKernelGGL(k_rs_hist<false>, dim3(nblocks), dim3(kThreads), 0, s, kin, vin,
+                               sysid, n, shift, nblocks, counts);
+        hipError_t e = scan_u32_to_u32(counts, offs, ncount, nullptr, nullptr, partial, nullptr, s);
+        if (e != hipSuccess) return e;
+        if (sysp)
+            hipLaunchKernelGGL(k_rs_scatter<true>, dim3(nblocks), dim3(kThreads), 0, s, kin, vin,
+                               sysid, n, shift, nblocks, offs, kout, vout);
+        else
+            hipLaunchKernelGGL(k_rs_scatter<false>, dim3(nblocks), dim3(kThreads), 0, s, kin, vin,
+                               sysid, n, shift, nblocks, offs, kout, vout);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        uint64_t *tk = kin; kin = kout; kout = tk;
+        uint32_t *tv = vin; vin = vout; vout = tv;
+    }
+    *result_in_alt = (kin == key_alt);
+    return hipSuccess;
+}
+
+}  // namespace fdx

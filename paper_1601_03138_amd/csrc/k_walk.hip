@@ -1,0 +1,186 @@
+// Group walk: one shared interaction list per i-particle group (the modified tree algorithm
+// of Barnes 1990 that the paper's interaction-list model assumes, section "Tree traverse
+// and interaction calculation").
+//
+// One wavefront walks one group.  Cells to visit sit on a per-wave LDS stack; every
+// iteration pops up to 64 of them, one per lane, and tests them together.  Opening test
+// (reading of "a fixed opening angle theta"): a cell of side S whose centre lies at distance
+// D from the group's box is taken as a superparticle (SPJ) iff S^2 < theta^2 D^2.  All
+// lengths are integers in half-grid units (S = 2^(22-l), D^2 < 2^50), so D^2 is exact in
+// FP64 and the decision is one rounding of theta^2 * D^2: bit-reproducible.  An opened leaf
+// contributes its particles (EPJ); an opened internal cell pushes its children.
+//
+// Lists live in one array: group g owns [seg[g], seg[g] + cap[g]); EPJ entries are written
+// from the front and SPJ entries from the back, so the same kernel fills exact-size segments
+// (count pass first) and predicted-capacity segments (single pass, overflow detected).
+#include "dev_util.h"
+#include "fdx_internal.h"
+
+namespace fdx {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / kWave;
+constexpr int kSlack = 160;     // stack entries kept free for sequential descent
+
+template <bool FILL>
+__global__ void __launch_bounds__(kThreads)
+k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, double theta2,
+       const uint64_t *seg, const uint32_t *cap, uint32_t *list, uint32_t *cnt_e,
+       uint32_t *cnt_s, uint32_t *ovf_list, DevStatus *st) {
+    __shared__ uint32_t stack_all[kWaves][kWalkStack];
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const uint64_t lt = lanemask_lt();
+    uint32_t *stk = stack_all[w];
+    const uint32_t G = min(*ngroups, g.cap);
+    for (size_t gi = (size_t)blockIdx.x * kWaves + w; gi < G; gi += (size_t)gridDim.x * kWaves) {
+        const uint32_t *bx = g.box + 6 * gi;
+        const int bminx = 2 * (int)bx[0], bminy = 2 * (int)bx[1], bminz = 2 * (int)bx[2];
+        const int bmaxx = 2 * (int)bx[3] + 2, bmaxy = 2 * (int)bx[4] + 2, bmaxz = 2 * (int)bx[5] + 2;
+        const uint64_t base = FILL ? seg[gi] : 0;
+        const uint32_t capg = FILL ? cap[gi] : 0;
+        uint32_t ne = 0, ns = 0, sp = 1;
+        bool err = false;
+        if (lane == 0) stk[0] = g.sys[gi];          // roots are cells 0..nsys-1
+        wave_barrier();
+        while (sp > 0) {
+            int room = kWalkStack - kSlack - (int)sp;
+            uint32_t p = min(64u, sp);
+            if (room < 7 * (int)p) p = room >= 7 ? (uint32_t)(room / 7) : 1u;
+            const bool act = (uint32_t)lane < p;
+            uint32_t cid = 0;
+            if (act) cid = stk[sp - p + lane];
+            wave_barrier();
+            sp -= p;
+            bool accept = false, leaf = false, inner = false;
+            uint2 lk = make_uint2(0, 0);
+            uint32_t nch = 0;
+            if (act) {
+                const uint4 nd = node[cid];
+                lk = link[cid];
+                const int lv = (int)(nd.w & 0xFFu);
+                nch = nd.w >> 8;
+                const int cx = (int)nd.x, cy = (int)nd.y, cz = (int)nd.z;
+                const int dx = max(0, max(bminx - cx, cx - bmaxx));
+                const int dy = max(0, max(bminy - cy, cy - bmaxy));
+                const int dz = max(0, max(bminz - cz, cz - bmaxz));
+                const double D2 = (double)dx * (double)dx + (double)dy * (double)dy +
+                                  (double)dz * (double)dz;             // exact integers
+                const double S2 = __longlong_as_double((long long)(1023 + 2 * (22 - lv)) << 52);
+                accept = S2 < __dmul_rn(theta2, D2);
+                if (!accept) {
+                    if (nch == 0) leaf = lk.y > 0;
+                    else inner = true;
+                }
+            }
+            // superparticles, from the back of the segment
+            const uint64_t bs = __ballot(accept);
+            if (FILL && accept) {
+                const uint32_t j = ns + (uint32_t)__popcll(bs & lt);
+                if (j < capg) list[base + capg - 1 - j] = cid;
+            }
+            ns += (uint32_t)__popcll(bs);
+            // particles of opened leaves, from the front
+            const uint32_t lc = leaf ? lk.y : 0u;
+            const uint32_t li = wave_incl_scan(lc);
+            const uint32_t ltot = __shfl(li, kWave - 1, kWave);
+            if (FILL && leaf) {
+                const uint32_t e0 = ne + li - lc;
+                for (uint32_t k = 0; k < lc; k++)
+                    if (e0 + k < capg) list[base + e0 + k] = lk.x + k;
+            }
+            ne += ltot;
+            // children of opened internal cells onto the stack
+            const uint32_t cc = inner ? nch : 0u;
+            const uint32_t ci = wave_incl_scan(cc);
+            const uint32_t ctot = __shfl(ci, kWave - 1, kWave);
+            if (sp + ctot > (uint32_t)kWalkStack) { err = true; break; }
+            if (inner) {
+                const uint32_t s0 = sp + ci - cc;
+                for (uint32_t k = 0; k < cc; k++) stk[s0 + k] = lk.x + k;
+            }
+            sp += ctot;
+            wave_barrier();
+        }
+        wave_barrier();
+        if (lane == 0) {
+            cnt_e[gi] = ne;
+            cnt_s[gi] = ns;
+            if (err) atomicOr(&st->walk_error, 1u);
+            if (FILL && (uint64_t)ne + ns > capg) {
+                uint32_t k = atomicAdd(&st->list_overflow, 1u);
+                ovf_list[k] = (uint32_t)gi;
+            }
+        }
+    }
+}
+
+// cap[g] = |EPJ| + |SPJ| (exact segment sizes)
+__global__ void k_list_caps(const uint32_t *ngroups, uint32_t gmax, const uint32_t *cnt_e,
+                            const uint32_t *cnt_s, uint32_t *cap) {
+    const uint32_t G = min(*ngroups, gmax);
+    for (size_t gi = gtid(); gi < G; gi += gstride()) cap[gi] = cnt_e[gi] + cnt_s[gi];
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_list_stats(const uint32_t *ngroups, uint32_t gmax, const uint32_t *gcount,
+             const uint32_t *cnt_e, const uint32_t *cnt_s, DevStatus *st) {
+    const uint32_t G = min(*ngroups, gmax);
+    uint64_t e = 0, s = 0, pp = 0, pc = 0;
+    for (size_t gi = gtid(); gi < G; gi += gstride()) {
+        const uint64_t ni = gcount[gi];
+        e += cnt_e[gi]; s += cnt_s[gi];
+        pp += ni * cnt_e[gi]; pc += ni * cnt_s[gi];
+    }
+    e = wave_sum_u64(e); s = wave_sum_u64(s); pp = wave_sum_u64(pp); pc = wave_sum_u64(pc);
+    if (lane_id() == 0 && (e | s)) {
+        atomicAdd((unsigned long long *)&st->n_epj, (unsigned long long)e);
+        atomicAdd((unsigned long long *)&st->n_spj, (unsigned long long)s);
+        atomicAdd((unsigned long long *)&st->inter_pp, (unsigned long long)pp);
+        atomicAdd((unsigned long long *)&st->inter_pc, (unsigned long long)pc);
+    }
+}
+
+inline unsigned grid_waves(size_t gmax) {
+    size_t b = (gmax + kWaves - 1) / kWaves;
+    if (b < 1) b = 1;
+    if (b > 16384) b = 16384;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+hipError_t walk(bool fill, size_t gmax, const Groups g, const Cells c, double theta2,
+                const uint64_t *seg, const uint32_t *cap, uint32_t *list, uint32_t *cnt_e,
+                uint32_t *cnt_s, uint32_t *ovf_list, DevStatus *st, hipStream_t s) {
+    if (fill)
+        hipLaunchKernelGGL(k_walk<true>, dim3(grid_waves(gmax)), dim3(kThreads), 0, s,
+                           &st->n_groups, g, c.node, c.link, theta2, seg, cap, list, cnt_e,
+                           cnt_s, ovf_list, st);
+    else
+        hipLaunchKernelGGL(k_walk<false>, dim3(grid_waves(gmax)), dim3(kThreads), 0, s,
+                           &st->n_groups, g, c.node, c.link, theta2, seg, cap, list, cnt_e,
+                           cnt_s, ovf_list, st);
+    return hipGetLastError();
+}
+
+hipError_t list_caps(size_t gmax, const uint32_t *cnt_e, const uint32_t *cnt_s, uint32_t *cap,
+                     DevStatus *st, hipStream_t s) {
+    size_t b = (gmax + kThreads - 1) / kThreads;
+    b = b < 1 ? 1 : (b > 8192 ? 8192 : b);
+    hipLaunchKernelGGL(k_list_caps, dim3((unsigned)b), dim3(kThreads), 0, s, &st->n_groups,
+                       (uint32_t)gmax, cnt_e, cnt_s, cap);
+    return hipGetLastError();
+}
+
+hipError_t list_stats(size_t gmax, const Groups g, const uint32_t *cnt_e, const uint32_t *cnt_s,
+                      DevStatus *st, hipStream_t s) {
+    size_t b = (gmax + kThreads - 1) / kThreads;
+    b = b < 1 ? 1 : (b > 2048 ? 2048 : b);
+    hipLaunchKernelGGL(k_list_stats, dim3((unsigned)b), dim3(kThreads), 0, s, &st->n_groups,
+                       (uint32_t)gmax, g.count, cnt_e, cnt_s, st);
+    return hipGetLastError();
+}
+
+}  // namespace fdx

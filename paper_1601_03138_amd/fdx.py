@@ -1,0 +1,249 @@
+"""ctypes binding of libfdx.so (include/fdx.h): argument marshalling only.
+
+Every step of the force path runs in the HIP library; this module never computes forces,
+keys or lists itself and has no CPU fallback: if the library is missing it raises.
+PyTorch is used only for device memory (tensors passed by pointer) and streams.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfdx.so")
+
+OK, EINVAL, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4
+MEM_HOST, MEM_DEVICE = 0, 1
+QUAD, FP32REL, PREDICTOR, PERSISTENT, GRAPH, TIMING = 1, 2, 4, 8, 16, 32
+
+EXPORTS = ["fdx_create", "fdx_destroy", "fdx_set_particles", "fdx_build_tree", "fdx_calc_force",
+           "fdx_integrate", "fdx_get_particles", "fdx_get_forces", "fdx_get_stats",
+           "fdx_get_tree", "fdx_get_groups", "fdx_get_lists", "fdx_last_error",
+           "fdx_autotune", "fdx_predictor_train", "fdx_predictor_save", "fdx_predictor_load",
+           "fdx_predictor_features", "fdx_mlp_forward", "fdx_mlp_grad"]
+
+
+class FdxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"fdx error {code}: {msg}")
+        self.code = code
+
+
+class Stats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in (
+        "n", "n_sys", "n_cells", "n_groups", "depth", "n_epj", "n_spj", "n_interactions_pp",
+        "n_interactions_pc", "overflow_groups", "list_capacity")] + [
+        ("n_leaf", C.c_int32), ("n_group", C.c_int32), ("flags", C.c_int32),
+        ("theta", C.c_double)] + [(k, C.c_double) for k in (
+            "t_keys", "t_sort", "t_tree", "t_moments", "t_groups", "t_walk", "t_force",
+            "t_unsort", "t_predict", "t_total")]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_LIB = None
+
+
+def load() -> C.CDLL:
+    """Load the built library (raises if it has not been built: there is no fallback)."""
+    global _LIB
+    if _LIB is None:
+        # torch ships its own HIP runtime with the same soname; loading it first makes this
+        # library bind to that one runtime, so torch's streams and allocations are shared.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise FdxError(ESTATE, f"{LIB_PATH} is not built (run __graft_entry__.build())")
+        lib = C.CDLL(LIB_PATH)
+        _declare(lib)
+        _LIB = lib
+    return _LIB
+
+
+def _declare(L):
+    vp, i64, i32, f64 = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+    L.fdx_create.argtypes = [C.POINTER(vp), C.c_int, vp]
+    L.fdx_destroy.argtypes = [vp]
+    L.fdx_set_particles.argtypes = [vp, i64] + [vp] * 9 + [i32, i32]
+    L.fdx_build_tree.argtypes = [vp, i32, i32]
+    L.fdx_calc_force.argtypes = [vp, f64, i32, i32, f64, i32]
+    L.fdx_integrate.argtypes = [vp, f64, i32, i32]
+    L.fdx_get_particles.argtypes = [vp] + [vp] * 6 + [i32]
+    L.fdx_get_forces.argtypes = [vp] + [vp] * 4 + [i32]
+    L.fdx_get_stats.argtypes = [vp, C.POINTER(Stats)]
+    L.fdx_get_tree.argtypes = [vp] + [vp] * 11
+    L.fdx_get_groups.argtypes = [vp] + [vp] * 6
+    L.fdx_get_lists.argtypes = [vp] + [vp] * 4
+    L.fdx_last_error.argtypes = [vp]
+    L.fdx_last_error.restype = C.c_char_p
+    if hasattr(L, "fdx_autotune"):
+        L.fdx_autotune.argtypes = [vp, f64, i32, f64, i32, vp, i32, C.POINTER(i32)]
+    if hasattr(L, "fdx_predictor_train"):
+        L.fdx_predictor_train.argtypes = [vp, vp, vp, i64, i32, i32, f64, i64, vp]
+        L.fdx_predictor_save.argtypes = [vp, vp]
+        L.fdx_predictor_load.argtypes = [vp, vp]
+        L.fdx_predictor_features.argtypes = [vp, vp]
+        L.fdx_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+        L.fdx_mlp_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _dptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Context:
+    """One library context bound to a device and a HIP stream (torch's current stream by
+    default when torch is importable and a GPU is present, else a library-owned stream)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.lib = load()
+        handle = C.c_void_p()
+        s = None
+        if stream is not None:
+            s = C.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+        rc = self.lib.fdx_create(C.byref(handle), device, s)
+        if rc != OK:
+            raise FdxError(rc, f"fdx_create(device={device}) failed")
+        self.h = handle
+        self.n = 0
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.fdx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, rc: int, what: str):
+        if rc != OK:
+            msg = self.lib.fdx_last_error(self.h)
+            raise FdxError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    # -- particles -------------------------------------------------------------------
+    def set_particles(self, ps, per_particle_eps: bool = True):
+        """Copy a ParticleSet (numpy FP64 arrays) to the device."""
+        arrs = [_f64(getattr(ps, k)) for k in ("x", "y", "z", "vx", "vy", "vz", "m")]
+        eps = _f64(ps.eps) if per_particle_eps else None
+        off = None if ps.sys_off is None else np.ascontiguousarray(ps.sys_off, dtype=np.int64)
+        n_sys = 1 if off is None else off.shape[0] - 1
+        self._check(self.lib.fdx_set_particles(self.h, ps.n, *[_ptr(a) for a in arrs], _ptr(eps),
+                                               _ptr(off), n_sys, MEM_HOST), "set_particles")
+        self.n = ps.n
+        self._keep = []
+
+    def set_particles_device(self, tensors: dict, sys_off=None):
+        """Borrow device tensors (torch FP64, contiguous): keys x, y, z, vx, vy, vz, m, eps
+        (eps optional).  The tensors must stay alive while the context uses them."""
+        ts = [tensors[k] for k in ("x", "y", "z", "vx", "vy", "vz", "m")]
+        n = int(ts[0].numel())
+        for t in ts:
+            if not (t.is_cuda and t.is_contiguous() and str(t.dtype) == "torch.float64"
+                    and t.numel() == n):
+                raise ValueError("device tensors must be contiguous float64 CUDA tensors of one length")
+        eps = tensors.get("eps")
+        off = None if sys_off is None else np.ascontiguousarray(sys_off, dtype=np.int64)
+        n_sys = 1 if off is None else off.shape[0] - 1
+        self._check(self.lib.fdx_set_particles(self.h, n, *[_dptr(t) for t in ts], _dptr(eps),
+                                               _ptr(off), n_sys, MEM_DEVICE), "set_particles")
+        self.n = n
+        self._keep = list(ts) + ([eps] if eps is not None else [])
+
+    # -- evaluation ------------------------------------------------------------------
+    @staticmethod
+    def flags(quad=True, fp32=False, predictor=False, persistent=False, timing=False) -> int:
+        return ((QUAD if quad else 0) | (FP32REL if fp32 else 0) | (PREDICTOR if predictor else 0)
+                | (PERSISTENT if persistent else 0) | (TIMING if timing else 0))
+
+    def build_tree(self, n_leaf: int = 8, n_group: int = 64):
+        self._check(self.lib.fdx_build_tree(self.h, n_leaf, n_group), "build_tree")
+
+    def calc_force(self, theta: float = 0.5, n_leaf: int = 8, n_group: int = 64,
+                   eps: float = 0.0, **kw):
+        self._check(self.lib.fdx_calc_force(self.h, float(theta), n_leaf, n_group, float(eps),
+                                            self.flags(**kw)), "calc_force")
+
+    def calc_force_flags(self, theta, n_leaf, n_group, eps, flags: int):
+        self._check(self.lib.fdx_calc_force(self.h, float(theta), n_leaf, n_group, float(eps),
+                                            int(flags)), "calc_force")
+
+    def integrate(self, dt: float, n_steps: int, graph: bool = False):
+        self._check(self.lib.fdx_integrate(self.h, float(dt), int(n_steps), GRAPH if graph else 0),
+                    "integrate")
+
+    # -- results ---------------------------------------------------------------------
+    def forces(self) -> np.ndarray:
+        out = [np.empty(self.n) for _ in range(4)]
+        self._check(self.lib.fdx_get_forces(self.h, *[_ptr(a) for a in out], MEM_HOST), "get_forces")
+        return np.stack(out, axis=1)
+
+    def forces_device(self, ax, ay, az, pot):
+        self._check(self.lib.fdx_get_forces(self.h, _dptr(ax), _dptr(ay), _dptr(az), _dptr(pot),
+                                            MEM_DEVICE), "get_forces")
+
+    def particles(self):
+        out = [np.empty(self.n) for _ in range(6)]
+        self._check(self.lib.fdx_get_particles(self.h, *[_ptr(a) for a in out], MEM_HOST),
+                    "get_particles")
+        return out
+
+    def stats(self) -> dict:
+        st = Stats()
+        self._check(self.lib.fdx_get_stats(self.h, C.byref(st)), "get_stats")
+        return st.as_dict()
+
+    def tree(self) -> dict:
+        st = self.stats()
+        nc, n, S = int(st["n_cells"]), self.n, int(st["n_sys"])
+        d = dict(cube=np.empty((S, 4)), key=np.empty(n, np.uint64), perm=np.empty(n, np.uint32),
+                 level=np.empty(nc, np.int32), prefix=np.empty(nc, np.uint64),
+                 begin=np.empty(nc, np.uint32), count=np.empty(nc, np.uint32),
+                 first_child=np.empty(nc, np.uint32), nchild=np.empty(nc, np.uint32),
+                 parent=np.empty(nc, np.uint32), mom=np.empty((nc, 10)))
+        order = ["cube", "key", "perm", "level", "prefix", "begin", "count", "first_child",
+                 "nchild", "parent", "mom"]
+        self._check(self.lib.fdx_get_tree(self.h, *[_ptr(d[k]) for k in order]), "get_tree")
+        return d
+
+    def groups(self) -> dict:
+        G = int(self.stats()["n_groups"])
+        d = dict(cell=np.empty(G, np.uint32), begin=np.empty(G, np.uint32),
+                 count=np.empty(G, np.uint32), qmin=np.empty((G, 3), np.uint32),
+                 qmax=np.empty((G, 3), np.uint32), centre=np.empty((G, 3)))
+        order = ["cell", "begin", "count", "qmin", "qmax", "centre"]
+        self._check(self.lib.fdx_get_groups(self.h, *[_ptr(d[k]) for k in order]), "get_groups")
+        return d
+
+    def lists(self):
+        st = self.stats()
+        G = int(st["n_groups"])
+        ne, ns = np.empty(G, np.uint32), np.empty(G, np.uint32)
+        epj = np.empty(max(1, int(st["n_epj"])), np.uint32)
+        spj = np.empty(max(1, int(st["n_spj"])), np.uint32)
+        self._check(self.lib.fdx_get_lists(self.h, _ptr(ne), _ptr(ns), _ptr(epj), _ptr(spj)),
+                    "get_lists")
+        return ne, ns, epj[:int(st["n_epj"])], spj[:int(st["n_spj"])]

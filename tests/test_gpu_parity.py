@@ -1,0 +1,235 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the same seeded
+inputs.  Keys, order, cells, groups and lists bit-exact; moments and forces to tolerances
+derived in parity_util."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1601_03138_amd import inputs as I
+
+from parity_util import (BAR_RMS_VS_DIRECT, F32_RMS_REL_VS_TREE, F64_MAX_REL, F64_RMS_REL,
+                         check_groups, check_lists, check_moments, check_tree, pot_rel_err,
+                         rel_err, tree_ref)
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fdx():
+    from paper_1601_03138_amd import fdx as F
+    return F
+
+
+@pytest.fixture(scope="module")
+def ctx(fdx):
+    c = fdx.Context(0)
+    yield c
+    c.close()
+
+
+CASES = {
+    # name: (particle set factory, n_leaf, n_group, theta, quad)
+    "plummer4k_mono": (lambda: I.workload("plummer4k"), 8, 64, 0.5, False),
+    "plummer20k_quad": (lambda: I.plummer(20000, seed=21, eps=1 / 256), 8, 256, 0.5, True),
+    "clustered_quad": (lambda: I.clustered(n_background=16384, n_clusters=8, n_per_cluster=2048,
+                                           seed=5), 8, 128, 0.5, True),
+    "ensemble_ragged": (lambda: I.concat([I.plummer(n, seed=30 + k, eps=0.02) for k, n in
+                                          enumerate([1, 2, 3, 64, 65, 1000, 4097, 257])]),
+                        8, 64, 0.6, True),
+    "leaf1_group5": (lambda: I.plummer(3000, seed=22, eps=0.01), 1, 5, 0.4, True),
+    "group512": (lambda: I.plummer(12000, seed=23, eps=0.01), 16, 512, 0.7, True),
+}
+
+
+def _coincident():
+    ps = I.uniform_cube(700, 41, 0.05)
+    ps.x[100:400] = ps.x[100]      # 300 coincident particles -> level-21 leaf, chunked groups
+    ps.y[100:400] = ps.y[100]
+    ps.z[100:400] = ps.z[100]
+    return ps
+
+
+CASES["coincident"] = (_coincident, 8, 64, 0.5, True)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_structure_and_fp64_forces(ctx, name):
+    make, n_leaf, n_group, theta, quad = CASES[name]
+    ps = make()
+    _say(f"[parity] {name}: n={ps.n} sys={ps.n_sys} leaf={n_leaf} group={n_group} theta={theta}")
+    t, g, lists = tree_ref(ps, n_leaf, n_group, theta)
+    ctx.set_particles(ps)
+    ctx.calc_force(theta, n_leaf, n_group, 0.0, quad=quad, fp32=False)
+    st = ctx.stats()
+    assert st["n_cells"] == t.n_cells and st["n_groups"] == g.n
+    check_tree(ctx.tree(), t)
+    check_moments(ctx.tree()["mom"], t)
+    check_groups(ctx.groups(), g)
+    check_lists(ctx.lists(), lists)
+    ref_sorted = lists.force(quad)
+    ref = np.empty_like(ref_sorted)
+    ref[t.perm.astype(np.int64)] = ref_sorted
+    a = ctx.forces()
+    ok = np.linalg.norm(ref[:, :3], axis=1) > 0
+    e = rel_err(a[ok], ref[ok])
+    _say(f"  fp64 vs tree: max {e.max():.3e} rms {np.sqrt(np.mean(e**2)):.3e}")
+    assert e.max() <= F64_MAX_REL and np.sqrt(np.mean(e ** 2)) <= F64_RMS_REL
+    okp = ref[:, 3] != 0
+    assert pot_rel_err(a[okp], ref[okp]).max() <= F64_MAX_REL
+    # counts reported by the library
+    assert st["n_epj"] == lists.n_epj.sum() and st["n_spj"] == lists.n_spj.sum()
+    assert st["n_interactions_pp"] == int(np.sum(lists.n_epj * g.count.astype(np.int64)))
+
+
+@pytest.mark.parametrize("name", ["plummer4k_mono", "plummer20k_quad", "clustered_quad",
+                                  "ensemble_ragged", "coincident"])
+def test_fp32_relative_forces(ctx, name):
+    make, n_leaf, n_group, theta, quad = CASES[name]
+    ps = make()
+    _say(f"[parity-fp32] {name}: n={ps.n}")
+    t, g, lists = tree_ref(ps, n_leaf, n_group, theta)
+    ref_sorted = lists.force(quad)
+    ref = np.empty_like(ref_sorted)
+    ref[t.perm.astype(np.int64)] = ref_sorted
+    ctx.set_particles(ps)
+    ctx.calc_force(theta, n_leaf, n_group, 0.0, quad=quad, fp32=True)
+    a = ctx.forces()
+    ok = np.linalg.norm(ref[:, :3], axis=1) > 0
+    e = rel_err(a[ok], ref[ok])
+    rms = float(np.sqrt(np.mean(e ** 2)))
+    _say(f"  fp32 vs tree: rms {rms:.3e} max {e.max():.3e}")
+    assert rms <= F32_RMS_REL_VS_TREE
+    # lists of the FP32 run are the same lists
+    check_lists(ctx.lists(), lists)
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_accuracy_bar_against_direct_sum(ctx, fp32):
+    ps = I.plummer(30000, seed=24, eps=1 / 256)
+    sub = I.subset(ps.n, 2048, seed=102)
+    d = O.direct(ps, sub)
+    ctx.set_particles(ps)
+    ctx.calc_force(0.5, 8, 256, 0.0, quad=True, fp32=fp32)
+    a = ctx.forces()[sub]
+    e = O.rms_rel_error(a, d)
+    _say(f"[bar] fp32={fp32}: rms vs direct {e:.3e}")
+    assert e <= BAR_RMS_VS_DIRECT
+
+
+def test_determinism(ctx):
+    ps = I.clustered(n_background=20000, n_clusters=4, n_per_cluster=3000, seed=8)
+    ctx.set_particles(ps)
+    outs = []
+    for _ in range(2):
+        ctx.calc_force(0.5, 8, 128, 0.0, quad=True, fp32=True)
+        outs.append((ctx.forces(), ctx.lists()))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    for a, b in zip(outs[0][1], outs[1][1]):
+        assert np.array_equal(a, b)
+
+
+def test_two_body_and_single_particle(ctx):
+    d, eps, m1, m2 = 0.7, 0.1, 0.3, 1.9
+    ps = I._pack(np.array([[0.0, 0, 0], [d, 0, 0]]), np.zeros((2, 3)), np.array([m1, m2]),
+                 np.full(2, eps))
+    ctx.set_particles(ps)
+    ctx.calc_force(0.5, 8, 64, 0.0, quad=True)
+    a = ctx.forces()
+    den = (d * d + eps * eps) ** 1.5
+    assert a[0, 0] == pytest.approx(m2 * d / den, rel=1e-14)
+    assert a[1, 0] == pytest.approx(-m1 * d / den, rel=1e-14)
+    one = I._pack(np.array([[0.3, 0.2, 0.1]]), np.zeros((1, 3)), np.array([1.0]), np.array([0.1]))
+    ctx.set_particles(one)
+    ctx.calc_force(0.5, 8, 64, 0.0, quad=True)
+    assert np.array_equal(ctx.forces(), np.zeros((1, 4)))
+
+
+def test_empty_input_and_empty_system(ctx, fdx):
+    empty = I._pack(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0), np.zeros(0))
+    ctx.set_particles(empty)
+    ctx.calc_force(0.5, 8, 64, 0.0)
+    assert ctx.forces().shape == (0, 4)
+    a = I.plummer(500, seed=3, eps=0.02)
+    b = I.plummer(300, seed=4, eps=0.02)
+    both = I.concat([a, b])
+    both.sys_off = np.array([0, 500, 500, 800], dtype=np.int64)   # empty middle system
+    t, g, lists = tree_ref(both, 8, 64, 0.5)
+    ctx.set_particles(both)
+    ctx.calc_force(0.5, 8, 64, 0.0, quad=True)
+    check_tree(ctx.tree(), t)
+    check_lists(ctx.lists(), lists)
+
+
+def test_invalid_arguments_return_codes(ctx, fdx):
+    ps = I.plummer(100, seed=1, eps=0.01)
+    ctx.set_particles(ps)
+    for theta, nl, ng in [(0.0, 8, 64), (1.5, 8, 64), (0.5, 0, 64), (0.5, 8, 0), (0.5, 8, 513)]:
+        with pytest.raises(fdx.FdxError) as ei:
+            ctx.calc_force(theta, nl, ng, 0.0)
+        assert ei.value.code == fdx.EINVAL
+    bad = I.plummer(100, seed=1, eps=0.01)
+    bad.x[5] = np.nan
+    with pytest.raises(fdx.FdxError) as ei:
+        ctx.set_particles(bad)
+    assert ei.value.code == fdx.EINVAL
+    bad = I.plummer(100, seed=1, eps=0.01)
+    bad.eps[3] = 0.0
+    with pytest.raises(fdx.FdxError):
+        ctx.set_particles(bad)
+    # global eps must be > 0 when no per-particle eps is given
+    ctx.set_particles(ps, per_particle_eps=False)
+    with pytest.raises(fdx.FdxError):
+        ctx.calc_force(0.5, 8, 64, 0.0)
+    ctx.calc_force(0.5, 8, 64, 0.01)
+
+
+def test_device_borrowed_input_and_device_check(ctx, fdx):
+    import torch
+    ps = I.plummer(5000, seed=25, eps=0.01)
+    dev = {k: torch.tensor(getattr(ps, k), dtype=torch.float64, device="cuda")
+           for k in ("x", "y", "z", "vx", "vy", "vz", "m", "eps")}
+    ctx.set_particles_device(dev)
+    ctx.calc_force(0.5, 8, 64, 0.0, quad=True)
+    a_dev = ctx.forces()
+    ctx.set_particles(ps)
+    ctx.calc_force(0.5, 8, 64, 0.0, quad=True)
+    assert np.array_equal(a_dev, ctx.forces())
+    dev["x"][7] = float("nan")
+    ctx.set_particles_device(dev)
+    with pytest.raises(fdx.FdxError) as ei:
+        ctx.calc_force(0.5, 8, 64, 0.0, quad=True)
+    assert ei.value.code == fdx.EINVAL
+
+
+def test_leapfrog_step_matches_oracle(ctx):
+    # one force evaluation plus one KDK step of the sample program, dt = 1/128, N = 4096
+    ps = I.workload("plummer4k")
+    ctx.set_particles(ps)
+    ctx.calc_force(0.5, 8, 64, 0.0, quad=False, fp32=False)
+    a0 = ctx.forces()
+    ctx.integrate(1.0 / 128.0, 1)
+    x, y, z, vx, vy, vz = ctx.particles()
+    # oracle: same step with the oracle tree's forces at the same positions
+    v = np.stack([ps.vx, ps.vy, ps.vz], 1).copy()
+    p = np.stack([ps.x, ps.y, ps.z], 1).copy()
+    aref0 = O.tree_force(ps, 0.5, 8, 64, quad=False)
+    assert np.allclose(a0, aref0, rtol=1e-9, atol=1e-12)
+    O.kick(v, aref0[:, :3], 1 / 128)
+    O.drift(p, v, 1 / 128)
+    assert np.allclose(np.stack([x, y, z], 1), p, rtol=0, atol=1e-13)
+    q = I._pack(np.stack([x, y, z], 1), np.zeros_like(p), ps.m, ps.eps)
+    aref1 = O.tree_force(q, 0.5, 8, 64, quad=False)   # the oracle fed the GPU's positions
+    O.kick(v, aref1[:, :3], 1 / 128)
+    assert np.allclose(np.stack([vx, vy, vz], 1), v, rtol=0, atol=1e-12)
+    # the force accuracy of the plain (monopole) method on this input, against direct sum
+    d = O.direct(ps)
+    e = O.rms_rel_error(a0, d)
+    _say(f"[plummer4k] monopole rms vs direct {e:.3e}")
+    assert e < 2e-3
