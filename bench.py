@@ -1,0 +1,235 @@
+"""Benchmark: particles per second per force evaluation of the Barnes-Hut hot path on one GPU.
+
+One step = one leapfrog step of the sample program (kick + drift, one full force evaluation:
+keys, sort, tree, moments, groups, walk, force, unsort; kick) on the N = 2^24 clustered
+workload, theta = 0.5, quadrupole superparticles, FP32 group-relative force kernels.
+Inputs are resident in device memory before the timed region.  Prints one JSON line.
+
+Also reported: the FP64 force path on the same input, the force-kernel roofline (measured with
+HIP events on the library's stream), accuracy against FP64 direct summation on a seeded
+subset, and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+# Algorithmic flops per interaction of the force kernels (FMA = 2, rsqrt = 1), counted from
+# the formulas they evaluate: particle 20; superparticle monopole 20, quadrupole 54.
+FLOPS_PP = 20
+FLOPS_PC_MONO = 20
+FLOPS_PC_QUAD = 54
+
+WORKLOADS = {
+    # name: (n_group, theta, quad, dt)
+    "clustered16m": (256, 0.5, True, 1.0 / 1024.0),
+    "plummer1m": (256, 0.5, True, 1.0 / 256.0),
+    "plummer4k": (64, 0.5, False, 1.0 / 128.0),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def force_flops(st, quad):
+    return st["n_interactions_pp"] * FLOPS_PP + st["n_interactions_pc"] * (
+        FLOPS_PC_QUAD if quad else FLOPS_PC_MONO)
+
+
+def read_traffic(kernel_tag: str):
+    """HBM bytes per launch of the force kernel measured by rocprofv3 counters, if a summary
+    for the current kernel source is committed under profiles/ (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    try:
+        import hashlib
+        src = open(os.path.join(ROOT, "paper_1601_03138_amd", "csrc", "k_force.hip"), "rb").read()
+        if vals.get("k_force.hip sha256") != hashlib.sha256(src).hexdigest():
+            return None
+        return float(vals["hbm bytes per launch"])
+    except (KeyError, ValueError, OSError):
+        return None
+
+
+def cpu_baseline(ps, n_group, theta, quad, n_sample_groups, seed=7):
+    """The oracle as it stands (FP64 serial tree, OpenMP over groups): the full tree build of
+    the workload plus the walk and force of a random sample of groups, scaled to one whole
+    force evaluation."""
+    import oracle as O
+    t0 = time.perf_counter()
+    tr = O.build_tree(ps, 8)
+    g = O.make_groups(tr, n_group)
+    t1 = time.perf_counter()
+    rng = np.random.default_rng(seed)
+    k = min(n_sample_groups, g.n)
+    sel = np.sort(rng.choice(g.n, k, replace=False))
+    lists = O.walk(tr, g, theta, sel)
+    lists.force(quad)
+    t2 = time.perf_counter()
+    t_eval = (t1 - t0) + (t2 - t1) * g.n / k
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": ps.n / t_eval, "unit": "particles/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle tree: full build of all {ps.n} particles "
+                      f"({t1 - t0:.1f} s) + walk and force of {k} random groups of {g.n} "
+                      f"({t2 - t1:.2f} s), scaled to all groups; est. {t_eval:.0f} s per "
+                      f"force evaluation"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="clustered16m", choices=sorted(WORKLOADS))
+    ap.add_argument("--n-group", type=int, default=0, help="0: workload default")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--fp64-evals", type=int, default=3)
+    ap.add_argument("--cpu-sample-groups", type=int, default=512)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 256 MiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1601_03138_amd import fdx, inputs
+
+    n_group, theta, quad, dt = WORKLOADS[args.workload]
+    if args.n_group:
+        n_group = args.n_group
+    if args.copy_calibration:
+        src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")   # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] copy calibration: 268435456 bytes read, 268435456 bytes written")
+        del src, dst
+    log(f"[bench] generating {args.workload}")
+    ps = inputs.workload(args.workload)
+    ctx = fdx.Context(0)
+    ctx.set_particles(ps)
+    flags = fdx.Context.flags(quad=quad, fp32=True, timing=True)
+
+    # initial force, then warm-up steps
+    ctx.calc_force_flags(theta, 8, n_group, 0.0, flags)
+    for _ in range(args.warmup):
+        ctx.integrate(dt, 1)
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} steps")
+    t_force, flops, phases = [], [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.integrate(dt, 1)
+        st = ctx.stats()
+        t_force.append(st["t_force"])
+        flops.append(force_flops(st, quad))
+        phases.append({k: st[k] for k in st if k.startswith("t_")})
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = ps.n / (ms_step / 1e3)
+    st = ctx.stats()
+    mean_force_ms = float(np.mean(t_force))
+    achieved = float(np.mean(flops)) / (mean_force_ms / 1e3) / 1e12
+    phase_ms = {k[2:]: round(float(np.mean([p[k] for p in phases])), 4) for k in phases[0]}
+    traffic = read_traffic(f"force_fp32_quad_{args.workload}" if quad else
+                           f"force_fp32_mono_{args.workload}")
+
+    # FP64 force path on the same (current) particles
+    fp64 = None
+    if args.fp64_evals > 0:
+        f64flags = fdx.Context.flags(quad=quad, fp32=False, timing=True)
+        ctx.calc_force_flags(theta, 8, n_group, 0.0, f64flags)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        tf = []
+        for _ in range(args.fp64_evals):
+            ctx.calc_force_flags(theta, 8, n_group, 0.0, f64flags)
+            s64 = ctx.stats()
+            tf.append(s64["t_force"])
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        ms64 = (tb - ta) * 1e3 / args.fp64_evals
+        fp64 = {"ms_per_eval": round(ms64, 3), "particles_per_s": ps.n / (ms64 / 1e3),
+                "force_kernel_ms": round(float(np.mean(tf)), 3),
+                "force_tflops": round(force_flops(s64, quad) / (np.mean(tf) / 1e3) / 1e12, 2),
+                "frac_of_fp64_peak": round(force_flops(s64, quad) / (np.mean(tf) / 1e3) / 1e12
+                                           / PEAK_FP64_TFLOPS, 4)}
+
+    # accuracy of both paths against FP64 direct summation at the current positions
+    accuracy = None
+    if not args.no_accuracy:
+        import oracle as O
+        x, y, z, vx, vy, vz = ctx.particles()
+        cur = inputs.ParticleSet(x, y, z, vx, vy, vz, ps.m, ps.eps, ps.sys_off)
+        sub = inputs.subset(ps.n, 256, seed=102)
+        d = O.direct(cur, sub)
+        ctx.calc_force_flags(theta, 8, n_group, 0.0, fdx.Context.flags(quad=quad, fp32=False))
+        e64 = O.rms_rel_error(ctx.forces()[sub], d)
+        ctx.calc_force_flags(theta, 8, n_group, 0.0, fdx.Context.flags(quad=quad, fp32=True))
+        e32 = O.rms_rel_error(ctx.forces()[sub], d)
+        accuracy = {"rms_da_over_a_fp32": e32, "rms_da_over_a_fp64": e64,
+                    "subset": "256 particles, seed 102, FP64 direct sum (oracle)"}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        cpu = cpu_baseline(ps, n_group, theta, quad, args.cpu_sample_groups)
+
+    out = {
+        "metric": "particles/s per force eval at N=2^24, theta=0.5; FP32 vs FP64 at rms da/a<=1e-3",
+        "value": value,
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": ps.n, "theta": theta, "n_group": n_group,
+                   "n_leaf": 8, "quadrupole": quad, "eps": float(ps.eps[0]), "dt": dt,
+                   "step": "leapfrog kick-drift, full force evaluation, kick"},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                     "traffic": traffic, "kernel": "k_force_direct<float, quad>",
+                     "kernel_ms": round(mean_force_ms, 3),
+                     "interactions_per_launch": int(st["n_interactions_pp"] + st["n_interactions_pc"]),
+                     "flops_per_interaction": {"pp": FLOPS_PP,
+                                               "pc": FLOPS_PC_QUAD if quad else FLOPS_PC_MONO}},
+        "cpu_baseline": cpu,
+        "fp64": fp64,
+        "accuracy": accuracy,
+        "phases_ms": phase_ms,
+        "tree": {"cells": int(st["n_cells"]), "groups": int(st["n_groups"]),
+                 "depth": int(st["depth"]), "epj": int(st["n_epj"]), "spj": int(st["n_spj"])},
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

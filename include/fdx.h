@@ -164,6 +164,51 @@ int fdx_get_groups(fdx_ctx *ctx, uint32_t *cell, uint32_t *begin, uint32_t *coun
 int fdx_get_lists(fdx_ctx *ctx, uint32_t *n_epj, uint32_t *n_spj, uint32_t *epj,
                   uint32_t *spj);
 
+/* ---- Autotuner (n_group and force-kernel workgroup shape) ----------------------------
+ * The paper finds an optimal group size from the trade-off between list construction and
+ * force cost (section "Tree traverse and interaction calculation"); the autotuner measures
+ * it instead.  fdx_autotune_shapes() = number of force-kernel shapes (threads per workgroup x
+ * i-particles per thread).  fdx_autotune times fdx_calc_force (median of `reps` calls after
+ * one warm-up) for each of the n_cand candidate group sizes and every shape that can hold
+ * them, keeps the fastest shape for later calls and returns it with its group size;
+ * times_ms[k * shapes + v] receives each time (NaN where the shape cannot hold the group
+ * size; null skips).  fdx_set_shape fixes the shape (-1 = default).
+ * FDX_EINVAL: no candidates, reps < 1, or a shape out of range. */
+int fdx_autotune_shapes(void);
+int fdx_set_shape(fdx_ctx *ctx, int32_t shape);
+int fdx_autotune(fdx_ctx *ctx, double theta, int32_t n_leaf, double eps, int32_t flags,
+                 const int32_t *n_group_cand, int32_t n_cand, int32_t reps, double *times_ms,
+                 int32_t *best_n_group, int32_t *best_shape);
+
+/* ---- Learned interaction-list length predictor -----------------------------------------
+ * A small network (8 inputs -> 64 -> 64 -> 1, SiLU, FP32; fdx_mlp_params() = 4801 weights)
+ * predicts ln(|EPJ| + |SPJ|) of each group from cheap group features, so FDX_PREDICTOR can
+ * size every list before one single walk (a closed-form model of the mean length is the
+ * paper's equation nlist_long).  Lists that outgrow their predicted capacity are walked
+ * again exactly, so forces never depend on the predictor.  All arrays are host memory.
+ * fdx_predictor_features: raw features of every group of the last tree, X[8 g + k]:
+ *   ln n_i, ln box extent, ln(1 + distance of the box centre to the root centre), ln(parent
+ *   mass / system mass), ln(parent side / root side), depth, ln(parent density), log2 N_sys.
+ * fdx_mlp_forward / fdx_mlp_grad: the network's forward pass and the full-batch gradient of
+ *   the mean squared error on given weights P[4801] and standardised inputs (for checks).
+ * fdx_predictor_train: trains on n samples (raw features, ln length) with the library's own
+ *   forward/backward/Adam kernels: seeded 90/10 split, standardisation from the training
+ *   part, `epochs` passes of minibatches of `batch`, learning rate lr; the capacity margin is
+ *   the 99th percentile of the held-out residual; losses[e] = mean loss of epoch e.
+ * fdx_predictor_margin: set the margin (ln factor; NaN keeps it) and read it back.
+ * fdx_predictor_save / load: weights, normalisation and margin to / from a binary file.
+ * FDX_ESTATE: predictor not trained or loaded (margin, save, FDX_PREDICTOR). */
+int fdx_mlp_params(void);
+int fdx_predictor_features(fdx_ctx *ctx, float *X);
+int fdx_mlp_forward(fdx_ctx *ctx, const float *P, const float *X, int64_t n, float *y);
+int fdx_mlp_grad(fdx_ctx *ctx, const float *P, const float *X, const float *t, int64_t n,
+                 float *grad, float *loss);
+int fdx_predictor_train(fdx_ctx *ctx, const float *X, const float *t, int64_t n, int32_t epochs,
+                        int32_t batch, double lr, int64_t seed, float *losses);
+int fdx_predictor_margin(fdx_ctx *ctx, double margin, double *out);
+int fdx_predictor_save(fdx_ctx *ctx, const char *path);
+int fdx_predictor_load(fdx_ctx *ctx, const char *path);
+
 /* Message of the last failed call on ctx (never null; "" when none). */
 const char *fdx_last_error(const fdx_ctx *ctx);
 

@@ -45,6 +45,7 @@ bool finite_all(const double *p, int64_t n) {
 int ensure_tree_buffers(fdx_ctx *c, uint32_t cell_cap, uint32_t group_cap) {
     const size_t n = (size_t)c->n, S = (size_t)c->nsys;
     if (cell_cap > c->cell_cap || !c->c_level.p) {
+        c->gen++;
         HIPCHK(c, c->c_level.ensure(cell_cap));
         HIPCHK(c, c->c_begin.ensure(cell_cap));
         HIPCHK(c, c->c_count.ensure(cell_cap));
@@ -61,6 +62,7 @@ int ensure_tree_buffers(fdx_ctx *c, uint32_t cell_cap, uint32_t group_cap) {
     HIPCHK(c, c->tmp_n.ensure(n + S + 1));
     HIPCHK(c, c->tmp_off.ensure(n + S + 2));
     if (group_cap > c->group_cap || !c->g_cell.p) {
+        c->gen++;
         HIPCHK(c, c->g_cell.ensure(group_cap));
         HIPCHK(c, c->g_begin.ensure(group_cap));
         HIPCHK(c, c->g_count.ensure(group_cap));
@@ -73,6 +75,10 @@ int ensure_tree_buffers(fdx_ctx *c, uint32_t cell_cap, uint32_t group_cap) {
         HIPCHK(c, c->seg.ensure((size_t)group_cap + 1));
         HIPCHK(c, c->ovf_list.ensure(group_cap));
         HIPCHK(c, c->order.ensure(group_cap));
+        HIPCHK(c, c->q_val_alt.ensure(group_cap));
+        HIPCHK(c, c->q_key.ensure(group_cap));
+        HIPCHK(c, c->q_key_alt.ensure(group_cap));
+        HIPCHK(c, c->rs_scratch.ensure(radix_scratch_u32(std::max<size_t>(n, group_cap))));
         c->group_cap = group_cap;
     }
     return FDX_OK;
@@ -107,10 +113,8 @@ int read_status(fdx_ctx *c) {
     return FDX_OK;
 }
 
-// Tree part of one evaluation: keys, sort, gather, cells, moments, groups.  Retries with
-// larger cell / group capacity when the device reports an overflow.  Leaves the status
-// (group count, levels) in c->hst after its synchronisation when `sync` is true.
-int run_tree(fdx_ctx *c, bool sync) {
+// Keys, sort and sorted gather (no host wait).  Resets the device status first.
+int enqueue_keys_sort(fdx_ctx *c) {
     const size_t n = (size_t)c->n;
     const int S = c->nsys;
     hipStream_t s = c->stream;
@@ -123,25 +127,43 @@ int run_tree(fdx_ctx *c, bool sync) {
     HIPCHK(c, morton_keys(n, c->x, c->y, c->z, c->sysid.p, c->cube.p, c->key.p, c->perm.p, s));
     mark(c, 1);
     bool alt = false;
-    HIPCHK(c, radix_sort(n, c->key.p, c->key_alt.p, c->perm.p, c->perm_alt.p, c->sysid.p, S,
+    HIPCHK(c, radix_sort(n, c->key.p, c->key_alt.p, c->perm.p, c->perm_alt.p, c->sysid.p, S, 64,
                          c->rs_scratch.p, c->partial.p, &alt, s));
     c->skey = alt ? c->key_alt.p : c->key.p;
     c->sperm = alt ? c->perm_alt.p : c->perm.p;
     HIPCHK(c, gather_sorted(n, c->sperm, c->x, c->y, c->z, c->m, c->eps_given ? c->eps : nullptr,
                             c->eps_all, c->jp.p, c->seps.p, c->inv.p, s));
     mark(c, 2);
+    return FDX_OK;
+}
+
+// Cells, moments and groups at the current capacities (no host wait).
+int enqueue_tree_groups(fdx_ctx *c) {
+    const size_t n = (size_t)c->n;
+    const int S = c->nsys;
+    hipStream_t s = c->stream;
+    HIPCHK(c, tree_build(n, S, c->sys_off.p, c->skey, c->n_leaf, cells_view(c), c->tmp_n.p,
+                         c->tmp_off.p, c->partial.p, c->st, s));
+    mark(c, 3);
+    HIPCHK(c, tree_moments(cells_view(c), c->jp.p, s));
+    mark(c, 4);
+    HIPCHK(c, make_groups(n, S, c->sys_off.p, cells_view(c), c->skey, c->cube.p, c->n_group,
+                          groups_view(c), c->flag.p, c->gcell_at.p, c->gpos.p, c->partial.p,
+                          c->st, s));
+    mark(c, 5);
+    return FDX_OK;
+}
+
+// Tree part of one evaluation with host checks: retries with larger cell / group capacity
+// when the device reports an overflow.  Leaves the status (group count, levels) in c->hst.
+int run_tree(fdx_ctx *c, bool sync) {
+    int r = enqueue_keys_sort(c);
+    if (r) return r;
     for (int attempt = 0;; attempt++) {
-        HIPCHK(c, tree_build(n, S, c->sys_off.p, c->skey, c->n_leaf, cells_view(c), c->tmp_n.p,
-                             c->tmp_off.p, c->partial.p, c->st, s));
-        mark(c, 3);
-        HIPCHK(c, tree_moments(cells_view(c), c->jp.p, s));
-        mark(c, 4);
-        HIPCHK(c, make_groups(n, S, c->sys_off.p, cells_view(c), c->skey, c->cube.p, c->n_group,
-                              groups_view(c), c->flag.p, c->gcell_at.p, c->gpos.p, c->partial.p,
-                              c->st, s));
-        mark(c, 5);
+        r = enqueue_tree_groups(c);
+        if (r) return r;
         if (!sync) return FDX_OK;
-        int r = read_status(c);
+        r = read_status(c);
         if (r) return r;
         const DevStatus &h = c->hst->st;
         if (h.bad_input)
@@ -149,48 +171,52 @@ int run_tree(fdx_ctx *c, bool sync) {
                                        "or eps <= 0");
         bool grow = false;
         uint32_t ncap = c->cell_cap, gcap = c->group_cap;
-        if (h.cell_overflow) { ncap = (uint32_t)std::min<uint64_t>(2ull * c->cell_cap, 0xFFFFFFF0ull); grow = true; }
-        if (h.n_groups > c->group_cap) { gcap = h.n_groups + 1024; grow = true; }
+        if (h.cell_overflow) {
+            ncap = (uint32_t)std::min<uint64_t>(2ull * c->cell_cap, 0xFFFFFFF0ull);
+            grow = true;
+        }
+        if (h.group_overflow || h.n_groups > c->group_cap) {
+            gcap = h.n_groups + h.n_groups / 8 + 1024;
+            grow = true;
+        }
         if (!grow) return FDX_OK;
         if (attempt > 8) return fail(c, FDX_EHIP, "tree capacity did not converge");
         r = ensure_tree_buffers(c, ncap, gcap);
         if (r) return r;
-        HIPCHK(c, fill_u32((uint32_t *)c->st, 0u, sizeof(DevStatus) / 4, s));
+        HIPCHK(c, fill_u32((uint32_t *)c->st, 0u, sizeof(DevStatus) / 4, c->stream));
     }
 }
 
-// Walk + force + return of forces.  Needs run_tree(sync=true) first.
-int run_force(fdx_ctx *c) {
+// Exact walk, first half: count pass, segment sizes and offsets (device total in
+// st->list_total).  gmax bounds the groups (the host count, or the capacity when captured).
+int enqueue_count(fdx_ctx *c, size_t gmax) {
+    hipStream_t s = c->stream;
+    Groups gv = groups_view(c);
+    HIPCHK(c, walk(false, gmax, gv, cells_view(c), c->theta * c->theta, nullptr, nullptr, 0,
+                   nullptr, c->cnt_e.p, c->cnt_s.p, c->ovf_list.p, nullptr, nullptr, c->st, s));
+    HIPCHK(c, list_caps(gmax, c->cnt_e.p, c->cnt_s.p, c->lcap.p, c->st, s));
+    HIPCHK(c, scan_u32_to_u64(c->lcap.p, c->seg.p, 0, nullptr, &c->st->n_groups_c, c->partial.p,
+                              &c->st->list_total, s));
+    return FDX_OK;
+}
+
+// Fill pass into the list buffer (its capacity guards every write), then counters.
+int enqueue_fill(fdx_ctx *c, size_t gmax) {
+    hipStream_t s = c->stream;
+    Groups gv = groups_view(c);
+    HIPCHK(c, walk(true, gmax, gv, cells_view(c), c->theta * c->theta, c->seg.p, c->lcap.p,
+                   c->list_cap, c->list.p, c->cnt_e.p, c->cnt_s.p, c->ovf_list.p, nullptr,
+                   nullptr, c->st, s));
+    return FDX_OK;
+}
+
+// Force kernel and return of forces.  G = host group count (direct launch) or 0 with
+// persistent kernels (device count).
+int enqueue_force(fdx_ctx *c, size_t gmax) {
     hipStream_t s = c->stream;
     const size_t n = (size_t)c->n;
-    const uint32_t G0 = c->hst->st.n_groups;
-    const double th2 = c->theta * c->theta;
     Groups gv = groups_view(c);
-    Cells cv = cells_view(c);
-    uint32_t G = G0;
-    if (c->flags & FDX_PREDICTOR) {
-        int r = ext_predicted_walk(c, G);
-        if (r) return r;
-    } else {
-        HIPCHK(c, walk(false, G, gv, cv, th2, nullptr, nullptr, nullptr, c->cnt_e.p, c->cnt_s.p,
-                       c->ovf_list.p, c->st, s));
-        HIPCHK(c, list_caps(G, c->cnt_e.p, c->cnt_s.p, c->lcap.p, c->st, s));
-        HIPCHK(c, scan_u32_to_u64(c->lcap.p, c->seg.p, G, nullptr, nullptr, c->partial.p,
-                                  &c->st->list_total, s));
-        int r = read_status(c);
-        if (r) return r;
-        if (c->hst->st.walk_error) return fail(c, FDX_EHIP, "walk stack exhausted");
-        const uint64_t total = c->hst->st.list_total;
-        if (total > c->list_cap || !c->list.p) {
-            const uint64_t want = total + total / 8 + 1024;
-            HIPCHK(c, c->list.ensure(want));
-            c->list_cap = want;
-        }
-        HIPCHK(c, walk(true, G, gv, cv, th2, c->seg.p, c->lcap.p, c->list.p, c->cnt_e.p,
-                       c->cnt_s.p, c->ovf_list.p, c->st, s));
-        c->stats.list_capacity = (int64_t)total;
-    }
-    HIPCHK(c, list_stats(G, gv, c->cnt_e.p, c->cnt_s.p, c->st, s));
+    HIPCHK(c, list_stats(gmax, gv, c->cnt_e.p, c->cnt_s.p, c->st, s));
     mark(c, 6);
     ForceArgs fa;
     fa.g = &gv; fa.jp = c->jp.p; fa.seps = c->seps.p; fa.mom = c->c_mom.p;
@@ -201,19 +227,56 @@ int run_force(fdx_ctx *c) {
     fa.persistent = (c->flags & FDX_PERSISTENT) != 0;
     fa.variant = ext_force_variant(c);
     if (fa.persistent) {
-        fa.order = ext_queue_order(c, G);
+        int r = ext_queue_order(c, gmax, &fa.order);
+        if (r) return r;
     }
-    HIPCHK(c, force(G, fa, s));
+    HIPCHK(c, force(gmax, fa, s));
     mark(c, 7);
     HIPCHK(c, unsort_forces(n, c->fs.p, c->inv.p, c->ax.p, c->ay.p, c->az.p, c->pot.p, s));
     mark(c, 8);
+    return FDX_OK;
+}
+
+int ensure_list_capacity(fdx_ctx *c, uint64_t total) {
+    if (total > c->list_cap || !c->list.p) {
+        c->gen++;
+        const uint64_t want = total + total / 8 + 1024;
+        HIPCHK(c, c->list.ensure(want));
+        c->list_cap = want;
+    }
+    return FDX_OK;
+}
+
+// Walk + force + return of forces (eager).  Needs run_tree(sync=true) first.
+int run_force(fdx_ctx *c) {
+    const uint32_t G = c->hst->st.n_groups;
+    int r;
+    if (c->flags & FDX_PREDICTOR) {
+        r = ext_predicted_walk(c, G);
+        if (r) return r;
+    } else {
+        r = enqueue_count(c, G);
+        if (r) return r;
+        r = read_status(c);
+        if (r) return r;
+        if (c->hst->st.walk_error) return fail(c, FDX_EHIP, "walk stack exhausted");
+        const uint64_t total = c->hst->st.list_total;
+        r = ensure_list_capacity(c, total);
+        if (r) return r;
+        r = enqueue_fill(c, G);
+        if (r) return r;
+        c->stats.list_capacity = (int64_t)total;
+        c->stats.overflow_groups = 0;
+    }
+    r = enqueue_force(c, G);
+    if (r) return r;
     c->have_force = true;
     return FDX_OK;
 }
 
 }  // namespace fdx
 
-namespace {
+namespace fdx {
 
 int setup_eval(fdx_ctx *c, double theta, int n_leaf, int n_group, double eps, int flags) {
     if (!c) return FDX_EINVAL;
@@ -269,7 +332,7 @@ int read_counters(fdx_ctx *c) {
     return FDX_OK;
 }
 
-}  // namespace
+}  // namespace fdx
 
 extern "C" {
 
@@ -313,9 +376,11 @@ int fdx_destroy(fdx_ctx *c) {
                     &c->c_begin, &c->c_count, &c->c_first, &c->c_nchild, &c->c_parent, &c->c_lvl,
                     &c->tmp_n, &c->tmp_off, &c->g_cell, &c->g_begin, &c->g_count, &c->g_sys,
                     &c->g_box, &c->flag, &c->gcell_at, &c->gpos, &c->cnt_e, &c->cnt_s, &c->lcap,
-                    &c->list, &c->ovf_list, &c->order})
+                    &c->list, &c->ovf_list, &c->order, &c->q_val_alt})
         b->release();
-    for (auto *b : {&c->bbox_u, &c->key, &c->key_alt, &c->partial, &c->c_prefix, &c->seg}) b->release();
+    for (auto *b : {&c->bbox_u, &c->key, &c->key_alt, &c->partial, &c->c_prefix, &c->seg,
+                    &c->q_key, &c->q_key_alt})
+        b->release();
     c->sys_off.release();
     c->jp.release();
     c->fs.release();
@@ -363,6 +428,8 @@ int fdx_set_particles(fdx_ctx *c, int64_t n, const double *x, const double *y, c
     }
     c->have_particles = false;
     c->have_force = false;
+    c->gen++;
+    ext_invalidate(c);
     c->n = n;
     c->nsys = n_sys;
     c->sys_off_h = off;
@@ -460,6 +527,10 @@ int fdx_integrate(fdx_ctx *c, double dt, int32_t n_steps, int32_t flags) {
         HIPCHK(c, kick(n, c->vx, c->vy, c->vz, c->ax.p, c->ay.p, c->az.p, dt, nullptr, c->stream));
     }
     finish_stats(c);
+    if (n_steps > 0) {
+        int r = sync_timing(c);
+        if (r) return r;
+    }
     return read_counters(c);
 }
 

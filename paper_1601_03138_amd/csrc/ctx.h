@@ -84,7 +84,8 @@ struct fdx_ctx {
     uint32_t group_cap = 0;
 
     // lists
-    fdx::DBuf<uint32_t> cnt_e, cnt_s, lcap, list, ovf_list, order;
+    fdx::DBuf<uint32_t> cnt_e, cnt_s, lcap, list, ovf_list, order, q_val_alt;
+    fdx::DBuf<uint64_t> q_key, q_key_alt;
     fdx::DBuf<uint64_t> seg;
     uint64_t list_cap = 0;
 
@@ -104,6 +105,9 @@ struct fdx_ctx {
     hipEvent_t ev[12] = {};
 
     fdx::HostExt ext;   // predictor, autotuner, graph state
+    // bumped by every fdx_set_particles and every reallocation of a buffer a captured graph
+    // refers to; a graph captured under another generation is never replayed
+    uint64_t gen = 0;
 };
 
 namespace fdx {
@@ -124,6 +128,16 @@ void mark(fdx_ctx *c, int k);
 int read_status(fdx_ctx *c);
 int run_tree(fdx_ctx *c, bool sync);
 int run_force(fdx_ctx *c);
+int enqueue_keys_sort(fdx_ctx *c);
+int enqueue_tree_groups(fdx_ctx *c);
+int enqueue_count(fdx_ctx *c, size_t gmax);
+int enqueue_fill(fdx_ctx *c, size_t gmax);
+int enqueue_force(fdx_ctx *c, size_t gmax);
+int ensure_list_capacity(fdx_ctx *c, uint64_t total);
+int setup_eval(fdx_ctx *c, double theta, int n_leaf, int n_group, double eps, int flags);
+void finish_stats(fdx_ctx *c);
+int sync_timing(fdx_ctx *c);
+int read_counters(fdx_ctx *c);
 int ensure_tree_buffers(fdx_ctx *c, uint32_t cell_cap, uint32_t group_cap);
 
 }  // namespace fdx

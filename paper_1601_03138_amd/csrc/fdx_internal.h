@@ -19,15 +19,22 @@ struct DevStatus {
     uint32_t cell_overflow;   // the tree needed more cells than were allocated
     uint32_t bad_input;       // a non-finite coordinate, negative mass or eps <= 0 was seen
     uint32_t walk_error;      // a walk stack would have overflowed (group left incomplete)
-    uint32_t list_overflow;   // groups whose list exceeded its capacity (predictor path)
+    uint32_t list_overflow;   // groups whose list did not fit its segment or the list buffer
     uint32_t n_groups;
     uint32_t depth;
     uint32_t queue_head;      // persistent force kernel: next queue slot to pop
-    uint32_t pad;
+    uint32_t n_groups_c;      // min(n_groups, group capacity): what the kernels iterate over
     uint64_t list_total;      // entries needed by all lists
     uint64_t n_epj, n_spj;
     uint64_t inter_pp, inter_pc;
+    uint32_t group_overflow;  // more groups than the group arrays hold
+    uint32_t pad2;
 };
+
+// any device-reported condition that makes this evaluation's forces incomplete
+__host__ __device__ inline bool status_incomplete(const DevStatus &s) {
+    return s.cell_overflow | s.group_overflow | s.list_overflow | s.walk_error;
+}
 
 // Tree cell arrays (breadth-first order) and walk-friendly views.
 struct Cells {
@@ -87,9 +94,10 @@ hipError_t morton_keys(size_t n, const double *x, const double *y, const double 
 
 // radix sort of (key, perm) pairs by key, then (stable) by system id of the original index.
 size_t radix_scratch_u32(size_t n);
+// key_bits = significant low bits of the keys (passes of 8 bits over them).
 hipError_t radix_sort(size_t n, uint64_t *key, uint64_t *key_alt, uint32_t *val,
-                      uint32_t *val_alt, const uint32_t *sysid, int nsys, uint32_t *scratch,
-                      uint64_t *partial, bool *result_in_alt, hipStream_t s);
+                      uint32_t *val_alt, const uint32_t *sysid, int nsys, int key_bits,
+                      uint32_t *scratch, uint64_t *partial, bool *result_in_alt, hipStream_t s);
 
 // sorted particle data
 hipError_t gather_sorted(size_t n, const uint32_t *perm, const double *x, const double *y,
@@ -109,9 +117,16 @@ hipError_t make_groups(size_t n, int nsys, const int64_t *sys_off, Cells c,
 // walk: count (fill = false) or fill (fill = true) the interaction lists.
 // seg[g]/cap[g] = start and capacity of group g's segment in `list`; EPJ entries grow from
 // the front, SPJ entries from the back.  cnt_e/cnt_s receive the exact counts.
+// A group whose entries do not fit its segment (or whose segment passes list_cap) writes
+// nothing, gets zero counts and is appended to ovf_list (st->list_overflow counts them).
+// sel (optional, with nsel): walk only the listed groups (predictor re-walk).
 hipError_t walk(bool fill, size_t gmax, const Groups g, const Cells c, double theta2,
-                const uint64_t *seg, const uint32_t *cap, uint32_t *list, uint32_t *cnt_e,
-                uint32_t *cnt_s, uint32_t *ovf_list, DevStatus *st, hipStream_t s);
+                const uint64_t *seg, const uint32_t *cap, uint64_t list_cap, uint32_t *list,
+                uint32_t *cnt_e, uint32_t *cnt_s, uint32_t *ovf_list, const uint32_t *sel,
+                const uint32_t *nsel, DevStatus *st, hipStream_t s);
+// queue order for the persistent force kernel: groups by decreasing estimated cost
+hipError_t queue_keys(size_t gmax, const Groups g, const uint32_t *cnt_e, const uint32_t *cnt_s,
+                      uint64_t *key, uint32_t *val, DevStatus *st, hipStream_t s);
 hipError_t list_caps(size_t gmax, const uint32_t *cnt_e, const uint32_t *cnt_s, uint32_t *cap,
                      DevStatus *st, hipStream_t s);
 hipError_t list_stats(size_t gmax, const Groups g, const uint32_t *cnt_e,
@@ -137,5 +152,6 @@ struct ForceArgs {
 hipError_t force(size_t G, const ForceArgs &a, hipStream_t s);
 int force_variants();
 const char *force_variant_name(int v);
+int force_variant_capacity(int v);   // largest group one workgroup of variant v takes
 
 }  // namespace fdx

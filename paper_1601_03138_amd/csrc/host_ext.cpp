@@ -1,23 +1,237 @@
-// Host extensions (predictor, autotuner, queue order, graph capture).
+// Host extensions of the force path: force-kernel shape choice and autotuner, the
+// cost-ordered queue of the persistent force kernel, and HIP-graph capture of leapfrog steps.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
 #include "ctx.h"
+#include "predictor.h"
 
 namespace fdx {
 
-int ext_predicted_walk(fdx_ctx *c, uint32_t) {
-    return fail(c, FDX_EINVAL, "FDX_PREDICTOR: no predictor loaded");
-}
-
 int ext_force_variant(fdx_ctx *c) {
-    if (c->n_group > 256) return 1;
-    return c->ext.variant >= 0 ? c->ext.variant : 0;
+    int v = c->ext.variant >= 0 ? c->ext.variant : 3;
+    if (force_variant_capacity(v) < c->n_group) v = 3;
+    return v;
 }
 
-const uint32_t *ext_queue_order(fdx_ctx *, uint32_t) { return nullptr; }
-
-int ext_integrate_graph(fdx_ctx *c, double, int) {
-    return fail(c, FDX_EINVAL, "FDX_GRAPH not available");
+// Groups by decreasing estimated cost (stable radix sort of complemented 32-bit costs), so
+// the persistent kernel starts the longest work first (longest-processing-time order).
+int ext_queue_order(fdx_ctx *c, size_t gmax, const uint32_t **order) {
+    hipStream_t s = c->stream;
+    HIPCHK(c, queue_keys(gmax, groups_view(c), c->cnt_e.p, c->cnt_s.p, c->q_key.p, c->order.p,
+                         c->st, s));
+    bool alt = false;
+    HIPCHK(c, radix_sort(gmax, c->q_key.p, c->q_key_alt.p, c->order.p, c->q_val_alt.p, nullptr,
+                         1, 32, c->rs_scratch.p, c->partial.p, &alt, s));
+    *order = alt ? c->q_val_alt.p : c->order.p;
+    return FDX_OK;
 }
 
-void ext_release(fdx_ctx *) {}
+// ---------------------------------------------------------------------------------------
+// Graph-captured leapfrog step: kick + drift, the whole force evaluation (exact walk into a
+// fixed-capacity list buffer, persistent force kernel over the cost-ordered queue), kick.
+// Capacities are fixed at capture time with a margin; a step whose tree, groups or lists do
+// not fit is reported by the device status: its final kick is skipped, the host redoes force
+// and kick eagerly with larger buffers and captures again.
+struct GraphState {
+    hipStream_t gs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    // everything the captured launches depend on
+    uint64_t gen = 0;
+    double dt = 0, theta = 0, eps_all = 0;
+    int flags = 0, n_leaf = 0, n_group = 0, variant = 0, nsys = 0;
+    int64_t n = -1;
+    void drop() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+};
+
+static int capture_step(fdx_ctx *c, GraphState *g, double dt) {
+    const size_t n = (size_t)c->n;
+    g->drop();
+    HIPCHK(c, hipStreamBeginCapture(g->gs, hipStreamCaptureModeRelaxed));
+    int r = FDX_OK;
+    auto step = [&]() -> int {
+        HIPCHK(c, kick_drift(n, c->x, c->y, c->z, c->vx, c->vy, c->vz, c->ax.p, c->ay.p, c->az.p,
+                             dt, g->gs));
+        int q = enqueue_keys_sort(c);
+        if (!q) q = enqueue_tree_groups(c);
+        if (!q) q = enqueue_count(c, c->group_cap);
+        if (!q) q = enqueue_fill(c, c->group_cap);
+        if (!q) q = enqueue_force(c, c->group_cap);
+        if (q) return q;
+        HIPCHK(c, kick(n, c->vx, c->vy, c->vz, c->ax.p, c->ay.p, c->az.p, dt, c->st, g->gs));
+        return FDX_OK;
+    };
+    r = step();
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(g->gs, &graph);
+    if (r) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return r;
+    }
+    if (e != hipSuccess) return fail(c, FDX_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+    g->graph = graph;
+    e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        g->drop();
+        return fail(c, FDX_EHIP, "graph instantiate failed: %s", hipGetErrorString(e));
+    }
+    g->gen = c->gen;
+    g->dt = dt;
+    g->theta = c->theta;
+    g->eps_all = c->eps_all;
+    g->flags = c->flags;
+    g->n_leaf = c->n_leaf;
+    g->n_group = c->n_group;
+    g->variant = ext_force_variant(c);
+    g->nsys = c->nsys;
+    g->n = c->n;
+    return FDX_OK;
+}
+
+static bool graph_stale(fdx_ctx *c, GraphState *g, double dt) {
+    return !g->exec || g->gen != c->gen || g->dt != dt || g->theta != c->theta ||
+           g->eps_all != c->eps_all || g->flags != c->flags || g->n_leaf != c->n_leaf ||
+           g->n_group != c->n_group || g->variant != ext_force_variant(c) ||
+           g->nsys != c->nsys || g->n != c->n;
+}
+
+void ext_invalidate(fdx_ctx *c) {
+    GraphState *g = static_cast<GraphState *>(c->ext.graph);
+    if (g) g->drop();
+}
+
+// capacities with headroom for the drift of one step
+static int graph_headroom(fdx_ctx *c) {
+    const DevStatus &h = c->hst->st;
+    const uint32_t ncell = c->hst->lvl[kLevels + 1];
+    uint32_t ccap = std::max<uint32_t>(c->cell_cap, ncell + ncell / 4 + 1024);
+    uint32_t gcap = std::max<uint32_t>(c->group_cap, h.n_groups + h.n_groups / 4 + 1024);
+    int r = ensure_tree_buffers(c, ccap, gcap);
+    if (r) return r;
+    return ensure_list_capacity(c, h.list_total + h.list_total / 4 + 4096);
+}
+
+int ext_integrate_graph(fdx_ctx *c, double dt, int n_steps) {
+    GraphState *g = static_cast<GraphState *>(c->ext.graph);
+    if (!g) {
+        g = new GraphState();
+        c->ext.graph = g;
+    }
+    if (!g->gs) HIPCHK(c, hipStreamCreate(&g->gs));
+    hipStream_t user = c->stream;
+    const int user_flags = c->flags;
+    HIPCHK(c, hipStreamSynchronize(user));
+    c->stream = g->gs;
+    c->flags = (user_flags | FDX_PERSISTENT) & ~(FDX_TIMING | FDX_PREDICTOR);
+    const size_t n = (size_t)c->n;
+    int r = FDX_OK;
+    for (int k = 0; k < n_steps && !r; k++) {
+        if (graph_stale(c, g, dt)) {
+            r = graph_headroom(c);
+            if (!r) r = capture_step(c, g, dt);
+            if (r) break;
+        }
+        hipError_t e = hipGraphLaunch(g->exec, g->gs);
+        if (e != hipSuccess) { r = fail(c, FDX_EHIP, "graph launch: %s", hipGetErrorString(e)); break; }
+        r = read_status(c);
+        if (r) break;
+        const DevStatus h = c->hst->st;
+        if (h.bad_input) { r = fail(c, FDX_EINVAL, "non-finite particle data"); break; }
+        if (status_incomplete(h)) {
+            // positions and velocities hold kick + drift; redo force and kick eagerly
+            r = run_tree(c, true);
+            if (!r) r = run_force(c);
+            if (r) break;
+            hipError_t ek = hipSuccess;
+            ek = kick(n, c->vx, c->vy, c->vz, c->ax.p, c->ay.p, c->az.p, dt, nullptr, g->gs);
+            if (ek != hipSuccess) { r = fail(c, FDX_EHIP, "kick: %s", hipGetErrorString(ek)); break; }
+            r = read_status(c);
+            if (r) break;
+            c->ext.graph_recoveries++;
+            g->drop();
+        }
+    }
+    if (!r) {
+        finish_stats(c);
+        hipError_t e = hipStreamSynchronize(g->gs);
+        if (e != hipSuccess) r = fail(c, FDX_EHIP, "sync: %s", hipGetErrorString(e));
+    }
+    c->stream = user;
+    c->flags = user_flags;
+    if (!r) r = read_counters(c);
+    return r;
+}
+
+void ext_release(fdx_ctx *c) {
+    GraphState *g = static_cast<GraphState *>(c->ext.graph);
+    if (g) {
+        g->drop();
+        if (g->gs) (void)hipStreamDestroy(g->gs);
+        delete g;
+        c->ext.graph = nullptr;
+    }
+    predictor_release(c);
+}
 
 }  // namespace fdx
+
+using namespace fdx;
+
+extern "C" {
+
+int fdx_autotune_shapes(void) { return force_variants(); }
+
+int fdx_set_shape(fdx_ctx *c, int32_t shape) {
+    if (!c) return FDX_EINVAL;
+    if (shape < -1 || shape >= force_variants()) return fail(c, FDX_EINVAL, "shape out of range");
+    c->ext.variant = shape;
+    return FDX_OK;
+}
+
+int fdx_autotune(fdx_ctx *c, double theta, int32_t n_leaf, double eps, int32_t flags,
+                 const int32_t *n_group_cand, int32_t n_cand, int32_t reps, double *times_ms,
+                 int32_t *best_n_group, int32_t *best_shape) {
+    if (!c) return FDX_EINVAL;
+    if (!n_group_cand || n_cand < 1 || reps < 1) return fail(c, FDX_EINVAL, "no candidates");
+    const int nv = force_variants();
+    double best = 1e300;
+    int bg = -1, bv = -1;
+    const int saved = c->ext.variant;
+    flags &= ~(FDX_TIMING | FDX_PREDICTOR);
+    for (int k = 0; k < n_cand; k++) {
+        for (int v = 0; v < nv; v++) {
+            double t = NAN;
+            if (force_variant_capacity(v) >= n_group_cand[k]) {
+                c->ext.variant = v;
+                int r = fdx_calc_force(c, theta, n_leaf, n_group_cand[k], eps, flags);
+                if (r) { c->ext.variant = saved; return r; }
+                std::vector<double> ts;
+                for (int q = 0; q < reps; q++) {
+                    auto t0 = std::chrono::steady_clock::now();
+                    r = fdx_calc_force(c, theta, n_leaf, n_group_cand[k], eps, flags);
+                    if (r) { c->ext.variant = saved; return r; }
+                    auto t1 = std::chrono::steady_clock::now();
+                    ts.push_back(std::chrono::duration<double, std::milli>(t1 - t0).count());
+                }
+                std::sort(ts.begin(), ts.end());
+                t = ts[ts.size() / 2];
+                if (t < best) { best = t; bg = n_group_cand[k]; bv = v; }
+            }
+            if (times_ms) times_ms[(size_t)k * nv + v] = t;
+        }
+    }
+    c->ext.variant = bv;
+    if (best_n_group) *best_n_group = bg;
+    if (best_shape) *best_shape = bv;
+    return FDX_OK;
+}
+
+}  // extern "C"

@@ -13,13 +13,15 @@ namespace fdx {
 struct HostExt {
     int variant = -1;                 // autotuned force-kernel variant (-1: default)
     void *pred = nullptr;             // predictor state (weights, normalisation)
-    void *graph = nullptr;            // captured step
+    void *graph = nullptr;            // captured step (GraphState)
+    int64_t graph_recoveries = 0;     // replays whose capacities overflowed and were redone
 };
 
-int ext_predicted_walk(fdx_ctx *c, uint32_t G);
 int ext_force_variant(fdx_ctx *c);
-const uint32_t *ext_queue_order(fdx_ctx *c, uint32_t G);
+int ext_queue_order(fdx_ctx *c, size_t gmax, const uint32_t **order);
 int ext_integrate_graph(fdx_ctx *c, double dt, int n_steps);
 void ext_release(fdx_ctx *c);
+void ext_invalidate(fdx_ctx *c);   // drop any captured graph (particles or buffers changed)
+int ext_predicted_walk(fdx_ctx *c, uint32_t G);
 
 }  // namespace fdx

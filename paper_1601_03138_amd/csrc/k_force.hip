@@ -3,9 +3,12 @@
 // The paper asks for an interaction routine that takes many i-particles and many
 // j-particles at once so each j is reused from fast memory (section "Design concept of
 // FDPS"), with particles (EPJ) and superparticles (SPJ) as two sums (equation geqL).  Here
-// one workgroup evaluates one group: j entries are gathered tile by tile into LDS, and every
-// thread owns IPL i-particles of the group and one slice of each tile; slices are combined
-// at the end in a fixed order, so the result is deterministic.
+// one workgroup evaluates one group: j entries are gathered tile by tile into LDS (the next
+// tile's global loads are issued before the current tile is computed), and thread t owns
+// IPL i-particles and one slice of every tile.  The group's n_i particles map onto
+// tps = ceil(n_i / IPL) threads per slice and floor(NT / tps) slices, so nearly all lanes
+// carry a real i-particle whatever n_i is.  Slices are combined at the end in slice order,
+// so the result is deterministic.
 //
 // Particle term (equation ParticleParticleNbody, G = 1):
 //   a_i += m_j (r_j - r_i) / (|r_j - r_i|^2 + eps_i^2)^{3/2},  phi_i -= m_j / (...)^{1/2}
@@ -21,15 +24,14 @@
 // rounded to FP32 when a tile is staged; the inner loop is FP32 (hardware reciprocal square
 // root); each slice sums a tile plainly and adds the tile total into a Kahan-compensated
 // accumulator; outputs are FP64.
+// FP64 variant: the same loop in FP64; 1/sqrt from the hardware estimate refined by two
+// Newton-Raphson steps.
 #include "dev_util.h"
 #include "fdx_internal.h"
 
 namespace fdx {
 
 namespace {
-
-constexpr int kThreads = 256;
-constexpr int kTile = 256;
 
 struct KArgs {
     const uint32_t *gbegin, *gcount;
@@ -68,7 +70,16 @@ template <> struct Acc<float> {
 };
 
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
+// Newton-Raphson for y = x^{-1/2}: y <- y + y (1 - x y^2) / 2, twice from the hardware estimate
+__device__ __forceinline__ double rsqrt_t(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        const double r = fma(-(x * y), y, 1.0);
+        y = fma(y * r, 0.5, y);
+    }
+    return y;
+}
 
 template <class T>
 __device__ __forceinline__ void pp(const typename V4<T>::t &J, T xi, T yi, T zi, T e2, T &ax,
@@ -115,23 +126,19 @@ __device__ __forceinline__ void pc(const typename V4<T>::t &A, const typename V4
     }
 }
 
-__device__ __forceinline__ uint32_t next_pow2(uint32_t v) {
-    return v <= 1 ? 1u : 1u << (32 - __clz((int)(v - 1)));
-}
-
-template <class T, bool QUAD, int IPL>
+template <class T, int NT, int IPL>
 struct Smem {
     using V = typename V4<T>::t;
     union {
-        struct { V e[kTile]; V s[3 * kTile]; } t;   // EPJ tile, SPJ tile (A, B, C per entry)
-        double red[kThreads * IPL * 4];     // per-thread slice partials
+        V e[NT];                        // particle tile
+        V s[3 * NT];                    // superparticle tile (A, B, C per entry)
+        double red[NT * IPL * 4];       // per-thread slice partials
     };
     uint32_t slot;
 };
 
-// one group: gi
-template <class T, bool QUAD, int IPL>
-__device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T, QUAD, IPL> &sm) {
+template <class T, bool QUAD, int NT, int IPL>
+__device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T, NT, IPL> &sm) {
     using V = typename V4<T>::t;
     const int tid = threadIdx.x;
     const uint32_t gb = a.gbegin[gi], ni = a.gcount[gi];
@@ -142,10 +149,11 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
     const double cx = fp32 ? a.gcentre[3 * gi] : 0.0, cy = fp32 ? a.gcentre[3 * gi + 1] : 0.0,
                  cz = fp32 ? a.gcentre[3 * gi + 2] : 0.0;
 
-    uint32_t tps = next_pow2((ni + IPL - 1) / IPL);
-    tps = tps > (uint32_t)kThreads ? (uint32_t)kThreads : tps;
-    const uint32_t nslice = kThreads / tps;
+    uint32_t tps = (ni + IPL - 1) / IPL;
+    tps = tps < 1 ? 1 : (tps > (uint32_t)NT ? (uint32_t)NT : tps);
+    const uint32_t nslice = NT / tps;
     const uint32_t slice = tid / tps, li = tid % tps;
+    const bool active = slice < nslice;
 
     T xi[IPL], yi[IPL], zi[IPL], e2[IPL];
     Acc<T> ax[IPL], ay[IPL], az[IPL], ph[IPL];
@@ -159,70 +167,95 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
         e2[k] = (T)(e * e);
     }
 
-    // particle tiles
-    for (uint32_t t0 = 0; t0 < ne; t0 += kTile) {
-        const uint32_t nt = min((uint32_t)kTile, ne - t0);
-        __syncthreads();
-        for (uint32_t k = tid; k < nt; k += kThreads) {
-            const double4 p = a.jp[epj[t0 + k]];
-            V v;
-            v.x = (T)(p.x - cx); v.y = (T)(p.y - cy); v.z = (T)(p.z - cz); v.w = (T)p.w;
-            sm.t.e[k] = v;
-        }
-        __syncthreads();
-        T tx[IPL], ty[IPL], tz[IPL], tp[IPL];
+    // particle tiles: one entry per thread per tile, next tile prefetched into registers
+    {
+        double4 nxt = make_double4(0, 0, 0, 0);
+        if ((uint32_t)tid < ne) nxt = a.jp[epj[tid]];
+        for (uint32_t t0 = 0; t0 < ne; t0 += NT) {
+            const uint32_t nt = min((uint32_t)NT, ne - t0);
+            __syncthreads();
+            if ((uint32_t)tid < nt) {
+                V v;
+                v.x = (T)(nxt.x - cx); v.y = (T)(nxt.y - cy); v.z = (T)(nxt.z - cz); v.w = (T)nxt.w;
+                sm.e[tid] = v;
+            }
+            __syncthreads();
+            if (t0 + NT + tid < ne) nxt = a.jp[epj[t0 + NT + tid]];
+            if (active) {
+                T tx[IPL], ty[IPL], tz[IPL], tp[IPL];
 #pragma unroll
-        for (int k = 0; k < IPL; k++) tx[k] = ty[k] = tz[k] = tp[k] = 0;
+                for (int k = 0; k < IPL; k++) tx[k] = ty[k] = tz[k] = tp[k] = 0;
 #pragma unroll 4
-        for (uint32_t j = slice; j < nt; j += nslice) {
-            const V J = sm.t.e[j];
+                for (uint32_t j = slice; j < nt; j += nslice) {
+                    const V J = sm.e[j];
 #pragma unroll
-            for (int k = 0; k < IPL; k++) pp<T>(J, xi[k], yi[k], zi[k], e2[k], tx[k], ty[k], tz[k], tp[k]);
+                    for (int k = 0; k < IPL; k++)
+                        pp<T>(J, xi[k], yi[k], zi[k], e2[k], tx[k], ty[k], tz[k], tp[k]);
+                }
+#pragma unroll
+                for (int k = 0; k < IPL; k++) {
+                    ax[k].add(tx[k]); ay[k].add(ty[k]); az[k].add(tz[k]); ph[k].add(tp[k]);
+                }
+            }
         }
-#pragma unroll
-        for (int k = 0; k < IPL; k++) { ax[k].add(tx[k]); ay[k].add(ty[k]); az[k].add(tz[k]); ph[k].add(tp[k]); }
     }
 
     // superparticle tiles
-    for (uint32_t t0 = 0; t0 < ns; t0 += kTile) {
-        const uint32_t nt = min((uint32_t)kTile, ns - t0);
-        __syncthreads();
-        for (uint32_t k = tid; k < nt; k += kThreads) {
-            const double *o = a.mom + 10 * (size_t)spj[t0 + k];
-            V A, B, C;
-            A.x = (T)(o[1] - cx); A.y = (T)(o[2] - cy); A.z = (T)(o[3] - cz); A.w = (T)o[0];
-            sm.t.s[3 * k] = A;
-            if (QUAD) {
-                B.x = (T)o[4]; B.y = (T)o[5]; B.z = (T)o[6]; B.w = (T)o[7];
-                C.x = (T)o[8]; C.y = (T)o[9]; C.z = 0; C.w = 0;
-                sm.t.s[3 * k + 1] = B;
-                sm.t.s[3 * k + 2] = C;
+    {
+        const double *o = nullptr;
+        double m0 = 0, m1 = 0, m2 = 0, m3 = 0, q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0, q5 = 0;
+        auto fetch = [&](uint32_t k) {
+            o = a.mom + 10 * (size_t)spj[k];
+            m0 = o[0]; m1 = o[1]; m2 = o[2]; m3 = o[3];
+            if (QUAD) { q0 = o[4]; q1 = o[5]; q2 = o[6]; q3 = o[7]; q4 = o[8]; q5 = o[9]; }
+        };
+        if ((uint32_t)tid < ns) fetch(tid);
+        for (uint32_t t0 = 0; t0 < ns; t0 += NT) {
+            const uint32_t nt = min((uint32_t)NT, ns - t0);
+            __syncthreads();
+            if ((uint32_t)tid < nt) {
+                V A;
+                A.x = (T)(m1 - cx); A.y = (T)(m2 - cy); A.z = (T)(m3 - cz); A.w = (T)m0;
+                sm.s[3 * tid] = A;
+                if (QUAD) {
+                    V B, C;
+                    B.x = (T)q0; B.y = (T)q1; B.z = (T)q2; B.w = (T)q3;
+                    C.x = (T)q4; C.y = (T)q5; C.z = 0; C.w = 0;
+                    sm.s[3 * tid + 1] = B;
+                    sm.s[3 * tid + 2] = C;
+                }
+            }
+            __syncthreads();
+            if (t0 + NT + tid < ns) fetch(t0 + NT + tid);
+            if (active) {
+                T tx[IPL], ty[IPL], tz[IPL], tp[IPL];
+#pragma unroll
+                for (int k = 0; k < IPL; k++) tx[k] = ty[k] = tz[k] = tp[k] = 0;
+#pragma unroll 2
+                for (uint32_t j = slice; j < nt; j += nslice) {
+                    const V A = sm.s[3 * j];
+                    V B, C;
+                    if (QUAD) { B = sm.s[3 * j + 1]; C = sm.s[3 * j + 2]; } else { B = A; C = A; }
+#pragma unroll
+                    for (int k = 0; k < IPL; k++)
+                        pc<T, QUAD>(A, B, C, xi[k], yi[k], zi[k], e2[k], tx[k], ty[k], tz[k], tp[k]);
+                }
+#pragma unroll
+                for (int k = 0; k < IPL; k++) {
+                    ax[k].add(tx[k]); ay[k].add(ty[k]); az[k].add(tz[k]); ph[k].add(tp[k]);
+                }
             }
         }
-        __syncthreads();
-        T tx[IPL], ty[IPL], tz[IPL], tp[IPL];
-#pragma unroll
-        for (int k = 0; k < IPL; k++) tx[k] = ty[k] = tz[k] = tp[k] = 0;
-#pragma unroll 2
-        for (uint32_t j = slice; j < nt; j += nslice) {
-            const V A = sm.t.s[3 * j];
-            V B, C;
-            if (QUAD) { B = sm.t.s[3 * j + 1]; C = sm.t.s[3 * j + 2]; } else { B = A; C = A; }
-#pragma unroll
-            for (int k = 0; k < IPL; k++)
-                pc<T, QUAD>(A, B, C, xi[k], yi[k], zi[k], e2[k], tx[k], ty[k], tz[k], tp[k]);
-        }
-#pragma unroll
-        for (int k = 0; k < IPL; k++) { ax[k].add(tx[k]); ay[k].add(ty[k]); az[k].add(tz[k]); ph[k].add(tp[k]); }
     }
 
     // combine slices in slice order (FP64), remove the self term of the potential
     __syncthreads();
-    double *red = sm.red;
+    if (active) {
 #pragma unroll
-    for (int k = 0; k < IPL; k++) {
-        double *o = red + 4 * ((size_t)k * kThreads + tid);
-        o[0] = ax[k].val(); o[1] = ay[k].val(); o[2] = az[k].val(); o[3] = ph[k].val();
+        for (int k = 0; k < IPL; k++) {
+            double *o = sm.red + 4 * ((size_t)k * NT + tid);
+            o[0] = ax[k].val(); o[1] = ay[k].val(); o[2] = az[k].val(); o[3] = ph[k].val();
+        }
     }
     __syncthreads();
     if (slice == 0) {
@@ -232,7 +265,7 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
             if (i >= ni) continue;
             double s[4] = {0, 0, 0, 0};
             for (uint32_t q = 0; q < nslice; q++) {
-                const double *o = red + 4 * ((size_t)k * kThreads + q * tps + li);
+                const double *o = sm.red + 4 * ((size_t)k * NT + q * tps + li);
                 s[0] += o[0]; s[1] += o[1]; s[2] += o[2]; s[3] += o[3];
             }
             const uint32_t r = gb + i;
@@ -241,64 +274,86 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
             a.fs[r] = make_double4(s[0], s[1], s[2], s[3] + (double)self);
         }
     }
+    __syncthreads();
 }
 
-template <class T, bool QUAD, int IPL>
-__global__ void __launch_bounds__(kThreads)
+template <class T, bool QUAD, int NT, int IPL>
+__global__ void __launch_bounds__(NT)
 k_force_direct(KArgs a) {
-    __shared__ Smem<T, QUAD, IPL> sm;
+    __shared__ Smem<T, NT, IPL> sm;
     // XCD-aware order: consecutive blocks go round-robin over the 8 XCDs, so hand each XCD a
     // contiguous run of groups (neighbouring groups share most of their lists -> L2 reuse).
     const uint32_t G = a.G;
     const uint32_t chunk = (G + 7) / 8;
-    const uint32_t gi = (blockIdx.x % 8) * chunk + blockIdx.x / 8;
-    if (gi >= G) return;
-    force_group<T, QUAD, IPL>(a, a.order ? a.order[gi] : gi, sm);
+    const uint32_t q = (blockIdx.x % 8) * chunk + blockIdx.x / 8;
+    if (q >= G) return;
+    force_group<T, QUAD, NT, IPL>(a, a.order ? a.order[q] : q, sm);
 }
 
-template <class T, bool QUAD, int IPL>
-__global__ void __launch_bounds__(kThreads)
+// Persistent variant: a fixed grid pops queue slots from a device counter (the queue order
+// lists the groups by decreasing cost, so the longest work starts first).
+template <class T, bool QUAD, int NT, int IPL>
+__global__ void __launch_bounds__(NT)
 k_force_persistent(KArgs a) {
-    __shared__ Smem<T, QUAD, IPL> sm;
+    __shared__ Smem<T, NT, IPL> sm;
     const uint32_t G = *a.ngroups;
     for (;;) {
-        __syncthreads();
         if (threadIdx.x == 0) sm.slot = atomicAdd(&a.st->queue_head, 1u);
         __syncthreads();
         const uint32_t slot = sm.slot;
+        __syncthreads();
         if (slot >= G) break;
-        force_group<T, QUAD, IPL>(a, a.order ? a.order[slot] : slot, sm);
+        force_group<T, QUAD, NT, IPL>(a, a.order ? a.order[slot] : slot, sm);
     }
 }
 
-template <class T, bool QUAD, int IPL>
-hipError_t launch(const KArgs &k, bool persistent, size_t gmax, hipStream_t s) {
+template <class T, bool QUAD, int NT, int IPL>
+hipError_t launch(const KArgs &k, bool persistent, hipStream_t s) {
     if (persistent) {
         int dev = 0, ncu = 256;
-        hipGetDevice(&dev);
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
         int per_cu = 0;
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_force_persistent<T, QUAD, IPL>,
-                                                     kThreads, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(k_force_persistent<T, QUAD, NT, IPL>), NT, 0);
         if (per_cu < 1) per_cu = 1;
         size_t grid = (size_t)ncu * per_cu;
-        if (grid > gmax) grid = gmax ? gmax : 1;
-        hipLaunchKernelGGL((k_force_persistent<T, QUAD, IPL>), dim3((unsigned)grid), dim3(kThreads),
+        if (k.G && grid > k.G) grid = k.G;
+        hipLaunchKernelGGL((k_force_persistent<T, QUAD, NT, IPL>), dim3((unsigned)grid), dim3(NT),
                            0, s, k);
     } else {
         if (k.G == 0) return hipSuccess;
         const uint32_t chunk = (k.G + 7) / 8;
-        hipLaunchKernelGGL((k_force_direct<T, QUAD, IPL>), dim3(8 * chunk), dim3(kThreads), 0, s, k);
+        hipLaunchKernelGGL((k_force_direct<T, QUAD, NT, IPL>), dim3(8 * chunk), dim3(NT), 0, s, k);
     }
     return hipGetLastError();
 }
 
-constexpr const char *kVariantNames[] = {"ipl1", "ipl2"};
+struct Variant { int nt, ipl; const char *name; };
+constexpr Variant kVariants[] = {
+    {256, 1, "nt256_ipl1"}, {256, 2, "nt256_ipl2"}, {512, 1, "nt512_ipl1"}, {512, 2, "nt512_ipl2"}};
+constexpr int kNumVariants = 4;
+
+template <class T, bool QUAD>
+hipError_t launch_v(const KArgs &k, bool persistent, int v, hipStream_t s) {
+    switch (v) {
+        case 0: return launch<T, QUAD, 256, 1>(k, persistent, s);
+        case 1: return launch<T, QUAD, 256, 2>(k, persistent, s);
+        case 2: return launch<T, QUAD, 512, 1>(k, persistent, s);
+        default: return launch<T, QUAD, 512, 2>(k, persistent, s);
+    }
+}
 
 }  // namespace
 
-int force_variants() { return 2; }
-const char *force_variant_name(int v) { return kVariantNames[v < 0 || v > 1 ? 0 : v]; }
+int force_variants() { return kNumVariants; }
+const char *force_variant_name(int v) {
+    return kVariants[v < 0 || v >= kNumVariants ? 0 : v].name;
+}
+int force_variant_capacity(int v) {
+    const Variant &x = kVariants[v < 0 || v >= kNumVariants ? 0 : v];
+    return x.nt * x.ipl;
+}
 
 hipError_t force(size_t G, const ForceArgs &fa, hipStream_t s) {
     KArgs k;
@@ -306,19 +361,13 @@ hipError_t force(size_t G, const ForceArgs &fa, hipStream_t s) {
     k.jp = fa.jp; k.seps = fa.seps; k.mom = fa.mom;
     k.seg = fa.seg; k.cap = fa.cap; k.cnt_e = fa.cnt_e; k.cnt_s = fa.cnt_s;
     k.list = fa.list;
-    k.order = fa.order; k.ngroups = &fa.st->n_groups; k.fs = fa.fs; k.st = fa.st;
+    k.order = fa.order; k.ngroups = &fa.st->n_groups_c; k.fs = fa.fs; k.st = fa.st;
     k.G = (uint32_t)G;
-    const int ipl = fa.variant == 1 ? 2 : 1;
-    if (fa.fp32) {
-        if (fa.quad) return ipl == 2 ? launch<float, true, 2>(k, fa.persistent, G, s)
-                                     : launch<float, true, 1>(k, fa.persistent, G, s);
-        return ipl == 2 ? launch<float, false, 2>(k, fa.persistent, G, s)
-                        : launch<float, false, 1>(k, fa.persistent, G, s);
-    }
-    if (fa.quad) return ipl == 2 ? launch<double, true, 2>(k, fa.persistent, G, s)
-                                 : launch<double, true, 1>(k, fa.persistent, G, s);
-    return ipl == 2 ? launch<double, false, 2>(k, fa.persistent, G, s)
-                    : launch<double, false, 1>(k, fa.persistent, G, s);
+    const int v = fa.variant;
+    if (fa.fp32) return fa.quad ? launch_v<float, true>(k, fa.persistent, v, s)
+                                : launch_v<float, false>(k, fa.persistent, v, s);
+    return fa.quad ? launch_v<double, true>(k, fa.persistent, v, s)
+                   : launch_v<double, false>(k, fa.persistent, v, s);
 }
 
 }  // namespace fdx

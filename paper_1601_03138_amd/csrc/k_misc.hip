@@ -66,7 +66,7 @@ __global__ void k_kick_drift(size_t n, double *x, double *y, double *z, double *
 // step reported an overflow (its forces are incomplete; the host redoes force and kick).
 __global__ void k_kick(size_t n, double *vx, double *vy, double *vz, const double *ax,
                        const double *ay, const double *az, double dt, const DevStatus *st) {
-    if (st && (st->cell_overflow | st->list_overflow | st->walk_error)) return;
+    if (st && status_incomplete(*st)) return;
     const double h = 0.5 * dt;
     for (size_t i = gtid(); i < n; i += gstride()) {
         vx[i] += h * ax[i]; vy[i] += h * ay[i]; vz[i] += h * az[i];

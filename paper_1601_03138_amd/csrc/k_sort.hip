@@ -116,8 +116,8 @@ size_t radix_scratch_u32(size_t n) {
 }
 
 hipError_t radix_sort(size_t n, uint64_t *key, uint64_t *key_alt, uint32_t *val,
-                      uint32_t *val_alt, const uint32_t *sysid, int nsys, uint32_t *scratch,
-                      uint64_t *partial, bool *result_in_alt, hipStream_t s) {
+                      uint32_t *val_alt, const uint32_t *sysid, int nsys, int key_bits,
+                      uint32_t *scratch, uint64_t *partial, bool *result_in_alt, hipStream_t s) {
     *result_in_alt = false;
     if (n <= 1) return hipSuccess;
     const uint32_t nblocks = (uint32_t)((n + kTile - 1) / kTile);
@@ -127,10 +127,11 @@ hipError_t radix_sort(size_t n, uint64_t *key, uint64_t *key_alt, uint32_t *val,
     uint32_t *vin = val, *vout = val_alt;
     int sys_passes = 0;
     for (int b = 0; (1ll << b) < (long long)nsys; b += 8) sys_passes++;
-    const int passes = 8 + sys_passes;           // key bits 0..63, then system id bytes
+    const int key_passes = (key_bits + 7) / 8;
+    const int passes = key_passes + sys_passes;  // key bytes, then system id bytes
     for (int p = 0; p < passes; p++) {
-        const bool sysp = p >= 8;
-        const int shift = sysp ? 8 * (p - 8) : 8 * p;
+        const bool sysp = p >= key_passes;
+        const int shift = sysp ? 8 * (p - key_passes) : 8 * p;
         if (sysp)
             hipLaunchKernelGGL(k_rs_hist<true>, dim3(nblocks), dim3(kThreads), 0, s, kin, vin,
                                sysid, n, shift, nblocks, counts);

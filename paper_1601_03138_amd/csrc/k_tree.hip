@@ -253,8 +253,12 @@ __global__ void k_group_emit(size_t n, int n_group, Cells c, const uint32_t *fla
 // and the group's system.
 __global__ void __launch_bounds__(kThreads)
 k_group_geom(const uint32_t *ngroups, int nsys, const int64_t *off, Cells c,
-             const uint64_t *skey, const double *cube, Groups g) {
+             const uint64_t *skey, const double *cube, Groups g, DevStatus *st) {
     const uint32_t G = min(*ngroups, g.cap);
+    if (gtid() == 0) {
+        st->n_groups_c = G;
+        if (*ngroups > g.cap) st->group_overflow = 1;
+    }
     const int lane = lane_id();
     const size_t wave0 = gtid() / kWave, nwaves = gstride() / kWave;
     for (size_t gi = wave0; gi < G; gi += nwaves) {
@@ -343,7 +347,7 @@ hipError_t make_groups(size_t n, int nsys, const int64_t *sys_off, Cells c,
     hipLaunchKernelGGL(k_group_emit, dim3(grid_for(n)), dim3(kThreads), 0, s, n, n_group, c, flag,
                        gcell_at, gpos, g);
     hipLaunchKernelGGL(k_group_geom, dim3(grid_for(n / 16 + 64, 4096)), dim3(kThreads), 0, s,
-                       &st->n_groups, nsys, sys_off, c, skey, cube, g);
+                       &st->n_groups, nsys, sys_off, c, skey, cube, g, st);
     return hipGetLastError();
 }
 

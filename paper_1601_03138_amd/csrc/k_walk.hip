@@ -27,19 +27,22 @@ constexpr int kSlack = 160;     // stack entries kept free for sequential descen
 template <bool FILL>
 __global__ void __launch_bounds__(kThreads)
 k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, double theta2,
-       const uint64_t *seg, const uint32_t *cap, uint32_t *list, uint32_t *cnt_e,
-       uint32_t *cnt_s, uint32_t *ovf_list, DevStatus *st) {
+       const uint64_t *seg, const uint32_t *cap, uint64_t list_cap, uint32_t *list,
+       uint32_t *cnt_e, uint32_t *cnt_s, uint32_t *ovf_list, const uint32_t *sel,
+       const uint32_t *nsel, DevStatus *st) {
     __shared__ uint32_t stack_all[kWaves][kWalkStack];
     const int w = threadIdx.x / kWave, lane = lane_id();
     const uint64_t lt = lanemask_lt();
     uint32_t *stk = stack_all[w];
-    const uint32_t G = min(*ngroups, g.cap);
-    for (size_t gi = (size_t)blockIdx.x * kWaves + w; gi < G; gi += (size_t)gridDim.x * kWaves) {
+    const uint32_t G = sel ? *nsel : min(*ngroups, g.cap);
+    for (size_t q = (size_t)blockIdx.x * kWaves + w; q < G; q += (size_t)gridDim.x * kWaves) {
+        const size_t gi = sel ? sel[q] : q;
         const uint32_t *bx = g.box + 6 * gi;
         const int bminx = 2 * (int)bx[0], bminy = 2 * (int)bx[1], bminz = 2 * (int)bx[2];
         const int bmaxx = 2 * (int)bx[3] + 2, bmaxy = 2 * (int)bx[4] + 2, bmaxz = 2 * (int)bx[5] + 2;
         const uint64_t base = FILL ? seg[gi] : 0;
-        const uint32_t capg = FILL ? cap[gi] : 0;
+        const bool seg_ok = !FILL || base + cap[gi] <= list_cap;
+        const uint32_t capg = FILL && seg_ok ? cap[gi] : 0;
         uint32_t ne = 0, ns = 0, sp = 1;
         bool err = false;
         if (lane == 0) stk[0] = g.sys[gi];          // roots are cells 0..nsys-1
@@ -105,12 +108,16 @@ k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, 
         }
         wave_barrier();
         if (lane == 0) {
-            cnt_e[gi] = ne;
-            cnt_s[gi] = ns;
             if (err) atomicOr(&st->walk_error, 1u);
-            if (FILL && (uint64_t)ne + ns > capg) {
+            if (FILL && ((uint64_t)ne + ns > capg || !seg_ok)) {
+                // the list did not fit: leave the group empty and queue it for an exact re-walk
+                cnt_e[gi] = 0;
+                cnt_s[gi] = 0;
                 uint32_t k = atomicAdd(&st->list_overflow, 1u);
-                ovf_list[k] = (uint32_t)gi;
+                if (ovf_list && k < g.cap) ovf_list[k] = (uint32_t)gi;
+            } else {
+                cnt_e[gi] = ne;
+                cnt_s[gi] = ns;
             }
         }
     }
@@ -142,6 +149,22 @@ k_list_stats(const uint32_t *ngroups, uint32_t gmax, const uint32_t *gcount,
     }
 }
 
+// Persistent-queue keys: estimated cost n_i * (|EPJ| + 2 |SPJ|) (a superparticle costs about
+// twice a particle), complemented so an ascending sort lists the costliest group first;
+// slots past the group count sort last.
+__global__ void k_queue_keys(uint32_t gmax, const uint32_t *ngroups_c, const uint32_t *gcount,
+                             const uint32_t *cnt_e, const uint32_t *cnt_s, uint64_t *key,
+                             uint32_t *val) {
+    const uint32_t G = *ngroups_c;
+    for (size_t gi = gtid(); gi < gmax; gi += gstride()) {
+        uint64_t cost = 0;
+        if (gi < G) cost = (uint64_t)gcount[gi] * ((uint64_t)cnt_e[gi] + 2ull * cnt_s[gi]);
+        cost = cost > 0xFFFFFFFEull ? 0xFFFFFFFEull : cost;
+        key[gi] = gi < G ? (uint64_t)(0xFFFFFFFEu - (uint32_t)cost) : 0xFFFFFFFFull;
+        val[gi] = (uint32_t)gi;
+    }
+}
+
 inline unsigned grid_waves(size_t gmax) {
     size_t b = (gmax + kWaves - 1) / kWaves;
     if (b < 1) b = 1;
@@ -152,16 +175,26 @@ inline unsigned grid_waves(size_t gmax) {
 }  // namespace
 
 hipError_t walk(bool fill, size_t gmax, const Groups g, const Cells c, double theta2,
-                const uint64_t *seg, const uint32_t *cap, uint32_t *list, uint32_t *cnt_e,
-                uint32_t *cnt_s, uint32_t *ovf_list, DevStatus *st, hipStream_t s) {
+                const uint64_t *seg, const uint32_t *cap, uint64_t list_cap, uint32_t *list,
+                uint32_t *cnt_e, uint32_t *cnt_s, uint32_t *ovf_list, const uint32_t *sel,
+                const uint32_t *nsel, DevStatus *st, hipStream_t s) {
     if (fill)
         hipLaunchKernelGGL(k_walk<true>, dim3(grid_waves(gmax)), dim3(kThreads), 0, s,
-                           &st->n_groups, g, c.node, c.link, theta2, seg, cap, list, cnt_e,
-                           cnt_s, ovf_list, st);
+                           &st->n_groups, g, c.node, c.link, theta2, seg, cap, list_cap, list,
+                           cnt_e, cnt_s, ovf_list, sel, nsel, st);
     else
         hipLaunchKernelGGL(k_walk<false>, dim3(grid_waves(gmax)), dim3(kThreads), 0, s,
-                           &st->n_groups, g, c.node, c.link, theta2, seg, cap, list, cnt_e,
-                           cnt_s, ovf_list, st);
+                           &st->n_groups, g, c.node, c.link, theta2, seg, cap, list_cap, list,
+                           cnt_e, cnt_s, ovf_list, sel, nsel, st);
+    return hipGetLastError();
+}
+
+hipError_t queue_keys(size_t gmax, const Groups g, const uint32_t *cnt_e, const uint32_t *cnt_s,
+                      uint64_t *key, uint32_t *val, DevStatus *st, hipStream_t s) {
+    size_t b = (gmax + kThreads - 1) / kThreads;
+    b = b < 1 ? 1 : (b > 8192 ? 8192 : b);
+    hipLaunchKernelGGL(k_queue_keys, dim3((unsigned)b), dim3(kThreads), 0, s, (uint32_t)gmax,
+                       &st->n_groups_c, g.count, cnt_e, cnt_s, key, val);
     return hipGetLastError();
 }
 
@@ -169,7 +202,7 @@ hipError_t list_caps(size_t gmax, const uint32_t *cnt_e, const uint32_t *cnt_s, 
                      DevStatus *st, hipStream_t s) {
     size_t b = (gmax + kThreads - 1) / kThreads;
     b = b < 1 ? 1 : (b > 8192 ? 8192 : b);
-    hipLaunchKernelGGL(k_list_caps, dim3((unsigned)b), dim3(kThreads), 0, s, &st->n_groups,
+    hipLaunchKernelGGL(k_list_caps, dim3((unsigned)b), dim3(kThreads), 0, s, &st->n_groups_c,
                        (uint32_t)gmax, cnt_e, cnt_s, cap);
     return hipGetLastError();
 }
@@ -178,7 +211,7 @@ hipError_t list_stats(size_t gmax, const Groups g, const uint32_t *cnt_e, const 
                       DevStatus *st, hipStream_t s) {
     size_t b = (gmax + kThreads - 1) / kThreads;
     b = b < 1 ? 1 : (b > 2048 ? 2048 : b);
-    hipLaunchKernelGGL(k_list_stats, dim3((unsigned)b), dim3(kThreads), 0, s, &st->n_groups,
+    hipLaunchKernelGGL(k_list_stats, dim3((unsigned)b), dim3(kThreads), 0, s, &st->n_groups_c,
                        (uint32_t)gmax, g.count, cnt_e, cnt_s, st);
     return hipGetLastError();
 }

@@ -22,8 +22,9 @@ QUAD, FP32REL, PREDICTOR, PERSISTENT, GRAPH, TIMING = 1, 2, 4, 8, 16, 32
 EXPORTS = ["fdx_create", "fdx_destroy", "fdx_set_particles", "fdx_build_tree", "fdx_calc_force",
            "fdx_integrate", "fdx_get_particles", "fdx_get_forces", "fdx_get_stats",
            "fdx_get_tree", "fdx_get_groups", "fdx_get_lists", "fdx_last_error",
-           "fdx_autotune", "fdx_predictor_train", "fdx_predictor_save", "fdx_predictor_load",
-           "fdx_predictor_features", "fdx_mlp_forward", "fdx_mlp_grad"]
+           "fdx_autotune_shapes", "fdx_set_shape", "fdx_autotune", "fdx_mlp_params",
+           "fdx_predictor_features", "fdx_mlp_forward", "fdx_mlp_grad", "fdx_predictor_train",
+           "fdx_predictor_margin", "fdx_predictor_save", "fdx_predictor_load"]
 
 
 class FdxError(RuntimeError):
@@ -82,15 +83,17 @@ def _declare(L):
     L.fdx_get_lists.argtypes = [vp] + [vp] * 4
     L.fdx_last_error.argtypes = [vp]
     L.fdx_last_error.restype = C.c_char_p
-    if hasattr(L, "fdx_autotune"):
-        L.fdx_autotune.argtypes = [vp, f64, i32, f64, i32, vp, i32, C.POINTER(i32)]
-    if hasattr(L, "fdx_predictor_train"):
-        L.fdx_predictor_train.argtypes = [vp, vp, vp, i64, i32, i32, f64, i64, vp]
-        L.fdx_predictor_save.argtypes = [vp, vp]
-        L.fdx_predictor_load.argtypes = [vp, vp]
-        L.fdx_predictor_features.argtypes = [vp, vp]
-        L.fdx_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
-        L.fdx_mlp_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+    L.fdx_autotune_shapes.argtypes = []
+    L.fdx_set_shape.argtypes = [vp, i32]
+    L.fdx_autotune.argtypes = [vp, f64, i32, f64, i32, vp, i32, i32, vp, vp, vp]
+    L.fdx_mlp_params.argtypes = []
+    L.fdx_predictor_features.argtypes = [vp, vp]
+    L.fdx_mlp_forward.argtypes = [vp, vp, vp, i64, vp]
+    L.fdx_mlp_grad.argtypes = [vp, vp, vp, vp, i64, vp, vp]
+    L.fdx_predictor_train.argtypes = [vp, vp, vp, i64, i32, i32, f64, i64, vp]
+    L.fdx_predictor_margin.argtypes = [vp, f64, vp]
+    L.fdx_predictor_save.argtypes = [vp, C.c_char_p]
+    L.fdx_predictor_load.argtypes = [vp, C.c_char_p]
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -247,3 +250,63 @@ class Context:
         self._check(self.lib.fdx_get_lists(self.h, _ptr(ne), _ptr(ns), _ptr(epj), _ptr(spj)),
                     "get_lists")
         return ne, ns, epj[:int(st["n_epj"])], spj[:int(st["n_spj"])]
+
+    # -- autotuner ---------------------------------------------------------------------
+    def autotune(self, theta, n_leaf, eps, flags, n_group_candidates, reps=2):
+        cand = np.ascontiguousarray(n_group_candidates, dtype=np.int32)
+        nv = self.lib.fdx_autotune_shapes()
+        times = np.full(cand.shape[0] * nv, np.nan)
+        bg, bv = C.c_int32(), C.c_int32()
+        self._check(self.lib.fdx_autotune(self.h, float(theta), n_leaf, float(eps), int(flags),
+                                          _ptr(cand), cand.shape[0], reps, _ptr(times),
+                                          C.byref(bg), C.byref(bv)), "autotune")
+        return int(bg.value), int(bv.value), times.reshape(cand.shape[0], nv)
+
+    def set_shape(self, shape: int):
+        self._check(self.lib.fdx_set_shape(self.h, int(shape)), "set_shape")
+
+    # -- learned list-length predictor -----------------------------------------------------
+    def predictor_features(self) -> np.ndarray:
+        G = int(self.stats()["n_groups"])
+        X = np.empty((max(G, 1), 8), np.float32)
+        self._check(self.lib.fdx_predictor_features(self.h, _ptr(X)), "predictor_features")
+        return X[:G]
+
+    def mlp_forward(self, P, X) -> np.ndarray:
+        P = np.ascontiguousarray(P, np.float32)
+        X = np.ascontiguousarray(X, np.float32)
+        y = np.empty(X.shape[0], np.float32)
+        self._check(self.lib.fdx_mlp_forward(self.h, _ptr(P), _ptr(X), X.shape[0], _ptr(y)),
+                    "mlp_forward")
+        return y
+
+    def mlp_grad(self, P, X, t):
+        P = np.ascontiguousarray(P, np.float32)
+        X = np.ascontiguousarray(X, np.float32)
+        t = np.ascontiguousarray(t, np.float32)
+        g = np.empty(P.shape[0], np.float32)
+        loss = np.zeros(1, np.float32)
+        self._check(self.lib.fdx_mlp_grad(self.h, _ptr(P), _ptr(X), _ptr(t), X.shape[0], _ptr(g),
+                                          _ptr(loss)), "mlp_grad")
+        return g, float(loss[0])
+
+    def predictor_train(self, X, t, epochs=20, batch=4096, lr=1e-3, seed=1):
+        X = np.ascontiguousarray(X, np.float32)
+        t = np.ascontiguousarray(t, np.float32)
+        losses = np.zeros(epochs, np.float32)
+        self._check(self.lib.fdx_predictor_train(self.h, _ptr(X), _ptr(t), X.shape[0], epochs,
+                                                 batch, float(lr), int(seed), _ptr(losses)),
+                    "predictor_train")
+        return losses
+
+    def predictor_margin(self, margin=float("nan")) -> float:
+        out = C.c_double()
+        self._check(self.lib.fdx_predictor_margin(self.h, float(margin), C.byref(out)),
+                    "predictor_margin")
+        return out.value
+
+    def predictor_save(self, path: str):
+        self._check(self.lib.fdx_predictor_save(self.h, path.encode()), "predictor_save")
+
+    def predictor_load(self, path: str):
+        self._check(self.lib.fdx_predictor_load(self.h, path.encode()), "predictor_load")

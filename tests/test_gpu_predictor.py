@@ -1,0 +1,150 @@
+"""GPU: the learned list-length predictor.  Network forward pass and gradients against the
+FP64 oracle, training with the library's own kernels, and the predicted single-pass walk:
+lists and forces bit-identical to the exact two-pass walk for any prediction scale."""
+import math
+import os
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+from paper_1601_03138_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fdx():
+    from paper_1601_03138_amd import fdx as F
+    return F
+
+
+@pytest.fixture(scope="module")
+def ctx(fdx):
+    c = fdx.Context(0)
+    yield c
+    c.close()
+
+
+def _params(seed, scale=0.3):
+    return (np.random.default_rng(seed).normal(size=M.N_PARAMS) * scale).astype(np.float32)
+
+
+def test_forward_matches_oracle(ctx):
+    rng = np.random.default_rng(1)
+    P = _params(2)
+    X = rng.normal(size=(1000, 8)).astype(np.float32)
+    y = ctx.mlp_forward(P, X)
+    ref = M.forward(P.astype(np.float64), X.astype(np.float64))
+    assert np.max(np.abs(y - ref)) <= 1e-4 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_gradients_match_oracle_per_tensor(ctx):
+    rng = np.random.default_rng(5)
+    P = _params(6)
+    X = rng.normal(size=(777, 8)).astype(np.float32)      # ragged vs the 32-sample blocks
+    t = rng.normal(size=777).astype(np.float32)
+    g, loss = ctx.mlp_grad(P, X, t)
+    lref, gref = M.loss_and_grad(P.astype(np.float64), X.astype(np.float64), t.astype(np.float64))
+    assert loss == pytest.approx(lref, rel=1e-4)
+    bounds = np.cumsum([0, 512, 64, 4096, 64, 64, 1])
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        err = np.linalg.norm(g[a:b] - gref[a:b]) / max(np.linalg.norm(gref[a:b]), 1e-30)
+        assert err < 1e-3, (a, b, err)
+
+
+def _harvest(ctx, sets, n_group, theta):
+    Xs, ts = [], []
+    for ps in sets:
+        ctx.set_particles(ps)
+        ctx.calc_force(theta, 8, n_group, 0.0, quad=True, fp32=True)
+        X = ctx.predictor_features()
+        ne, ns, _, _ = ctx.lists()
+        Xs.append(X)
+        ts.append(np.log(ne.astype(np.float64) + ns).astype(np.float32))
+    return np.concatenate(Xs), np.concatenate(ts)
+
+
+@pytest.fixture(scope="module")
+def trained(ctx):
+    sets = [I.plummer(40000, seed=900 + k, eps=1 / 256) for k in range(3)]
+    sets += [I.clustered(n_background=32768, n_clusters=8, n_per_cluster=4096, seed=910 + k)
+             for k in range(3)]
+    X, t = _harvest(ctx, sets, 128, 0.5)
+    _say(f"[predictor] harvested {X.shape[0]} groups")
+    losses = ctx.predictor_train(X, t, epochs=30, batch=1024, lr=3e-3, seed=7)
+    _say("[predictor] losses", np.round(losses[[0, 5, 10, 20, -1]], 4),
+         "margin", ctx.predictor_margin())
+    return X, t, losses
+
+
+def test_training_reduces_loss(trained):
+    X, t, losses = trained
+    assert losses[-1] < 0.01 * losses[0]
+    # explains most of the variance of ln(list length) across groups (R^2 > 0.75)
+    assert losses[-1] < 0.25 * np.var(t)
+
+
+@pytest.mark.parametrize("margin", [None, math.log(0.01), math.log(100.0)])
+def test_predicted_walk_is_exact(ctx, trained, margin):
+    ps = I.clustered(n_background=40000, n_clusters=8, n_per_cluster=3000, seed=3)
+    ctx.set_particles(ps)
+    ctx.calc_force(0.5, 8, 128, 0.0, quad=True, fp32=True)
+    a_exact = ctx.forces()
+    lists_exact = ctx.lists()
+    trained_margin = ctx.predictor_margin()
+    if margin is not None:
+        ctx.predictor_margin(margin)
+    try:
+        ctx.calc_force(0.5, 8, 128, 0.0, quad=True, fp32=True, predictor=True)
+        st = ctx.stats()
+        a_pred = ctx.forces()
+        lists_pred = ctx.lists()
+    finally:
+        ctx.predictor_margin(trained_margin)
+    _say(f"[predicted walk] margin={margin} overflow groups {st['overflow_groups']} of "
+         f"{st['n_groups']}, capacity {st['list_capacity']} vs exact "
+         f"{int(lists_exact[0].sum() + lists_exact[1].sum())}")
+    assert np.array_equal(a_pred, a_exact)
+    for a, b in zip(lists_pred, lists_exact):
+        assert np.array_equal(a, b)
+    if margin == math.log(0.01):
+        assert st["overflow_groups"] > 0.9 * st["n_groups"]
+    if margin == math.log(100.0):
+        assert st["overflow_groups"] == 0
+    if margin is None:
+        # a small training set and an input of another size and seed: most groups still fit
+        assert st["overflow_groups"] <= 0.25 * st["n_groups"]
+        assert st["list_capacity"] < 3 * int(lists_exact[0].sum() + lists_exact[1].sum())
+
+
+def test_save_load_round_trip(ctx, fdx, trained):
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "pred.bin")
+        ctx.predictor_save(path)
+        c2 = fdx.Context(0)
+        c2.predictor_load(path)
+        assert c2.predictor_margin() == ctx.predictor_margin()
+        ps = I.plummer(20000, seed=77, eps=1 / 256)
+        for c in (ctx, c2):
+            c.set_particles(ps)
+            c.calc_force(0.5, 8, 128, 0.0, quad=True, fp32=True, predictor=True)
+        assert ctx.stats()["list_capacity"] == c2.stats()["list_capacity"]
+        assert np.array_equal(ctx.forces(), c2.forces())
+        c2.close()
+
+
+def test_predictor_without_weights_is_a_state_error(fdx):
+    c = fdx.Context(0)
+    c.set_particles(I.plummer(1000, seed=1, eps=0.01))
+    with pytest.raises(fdx.FdxError) as ei:
+        c.calc_force(0.5, 8, 64, 0.0, predictor=True)
+    assert ei.value.code == fdx.ESTATE
+    c.close()
