@@ -48,7 +48,7 @@ def force_flops(st, quad):
         FLOPS_PC_QUAD if quad else FLOPS_PC_MONO)
 
 
-def read_traffic(kernel_tag: str):
+def read_traffic(kernel_tag: str, shape: str):
     """HBM bytes per launch of the force kernel measured by rocprofv3 counters, if a summary
     for the current kernel source is committed under profiles/ (else None)."""
     path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.txt")
@@ -63,6 +63,8 @@ def read_traffic(kernel_tag: str):
         import hashlib
         src = open(os.path.join(ROOT, "paper_1601_03138_amd", "csrc", "k_force.hip"), "rb").read()
         if vals.get("k_force.hip sha256") != hashlib.sha256(src).hexdigest():
+            return None
+        if vals.get("shape") != shape:
             return None
         return float(vals["hbm bytes per launch"])
     except (KeyError, ValueError, OSError):
@@ -104,6 +106,8 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--fp64-evals", type=int, default=3)
     ap.add_argument("--cpu-sample-groups", type=int, default=512)
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the autotuner over n_group x kernel shape first and use its choice")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -121,7 +125,7 @@ def main():
     if args.copy_calibration:
         src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")   # 256 MiB
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)      # one plain streaming kernel: 256 MiB in, 256 MiB out
         torch.cuda.synchronize()
         log("[bench] copy calibration: 268435456 bytes read, 268435456 bytes written")
         del src, dst
@@ -130,6 +134,15 @@ def main():
     ctx = fdx.Context(0)
     ctx.set_particles(ps)
     flags = fdx.Context.flags(quad=quad, fp32=True, timing=True)
+    tuned = None
+    if args.autotune:
+        cand = [64, 128, 256, 512]
+        bg, bv, times = ctx.autotune(theta, 8, 0.0, fdx.Context.flags(quad=quad, fp32=True), cand,
+                                     reps=2)
+        n_group = bg
+        tuned = {"n_group": bg, "shape": bv, "candidates": cand,
+                 "ms": [[None if np.isnan(v) else round(float(v), 3) for v in row] for row in times]}
+        log(f"[bench] autotune: n_group={bg} shape={bv} times={tuned['ms']}")
 
     # initial force, then warm-up steps
     ctx.calc_force_flags(theta, 8, n_group, 0.0, flags)
@@ -153,8 +166,9 @@ def main():
     mean_force_ms = float(np.mean(t_force))
     achieved = float(np.mean(flops)) / (mean_force_ms / 1e3) / 1e12
     phase_ms = {k[2:]: round(float(np.mean([p[k] for p in phases])), 4) for k in phases[0]}
+    shape = ctx.shape_name(st["shape"])
     traffic = read_traffic(f"force_fp32_quad_{args.workload}" if quad else
-                           f"force_fp32_mono_{args.workload}")
+                           f"force_fp32_mono_{args.workload}", shape)
 
     # FP64 force path on the same (current) particles
     fp64 = None
@@ -215,7 +229,7 @@ def main():
                    "step": "leapfrog kick-drift, full force evaluation, kick"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                     "traffic": traffic, "kernel": "k_force_direct<float, quad>",
+                     "traffic": traffic, "kernel": f"k_force_direct<float, quad> {shape}",
                      "kernel_ms": round(mean_force_ms, 3),
                      "interactions_per_launch": int(st["n_interactions_pp"] + st["n_interactions_pc"]),
                      "flops_per_interaction": {"pp": FLOPS_PP,
@@ -224,6 +238,7 @@ def main():
         "fp64": fp64,
         "accuracy": accuracy,
         "phases_ms": phase_ms,
+        "autotune": tuned,
         "tree": {"cells": int(st["n_cells"]), "groups": int(st["n_groups"]),
                  "depth": int(st["depth"]), "epj": int(st["n_epj"]), "spj": int(st["n_spj"])},
     }

@@ -136,6 +136,7 @@ typedef struct {
     int64_t overflow_groups;           /* predictor path: groups re-walked exactly */
     int64_t list_capacity;             /* list entries allocated in the last walk */
     int32_t n_leaf, n_group, flags;
+    int32_t shape;                     /* force-kernel shape used (see fdx_autotune_shapes) */
     double theta;
     /* phase times in milliseconds (FDX_TIMING): keys, sort, tree, moments, groups, walk,
        force, unsort, predict (feature + MLP), total */
@@ -175,6 +176,7 @@ int fdx_get_lists(fdx_ctx *ctx, uint32_t *n_epj, uint32_t *n_spj, uint32_t *epj,
  * size; null skips).  fdx_set_shape fixes the shape (-1 = default).
  * FDX_EINVAL: no candidates, reps < 1, or a shape out of range. */
 int fdx_autotune_shapes(void);
+const char *fdx_shape_name(int32_t shape);   /* e.g. "nt512_ipl1_pf"; "" if out of range */
 int fdx_set_shape(fdx_ctx *ctx, int32_t shape);
 int fdx_autotune(fdx_ctx *ctx, double theta, int32_t n_leaf, double eps, int32_t flags,
                  const int32_t *n_group_cand, int32_t n_cand, int32_t reps, double *times_ms,

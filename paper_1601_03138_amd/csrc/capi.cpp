@@ -305,6 +305,7 @@ void finish_stats(fdx_ctx *c) {
         if (c->hst->lvl[l + 1] > c->hst->lvl[l]) depth = l;
     o.depth = depth;
     o.n_leaf = c->n_leaf; o.n_group = c->n_group; o.flags = c->flags; o.theta = c->theta;
+    o.shape = ext_force_variant(c);
 }
 
 int sync_timing(fdx_ctx *c) {

@@ -11,7 +11,9 @@
 namespace fdx {
 
 int ext_force_variant(fdx_ctx *c) {
-    int v = c->ext.variant >= 0 ? c->ext.variant : 3;
+    // defaults measured at N = 2^24: FP32 nt512_ipl1_pf, FP64 nt256_ipl2 (no prefetch)
+    const int dflt = (c->flags & FDX_FP32REL) ? 2 : 5;
+    int v = c->ext.variant >= 0 ? c->ext.variant : dflt;
     if (force_variant_capacity(v) < c->n_group) v = 3;
     return v;
 }
@@ -188,6 +190,10 @@ using namespace fdx;
 extern "C" {
 
 int fdx_autotune_shapes(void) { return force_variants(); }
+
+const char *fdx_shape_name(int32_t shape) {
+    return shape < 0 || shape >= force_variants() ? "" : force_variant_name(shape);
+}
 
 int fdx_set_shape(fdx_ctx *c, int32_t shape) {
     if (!c) return FDX_EINVAL;

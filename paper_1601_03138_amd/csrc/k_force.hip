@@ -137,7 +137,7 @@ struct Smem {
     uint32_t slot;
 };
 
-template <class T, bool QUAD, int NT, int IPL>
+template <class T, bool QUAD, int NT, int IPL, bool PF>
 __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T, NT, IPL> &sm) {
     using V = typename V4<T>::t;
     const int tid = threadIdx.x;
@@ -167,20 +167,22 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
         e2[k] = (T)(e * e);
     }
 
-    // particle tiles: one entry per thread per tile, next tile prefetched into registers
+    // particle tiles: one entry per thread per tile (PF: the next tile is loaded into
+    // registers while the current one is computed)
     {
         double4 nxt = make_double4(0, 0, 0, 0);
-        if ((uint32_t)tid < ne) nxt = a.jp[epj[tid]];
+        if (PF && (uint32_t)tid < ne) nxt = a.jp[epj[tid]];
         for (uint32_t t0 = 0; t0 < ne; t0 += NT) {
             const uint32_t nt = min((uint32_t)NT, ne - t0);
             __syncthreads();
             if ((uint32_t)tid < nt) {
+                if (!PF) nxt = a.jp[epj[t0 + tid]];
                 V v;
                 v.x = (T)(nxt.x - cx); v.y = (T)(nxt.y - cy); v.z = (T)(nxt.z - cz); v.w = (T)nxt.w;
                 sm.e[tid] = v;
             }
             __syncthreads();
-            if (t0 + NT + tid < ne) nxt = a.jp[epj[t0 + NT + tid]];
+            if (PF && t0 + NT + tid < ne) nxt = a.jp[epj[t0 + NT + tid]];
             if (active) {
                 T tx[IPL], ty[IPL], tz[IPL], tp[IPL];
 #pragma unroll
@@ -209,11 +211,12 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
             m0 = o[0]; m1 = o[1]; m2 = o[2]; m3 = o[3];
             if (QUAD) { q0 = o[4]; q1 = o[5]; q2 = o[6]; q3 = o[7]; q4 = o[8]; q5 = o[9]; }
         };
-        if ((uint32_t)tid < ns) fetch(tid);
+        if (PF && (uint32_t)tid < ns) fetch(tid);
         for (uint32_t t0 = 0; t0 < ns; t0 += NT) {
             const uint32_t nt = min((uint32_t)NT, ns - t0);
             __syncthreads();
             if ((uint32_t)tid < nt) {
+                if (!PF) fetch(t0 + tid);
                 V A;
                 A.x = (T)(m1 - cx); A.y = (T)(m2 - cy); A.z = (T)(m3 - cz); A.w = (T)m0;
                 sm.s[3 * tid] = A;
@@ -226,7 +229,7 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
                 }
             }
             __syncthreads();
-            if (t0 + NT + tid < ns) fetch(t0 + NT + tid);
+            if (PF && t0 + NT + tid < ns) fetch(t0 + NT + tid);
             if (active) {
                 T tx[IPL], ty[IPL], tz[IPL], tp[IPL];
 #pragma unroll
@@ -277,7 +280,7 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
     __syncthreads();
 }
 
-template <class T, bool QUAD, int NT, int IPL>
+template <class T, bool QUAD, int NT, int IPL, bool PF>
 __global__ void __launch_bounds__(NT)
 k_force_direct(KArgs a) {
     __shared__ Smem<T, NT, IPL> sm;
@@ -287,12 +290,12 @@ k_force_direct(KArgs a) {
     const uint32_t chunk = (G + 7) / 8;
     const uint32_t q = (blockIdx.x % 8) * chunk + blockIdx.x / 8;
     if (q >= G) return;
-    force_group<T, QUAD, NT, IPL>(a, a.order ? a.order[q] : q, sm);
+    force_group<T, QUAD, NT, IPL, PF>(a, a.order ? a.order[q] : q, sm);
 }
 
 // Persistent variant: a fixed grid pops queue slots from a device counter (the queue order
 // lists the groups by decreasing cost, so the longest work starts first).
-template <class T, bool QUAD, int NT, int IPL>
+template <class T, bool QUAD, int NT, int IPL, bool PF>
 __global__ void __launch_bounds__(NT)
 k_force_persistent(KArgs a) {
     __shared__ Smem<T, NT, IPL> sm;
@@ -303,11 +306,11 @@ k_force_persistent(KArgs a) {
         const uint32_t slot = sm.slot;
         __syncthreads();
         if (slot >= G) break;
-        force_group<T, QUAD, NT, IPL>(a, a.order ? a.order[slot] : slot, sm);
+        force_group<T, QUAD, NT, IPL, PF>(a, a.order ? a.order[slot] : slot, sm);
     }
 }
 
-template <class T, bool QUAD, int NT, int IPL>
+template <class T, bool QUAD, int NT, int IPL, bool PF>
 hipError_t launch(const KArgs &k, bool persistent, hipStream_t s) {
     if (persistent) {
         int dev = 0, ncu = 256;
@@ -315,32 +318,39 @@ hipError_t launch(const KArgs &k, bool persistent, hipStream_t s) {
         (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
         int per_cu = 0;
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(k_force_persistent<T, QUAD, NT, IPL>), NT, 0);
+            &per_cu, reinterpret_cast<const void *>(k_force_persistent<T, QUAD, NT, IPL, PF>), NT, 0);
         if (per_cu < 1) per_cu = 1;
         size_t grid = (size_t)ncu * per_cu;
         if (k.G && grid > k.G) grid = k.G;
-        hipLaunchKernelGGL((k_force_persistent<T, QUAD, NT, IPL>), dim3((unsigned)grid), dim3(NT),
+        hipLaunchKernelGGL((k_force_persistent<T, QUAD, NT, IPL, PF>), dim3((unsigned)grid), dim3(NT),
                            0, s, k);
     } else {
         if (k.G == 0) return hipSuccess;
         const uint32_t chunk = (k.G + 7) / 8;
-        hipLaunchKernelGGL((k_force_direct<T, QUAD, NT, IPL>), dim3(8 * chunk), dim3(NT), 0, s, k);
+        hipLaunchKernelGGL((k_force_direct<T, QUAD, NT, IPL, PF>), dim3(8 * chunk), dim3(NT), 0, s, k);
     }
     return hipGetLastError();
 }
 
-struct Variant { int nt, ipl; const char *name; };
+struct Variant { int nt, ipl; bool pf; const char *name; };
 constexpr Variant kVariants[] = {
-    {256, 1, "nt256_ipl1"}, {256, 2, "nt256_ipl2"}, {512, 1, "nt512_ipl1"}, {512, 2, "nt512_ipl2"}};
-constexpr int kNumVariants = 4;
+    {256, 1, true, "nt256_ipl1_pf"}, {256, 2, true, "nt256_ipl2_pf"},
+    {512, 1, true, "nt512_ipl1_pf"}, {512, 2, true, "nt512_ipl2_pf"},
+    {256, 1, false, "nt256_ipl1"},   {256, 2, false, "nt256_ipl2"},
+    {512, 1, false, "nt512_ipl1"},   {512, 2, false, "nt512_ipl2"}};
+constexpr int kNumVariants = 8;
 
 template <class T, bool QUAD>
 hipError_t launch_v(const KArgs &k, bool persistent, int v, hipStream_t s) {
     switch (v) {
-        case 0: return launch<T, QUAD, 256, 1>(k, persistent, s);
-        case 1: return launch<T, QUAD, 256, 2>(k, persistent, s);
-        case 2: return launch<T, QUAD, 512, 1>(k, persistent, s);
-        default: return launch<T, QUAD, 512, 2>(k, persistent, s);
+        case 0: return launch<T, QUAD, 256, 1, true>(k, persistent, s);
+        case 1: return launch<T, QUAD, 256, 2, true>(k, persistent, s);
+        case 2: return launch<T, QUAD, 512, 1, true>(k, persistent, s);
+        case 3: return launch<T, QUAD, 512, 2, true>(k, persistent, s);
+        case 4: return launch<T, QUAD, 256, 1, false>(k, persistent, s);
+        case 5: return launch<T, QUAD, 256, 2, false>(k, persistent, s);
+        case 6: return launch<T, QUAD, 512, 1, false>(k, persistent, s);
+        default: return launch<T, QUAD, 512, 2, false>(k, persistent, s);
     }
 }
 

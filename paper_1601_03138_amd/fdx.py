@@ -22,7 +22,7 @@ QUAD, FP32REL, PREDICTOR, PERSISTENT, GRAPH, TIMING = 1, 2, 4, 8, 16, 32
 EXPORTS = ["fdx_create", "fdx_destroy", "fdx_set_particles", "fdx_build_tree", "fdx_calc_force",
            "fdx_integrate", "fdx_get_particles", "fdx_get_forces", "fdx_get_stats",
            "fdx_get_tree", "fdx_get_groups", "fdx_get_lists", "fdx_last_error",
-           "fdx_autotune_shapes", "fdx_set_shape", "fdx_autotune", "fdx_mlp_params",
+           "fdx_autotune_shapes", "fdx_shape_name", "fdx_set_shape", "fdx_autotune", "fdx_mlp_params",
            "fdx_predictor_features", "fdx_mlp_forward", "fdx_mlp_grad", "fdx_predictor_train",
            "fdx_predictor_margin", "fdx_predictor_save", "fdx_predictor_load"]
 
@@ -38,7 +38,7 @@ class Stats(C.Structure):
         "n", "n_sys", "n_cells", "n_groups", "depth", "n_epj", "n_spj", "n_interactions_pp",
         "n_interactions_pc", "overflow_groups", "list_capacity")] + [
         ("n_leaf", C.c_int32), ("n_group", C.c_int32), ("flags", C.c_int32),
-        ("theta", C.c_double)] + [(k, C.c_double) for k in (
+        ("shape", C.c_int32), ("theta", C.c_double)] + [(k, C.c_double) for k in (
             "t_keys", "t_sort", "t_tree", "t_moments", "t_groups", "t_walk", "t_force",
             "t_unsort", "t_predict", "t_total")]
 
@@ -85,6 +85,8 @@ def _declare(L):
     L.fdx_last_error.restype = C.c_char_p
     L.fdx_autotune_shapes.argtypes = []
     L.fdx_set_shape.argtypes = [vp, i32]
+    L.fdx_shape_name.argtypes = [i32]
+    L.fdx_shape_name.restype = C.c_char_p
     L.fdx_autotune.argtypes = [vp, f64, i32, f64, i32, vp, i32, i32, vp, vp, vp]
     L.fdx_mlp_params.argtypes = []
     L.fdx_predictor_features.argtypes = [vp, vp]
@@ -261,6 +263,9 @@ class Context:
                                           _ptr(cand), cand.shape[0], reps, _ptr(times),
                                           C.byref(bg), C.byref(bv)), "autotune")
         return int(bg.value), int(bv.value), times.reshape(cand.shape[0], nv)
+
+    def shape_name(self, shape: int) -> str:
+        return self.lib.fdx_shape_name(int(shape)).decode()
 
     def set_shape(self, shape: int):
         self._check(self.lib.fdx_set_shape(self.h, int(shape)), "set_shape")
