@@ -34,6 +34,7 @@ FLOPS_PC_QUAD = 54
 WORKLOADS = {
     # name: (n_group, theta, quad, dt)
     "clustered16m": (256, 0.5, True, 1.0 / 1024.0),
+    "ensemble512": (128, 0.6, True, 1.0 / 256.0),
     "plummer1m": (256, 0.5, True, 1.0 / 256.0),
     "plummer4k": (64, 0.5, False, 1.0 / 128.0),
 }
@@ -95,6 +96,19 @@ def cpu_baseline(ps, n_group, theta, quad, n_sample_groups, seed=7):
                       f"force evaluation"}
 
 
+def system_energies(ps, ctx):
+    """Kinetic + potential energy of every system at the context's current state."""
+    a = ctx.forces()
+    x, y, z, vx, vy, vz = ctx.particles()
+    off = ps.offsets()
+    e = np.empty(ps.n_sys)
+    for s in range(ps.n_sys):
+        sl = slice(off[s], off[s + 1])
+        e[s] = (0.5 * np.sum(ps.m[sl] * (vx[sl] ** 2 + vy[sl] ** 2 + vz[sl] ** 2))
+                + 0.5 * np.sum(ps.m[sl] * a[sl, 3]))
+    return e
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +120,12 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--fp64-evals", type=int, default=3)
     ap.add_argument("--cpu-sample-groups", type=int, default=512)
+    ap.add_argument("--graph", action="store_true",
+                    help="replay each leapfrog step as a captured HIP graph (persistent force)")
+    ap.add_argument("--persistent", action="store_true",
+                    help="persistent force kernel over the cost-ordered group queue")
+    ap.add_argument("--predictor", default="",
+                    help="predictor weights: also time the predicted single-pass walk")
     ap.add_argument("--autotune", action="store_true",
                     help="run the autotuner over n_group x kernel shape first and use its choice")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -133,7 +153,8 @@ def main():
     ps = inputs.workload(args.workload)
     ctx = fdx.Context(0)
     ctx.set_particles(ps)
-    flags = fdx.Context.flags(quad=quad, fp32=True, timing=True)
+    persistent = args.persistent or args.graph
+    flags = fdx.Context.flags(quad=quad, fp32=True, timing=True, persistent=persistent)
     tuned = None
     if args.autotune:
         cand = [64, 128, 256, 512]
@@ -146,22 +167,38 @@ def main():
 
     # initial force, then warm-up steps
     ctx.calc_force_flags(theta, 8, n_group, 0.0, flags)
+    energy0 = system_energies(ps, ctx) if ps.n_sys > 1 else None
     for _ in range(args.warmup):
-        ctx.integrate(dt, 1)
+        ctx.integrate(dt, 1, graph=args.graph)
     torch.cuda.synchronize()
     log(f"[bench] timing {args.steps} steps")
     t_force, flops, phases = [], [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        ctx.integrate(dt, 1)
-        st = ctx.stats()
-        t_force.append(st["t_force"])
-        flops.append(force_flops(st, quad))
-        phases.append({k: st[k] for k in st if k.startswith("t_")})
+        ctx.integrate(dt, 1, graph=args.graph)
+        if not args.graph:
+            st = ctx.stats()
+            t_force.append(st["t_force"])
+            flops.append(force_flops(st, quad))
+            phases.append({k: st[k] for k in st if k.startswith("t_")})
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
     value = ps.n / (ms_step / 1e3)
+    drift = None
+    if energy0 is not None:
+        e1 = system_energies(ps, ctx)
+        d = np.abs((e1 - energy0) / energy0)
+        drift = {"max": float(d.max()), "median": float(np.median(d)),
+                 "steps": args.warmup + args.steps}
+    if args.graph:
+        # kernel timing of the same evaluation, eager, on the current particles
+        for _ in range(2):
+            ctx.calc_force_flags(theta, 8, n_group, 0.0, flags)
+            st = ctx.stats()
+            t_force.append(st["t_force"])
+            flops.append(force_flops(st, quad))
+            phases.append({k: st[k] for k in st if k.startswith("t_")})
     st = ctx.stats()
     mean_force_ms = float(np.mean(t_force))
     achieved = float(np.mean(flops)) / (mean_force_ms / 1e3) / 1e12
@@ -169,6 +206,38 @@ def main():
     shape = ctx.shape_name(st["shape"])
     traffic = read_traffic(f"force_fp32_quad_{args.workload}" if quad else
                            f"force_fp32_mono_{args.workload}", shape)
+
+    # learned predictor: the same evaluation with the predicted single-pass walk
+    pred = None
+    if args.predictor:
+        ctx.predictor_load(args.predictor)
+        pflags = flags | fdx.PREDICTOR
+        ctx.calc_force_flags(theta, 8, n_group, 0.0, flags)
+        exact_total = int(sum(int(a.sum()) for a in ctx.list_counts()))
+        a_exact = ctx.forces()
+        ctx.calc_force_flags(theta, 8, n_group, 0.0, pflags)
+        identical = bool(np.array_equal(ctx.forces(), a_exact))
+        rows = {"exact": [], "predicted": []}
+        for _ in range(max(3, args.steps // 2)):
+            for key, fl in (("exact", flags), ("predicted", pflags)):
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                ctx.calc_force_flags(theta, 8, n_group, 0.0, fl)
+                torch.cuda.synchronize()
+                sp = ctx.stats()
+                rows[key].append(((time.perf_counter() - ta) * 1e3, sp["t_walk"],
+                                  sp["overflow_groups"], sp["list_capacity"], sp["n_groups"]))
+        med = {k: np.median(np.array(v), axis=0) for k, v in rows.items()}
+        pred = {"ms_per_eval_exact": round(float(med["exact"][0]), 3),
+                "ms_per_eval_predicted": round(float(med["predicted"][0]), 3),
+                "walk_ms_exact": round(float(med["exact"][1]), 3),
+                "walk_ms_predicted": round(float(med["predicted"][1]), 3),
+                "overflow_groups": int(med["predicted"][2]), "groups": int(med["predicted"][4]),
+                "list_entries_exact": exact_total,
+                "list_capacity_predicted": int(med["predicted"][3]),
+                "margin": ctx.predictor_margin(),
+                "forces_bit_identical": identical}
+        log(f"[bench] predictor: {pred}")
 
     # FP64 force path on the same (current) particles
     fp64 = None
@@ -224,8 +293,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": ps.n, "theta": theta, "n_group": n_group,
-                   "n_leaf": 8, "quadrupole": quad, "eps": float(ps.eps[0]), "dt": dt,
+        "config": {"workload": args.workload, "n": ps.n, "systems": ps.n_sys, "theta": theta,
+                   "n_group": n_group, "n_leaf": 8, "quadrupole": quad,
+                   "eps": float(ps.eps[0]) if ps.n_sys == 1 else "4/N_s^(1/3)", "dt": dt,
+                   "graph": args.graph, "persistent": persistent,
                    "step": "leapfrog kick-drift, full force evaluation, kick"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
@@ -238,6 +309,8 @@ def main():
         "fp64": fp64,
         "accuracy": accuracy,
         "phases_ms": phase_ms,
+        "energy_drift": drift,
+        "predictor": pred,
         "autotune": tuned,
         "tree": {"cells": int(st["n_cells"]), "groups": int(st["n_groups"]),
                  "depth": int(st["depth"]), "epj": int(st["n_epj"]), "spj": int(st["n_spj"])},

@@ -161,7 +161,8 @@ int fdx_get_groups(fdx_ctx *ctx, uint32_t *cell, uint32_t *begin, uint32_t *coun
 
 /* Interaction lists of the last walk: n_epj[g], n_spj[g]; epj = the EPJ entries (sorted
  * particle ranks) of all groups concatenated, spj = the SPJ entries (cell ids) likewise
- * (each group's entries in the library's emission order). */
+ * (each group's entries in the library's emission order).  Null epj and spj copy the
+ * counts only. */
 int fdx_get_lists(fdx_ctx *ctx, uint32_t *n_epj, uint32_t *n_spj, uint32_t *epj,
                   uint32_t *spj);
 

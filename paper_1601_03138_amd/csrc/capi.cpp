@@ -633,8 +633,11 @@ int fdx_get_lists(fdx_ctx *c, uint32_t *n_epj, uint32_t *n_spj, uint32_t *epj, u
     HIPCHK(c, hipStreamSynchronize(s));
     uint64_t end = 0;
     for (size_t g = 0; g < G; g++) end = std::max<uint64_t>(end, seg[g] + cap[g]);
-    std::vector<uint32_t> all(end ? end : 1);
-    if (end) HIPCHK(c, hipMemcpy(all.data(), c->list.p, 4 * end, hipMemcpyDeviceToHost));
+    std::vector<uint32_t> all;
+    if (epj || spj) {
+        all.resize(end ? end : 1);
+        if (end) HIPCHK(c, hipMemcpy(all.data(), c->list.p, 4 * end, hipMemcpyDeviceToHost));
+    }
     uint64_t oe = 0, os = 0;
     for (size_t g = 0; g < G; g++) {
         if (n_epj) n_epj[g] = ce[g];

@@ -243,6 +243,12 @@ class Context:
         self._check(self.lib.fdx_get_groups(self.h, *[_ptr(d[k]) for k in order]), "get_groups")
         return d
 
+    def list_counts(self):
+        G = int(self.stats()["n_groups"])
+        ne, ns = np.empty(G, np.uint32), np.empty(G, np.uint32)
+        self._check(self.lib.fdx_get_lists(self.h, _ptr(ne), _ptr(ns), None, None), "get_lists")
+        return ne, ns
+
     def lists(self):
         st = self.stats()
         G = int(st["n_groups"])
