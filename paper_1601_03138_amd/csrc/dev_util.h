@@ -57,6 +57,24 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     return v;
 }
 
+// Exclusive prefix sum over the wave of small non-negative counts, one bit plane at a time:
+// prefix = sum_b 2^b * (number of lower lanes with bit b set), from a ballot per bit and
+// mbcnt (no cross-lane data movement).  *total receives the wave total.  Loops only over the
+// bit planes in use, so counts below 16 cost four ballots.
+__device__ __forceinline__ uint32_t wave_excl_scan_small(uint32_t v, uint32_t *total) {
+    uint32_t pre = 0, tot = 0;
+    for (int b = 0; b < 32; b++) {
+        if (!__ballot((v >> b) != 0u)) break;
+        const uint64_t m = __ballot((v >> b) & 1u);
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        pre += below << b;
+        tot += (uint32_t)__popcll(m) << b;
+    }
+    *total = tot;
+    return pre;
+}
+
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);

@@ -12,7 +12,7 @@ namespace fdx {
 constexpr int kLevels = 21;              // key bits per axis; deepest cell level
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kMaxGroup = 512;           // largest n_group the force kernels take
-constexpr int kWalkStack = 2048;         // per-wave LDS stack of the group walk (entries)
+constexpr int kWalkStack = 1024;         // per-wave LDS stack of the group walk (entries)
 
 // Device-side status and counters of one evaluation, read back once per force call.
 struct DevStatus {

@@ -86,21 +86,21 @@ k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, 
             ns += (uint32_t)__popcll(bs);
             // particles of opened leaves, from the front
             const uint32_t lc = leaf ? lk.y : 0u;
-            const uint32_t li = wave_incl_scan(lc);
-            const uint32_t ltot = __shfl(li, kWave - 1, kWave);
+            uint32_t ltot;
+            const uint32_t lex = wave_excl_scan_small(lc, &ltot);
             if (FILL && leaf) {
-                const uint32_t e0 = ne + li - lc;
+                const uint32_t e0 = ne + lex;
                 for (uint32_t k = 0; k < lc; k++)
                     if (e0 + k < capg) list[base + e0 + k] = lk.x + k;
             }
             ne += ltot;
             // children of opened internal cells onto the stack
             const uint32_t cc = inner ? nch : 0u;
-            const uint32_t ci = wave_incl_scan(cc);
-            const uint32_t ctot = __shfl(ci, kWave - 1, kWave);
+            uint32_t ctot;
+            const uint32_t cex = wave_excl_scan_small(cc, &ctot);
             if (sp + ctot > (uint32_t)kWalkStack) { err = true; break; }
             if (inner) {
-                const uint32_t s0 = sp + ci - cc;
+                const uint32_t s0 = sp + cex;
                 for (uint32_t k = 0; k < cc; k++) stk[s0 + k] = lk.x + k;
             }
             sp += ctot;
