@@ -1,0 +1,162 @@
+"""GPU parity at the benchmark configurations' full sizes, in the launch configuration bench.py
+times: keys, order, every cell and every group bit-exact against the oracle's full serial
+build; lists and forces on sampled groups; accuracy against FP64 direct summation on seeded
+subsets; the ensemble with graph-captured steps; the predictor path at full size."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1601_03138_amd import inputs as I
+
+from parity_util import (BAR_RMS_VS_DIRECT, F32_RMS_REL_VS_TREE, check_groups, check_moments,
+                         rel_err)
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+WEIGHTS = os.path.join(os.path.dirname(HERE), "paper_1601_03138_amd",
+                       "predictor_clustered16m_ng256.bin")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fdx():
+    from paper_1601_03138_amd import fdx as F
+    return F
+
+
+@pytest.fixture(scope="module")
+def ctx(fdx):
+    c = fdx.Context(0)
+    yield c
+    c.close()
+
+
+def _compare_full(ctx, ps, n_leaf, n_group, theta, quad, n_sample_groups, seed):
+    """Everything the oracle can afford at this size; returns (tree, groups, sampled lists)."""
+    t = O.build_tree(ps, n_leaf)
+    g = O.make_groups(t, n_group)
+    tree = ctx.tree()
+    assert np.array_equal(tree["cube"], t.cube)
+    assert np.array_equal(tree["key"], t.skey)
+    assert np.array_equal(tree["perm"], t.perm)
+    for k in ("level", "prefix", "begin", "count", "first_child", "nchild", "parent"):
+        assert np.array_equal(tree[k], getattr(t, k).astype(tree[k].dtype)), k
+    check_moments(tree["mom"], t)
+    check_groups(ctx.groups(), g)
+    # lists of sampled groups
+    rng = np.random.default_rng(seed)
+    sel = np.sort(rng.choice(g.n, min(n_sample_groups, g.n), replace=False))
+    lists = O.walk(t, g, theta, sel)
+    ne, ns = ctx.list_counts()
+    assert np.array_equal(ne[sel].astype(np.int64), lists.n_epj)
+    assert np.array_equal(ns[sel].astype(np.int64), lists.n_spj)
+    return t, g, sel, lists
+
+
+def _sampled_force_check(ctx, t, g, sel, lists, quad):
+    ref = lists.force(quad)                       # sorted order, rows of sampled groups
+    a = ctx.forces()
+    rows = np.concatenate([np.arange(g.begin[k], g.begin[k] + g.count[k]) for k in sel])
+    user = t.perm[rows].astype(np.int64)
+    e = rel_err(a[user], ref[rows])
+    return float(np.sqrt(np.mean(e ** 2)))
+
+
+def test_clustered16m_bench_configuration(ctx, fdx):
+    ps = I.workload("clustered16m")
+    _say(f"[fullsize] clustered16m n={ps.n}")
+    ctx.set_particles(ps)
+    ctx.calc_force(0.5, 8, 256, 0.0, quad=True, fp32=True)
+    t, g, sel, lists = _compare_full(ctx, ps, 8, 256, 0.5, True, 48, seed=5)
+    e_tree = _sampled_force_check(ctx, t, g, sel, lists, True)
+    sub = I.subset(ps.n, 256, seed=102)
+    e_direct = O.rms_rel_error(ctx.forces()[sub], O.direct(ps, sub))
+    _say(f"  cells {t.n_cells} groups {g.n}; fp32 vs tree (sampled) {e_tree:.2e}; "
+         f"vs direct {e_direct:.2e}")
+    assert e_tree <= F32_RMS_REL_VS_TREE
+    assert e_direct <= BAR_RMS_VS_DIRECT
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained predictor weights not present")
+def test_clustered16m_predictor_path_is_exact(ctx, fdx):
+    ps = I.workload("clustered16m")
+    ctx.set_particles(ps)
+    ctx.calc_force(0.5, 8, 256, 0.0, quad=True, fp32=True)
+    a = ctx.forces()
+    counts = ctx.list_counts()
+    ctx.predictor_load(WEIGHTS)
+    ctx.calc_force(0.5, 8, 256, 0.0, quad=True, fp32=True, predictor=True)
+    st = ctx.stats()
+    _say(f"[fullsize] predictor: overflow {st['overflow_groups']} of {st['n_groups']}, capacity "
+         f"{st['list_capacity']} vs exact {int(counts[0].sum() + counts[1].sum())}")
+    assert np.array_equal(ctx.forces(), a)
+    for x, y in zip(ctx.list_counts(), counts):
+        assert np.array_equal(x, y)
+    assert st["overflow_groups"] <= 0.02 * st["n_groups"]
+
+
+def test_plummer1m_fp64_fp32_and_ten_steps(ctx, fdx):
+    ps = I.workload("plummer1m")
+    _say(f"[fullsize] plummer1m n={ps.n}")
+    sub = I.subset(ps.n, 4096, seed=102)
+    d = O.direct(ps, sub)
+    ctx.set_particles(ps)
+    ctx.calc_force(0.5, 8, 256, 0.0, quad=True, fp32=False)
+    t, g, sel, lists = _compare_full(ctx, ps, 8, 256, 0.5, True, 64, seed=6)
+    a64 = ctx.forces()
+    ref = lists.force(True)
+    rows = np.concatenate([np.arange(g.begin[k], g.begin[k] + g.count[k]) for k in sel])
+    e64_tree = rel_err(a64[t.perm[rows].astype(np.int64)], ref[rows])
+    assert e64_tree.max() <= 1e-9
+    ctx.calc_force(0.5, 8, 256, 0.0, quad=True, fp32=True)
+    a32 = ctx.forces()
+    e32 = O.rms_rel_error(a32[sub], d)
+    e64 = O.rms_rel_error(a64[sub], d)
+    _say(f"  rms vs direct (4096 subset): fp32 {e32:.3e} fp64 {e64:.3e}")
+    assert e32 <= BAR_RMS_VS_DIRECT and e64 <= BAR_RMS_VS_DIRECT
+    # ten leapfrog steps of dt = 1/256; energy from the tree potential
+    def energy():
+        x, y, z, vx, vy, vz = ctx.particles()
+        return (0.5 * np.sum(ps.m * (vx ** 2 + vy ** 2 + vz ** 2))
+                + 0.5 * np.sum(ps.m * ctx.forces()[:, 3]))
+    E0 = energy()
+    ctx.integrate(1.0 / 256.0, 10)
+    E1 = energy()
+    _say(f"  energy drift after 10 steps: {abs((E1 - E0) / E0):.2e}")
+    assert abs((E1 - E0) / E0) < 1e-4
+
+
+def test_ensemble512_graph_configuration(ctx, fdx):
+    ens = I.workload("ensemble512")
+    _say(f"[fullsize] ensemble512 n={ens.n} systems={ens.n_sys}")
+    ctx.set_particles(ens)
+    ctx.calc_force(0.6, 8, 128, 0.0, quad=True, fp32=True, persistent=True)
+    t, g, sel, lists = _compare_full(ctx, ens, 8, 128, 0.6, True, 64, seed=7)
+    assert _sampled_force_check(ctx, t, g, sel, lists, True) <= F32_RMS_REL_VS_TREE
+    # a subset of systems against direct summation, all their particles
+    off = ens.offsets()
+    errs = []
+    for s in (0, 100, 511):
+        sl = np.arange(off[s], off[s + 1])
+        errs.append(O.rms_rel_error(ctx.forces()[sl], O.direct(ens, sl)))
+    _say(f"  rms da/a (theta 0.6) of systems 0, 100, 511: {np.round(errs, 5)}")
+    assert max(errs) < 5e-3
+    # graph-captured steps equal eager steps
+    x0 = ctx.particles()
+    ctx.integrate(1.0 / 256.0, 3, graph=True)
+    g_state = (ctx.particles(), ctx.forces())
+    ctx.set_particles(ens)
+    ctx.calc_force(0.6, 8, 128, 0.0, quad=True, fp32=True, persistent=True)
+    assert all(np.array_equal(a, b) for a, b in zip(ctx.particles(), x0))
+    ctx.integrate(1.0 / 256.0, 3)
+    for a, b in zip(ctx.particles(), g_state[0]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(ctx.forces(), g_state[1])
