@@ -125,13 +125,14 @@ int enqueue_keys_sort(fdx_ctx *c) {
     HIPCHK(c, bbox(n, c->x, c->y, c->z, c->sysid.p, S, c->bbox_u.p, s));
     HIPCHK(c, root_cubes(S, c->bbox_u.p, c->cube.p, s));
     HIPCHK(c, morton_keys(n, c->x, c->y, c->z, c->sysid.p, c->cube.p, c->key.p, c->perm.p, s));
+    HIPCHK(c, pack_particles(n, c->x, c->y, c->z, c->m, c->packed.p, s));
     mark(c, 1);
     bool alt = false;
     HIPCHK(c, radix_sort(n, c->key.p, c->key_alt.p, c->perm.p, c->perm_alt.p, c->sysid.p, S, 64,
                          c->rs_scratch.p, c->partial.p, &alt, s));
     c->skey = alt ? c->key_alt.p : c->key.p;
     c->sperm = alt ? c->perm_alt.p : c->perm.p;
-    HIPCHK(c, gather_sorted(n, c->sperm, c->x, c->y, c->z, c->m, c->eps_given ? c->eps : nullptr,
+    HIPCHK(c, gather_sorted(n, c->sperm, c->packed.p, c->eps_given ? c->eps : nullptr,
                             c->eps_all, c->jp.p, c->seps.p, c->inv.p, s));
     mark(c, 2);
     return FDX_OK;
@@ -384,6 +385,7 @@ int fdx_destroy(fdx_ctx *c) {
         b->release();
     c->sys_off.release();
     c->jp.release();
+    c->packed.release();
     c->fs.release();
     c->c_node.release();
     c->c_link.release();
@@ -468,6 +470,7 @@ int fdx_set_particles(fdx_ctx *c, int64_t n, const double *x, const double *y, c
     HIPCHK(c, c->inv.ensure(N));
     HIPCHK(c, c->rs_scratch.ensure(radix_scratch_u32(N)));
     HIPCHK(c, c->jp.ensure(N));
+    HIPCHK(c, c->packed.ensure(N));
     HIPCHK(c, c->seps.ensure(N));
     HIPCHK(c, c->flag.ensure(N));
     HIPCHK(c, c->gcell_at.ensure(N));

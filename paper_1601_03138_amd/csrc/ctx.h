@@ -66,7 +66,7 @@ struct fdx_ctx {
     fdx::DBuf<uint64_t> partial;
     uint64_t *skey = nullptr;
     uint32_t *sperm = nullptr;
-    fdx::DBuf<double4> jp;
+    fdx::DBuf<double4> jp, packed;
     fdx::DBuf<double> seps;
 
     // tree

@@ -100,9 +100,11 @@ hipError_t radix_sort(size_t n, uint64_t *key, uint64_t *key_alt, uint32_t *val,
                       uint32_t *scratch, uint64_t *partial, bool *result_in_alt, hipStream_t s);
 
 // sorted particle data
-hipError_t gather_sorted(size_t n, const uint32_t *perm, const double *x, const double *y,
-                         const double *z, const double *m, const double *eps, double eps_all,
-                         double4 *jp, double *seps, uint32_t *inv, hipStream_t s);
+hipError_t pack_particles(size_t n, const double *x, const double *y, const double *z,
+                          const double *m, double4 *packed, hipStream_t s);
+hipError_t gather_sorted(size_t n, const uint32_t *perm, const double4 *packed,
+                         const double *eps, double eps_all, double4 *jp, double *seps,
+                         uint32_t *inv, hipStream_t s);
 
 // tree
 hipError_t tree_build(size_t n, int nsys, const int64_t *sys_off, const uint64_t *skey,

@@ -104,8 +104,8 @@ __device__ __forceinline__ void pc(const typename V4<T>::t &A, const typename V4
     const T Ri = rsqrt_t(R2);
     const T Ri2 = Ri * Ri;
     const T MRi = A.w * Ri;
-    const T MRi3 = MRi * Ri2;
     if (!QUAD) {
+        const T MRi3 = MRi * Ri2;
         ax = fma(-MRi3, rx, ax);
         ay = fma(-MRi3, ry, ay);
         az = fma(-MRi3, rz, az);
@@ -117,8 +117,8 @@ __device__ __forceinline__ void pc(const typename V4<T>::t &A, const typename V4
         const T qz = fma(C.x, rx, fma(C.y, ry, B.z * rz));
         const T rqr = fma(rx, qx, fma(ry, qy, rz * qz));
         const T Ri5 = Ri * Ri2 * Ri2;
-        const T t = rqr * Ri5;
-        const T u = fma((T)2.5 * t, Ri2, MRi3);
+        const T t = rqr * Ri5;                       // r.Q.r / R^5
+        const T u = Ri2 * fma((T)2.5, t, MRi);       // M/R^3 + (5/2) r.Q.r / R^7
         ax = fma(-u, rx, fma(Ri5, qx, ax));
         ay = fma(-u, ry, fma(Ri5, qy, ay));
         az = fma(-u, rz, fma(Ri5, qz, az));
@@ -187,8 +187,18 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
                 T tx[IPL], ty[IPL], tz[IPL], tp[IPL];
 #pragma unroll
                 for (int k = 0; k < IPL; k++) tx[k] = ty[k] = tz[k] = tp[k] = 0;
+                // entries slice, slice + nslice, ...: a block-uniform trip count (scalar loop
+                // counter), then at most one tail entry
+                const uint32_t kmain = nt / nslice;
+                uint32_t j = slice;
 #pragma unroll 4
-                for (uint32_t j = slice; j < nt; j += nslice) {
+                for (uint32_t q = 0; q < kmain; q++, j += nslice) {
+                    const V J = sm.e[j];
+#pragma unroll
+                    for (int k = 0; k < IPL; k++)
+                        pp<T>(J, xi[k], yi[k], zi[k], e2[k], tx[k], ty[k], tz[k], tp[k]);
+                }
+                if (j < nt) {
                     const V J = sm.e[j];
 #pragma unroll
                     for (int k = 0; k < IPL; k++)
@@ -234,8 +244,18 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
                 T tx[IPL], ty[IPL], tz[IPL], tp[IPL];
 #pragma unroll
                 for (int k = 0; k < IPL; k++) tx[k] = ty[k] = tz[k] = tp[k] = 0;
+                const uint32_t kmain = nt / nslice;
+                uint32_t j = slice;
 #pragma unroll 2
-                for (uint32_t j = slice; j < nt; j += nslice) {
+                for (uint32_t q = 0; q < kmain; q++, j += nslice) {
+                    const V A = sm.s[3 * j];
+                    V B, C;
+                    if (QUAD) { B = sm.s[3 * j + 1]; C = sm.s[3 * j + 2]; } else { B = A; C = A; }
+#pragma unroll
+                    for (int k = 0; k < IPL; k++)
+                        pc<T, QUAD>(A, B, C, xi[k], yi[k], zi[k], e2[k], tx[k], ty[k], tz[k], tp[k]);
+                }
+                if (j < nt) {
                     const V A = sm.s[3 * j];
                     V B, C;
                     if (QUAD) { B = sm.s[3 * j + 1]; C = sm.s[3 * j + 2]; } else { B = A; C = A; }

@@ -29,13 +29,19 @@ inline unsigned grid_for(size_t n, unsigned cap = 16384) {
     return (unsigned)b;
 }
 
-__global__ void k_gather_sorted(size_t n, const uint32_t *perm, const double *x,
-                                const double *y, const double *z, const double *m,
+// (x, y, z, m) of every particle as one 32-byte record in the caller's order (coalesced), so
+// the sorted gather below reads one sector per particle instead of four.
+__global__ void k_pack(size_t n, const double *x, const double *y, const double *z,
+                       const double *m, double4 *packed) {
+    for (size_t i = gtid(); i < n; i += gstride()) packed[i] = make_double4(x[i], y[i], z[i], m[i]);
+}
+
+__global__ void k_gather_sorted(size_t n, const uint32_t *perm, const double4 *packed,
                                 const double *eps, double eps_all, double4 *jp, double *seps,
                                 uint32_t *inv) {
     for (size_t r = gtid(); r < n; r += gstride()) {
         const uint32_t i = perm[r];
-        jp[r] = make_double4(x[i], y[i], z[i], m[i]);
+        jp[r] = packed[i];
         seps[r] = eps ? eps[i] : eps_all;
         inv[i] = (uint32_t)r;
     }
@@ -298,12 +304,19 @@ k_group_geom(const uint32_t *ngroups, int nsys, const int64_t *off, Cells c,
 
 }  // namespace
 
-hipError_t gather_sorted(size_t n, const uint32_t *perm, const double *x, const double *y,
-                         const double *z, const double *m, const double *eps, double eps_all,
-                         double4 *jp, double *seps, uint32_t *inv, hipStream_t s) {
+hipError_t pack_particles(size_t n, const double *x, const double *y, const double *z,
+                          const double *m, double4 *packed, hipStream_t s) {
     if (!n) return hipSuccess;
-    hipLaunchKernelGGL(k_gather_sorted, dim3(grid_for(n)), dim3(kThreads), 0, s, n, perm, x, y, z,
-                       m, eps, eps_all, jp, seps, inv);
+    hipLaunchKernelGGL(k_pack, dim3(grid_for(n)), dim3(kThreads), 0, s, n, x, y, z, m, packed);
+    return hipGetLastError();
+}
+
+hipError_t gather_sorted(size_t n, const uint32_t *perm, const double4 *packed,
+                         const double *eps, double eps_all, double4 *jp, double *seps,
+                         uint32_t *inv, hipStream_t s) {
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_sorted, dim3(grid_for(n)), dim3(kThreads), 0, s, n, perm, packed,
+                       eps, eps_all, jp, seps, inv);
     return hipGetLastError();
 }
 
