@@ -11,8 +11,8 @@
 namespace fdx {
 
 int ext_force_variant(fdx_ctx *c) {
-    // defaults measured at N = 2^24: FP32 nt512_ipl1_pf, FP64 nt256_ipl2 (no prefetch)
-    const int dflt = (c->flags & FDX_FP32REL) ? 2 : 5;
+    // defaults measured at N = 2^24: FP32 nt512_ipl1_pf_w8, FP64 nt256_ipl2 (no prefetch)
+    const int dflt = (c->flags & FDX_FP32REL) ? 8 : 5;
     int v = c->ext.variant >= 0 ? c->ext.variant : dflt;
     if (force_variant_capacity(v) < c->n_group) v = 3;
     return v;

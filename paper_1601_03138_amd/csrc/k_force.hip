@@ -300,8 +300,9 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
     __syncthreads();
 }
 
-template <class T, bool QUAD, int NT, int IPL, bool PF>
-__global__ void __launch_bounds__(NT)
+// OCC: minimum waves per SIMD the register allocation must allow (1 = no constraint).
+template <class T, bool QUAD, int NT, int IPL, bool PF, int OCC>
+__global__ void __launch_bounds__(NT, OCC)
 k_force_direct(KArgs a) {
     __shared__ Smem<T, NT, IPL> sm;
     // XCD-aware order: consecutive blocks go round-robin over the 8 XCDs, so hand each XCD a
@@ -315,8 +316,8 @@ k_force_direct(KArgs a) {
 
 // Persistent variant: a fixed grid pops queue slots from a device counter (the queue order
 // lists the groups by decreasing cost, so the longest work starts first).
-template <class T, bool QUAD, int NT, int IPL, bool PF>
-__global__ void __launch_bounds__(NT)
+template <class T, bool QUAD, int NT, int IPL, bool PF, int OCC>
+__global__ void __launch_bounds__(NT, OCC)
 k_force_persistent(KArgs a) {
     __shared__ Smem<T, NT, IPL> sm;
     const uint32_t G = *a.ngroups;
@@ -330,7 +331,7 @@ k_force_persistent(KArgs a) {
     }
 }
 
-template <class T, bool QUAD, int NT, int IPL, bool PF>
+template <class T, bool QUAD, int NT, int IPL, bool PF, int OCC = 1>
 hipError_t launch(const KArgs &k, bool persistent, hipStream_t s) {
     if (persistent) {
         int dev = 0, ncu = 256;
@@ -338,16 +339,16 @@ hipError_t launch(const KArgs &k, bool persistent, hipStream_t s) {
         (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
         int per_cu = 0;
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(k_force_persistent<T, QUAD, NT, IPL, PF>), NT, 0);
+            &per_cu, reinterpret_cast<const void *>(k_force_persistent<T, QUAD, NT, IPL, PF, OCC>), NT, 0);
         if (per_cu < 1) per_cu = 1;
         size_t grid = (size_t)ncu * per_cu;
         if (k.G && grid > k.G) grid = k.G;
-        hipLaunchKernelGGL((k_force_persistent<T, QUAD, NT, IPL, PF>), dim3((unsigned)grid), dim3(NT),
+        hipLaunchKernelGGL((k_force_persistent<T, QUAD, NT, IPL, PF, OCC>), dim3((unsigned)grid), dim3(NT),
                            0, s, k);
     } else {
         if (k.G == 0) return hipSuccess;
         const uint32_t chunk = (k.G + 7) / 8;
-        hipLaunchKernelGGL((k_force_direct<T, QUAD, NT, IPL, PF>), dim3(8 * chunk), dim3(NT), 0, s, k);
+        hipLaunchKernelGGL((k_force_direct<T, QUAD, NT, IPL, PF, OCC>), dim3(8 * chunk), dim3(NT), 0, s, k);
     }
     return hipGetLastError();
 }
@@ -357,8 +358,9 @@ constexpr Variant kVariants[] = {
     {256, 1, true, "nt256_ipl1_pf"}, {256, 2, true, "nt256_ipl2_pf"},
     {512, 1, true, "nt512_ipl1_pf"}, {512, 2, true, "nt512_ipl2_pf"},
     {256, 1, false, "nt256_ipl1"},   {256, 2, false, "nt256_ipl2"},
-    {512, 1, false, "nt512_ipl1"},   {512, 2, false, "nt512_ipl2"}};
-constexpr int kNumVariants = 8;
+    {512, 1, false, "nt512_ipl1"},   {512, 2, false, "nt512_ipl2"},
+    {512, 1, true, "nt512_ipl1_pf_w8"}, {512, 1, false, "nt512_ipl1_w8"}};
+constexpr int kNumVariants = 10;
 
 template <class T, bool QUAD>
 hipError_t launch_v(const KArgs &k, bool persistent, int v, hipStream_t s) {
@@ -370,7 +372,10 @@ hipError_t launch_v(const KArgs &k, bool persistent, int v, hipStream_t s) {
         case 4: return launch<T, QUAD, 256, 1, false>(k, persistent, s);
         case 5: return launch<T, QUAD, 256, 2, false>(k, persistent, s);
         case 6: return launch<T, QUAD, 512, 1, false>(k, persistent, s);
-        default: return launch<T, QUAD, 512, 2, false>(k, persistent, s);
+        case 7: return launch<T, QUAD, 512, 2, false>(k, persistent, s);
+        // register allocation held to 64 VGPRs: 8 waves per SIMD (4 workgroups per CU)
+        case 8: return launch<T, QUAD, 512, 1, true, 8>(k, persistent, s);
+        default: return launch<T, QUAD, 512, 1, false, 8>(k, persistent, s);
     }
 }
 

@@ -26,7 +26,8 @@ constexpr int kSlack = 160;     // stack entries kept free for sequential descen
 
 template <bool FILL>
 __global__ void __launch_bounds__(kThreads)
-k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, double theta2,
+k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, uint32_t ccap,
+       double theta2,
        const uint64_t *seg, const uint32_t *cap, uint64_t list_cap, uint32_t *list,
        uint32_t *cnt_e, uint32_t *cnt_s, uint32_t *ovf_list, const uint32_t *sel,
        const uint32_t *nsel, DevStatus *st) {
@@ -54,6 +55,7 @@ k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, 
             const bool act = (uint32_t)lane < p;
             uint32_t cid = 0;
             if (act) cid = stk[sp - p + lane];
+            if (__ballot(act && cid >= ccap)) { err = true; break; }     // never: stack intact
             wave_barrier();
             sp -= p;
             bool accept = false, leaf = false, inner = false;
@@ -84,10 +86,26 @@ k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, 
                 if (j < capg) list[base + capg - 1 - j] = cid;
             }
             ns += (uint32_t)__popcll(bs);
-            // particles of opened leaves, from the front
+            // particles of opened leaves (front of the segment) and children of opened
+            // internal cells (stack): offsets from one prefix sum of both counts packed in a
+            // word (children, at most 8 per lane, in bits 22-31), unless a leaf holds 2^16
+            // particles or more (coincident keys at the deepest level)
             const uint32_t lc = leaf ? lk.y : 0u;
-            uint32_t ltot;
-            const uint32_t lex = wave_excl_scan_small(lc, &ltot);
+            const uint32_t cc = inner ? nch : 0u;
+            uint32_t lex, ltot, cex, ctot;
+            if (__ballot(lc >= (1u << 16)) == 0) {
+                const uint32_t pk = lc | (cc << 22);
+                const uint32_t inc = wave_incl_scan_dpp(pk);
+                const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
+                const uint32_t ex = inc - pk;
+                lex = ex & 0x3FFFFFu; cex = ex >> 22;
+                ltot = tot & 0x3FFFFFu; ctot = tot >> 22;
+            } else {
+                const uint32_t li = wave_incl_scan_dpp(lc), ci = wave_incl_scan_dpp(cc);
+                ltot = (uint32_t)__builtin_amdgcn_readlane((int)li, kWave - 1);
+                ctot = (uint32_t)__builtin_amdgcn_readlane((int)ci, kWave - 1);
+                lex = li - lc; cex = ci - cc;
+            }
             if (FILL && leaf) {
                 const uint32_t e0 = ne + lex;
                 for (uint32_t k = 0; k < lc; k++)
@@ -95,9 +113,6 @@ k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, 
             }
             ne += ltot;
             // children of opened internal cells onto the stack
-            const uint32_t cc = inner ? nch : 0u;
-            uint32_t ctot;
-            const uint32_t cex = wave_excl_scan_small(cc, &ctot);
             if (sp + ctot > (uint32_t)kWalkStack) { err = true; break; }
             if (inner) {
                 const uint32_t s0 = sp + cex;
@@ -180,11 +195,11 @@ hipError_t walk(bool fill, size_t gmax, const Groups g, const Cells c, double th
                 const uint32_t *nsel, DevStatus *st, hipStream_t s) {
     if (fill)
         hipLaunchKernelGGL(k_walk<true>, dim3(grid_waves(gmax)), dim3(kThreads), 0, s,
-                           &st->n_groups, g, c.node, c.link, theta2, seg, cap, list_cap, list,
+                           &st->n_groups, g, c.node, c.link, c.cap, theta2, seg, cap, list_cap, list,
                            cnt_e, cnt_s, ovf_list, sel, nsel, st);
     else
         hipLaunchKernelGGL(k_walk<false>, dim3(grid_waves(gmax)), dim3(kThreads), 0, s,
-                           &st->n_groups, g, c.node, c.link, theta2, seg, cap, list_cap, list,
+                           &st->n_groups, g, c.node, c.link, c.cap, theta2, seg, cap, list_cap, list,
                            cnt_e, cnt_s, ovf_list, sel, nsel, st);
     return hipGetLastError();
 }

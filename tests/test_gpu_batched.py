@@ -44,7 +44,7 @@ def test_every_shape_and_the_persistent_queue(ctx, fdx):
     _say(f"[shapes] n={ps.n}")
     ref = _ref_forces(ps, 8, 200, 0.5, True)
     ctx.set_particles(ps)
-    for shape in range(4):
+    for shape in range(ctx.lib.fdx_autotune_shapes()):
         ctx.set_shape(shape)
         for fp32 in (False, True):
             ctx.calc_force(0.5, 8, 200, 0.0, quad=True, fp32=fp32)
