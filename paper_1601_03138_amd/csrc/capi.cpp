@@ -59,8 +59,8 @@ int ensure_tree_buffers(fdx_ctx *c, uint32_t cell_cap, uint32_t group_cap) {
         c->cell_cap = cell_cap;
     }
     HIPCHK(c, c->c_lvl.ensure(kLevels + 2));
-    HIPCHK(c, c->tmp_n.ensure(n + S + 1));
-    HIPCHK(c, c->tmp_off.ensure(n + S + 2));
+    HIPCHK(c, c->tmp_n.ensure(n + S + 1));                 // >= 3 n bytes
+    HIPCHK(c, c->tmp_off.ensure(std::max(n + S + 2, tree_scratch_u32(n))));
     if (group_cap > c->group_cap || !c->g_cell.p) {
         c->gen++;
         HIPCHK(c, c->g_cell.ensure(group_cap));
@@ -143,8 +143,8 @@ int enqueue_tree_groups(fdx_ctx *c) {
     const size_t n = (size_t)c->n;
     const int S = c->nsys;
     hipStream_t s = c->stream;
-    HIPCHK(c, tree_build(n, S, c->sys_off.p, c->skey, c->n_leaf, cells_view(c), c->tmp_n.p,
-                         c->tmp_off.p, c->partial.p, c->st, s));
+    HIPCHK(c, tree_build(n, S, c->sys_off.p, c->skey, c->n_leaf, cells_view(c),
+                         (uint8_t *)c->tmp_n.p, c->tmp_off.p, c->partial.p, c->st, s));
     mark(c, 3);
     HIPCHK(c, tree_moments(cells_view(c), c->jp.p, s));
     mark(c, 4);

@@ -28,7 +28,7 @@ struct DevStatus {
     uint64_t n_epj, n_spj;
     uint64_t inter_pp, inter_pc;
     uint32_t group_overflow;  // more groups than the group arrays hold
-    uint32_t pad2;
+    uint32_t top_level;       // deepest tree level whose cells fit the cell capacity
 };
 
 // any device-reported condition that makes this evaluation's forces incomplete
@@ -107,8 +107,10 @@ hipError_t gather_sorted(size_t n, const uint32_t *perm, const double4 *packed,
                          uint32_t *inv, hipStream_t s);
 
 // tree
+// scratch words tree_build needs besides 3 n bytes
+size_t tree_scratch_u32(size_t n);
 hipError_t tree_build(size_t n, int nsys, const int64_t *sys_off, const uint64_t *skey,
-                      int n_leaf, Cells c, uint32_t *tmp_n, uint32_t *tmp_off,
+                      int n_leaf, Cells c, uint8_t *bytes, uint32_t *scratch,
                       uint64_t *partial, DevStatus *st, hipStream_t s);
 hipError_t tree_moments(Cells c, const double4 *jp, hipStream_t s);
 hipError_t make_groups(size_t n, int nsys, const int64_t *sys_off, Cells c,

@@ -66,104 +66,208 @@ __global__ void k_tree_init(int nsys, const int64_t *off, Cells c, DevStatus *st
     }
 }
 
-// first index in [b, e) whose octant digit (bits sh..sh+2) is >= o; digits ascend on [b, e)
-__device__ __forceinline__ uint32_t lower_digit(const uint64_t *k, uint32_t b, uint32_t e,
-                                                int sh, uint32_t o) {
-    while (b < e) {
-        uint32_t mid = b + ((e - b) >> 1);
-        if ((uint32_t)((k[mid] >> sh) & 7u) < o) b = mid + 1; else e = mid;
+// ---------------------------------------------------------------------------------------
+// Topology from the sorted keys in O(N) work and a fixed number of launches.
+//
+// Two sorted keys of one system lie in the same level-L cell iff they share their first L
+// octal digits; shared(a, b) = number of leading digits a and b have in common.  With
+// lo(r) = shared(k[r-1], k[r]) + 1 (1 at the start of a system), a cell of level L >= 1 can
+// start at sorted position r only if L >= lo(r).  It exists iff its parent (the level L-1
+// cell holding r) has more than n_leaf particles and L <= 21.  The level-m cell holding r has
+// more than n_leaf particles iff some window of n_leaf + 1 consecutive keys of the system
+// that contains r shares m digits, so with c(a) = shared(k[a], k[a + n_leaf]) (-1 past the
+// end of the system) and D(r) = max c(a) over a in [r - n_leaf, r] (within the system), the
+// cells starting at r are exactly the levels L in [lo(r), hi(r)], hi(r) = min(D(r) + 1, 21).
+// A cell (L, r) is split iff c(r) >= L and L < 21; its first child is then (L + 1, r).
+// Breadth-first numbering (level by level, by position within a level) comes from one
+// exclusive scan over per-wave-tile cell counts laid out level-major.
+// ---------------------------------------------------------------------------------------
+
+constexpr int kTileRounds = 16;                    // rounds of 64 positions per wave tile
+constexpr int kTileW = kTileRounds * kWave;        // 1024 positions per wave tile
+
+__device__ __forceinline__ int shared_levels(uint64_t a, uint64_t b) {
+    const uint64_t x = a ^ b;                       // keys use the low 63 bits
+    return x ? (__clzll((long long)x) - 1) / 3 : kLevels;
+}
+
+// system holding sorted position r: the last s with off[s] <= r (skips empty systems)
+__device__ __forceinline__ int system_of(const int64_t *off, int nsys, size_t r) {
+    int lo = 0, hi = nsys - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((uint64_t)off[mid] <= r) lo = mid; else hi = mid - 1;
     }
-    return b;
+    return lo;
 }
 
-__device__ __forceinline__ void octant_bounds(const uint64_t *skey, uint32_t b, uint32_t e,
-                                              int sh, uint32_t *bd) {
-    bd[0] = b;
-    bd[8] = e;
-    // 7 boundaries by nested binary search: octants 4, then 2/6, then odd
-    bd[4] = lower_digit(skey, b, e, sh, 4);
-    bd[2] = lower_digit(skey, b, bd[4], sh, 2);
-    bd[6] = lower_digit(skey, bd[4], e, sh, 6);
-    bd[1] = lower_digit(skey, b, bd[2], sh, 1);
-    bd[3] = lower_digit(skey, bd[2], bd[4], sh, 3);
-    bd[5] = lower_digit(skey, bd[4], bd[6], sh, 5);
-    bd[7] = lower_digit(skey, bd[6], e, sh, 7);
+// per position: lo(r) and c(r)
+__global__ void k_cells_prefix(size_t n, int nsys, const int64_t *off, const uint64_t *skey,
+                               int n_leaf, uint8_t *lo8, int8_t *c8) {
+    for (size_t r = gtid(); r < n; r += gstride()) {
+        const int sys = system_of(off, nsys, r);
+        const size_t s0 = (size_t)off[sys], s1 = (size_t)off[sys + 1];
+        const uint64_t k = skey[r];
+        lo8[r] = (uint8_t)(r == s0 ? 1 : shared_levels(skey[r - 1], k) + 1);
+        c8[r] = (int8_t)(r + (size_t)n_leaf < s1 ? shared_levels(k, skey[r + n_leaf]) : -1);
+    }
 }
 
-// number of children of every cell of level l
-__global__ void k_tree_split(int l, int n_leaf, const uint64_t *skey, Cells c, uint32_t *tmp_n) {
-    const uint32_t c0 = c.lvl[l], c1 = c.lvl[l + 1];
-    const int sh = 3 * (kLevels - 1 - l);
-    for (size_t k = gtid(); k < c1 - c0; k += gstride()) {
-        const uint32_t cid = c0 + (uint32_t)k;
-        uint32_t nch = 0;
-        const uint32_t cnt = c.count[cid];
-        if (l < kLevels && cnt > (uint32_t)n_leaf) {
-            uint32_t bd[9];
-            octant_bounds(skey, c.begin[cid], c.begin[cid] + cnt, sh, bd);
-#pragma unroll
-            for (int o = 0; o < 8; o++) nch += bd[o + 1] > bd[o] ? 1u : 0u;
+// per position hi(r); per wave tile and level, the number of cells starting in the tile:
+// wcount[(L - 1) * ntiles + tile]
+__global__ void __launch_bounds__(kThreads)
+k_cells_count(size_t n, int nsys, const int64_t *off, int n_leaf, const uint8_t *lo8,
+              const int8_t *c8, uint8_t *hi8, uint32_t ntiles, uint32_t *wcount) {
+    const size_t tile = gtid() / kWave;
+    if (tile >= ntiles) return;
+    const int lane = lane_id();
+    uint32_t cnt = 0;                              // lane L-1 counts level L
+    for (int q = 0; q < kTileRounds; q++) {
+        const size_t r = tile * kTileW + (size_t)q * kWave + lane;
+        int lo = kLevels + 1, hi = 0;
+        if (r < n) {
+            const int sys = system_of(off, nsys, r);
+            const size_t s0 = (size_t)off[sys];
+            const size_t a0 = r >= s0 + (size_t)n_leaf ? r - (size_t)n_leaf : s0;
+            int d = -1;
+            for (size_t a = a0; a <= r; a++) d = max(d, (int)c8[a]);
+            hi = min(d + 1, kLevels);
+            lo = lo8[r];
+            hi8[r] = (uint8_t)hi;
         }
-        tmp_n[k] = nch;
+        // levels present in this round: a ballot per level, counts kept by lane L-1
+        const int lmin = (int)wave_min_u32((uint32_t)lo);
+        const int lmax = (int)wave_max_u32((uint32_t)hi);
+        for (int L = lmin; L <= lmax; L++) {
+            const uint32_t c = (uint32_t)__popcll(__ballot(lo <= L && L <= hi));
+            if (lane == L - 1) cnt += c;
+        }
     }
+    if (lane < kLevels) wcount[(size_t)lane * ntiles + tile] = cnt;
 }
 
-// write the children of level l (first child index from the scan of tmp_n); *total = number
-// of cells of level l+1
-__global__ void k_tree_emit(int l, const uint64_t *skey, Cells c, const uint32_t *tmp_n,
-                            const uint32_t *tmp_off, const uint32_t *total, DevStatus *st) {
-    const uint32_t c0 = c.lvl[l], c1 = c.lvl[l + 1];
-    const uint32_t next = c1 + *total;
-    const bool ovf = next > c.cap || st->cell_overflow;
-    if (gtid() == 0) {
-        if (ovf) st->cell_overflow = 1;
-        c.lvl[l + 2] = ovf ? c1 : next;
-        for (int k = l + 3; k <= kLevels + 1; k++) c.lvl[k] = ovf ? c1 : next;
+// level starts from the scanned counts; if the cells of every level do not fit the capacity,
+// keep the levels that do (the deepest kept level's cells become leaves) and flag it
+__global__ void k_cells_levels(int nsys, uint32_t ntiles, const uint32_t *woff,
+                               const uint32_t *total, Cells c, DevStatus *st) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    uint32_t lv[kLevels + 2];
+    lv[0] = 0;
+    lv[1] = (uint32_t)nsys;
+    for (int L = 1; L <= kLevels; L++) {
+        const uint32_t nxt = L < kLevels ? woff[(size_t)L * ntiles] : *total;
+        lv[L + 1] = (uint32_t)nsys + nxt;
     }
-    const int sh = 3 * (kLevels - 1 - l);
-    for (size_t k = gtid(); k < c1 - c0; k += gstride()) {
-        const uint32_t cid = c0 + (uint32_t)k;
-        const uint32_t nch = ovf ? 0u : tmp_n[k];
-        c.nchild[cid] = nch;
-        if (nch == 0) { c.first[cid] = kNone; continue; }
-        const uint32_t first = c1 + tmp_off[k];
-        c.first[cid] = first;
-        uint32_t bd[9];
-        const uint32_t b = c.begin[cid];
-        octant_bounds(skey, b, b + c.count[cid], sh, bd);
-        const uint64_t pre = c.prefix[cid] << 3;
-        uint32_t j = first;
+    int top = kLevels;
+    while (top > 0 && lv[top + 1] > c.cap) top--;
+    const bool ovf = top < kLevels && lv[kLevels + 1] > c.cap;
+    for (int L = 0; L <= kLevels + 1; L++) c.lvl[L] = L <= top + 1 ? lv[L] : lv[top + 1];
+    st->cell_overflow = ovf ? 1u : 0u;
+    st->top_level = (uint32_t)top;
+}
+
+// write the cells of levels 1..top starting in each wave tile: level, prefix, begin, and
+// first-child links (a split cell's first child starts at the same position one level down)
+__global__ void __launch_bounds__(kThreads)
+k_cells_emit(size_t n, int nsys, const int64_t *off, const uint64_t *skey, const uint8_t *lo8,
+             const uint8_t *hi8, uint32_t ntiles, const uint32_t *woff, Cells c,
+             const DevStatus *st) {
+    const size_t tile = gtid() / kWave;
+    if (tile >= ntiles) return;
+    const int lane = lane_id();
+    const uint64_t lt = lanemask_lt();
+    const int top = (int)st->top_level;
+    uint8_t lo[kTileRounds], hi[kTileRounds];
+    uint32_t prev[kTileRounds];
+    int lmin = kLevels + 1, lmax = 0;
 #pragma unroll
-        for (int o = 0; o < 8; o++) {
-            if (bd[o + 1] > bd[o]) {
-                c.level[j] = (uint32_t)(l + 1);
-                c.prefix[j] = pre | (uint64_t)o;
-                c.begin[j] = bd[o];
-                c.count[j] = bd[o + 1] - bd[o];
-                c.parent[j] = cid;
-                c.first[j] = kNone;
-                c.nchild[j] = 0;
-                j++;
+    for (int q = 0; q < kTileRounds; q++) {
+        const size_t r = tile * kTileW + (size_t)q * kWave + lane;
+        lo[q] = r < n ? lo8[r] : (uint8_t)(kLevels + 1);
+        hi[q] = r < n ? hi8[r] : (uint8_t)0;
+        prev[q] = kNone;
+        lmin = min(lmin, (int)lo[q]);
+        lmax = max(lmax, (int)hi[q]);
+    }
+    lmin = (int)wave_min_u32((uint32_t)lmin);
+    lmax = min((int)wave_max_u32((uint32_t)lmax), top);
+    for (int L = lmin; L <= lmax; L++) {
+        uint32_t run = (uint32_t)nsys + woff[(size_t)(L - 1) * ntiles + tile];
+        const int sh = 3 * (kLevels - L);
+#pragma unroll
+        for (int q = 0; q < kTileRounds; q++) {
+            const bool has = lo[q] <= L && L <= hi[q];
+            const uint64_t b = __ballot(has);
+            if (has) {
+                const size_t r = tile * kTileW + (size_t)q * kWave + lane;
+                const uint32_t idx = run + (uint32_t)__popcll(b & lt);
+                c.level[idx] = (uint32_t)L;
+                c.prefix[idx] = skey[r] >> sh;
+                c.begin[idx] = (uint32_t)r;
+                c.first[idx] = kNone;
+                if (L > lo[q]) {
+                    c.first[prev[q]] = idx;               // parent (L-1, r) was split
+                } else if (L == 1) {
+                    const int sys = system_of(off, nsys, r);
+                    if ((size_t)off[sys] == r) c.first[sys] = idx;   // root split
+                }
+                prev[q] = idx;
             }
+            run += (uint32_t)__popcll(b);
         }
     }
 }
 
-// walk views: half-grid centre + level/nchild, and the leaf/internal link
-__global__ void k_tree_nodes(Cells c) {
+// per cell: particle count (end of the run of keys sharing the cell's L digits, found by a
+// galloping search bounded by the system's end), children (the at most 8 cells of level
+// L + 1 from the first child on that start before the end) and their parent link, and the
+// walk views (half-grid centre + level/nchild, leaf or internal link)
+__global__ void k_cells_finish(int nsys, const int64_t *off, const uint64_t *skey, Cells c) {
     const uint32_t nc = c.lvl[kLevels + 1];
     for (size_t k = gtid(); k < nc; k += gstride()) {
-        const uint32_t l = c.level[k];
-        const uint64_t corner = c.prefix[k] << (3 * (kLevels - l));
-        const uint32_t half = 1u << (kLevels - l);
+        const uint32_t cid = (uint32_t)k;
+        const uint32_t L = c.level[cid];
+        const uint32_t b = c.begin[cid];
+        uint32_t cnt;
+        if (cid < (uint32_t)nsys) {
+            cnt = c.count[cid];
+        } else {
+            const int sys = system_of(off, nsys, b);
+            const uint32_t s1 = (uint32_t)off[sys + 1];
+            const uint64_t kb = skey[b];
+            // last position known inside (in) and first known outside or at the end (out)
+            uint32_t in = b, out = s1;
+            for (uint64_t step = 1; (uint64_t)in + step < s1; step <<= 1) {
+                const uint32_t pr = in + (uint32_t)step;
+                if (shared_levels(skey[pr], kb) < (int)L) { out = pr; break; }
+                in = pr;
+            }
+            while (out - in > 1) {
+                const uint32_t mid = in + (out - in) / 2;
+                if (shared_levels(skey[mid], kb) >= (int)L) in = mid; else out = mid;
+            }
+            cnt = out - b;
+            c.count[cid] = cnt;
+        }
+        const uint32_t first = c.first[cid];
+        uint32_t nch = 0;
+        if (first != kNone && L + 2 <= (uint32_t)kLevels + 1) {
+            const uint32_t e = b + cnt, lim = min(first + 8u, c.lvl[L + 2]);
+            for (uint32_t j = first; j < lim && c.begin[j] < e; j++) {
+                c.parent[j] = cid;
+                nch++;
+            }
+        }
+        c.nchild[cid] = nch;
+        const uint64_t corner = c.prefix[cid] << (3 * (kLevels - L));
+        const uint32_t half = 1u << (kLevels - L);
         uint4 nd;
         nd.x = 2u * compact3(corner >> 2) + half;
         nd.y = 2u * compact3(corner >> 1) + half;
         nd.z = 2u * compact3(corner) + half;
-        nd.w = l | (c.nchild[k] << 8);
-        c.node[k] = nd;
-        c.link[k] = c.nchild[k] ? make_uint2(c.first[k], c.count[k])
-                                : make_uint2(c.begin[k], c.count[k]);
+        nd.w = L | (nch << 8);
+        c.node[cid] = nd;
+        c.link[cid] = nch ? make_uint2(first, cnt) : make_uint2(b, cnt);
     }
 }
 
@@ -320,23 +424,36 @@ hipError_t gather_sorted(size_t n, const uint32_t *perm, const double4 *packed,
     return hipGetLastError();
 }
 
+size_t tree_scratch_u32(size_t n) {
+    const size_t ntiles = (n + kTileW - 1) / kTileW;
+    return 2 * (size_t)kLevels * (ntiles ? ntiles : 1) + 2;
+}
+
 hipError_t tree_build(size_t n, int nsys, const int64_t *sys_off, const uint64_t *skey,
-                      int n_leaf, Cells c, uint32_t *tmp_n, uint32_t *tmp_off,
+                      int n_leaf, Cells c, uint8_t *bytes, uint32_t *scratch,
                       uint64_t *partial, DevStatus *st, hipStream_t s) {
     hipLaunchKernelGGL(k_tree_init, dim3((nsys + 255) / 256), dim3(256), 0, s, nsys, sys_off, c, st);
-    // Level sizes are bounded by n (cells of one level are disjoint and non-empty, roots
-    // aside), so the grids are sized from n and the kernels stride over the true size.
-    const unsigned grid = grid_for(n + (size_t)nsys, 4096);
-    uint32_t *total = tmp_off + (n + (size_t)nsys);  // one word past the offsets
-    for (int l = 0; l < kLevels; l++) {
-        hipLaunchKernelGGL(k_tree_split, dim3(grid), dim3(kThreads), 0, s, l, n_leaf, skey, c, tmp_n);
-        hipError_t e = scan_u32_to_u32(tmp_n, tmp_off, 0, c.lvl + l, c.lvl + l + 1, partial,
-                                       total, s);
+    const size_t ntiles = (n + kTileW - 1) / kTileW;
+    uint8_t *lo8 = bytes, *hi8 = bytes + n;
+    int8_t *c8 = (int8_t *)(bytes + 2 * n);
+    uint32_t *wcount = scratch, *woff = scratch + (size_t)kLevels * ntiles;
+    uint32_t *total = woff + (size_t)kLevels * ntiles;
+    if (n) {
+        hipLaunchKernelGGL(k_cells_prefix, dim3(grid_for(n)), dim3(kThreads), 0, s, n, nsys,
+                           sys_off, skey, n_leaf, lo8, c8);
+        const unsigned tb = (unsigned)((ntiles * kWave + kThreads - 1) / kThreads);
+        hipLaunchKernelGGL(k_cells_count, dim3(tb), dim3(kThreads), 0, s, n, nsys, sys_off,
+                           n_leaf, lo8, c8, hi8, (uint32_t)ntiles, wcount);
+        hipError_t e = scan_u32_to_u32(wcount, woff, (size_t)kLevels * ntiles, nullptr, nullptr,
+                                       partial, total, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_tree_emit, dim3(grid), dim3(kThreads), 0, s, l, skey, c, tmp_n,
-                           tmp_off, total, st);
+        hipLaunchKernelGGL(k_cells_levels, dim3(1), dim3(64), 0, s, nsys, (uint32_t)ntiles, woff,
+                           total, c, st);
+        hipLaunchKernelGGL(k_cells_emit, dim3(tb), dim3(kThreads), 0, s, n, nsys, sys_off, skey,
+                           lo8, hi8, (uint32_t)ntiles, woff, c, st);
     }
-    hipLaunchKernelGGL(k_tree_nodes, dim3(grid_for(c.cap, 8192)), dim3(kThreads), 0, s, c);
+    hipLaunchKernelGGL(k_cells_finish, dim3(grid_for(c.cap, 8192)), dim3(kThreads), 0, s, nsys,
+                       sys_off, skey, c);
     return hipGetLastError();
 }
 
