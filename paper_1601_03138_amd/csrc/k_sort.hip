@@ -1,7 +1,8 @@
 // Stable LSD radix sort of (63-bit key, u32 index) pairs, then stably by system id, so the
 // result is ordered by (system, key, original index).  8-bit digits; per pass: per-tile
 // digit histograms, a device-wide exclusive scan over (digit, tile), and a scatter in which
-// each wave ranks its elements with ballot-based multisplit so the order is stable.
+// each wave ranks its elements with ballot-based multisplit so the order is stable, and the
+// tile is reordered in LDS so each digit's run is written contiguously.
 #include "dev_util.h"
 #include "fdx_internal.h"
 
@@ -11,9 +12,9 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;     // 4
-constexpr int kItems = 16;                   // rounds of 64 per wave
-constexpr int kWaveTile = kItems * kWave;    // 1024 elements per wave
-constexpr int kTile = kWaves * kWaveTile;    // 4096 elements per block
+constexpr int kItems = 8;                    // rounds of 64 per wave
+constexpr int kWaveTile = kItems * kWave;    // 512 elements per wave
+constexpr int kTile = kWaves * kWaveTile;    // 2048 elements per block
 constexpr int kRadix = 256;
 
 template <bool SYS>
@@ -44,13 +45,21 @@ k_rs_hist(const uint64_t *key, const uint32_t *val, const uint32_t *sysid, size_
     counts[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
+// Scatter of one tile: every element's rank among the tile's elements of its digit (ballot
+// multisplit per wave, waves in order), the elements laid out in LDS in digit order, then
+// each digit's run written to its global range with consecutive threads on consecutive
+// addresses.
 template <bool SYS>
 __global__ void __launch_bounds__(kThreads)
 k_rs_scatter(const uint64_t *key_in, const uint32_t *val_in, const uint32_t *sysid, size_t n,
              int shift, uint32_t nblocks, const uint32_t *offs, uint64_t *key_out,
              uint32_t *val_out) {
-    __shared__ uint32_t wcnt[kWaves][kRadix];
-    __shared__ uint32_t woff[kWaves][kRadix];
+    __shared__ uint64_t sk[kTile];
+    __shared__ uint32_t sv[kTile];
+    __shared__ uint32_t wcnt[kWaves][kRadix];     // per wave and digit: count, then offset
+    __shared__ uint32_t lstart[kRadix];           // first LDS slot of each digit
+    __shared__ uint32_t gstart[kRadix];           // global position of that slot
+    __shared__ uint64_t scan_tmp[kWaves];
     for (int k = threadIdx.x; k < kWaves * kRadix; k += kThreads) (&wcnt[0][0])[k] = 0;
     __syncthreads();
     const int w = threadIdx.x / kWave, lane = lane_id();
@@ -83,25 +92,42 @@ k_rs_scatter(const uint64_t *key_in, const uint32_t *val_in, const uint32_t *sys
         wave_barrier();
         kk[r] = k;
         vv[r] = v;
-        rk[r] = (d << 16) | (prev + before);
+        rk[r] = valid ? (d << 16) | (prev + before) : 0xFFFFFFFFu;
     }
     __syncthreads();
     {
         const int d = threadIdx.x;                 // kThreads == kRadix
-        uint32_t run = offs[(size_t)d * nblocks + blockIdx.x];
+        uint32_t tot = 0;
 #pragma unroll
-        for (int ww = 0; ww < kWaves; ww++) { woff[ww][d] = run; run += wcnt[ww][d]; }
+        for (int ww = 0; ww < kWaves; ww++) {
+            const uint32_t c = wcnt[ww][d];
+            wcnt[ww][d] = tot;
+            tot += c;
+        }
+        uint64_t btot;
+        lstart[d] = (uint32_t)block_excl_scan<kThreads>(tot, scan_tmp, &btot);
+        gstart[d] = offs[(size_t)d * nblocks + blockIdx.x];
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kItems; r++) {
-        const size_t i = base + (size_t)r * kWave + lane;
-        if (i < n) {
+        if (rk[r] != 0xFFFFFFFFu) {
             const uint32_t d = rk[r] >> 16;
-            const uint32_t pos = woff[w][d] + (rk[r] & 0xFFFFu);
-            key_out[pos] = kk[r];
-            val_out[pos] = vv[r];
+            const uint32_t slot = lstart[d] + wcnt[w][d] + (rk[r] & 0xFFFFu);
+            sk[slot] = kk[r];
+            sv[slot] = vv[r];
         }
+    }
+    __syncthreads();
+    const size_t b0 = (size_t)blockIdx.x * kTile;
+    const uint32_t cnt = (uint32_t)min((size_t)kTile, n - b0);
+    for (uint32_t j = threadIdx.x; j < cnt; j += kThreads) {
+        const uint64_t k = sk[j];
+        const uint32_t v = sv[j];
+        const uint32_t d = digit_of<SYS>(k, v, sysid, shift);
+        const uint32_t pos = gstart[d] + (j - lstart[d]);
+        key_out[pos] = k;
+        val_out[pos] = v;
     }
 }
 

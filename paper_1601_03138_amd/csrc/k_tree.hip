@@ -271,58 +271,61 @@ __global__ void k_cells_finish(int nsys, const int64_t *off, const uint64_t *ske
     }
 }
 
+// moments of one cell: a leaf from its particles, an internal cell from its children (in
+// child order) by the parallel-axis shift
+__device__ void cell_moments(const Cells &c, const double4 *jp, uint32_t cid) {
+    double M = 0, X = 0, Y = 0, Z = 0;
+    double q[6] = {0, 0, 0, 0, 0, 0};
+    const uint32_t nch = c.nchild[cid];
+    if (nch == 0) {
+        const uint32_t b = c.begin[cid], e = b + c.count[cid];
+        double sx = 0, sy = 0, sz = 0;
+        for (uint32_t i = b; i < e; i++) {
+            double4 p = jp[i];
+            M += p.w; sx += p.w * p.x; sy += p.w * p.y; sz += p.w * p.z;
+        }
+        if (M > 0) { X = sx / M; Y = sy / M; Z = sz / M; }
+        for (uint32_t i = b; i < e; i++) {
+            double4 p = jp[i];
+            double dx = p.x - X, dy = p.y - Y, dz = p.z - Z;
+            double d2 = dx * dx + dy * dy + dz * dz;
+            q[0] += p.w * (3.0 * dx * dx - d2);
+            q[1] += p.w * (3.0 * dy * dy - d2);
+            q[2] += p.w * (3.0 * dz * dz - d2);
+            q[3] += p.w * (3.0 * dx * dy);
+            q[4] += p.w * (3.0 * dx * dz);
+            q[5] += p.w * (3.0 * dy * dz);
+        }
+    } else {
+        const uint32_t f = c.first[cid];
+        double sx = 0, sy = 0, sz = 0;
+        for (uint32_t j = f; j < f + nch; j++) {
+            const double *o = c.mom + 10 * (size_t)j;
+            M += o[0]; sx += o[0] * o[1]; sy += o[0] * o[2]; sz += o[0] * o[3];
+        }
+        if (M > 0) { X = sx / M; Y = sy / M; Z = sz / M; }
+        for (uint32_t j = f; j < f + nch; j++) {
+            const double *o = c.mom + 10 * (size_t)j;
+            double dx = o[1] - X, dy = o[2] - Y, dz = o[3] - Z;
+            double d2 = dx * dx + dy * dy + dz * dz;
+            q[0] += o[4] + o[0] * (3.0 * dx * dx - d2);
+            q[1] += o[5] + o[0] * (3.0 * dy * dy - d2);
+            q[2] += o[6] + o[0] * (3.0 * dz * dz - d2);
+            q[3] += o[7] + o[0] * (3.0 * dx * dy);
+            q[4] += o[8] + o[0] * (3.0 * dx * dz);
+            q[5] += o[9] + o[0] * (3.0 * dy * dz);
+        }
+    }
+    double *o = c.mom + 10 * (size_t)cid;
+    o[0] = M; o[1] = X; o[2] = Y; o[3] = Z;
+#pragma unroll
+    for (int a = 0; a < 6; a++) o[4 + a] = q[a];
+}
+
 // moments of the cells of one level (children already done)
 __global__ void k_moments(int l, Cells c, const double4 *jp) {
     const uint32_t c0 = c.lvl[l], c1 = c.lvl[l + 1];
-    for (size_t k = gtid(); k < c1 - c0; k += gstride()) {
-        const uint32_t cid = c0 + (uint32_t)k;
-        double M = 0, X = 0, Y = 0, Z = 0;
-        double q[6] = {0, 0, 0, 0, 0, 0};
-        const uint32_t nch = c.nchild[cid];
-        if (nch == 0) {
-            const uint32_t b = c.begin[cid], e = b + c.count[cid];
-            double sx = 0, sy = 0, sz = 0;
-            for (uint32_t i = b; i < e; i++) {
-                double4 p = jp[i];
-                M += p.w; sx += p.w * p.x; sy += p.w * p.y; sz += p.w * p.z;
-            }
-            if (M > 0) { X = sx / M; Y = sy / M; Z = sz / M; }
-            for (uint32_t i = b; i < e; i++) {
-                double4 p = jp[i];
-                double dx = p.x - X, dy = p.y - Y, dz = p.z - Z;
-                double d2 = dx * dx + dy * dy + dz * dz;
-                q[0] += p.w * (3.0 * dx * dx - d2);
-                q[1] += p.w * (3.0 * dy * dy - d2);
-                q[2] += p.w * (3.0 * dz * dz - d2);
-                q[3] += p.w * (3.0 * dx * dy);
-                q[4] += p.w * (3.0 * dx * dz);
-                q[5] += p.w * (3.0 * dy * dz);
-            }
-        } else {
-            const uint32_t f = c.first[cid];
-            double sx = 0, sy = 0, sz = 0;
-            for (uint32_t j = f; j < f + nch; j++) {
-                const double *o = c.mom + 10 * (size_t)j;
-                M += o[0]; sx += o[0] * o[1]; sy += o[0] * o[2]; sz += o[0] * o[3];
-            }
-            if (M > 0) { X = sx / M; Y = sy / M; Z = sz / M; }
-            for (uint32_t j = f; j < f + nch; j++) {
-                const double *o = c.mom + 10 * (size_t)j;
-                double dx = o[1] - X, dy = o[2] - Y, dz = o[3] - Z;
-                double d2 = dx * dx + dy * dy + dz * dz;
-                q[0] += o[4] + o[0] * (3.0 * dx * dx - d2);
-                q[1] += o[5] + o[0] * (3.0 * dy * dy - d2);
-                q[2] += o[6] + o[0] * (3.0 * dz * dz - d2);
-                q[3] += o[7] + o[0] * (3.0 * dx * dy);
-                q[4] += o[8] + o[0] * (3.0 * dx * dz);
-                q[5] += o[9] + o[0] * (3.0 * dy * dz);
-            }
-        }
-        double *o = c.mom + 10 * (size_t)cid;
-        o[0] = M; o[1] = X; o[2] = Y; o[3] = Z;
-#pragma unroll
-        for (int a = 0; a < 6; a++) o[4 + a] = q[a];
-    }
+    for (size_t k = gtid(); k < c1 - c0; k += gstride()) cell_moments(c, jp, c0 + (uint32_t)k);
 }
 
 // Mark the first particle of every group: flag[r] = 1, gcell_at[r] = its cell.
