@@ -58,27 +58,23 @@ k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, 
             if (__ballot(act && cid >= ccap)) { err = true; break; }     // never: stack intact
             wave_barrier();
             sp -= p;
-            bool accept = false, leaf = false, inner = false;
-            uint2 lk = make_uint2(0, 0);
-            uint32_t nch = 0;
-            if (act) {
-                const uint4 nd = node[cid];
-                lk = link[cid];
-                const int lv = (int)(nd.w & 0xFFu);
-                nch = nd.w >> 8;
-                const int cx = (int)nd.x, cy = (int)nd.y, cz = (int)nd.z;
-                const int dx = max(0, max(bminx - cx, cx - bmaxx));
-                const int dy = max(0, max(bminy - cy, cy - bmaxy));
-                const int dz = max(0, max(bminz - cz, cz - bmaxz));
-                const double D2 = (double)dx * (double)dx + (double)dy * (double)dy +
-                                  (double)dz * (double)dz;             // exact integers
-                const double S2 = __longlong_as_double((long long)(1023 + 2 * (22 - lv)) << 52);
-                accept = S2 < __dmul_rn(theta2, D2);
-                if (!accept) {
-                    if (nch == 0) leaf = lk.y > 0;
-                    else inner = true;
-                }
-            }
+            // every lane loads (idle lanes read cell 0) and the outcome is selected without
+            // branches, so both loads are issued together and nothing is loaded later
+            const uint4 nd = node[cid];
+            const uint2 lk = link[cid];
+            const int lv = (int)(nd.w & 0xFFu);
+            const uint32_t nch = nd.w >> 8;
+            const int cx = (int)nd.x, cy = (int)nd.y, cz = (int)nd.z;
+            const int dx = max(0, max(bminx - cx, cx - bmaxx));
+            const int dy = max(0, max(bminy - cy, cy - bmaxy));
+            const int dz = max(0, max(bminz - cz, cz - bmaxz));
+            const double D2 = (double)dx * (double)dx + (double)dy * (double)dy +
+                              (double)dz * (double)dz;                 // exact integers
+            const double S2 = __longlong_as_double((long long)(1023 + 2 * (22 - lv)) << 52);
+            const bool accept = act && S2 < __dmul_rn(theta2, D2);
+            const bool open = act && !accept;
+            const bool leaf = open && nch == 0 && lk.y > 0;
+            const bool inner = open && nch != 0;
             // superparticles, from the back of the segment
             const uint64_t bs = __ballot(accept);
             if (FILL && accept) {
