@@ -40,6 +40,12 @@ WORKLOADS = {
 }
 
 
+# list-length predictor weights shipped with the package: (workload, n_group, theta) they were
+# trained for (on inputs of other seeds)
+PREDICTOR_WEIGHTS = {("clustered16m", 256, 0.5):
+                     os.path.join(ROOT, "paper_1601_03138_amd", "predictor_clustered16m_ng256.bin")}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -124,8 +130,13 @@ def main():
                     help="replay each leapfrog step as a captured HIP graph (persistent force)")
     ap.add_argument("--persistent", action="store_true",
                     help="persistent force kernel over the cost-ordered group queue")
+    ap.add_argument("--walk", default="auto", choices=["auto", "exact", "predicted"],
+                    help="exact: count pass + fill pass; predicted: the learned list-length "
+                         "predictor sizes the lists for a single fill pass (groups that do not "
+                         "fit are re-walked exactly; results are identical); auto: predicted "
+                         "when weights for the workload exist")
     ap.add_argument("--predictor", default="",
-                    help="predictor weights: also time the predicted single-pass walk")
+                    help="predictor weights (default: the shipped ones for the workload)")
     ap.add_argument("--autotune", action="store_true",
                     help="run the autotuner over n_group x kernel shape first and use its choice")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -165,8 +176,21 @@ def main():
                  "ms": [[None if np.isnan(v) else round(float(v), 3) for v in row] for row in times]}
         log(f"[bench] autotune: n_group={bg} shape={bv} times={tuned['ms']}")
 
-    # initial force, then warm-up steps
-    ctx.calc_force_flags(theta, 8, n_group, 0.0, flags)
+    weights = args.predictor or PREDICTOR_WEIGHTS.get((args.workload, n_group, theta), "")
+    if weights and not os.path.exists(weights):
+        weights = ""
+    walk = args.walk
+    if walk == "auto":
+        walk = "predicted" if weights and not args.graph else "exact"
+    if walk == "predicted" and (not weights or args.graph):
+        print("bench.py: --walk predicted needs predictor weights and no --graph", file=sys.stderr)
+        sys.exit(2)
+    if weights:
+        ctx.predictor_load(weights)
+
+    # initial force (its flags, walk included, are those of every step), then warm-up steps
+    step_flags = flags | (fdx.PREDICTOR if walk == "predicted" else 0)
+    ctx.calc_force_flags(theta, 8, n_group, 0.0, step_flags)
     energy0 = system_energies(ps, ctx) if ps.n_sys > 1 else None
     for _ in range(args.warmup):
         ctx.integrate(dt, 1, graph=args.graph)
@@ -207,10 +231,9 @@ def main():
     traffic = read_traffic(f"force_fp32_quad_{args.workload}" if quad else
                            f"force_fp32_mono_{args.workload}", shape)
 
-    # learned predictor: the same evaluation with the predicted single-pass walk
+    # the same evaluation with the exact and the predicted walk
     pred = None
-    if args.predictor:
-        ctx.predictor_load(args.predictor)
+    if weights:
         pflags = flags | fdx.PREDICTOR
         ctx.calc_force_flags(theta, 8, n_group, 0.0, flags)
         exact_total = int(sum(int(a.sum()) for a in ctx.list_counts()))
@@ -297,6 +320,8 @@ def main():
                    "n_group": n_group, "n_leaf": 8, "quadrupole": quad,
                    "eps": float(ps.eps[0]) if ps.n_sys == 1 else "4/N_s^(1/3)", "dt": dt,
                    "graph": args.graph, "persistent": persistent,
+                   "walk": ("predicted single pass, exact re-walk of groups that overflow"
+                            if walk == "predicted" else "exact count + fill passes"),
                    "step": "leapfrog kick-drift, full force evaluation, kick"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),

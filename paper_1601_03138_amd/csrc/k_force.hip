@@ -187,17 +187,18 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
                 T tx[IPL], ty[IPL], tz[IPL], tp[IPL];
 #pragma unroll
                 for (int k = 0; k < IPL; k++) tx[k] = ty[k] = tz[k] = tp[k] = 0;
-                // entries slice, slice + nslice, ...: a block-uniform trip count (scalar loop
-                // counter), then at most one tail entry
+                // a contiguous run of kmain entries per slice (block-uniform trip count,
+                // constant LDS stride), then the nt mod nslice leftover entries one per slice
                 const uint32_t kmain = nt / nslice;
-                uint32_t j = slice;
+                const V *run = sm.e + slice * kmain;
 #pragma unroll 4
-                for (uint32_t q = 0; q < kmain; q++, j += nslice) {
-                    const V J = sm.e[j];
+                for (uint32_t q = 0; q < kmain; q++) {
+                    const V J = run[q];
 #pragma unroll
                     for (int k = 0; k < IPL; k++)
                         pp<T>(J, xi[k], yi[k], zi[k], e2[k], tx[k], ty[k], tz[k], tp[k]);
                 }
+                const uint32_t j = kmain * nslice + slice;
                 if (j < nt) {
                     const V J = sm.e[j];
 #pragma unroll
@@ -245,16 +246,17 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
 #pragma unroll
                 for (int k = 0; k < IPL; k++) tx[k] = ty[k] = tz[k] = tp[k] = 0;
                 const uint32_t kmain = nt / nslice;
-                uint32_t j = slice;
+                const V *run = sm.s + 3 * slice * kmain;
 #pragma unroll 2
-                for (uint32_t q = 0; q < kmain; q++, j += nslice) {
-                    const V A = sm.s[3 * j];
+                for (uint32_t q = 0; q < kmain; q++) {
+                    const V A = run[3 * q];
                     V B, C;
-                    if (QUAD) { B = sm.s[3 * j + 1]; C = sm.s[3 * j + 2]; } else { B = A; C = A; }
+                    if (QUAD) { B = run[3 * q + 1]; C = run[3 * q + 2]; } else { B = A; C = A; }
 #pragma unroll
                     for (int k = 0; k < IPL; k++)
                         pc<T, QUAD>(A, B, C, xi[k], yi[k], zi[k], e2[k], tx[k], ty[k], tz[k], tp[k]);
                 }
+                const uint32_t j = kmain * nslice + slice;
                 if (j < nt) {
                     const V A = sm.s[3 * j];
                     V B, C;
@@ -373,9 +375,9 @@ hipError_t launch_v(const KArgs &k, bool persistent, int v, hipStream_t s) {
         case 5: return launch<T, QUAD, 256, 2, false>(k, persistent, s);
         case 6: return launch<T, QUAD, 512, 1, false>(k, persistent, s);
         case 7: return launch<T, QUAD, 512, 2, false>(k, persistent, s);
-        // register allocation held to 64 VGPRs: 8 waves per SIMD (4 workgroups per CU)
-        case 8: return launch<T, QUAD, 512, 1, true, 8>(k, persistent, s);
-        default: return launch<T, QUAD, 512, 1, false, 8>(k, persistent, s);
+        // FP32: register allocation held to 64 VGPRs, 8 waves per SIMD (4 workgroups per CU)
+        case 8: return launch<T, QUAD, 512, 1, true, sizeof(T) == 4 ? 8 : 1>(k, persistent, s);
+        default: return launch<T, QUAD, 512, 1, false, sizeof(T) == 4 ? 8 : 1>(k, persistent, s);
     }
 }
 
