@@ -59,6 +59,20 @@ def _coincident():
 CASES["coincident"] = (_coincident, 8, 64, 0.5, True)
 
 
+def _deep_pairs():
+    # 400 pairs about two grid units apart: with n_leaf = 1 every pair is a chain of
+    # single-child cells down to level ~20, so the tree needs ~8 cells per particle, more
+    # than the first allocation (n + 1024): the build is truncated, flagged and retried larger
+    ps = I.uniform_cube(800, 43, 0.05)
+    ps.x[1::2] = ps.x[0::2] + 1e-6
+    ps.y[1::2] = ps.y[0::2]
+    ps.z[1::2] = ps.z[0::2]
+    return ps
+
+
+CASES["deep_pairs"] = (_deep_pairs, 1, 8, 0.5, True)
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_structure_and_fp64_forces(ctx, name):
     make, n_leaf, n_group, theta, quad = CASES[name]
