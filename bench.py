@@ -228,6 +228,16 @@ def main():
     achieved = float(np.mean(flops)) / (mean_force_ms / 1e3) / 1e12
     phase_ms = {k[2:]: round(float(np.mean([p[k] for p in phases])), 4) for k in phases[0]}
     shape = ctx.shape_name(st["shape"])
+    # algorithmic bytes of the HBM-bound phases (per particle unless stated): keys = bbox read
+    # 24 + key read 24 / write 12 + AoS pack read 32 / write 32; sort = 32 per radix pass (8 B
+    # histogram read, 12 B pair read and written) + sorted gather (4 perm + 32 record + 32 out
+    # + 8 eps + 4 inverse); walk = the 4-byte list entries written by the fill pass
+    passes = 8 + (0 if ps.n_sys <= 1 else (int(np.ceil(np.log2(ps.n_sys))) + 7) // 8)
+    gbs = lambda b, ms: round(b / (ms / 1e3) / 1e9, 1) if ms > 0 else None
+    phase_gbs = {"keys": gbs(124 * ps.n, phase_ms["keys"]),
+                 "sort": gbs((32 * passes + 80) * ps.n, phase_ms["sort"]),
+                 "walk_list_write": gbs(4 * (int(st["n_epj"]) + int(st["n_spj"])),
+                                        phase_ms["walk"])}
     traffic = read_traffic(f"force_fp32_quad_{args.workload}" if quad else
                            f"force_fp32_mono_{args.workload}", shape)
 
@@ -328,12 +338,15 @@ def main():
                      "traffic": traffic, "kernel": f"k_force_direct<float, quad> {shape}",
                      "kernel_ms": round(mean_force_ms, 3),
                      "interactions_per_launch": int(st["n_interactions_pp"] + st["n_interactions_pc"]),
+                     "interactions_per_s": round((st["n_interactions_pp"] + st["n_interactions_pc"])
+                                                 / (mean_force_ms / 1e3), -8),
                      "flops_per_interaction": {"pp": FLOPS_PP,
                                                "pc": FLOPS_PC_QUAD if quad else FLOPS_PC_MONO}},
         "cpu_baseline": cpu,
         "fp64": fp64,
         "accuracy": accuracy,
         "phases_ms": phase_ms,
+        "phase_gbs": phase_gbs,
         "energy_drift": drift,
         "predictor": pred,
         "autotune": tuned,
