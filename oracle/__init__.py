@@ -10,8 +10,10 @@ Two parts:
   O-T  `build_tree`, `make_groups`, `walk`, `tree_force`
                      a plain serial tree that fixes keys, order, cells, groups and lists
                      (the readings are documented in oracle.c next to each step).
-Plus the leapfrog of the sample program (`kdk`), energy and error diagnostics and the
-interaction-list length model (equation nlist_long).
+Plus the exchange lists between domains (`exchange`, section "Exchange of particles and
+superparticles") with the force from received lists (`list_force`), the leapfrog of the
+sample program (`kdk`), energy and error diagnostics, and the list-length models (equations
+nlist_long and n_list_long).
 """
 from __future__ import annotations
 
@@ -68,6 +70,8 @@ def _declare(L):
     L.or_walk_export.argtypes = [vp, vp, vp]
     L.or_walk_free.argtypes = [vp]
     L.or_force.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp]
+    L.or_exchange.argtypes = [vp, i64, vp, vp, vp, f64, vp]
+    L.or_exchange.restype = vp
 
 
 def _c(a, dt):
@@ -283,6 +287,121 @@ def energy(ps, pot: np.ndarray):
     K = 0.5 * float(np.sum(ps.m * (ps.vx ** 2 + ps.vy ** 2 + ps.vz ** 2)))
     W = 0.5 * float(np.sum(ps.m * pot))
     return K, W, K + W
+
+
+class ExchangeLists:
+    """Exchange lists between the domains of a particle set (each system is one domain with
+    its own local tree; section "Exchange of particles and superparticles", long-range
+    mode): for every ordered pair (sender s, receiver r != s), pairs ordered by sender then
+    receiver, the sender's particles (EPJ, sorted positions) and cells (SPJ, cell ids)
+    that r needs.  The reading is documented at or_exchange in oracle.c."""
+
+    def __init__(self, tree: Tree, theta: float):
+        L = lib()
+        self.tree, self.theta = tree, theta
+        ns = tree.n_sys
+        off, ps = tree.off, tree.ps
+        if ns < 2 or np.any(np.diff(off) == 0):
+            raise ValueError("exchange lists need at least two non-empty domains")
+        blo = np.zeros((ns, 3))
+        bhi = np.zeros((ns, 3))
+        for s in range(ns):
+            sl = slice(off[s], off[s + 1])
+            for a, k in enumerate(("x", "y", "z")):
+                v = getattr(ps, k)[sl]
+                blo[s, a], bhi[s, a] = v.min(), v.max()
+        self.blo, self.bhi = blo, bhi
+        self.pairs = [(s, r) for s in range(ns) for r in range(ns) if r != s]
+        k = len(self.pairs)
+        counts = np.zeros(2 * k, np.int64)
+        self._h = L.or_exchange(tree._h, ns, _p(_c(tree.cube, np.float64)), _p(_c(blo, np.float64)),
+                                _p(_c(bhi, np.float64)), float(theta), _p(counts))
+        self.n_epj = counts[0::2].copy()
+        self.n_spj = counts[1::2].copy()
+        self.epj_off = np.concatenate([[0], np.cumsum(self.n_epj)]).astype(np.int64)
+        self.spj_off = np.concatenate([[0], np.cumsum(self.n_spj)]).astype(np.int64)
+        self.epj = np.zeros(int(self.epj_off[-1]), np.uint32)
+        self.spj = np.zeros(int(self.spj_off[-1]), np.uint32)
+        L.or_walk_export(self._h, _p(self.epj), _p(self.spj))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().or_walk_free(h)
+            self._h = None
+
+    def index(self, s: int, r: int) -> int:
+        return self.pairs.index((s, r))
+
+    def pair_lists(self, s: int, r: int):
+        k = self.index(s, r)
+        return (self.epj[self.epj_off[k]:self.epj_off[k + 1]],
+                self.spj[self.spj_off[k]:self.spj_off[k + 1]])
+
+    def received(self, r: int):
+        """Everything domain r receives: (EPJ sorted positions, SPJ cell ids)."""
+        es, ss = [], []
+        for s in range(self.tree.n_sys):
+            if s != r:
+                e, c = self.pair_lists(s, r)
+                es.append(e)
+                ss.append(c)
+        return np.concatenate(es), np.concatenate(ss)
+
+
+def exchange(tree: Tree, theta: float) -> ExchangeLists:
+    return ExchangeLists(tree, theta)
+
+
+def list_force(x, y, z, eps, jx, jy, jz, jm, mom, quad: bool = True, self_mask=None):
+    """{ax, ay, az, phi} on the targets (x, y, z, eps) from particles (jx, jy, jz, jm) and
+    superparticles (rows of `mom`: M, X, Y, Z, Qxx, Qyy, Qzz, Qxy, Qxz, Qyz), FP64, with the
+    particle term of equation ParticleParticleNbody and the quadrupole superparticle term
+    (reading R6); pairs at zero separation contribute nothing (the self term)."""
+    out = np.zeros((x.shape[0], 4))
+    e2 = (eps * eps)[:, None]
+    if jx.shape[0]:
+        dx, dy, dz = jx[None, :] - x[:, None], jy[None, :] - y[:, None], jz[None, :] - z[:, None]
+        d2 = dx * dx + dy * dy + dz * dz
+        same = d2 == 0.0
+        ri = 1.0 / np.sqrt(d2 + e2)
+        mri = np.where(same, 0.0, jm[None, :] * ri)
+        mri3 = mri * ri * ri
+        out[:, 0] += np.sum(mri3 * dx, axis=1)
+        out[:, 1] += np.sum(mri3 * dy, axis=1)
+        out[:, 2] += np.sum(mri3 * dz, axis=1)
+        out[:, 3] -= np.sum(mri, axis=1)
+    if mom.shape[0]:
+        M, X, Y, Z = (mom[:, k][None, :] for k in range(4))
+        rx, ry, rz = x[:, None] - X, y[:, None] - Y, z[:, None] - Z
+        R2 = rx * rx + ry * ry + rz * rz + e2
+        Ri = 1.0 / np.sqrt(R2)
+        Ri2, Ri3 = Ri * Ri, Ri * Ri * Ri
+        ax, ay, az, ph = -M * Ri3 * rx, -M * Ri3 * ry, -M * Ri3 * rz, -M * Ri
+        if quad:
+            Qxx, Qyy, Qzz, Qxy, Qxz, Qyz = (mom[:, k][None, :] for k in range(4, 10))
+            qx = Qxx * rx + Qxy * ry + Qxz * rz
+            qy = Qxy * rx + Qyy * ry + Qyz * rz
+            qz = Qxz * rx + Qyz * ry + Qzz * rz
+            rqr = rx * qx + ry * qy + rz * qz
+            Ri5 = Ri3 * Ri2
+            ax = ax + Ri5 * qx - 2.5 * rqr * Ri5 * Ri2 * rx
+            ay = ay + Ri5 * qy - 2.5 * rqr * Ri5 * Ri2 * ry
+            az = az + Ri5 * qz - 2.5 * rqr * Ri5 * Ri2 * rz
+            ph = ph - 0.5 * rqr * Ri5
+        out[:, 0] += ax.sum(axis=1)
+        out[:, 1] += ay.sum(axis=1)
+        out[:, 2] += az.sum(axis=1)
+        out[:, 3] += ph.sum(axis=1)
+    return out
+
+
+def exchange_list_model(n: float, theta: float, n_p: float) -> float:
+    """Total exchange-list length of one domain of n particles among n_p cubic domains,
+    equation n_list_long of section "Exchange of particles and superparticles"."""
+    return (14.0 * n ** (2.0 / 3.0) / theta + 21.0 * math.pi * n ** (1.0 / 3.0) / theta ** 2
+            + 28.0 * math.pi / (3.0 * theta ** 3)
+            * math.log2(theta / 2.8 * ((n * n_p) ** (1.0 / 3.0) - n ** (1.0 / 3.0))))
 
 
 def rms_rel_error(a: np.ndarray, a_ref: np.ndarray) -> float:

@@ -378,14 +378,14 @@ void or_group_geometry(int64_t ng, const uint32_t *gcell, const uint32_t *gbegin
  *   D^2 = sum_a max(0, Bmin_a - C_a, C_a - Bmax_a)^2,  theta^2 = theta * theta.
  * The box bounds every member, so the test is conservative for each i of the group, as
  * one shared list requires. */
-static int accept_cell(int32_t l, uint64_t prefix, const uint32_t *bq_lo, const uint32_t *bq_hi,
+static int accept_cell(int32_t l, uint64_t prefix, const int64_t *bq_lo, const int64_t *bq_hi,
                        double th2) {
     uint32_t cq[3];
     deinterleave(prefix << (3 * (OR_LEVELS - l)), &cq[0], &cq[1], &cq[2]);
     double D2 = 0.0;
     for (int a = 0; a < 3; a++) {
         int64_t C = 2 * (int64_t)cq[a] + ((int64_t)1 << (OR_LEVELS - l));
-        int64_t bmin = 2 * (int64_t)bq_lo[a], bmax = 2 * (int64_t)bq_hi[a] + 2;
+        int64_t bmin = 2 * bq_lo[a], bmax = 2 * bq_hi[a] + 2;
         int64_t d = 0;
         if (bmin - C > d) d = bmin - C;
         if (C - bmax > d) d = C - bmax;
@@ -404,7 +404,7 @@ static void vpush(u32vec *a, uint32_t x) {
     if (a->n == a->cap) { a->cap = a->cap ? 2 * a->cap : 256; a->v = realloc(a->v, 4 * a->cap); }
     a->v[a->n++] = x;
 }
-static void walk_visit(const or_cells *t, uint32_t c, const uint32_t *lo, const uint32_t *hi,
+static void walk_visit(const or_cells *t, uint32_t c, const int64_t *lo, const int64_t *hi,
                        double th2, u32vec *epj, u32vec *spj) {
     if (t->count[c] == 0) return;
     if (accept_cell(t->level[c], t->prefix[c], lo, hi, th2)) { vpush(spj, c); return; }
@@ -431,12 +431,58 @@ void *or_walk(void *h, int64_t nsel, const int64_t *gsel, const uint32_t *groot,
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t k = 0; k < nsel; k++) {
         int64_t g = gsel[k];
-        walk_visit(t, groot[g], qmin + 3 * g, qmax + 3 * g, th2, &w->epj[k], &w->spj[k]);
+        int64_t lo[3], hi[3];
+        for (int a = 0; a < 3; a++) { lo[a] = qmin[3 * g + a]; hi[a] = qmax[3 * g + a]; }
+        walk_visit(t, groot[g], lo, hi, th2, &w->epj[k], &w->spj[k]);
         counts[2 * k] = w->epj[k].n;
         counts[2 * k + 1] = w->spj[k].n;
     }
     return w;
 }
+/* Exchange lists (section "Exchange of particles and superparticles", long-range mode):
+ * every domain -- one system of the set, with its own local tree -- sends every other
+ * domain the particles and superparticles it needs, found by the usual traversal of the
+ * sender's tree with the fixed opening angle theta.  Reading: the receiving domain is
+ * represented by the exact bounding box of its particles (blo, bhi: 3 per system), mapped
+ * into the sender's integer grid as q = floor((x - o) * 2^21 / Lr) per axis for the lower and
+ * the upper corner (cube: o_x, o_y, o_z, Lr per system), clamped to [-2^24, 2^24] so that
+ * half-grid distances stay exact in FP64 (the clamp only moves a distant box closer, which
+ * opens more cells: the list stays sufficient).  The traversal is the group walk with that
+ * box: accepted cells are superparticles, opened leaves give their particles.  Pairs are
+ * ordered by sender, then receiver (receiver != sender); counts[2k] = |EPJ|,
+ * counts[2k+1] = |SPJ| of pair k. */
+static int64_t grid_signed(double xv, double o, double Lr) {
+    double s = 2097152.0 / Lr;
+    double f = floor((xv - o) * s);
+    if (f < -16777216.0) f = -16777216.0;
+    if (f > 16777216.0) f = 16777216.0;
+    return (int64_t)f;
+}
+
+void *or_exchange(void *h, int64_t nsys, const double *cube, const double *blo,
+                  const double *bhi, double theta, int64_t *counts) {
+    const or_cells *t = (const or_cells *)h;
+    const int64_t np = nsys * (nsys - 1);
+    walk_res *w = (walk_res *)calloc(1, sizeof(walk_res));
+    w->nsel = np;
+    w->epj = (u32vec *)calloc((size_t)(np > 0 ? np : 1), sizeof(u32vec));
+    w->spj = (u32vec *)calloc((size_t)(np > 0 ? np : 1), sizeof(u32vec));
+    double th2 = theta * theta;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < np; k++) {
+        const int64_t s = k / (nsys - 1), j = k % (nsys - 1), r = j < s ? j : j + 1;
+        int64_t lo[3], hi[3];
+        for (int a = 0; a < 3; a++) {
+            lo[a] = grid_signed(blo[3 * r + a], cube[4 * s + a], cube[4 * s + 3]);
+            hi[a] = grid_signed(bhi[3 * r + a], cube[4 * s + a], cube[4 * s + 3]);
+        }
+        walk_visit(t, (uint32_t)s, lo, hi, th2, &w->epj[k], &w->spj[k]);
+        counts[2 * k] = w->epj[k].n;
+        counts[2 * k + 1] = w->spj[k].n;
+    }
+    return w;
+}
+
 void or_walk_export(void *wh, uint32_t *epj, uint32_t *spj) {
     walk_res *w = (walk_res *)wh;
     int64_t oe = 0, os = 0;

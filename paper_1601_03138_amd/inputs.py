@@ -201,6 +201,33 @@ def uniform_cube(n: int, seed: int, eps: float, side: float = 1.0) -> ParticleSe
     return _pack(pos, vel, m, np.full(n, float(eps)))
 
 
+def multisection(ps: ParticleSet, nx: int, ny: int, nz: int):
+    """The particles of a one-system set regrouped into nx * ny * nz domains laid end to end
+    as systems: equal-count slabs along x, each slab cut into equal-count columns along y,
+    each column into equal-count blocks along z (stable order, ties by index).  An input
+    layout for exchange-list tests and benchmarks (the domains stand in for processes); the
+    paper's sampling-based decomposition is not this.  Returns (domain set, order), order[k]
+    = the original index of the k-th particle of the domain set."""
+    if ps.n_sys != 1:
+        raise ValueError("multisection takes a one-system set")
+    n = ps.n
+    order = np.argsort(ps.x, kind="stable")
+    pieces = []
+    for sx in np.array_split(order, nx):
+        sx = sx[np.argsort(ps.y[sx], kind="stable")]
+        for sy in np.array_split(sx, ny):
+            sy = sy[np.argsort(ps.z[sy], kind="stable")]
+            pieces.extend(np.array_split(sy, nz))
+    order = np.concatenate(pieces).astype(np.int64)
+    sys_off = np.zeros(len(pieces) + 1, dtype=np.int64)
+    sys_off[1:] = np.cumsum([len(p) for p in pieces])
+    take = lambda a: np.ascontiguousarray(a[order])
+    dom = ParticleSet(take(ps.x), take(ps.y), take(ps.z), take(ps.vx), take(ps.vy), take(ps.vz),
+                      take(ps.m), take(ps.eps), sys_off)
+    assert sys_off[-1] == n
+    return dom, order
+
+
 def subset(n: int, k: int, seed: int) -> np.ndarray:
     """k distinct particle indices out of n, ascending (error-measurement subsets)."""
     rng = np.random.Generator(np.random.PCG64(seed))
