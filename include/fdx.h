@@ -212,6 +212,40 @@ int fdx_predictor_margin(fdx_ctx *ctx, double margin, double *out);
 int fdx_predictor_save(fdx_ctx *ctx, const char *path);
 int fdx_predictor_load(fdx_ctx *ctx, const char *path);
 
+/* ---- Exchange lists between domains ----------------------------------------------------
+ * Before the force step every process sends every other process the particles and
+ * superparticles it needs, found by the usual tree traversal of its own local tree with the
+ * fixed opening angle theta (section "Exchange of particles and superparticles", long-range
+ * mode; the total length per domain is modelled by equation n_list_long).  Here the domains
+ * are the systems of the particle set (sys_off), each with its own local tree, as virtual
+ * processes on one GPU.  The receiving domain enters the traversal as the exact bounding box
+ * of its particles mapped into the sender's integer grid (floor((x - o) * 2^21 / Lr) per
+ * axis, clamped to [-2^24, 2^24]); a cell of side S whose centre lies at distance D from that
+ * box is sent as a superparticle iff S^2 < theta^2 D^2, otherwise opened, and an opened leaf
+ * sends its particles.  Pairs (sender s, receiver r != s) are ordered by sender, then
+ * receiver: pair k = s * (n_sys - 1) + (r < s ? r : r - 1).
+ * fdx_build_exchange_lists: builds the local trees (keys, sort, cells, moments) and every
+ *   pair's list; theta in (0, 1], n_leaf >= 1.  FDX_EINVAL: fewer than two domains, an empty
+ *   domain or a parameter out of range; FDX_ESTATE: no particles.
+ * fdx_get_exchange_counts: n_epj[s * n_sys + r], n_spj[s * n_sys + r] (host, n_sys^2 each,
+ *   zero on the diagonal; null skips).
+ * fdx_get_exchange_lists: all pairs' entries concatenated in pair order (host memory):
+ *   epj = caller's particle indices, spj = cell ids of fdx_get_tree (whose mom rows are the
+ *   superparticles), each pair's entries in the library's emission order (null skips).
+ * fdx_get_exchange_stats: sizes and the device time of the two parts.
+ * The getters return FDX_ESTATE if no lists were built since the last fdx_set_particles. */
+typedef struct {
+    int64_t n_domains, n_pairs;
+    int64_t n_epj, n_spj;              /* entries over all pairs */
+    double ms_tree;                    /* keys, sort, cells and moments of all local trees */
+    double ms_lists;                   /* pair boxes, count walk, offsets, fill walk */
+} fdx_exchange_stats;
+
+int fdx_build_exchange_lists(fdx_ctx *ctx, double theta, int32_t n_leaf);
+int fdx_get_exchange_counts(fdx_ctx *ctx, uint32_t *n_epj, uint32_t *n_spj);
+int fdx_get_exchange_lists(fdx_ctx *ctx, uint32_t *epj, uint32_t *spj);
+int fdx_get_exchange_stats(fdx_ctx *ctx, fdx_exchange_stats *out);
+
 /* Message of the last failed call on ctx (never null; "" when none). */
 const char *fdx_last_error(const fdx_ctx *ctx);
 

@@ -1,0 +1,211 @@
+// Exchange lists between domains (section "Exchange of particles and superparticles",
+// long-range mode): the domains are the systems of the particle set, each with its own local
+// tree; every ordered pair (sender, receiver) is one walk of the sender's tree against the
+// receiver's particle box, run by the group-walk kernels through their selection arguments
+// (count pass, offsets, one read of the total, fill pass).
+#include <algorithm>
+#include <vector>
+
+#include "ctx.h"
+
+namespace fdx {
+
+namespace {
+
+struct ExchangeState {
+    DBuf<uint32_t> box, sys, sel, ne, ns, cap, list, np_dev;
+    DBuf<uint64_t> seg, total;
+    uint64_t list_cap = 0;
+    int nsys = 0;
+    size_t pairs = 0;
+    uint64_t entries = 0, n_epj = 0, n_spj = 0;
+    double ms_tree = 0, ms_lists = 0;
+    bool built = false;
+    uint64_t gen = 0;            // context generation the lists belong to
+    hipEvent_t ev[3] = {};
+
+    void release() {
+        for (auto *b : {&box, &sys, &sel, &ne, &ns, &cap, &list, &np_dev}) b->release();
+        seg.release();
+        total.release();
+        for (auto &e : ev)
+            if (e) { (void)hipEventDestroy(e); e = nullptr; }
+        list_cap = 0;
+        built = false;
+    }
+};
+
+ExchangeState *state(fdx_ctx *c) {
+    if (!c->ext.exch) c->ext.exch = new ExchangeState();
+    return static_cast<ExchangeState *>(c->ext.exch);
+}
+
+int check_built(fdx_ctx *c) {
+    ExchangeState *x = static_cast<ExchangeState *>(c->ext.exch);
+    if (!x || !x->built || x->gen != c->gen)
+        return fail(c, FDX_ESTATE, "no exchange lists built for the current particles");
+    return FDX_OK;
+}
+
+}  // namespace
+
+void exchange_release(fdx_ctx *c) {
+    ExchangeState *x = static_cast<ExchangeState *>(c->ext.exch);
+    if (!x) return;
+    x->release();
+    delete x;
+    c->ext.exch = nullptr;
+}
+
+}  // namespace fdx
+
+using namespace fdx;
+
+extern "C" {
+
+int fdx_build_exchange_lists(fdx_ctx *c, double theta, int32_t n_leaf) {
+    if (!c) return FDX_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, FDX_EHIP, "hipSetDevice failed");
+    if (!c->have_particles) return fail(c, FDX_ESTATE, "no particles: call fdx_set_particles first");
+    if (c->nsys < 2) return fail(c, FDX_EINVAL, "exchange lists need at least two domains");
+    for (int s = 0; s < c->nsys; s++)
+        if (c->sys_off_h[s + 1] == c->sys_off_h[s])
+            return fail(c, FDX_EINVAL, "domain %d is empty", s);
+    const size_t P = (size_t)c->nsys * (size_t)(c->nsys - 1);
+    if (P > 0x7FFFFFFFull) return fail(c, FDX_EINVAL, "too many domains");
+    // the local trees: keys, sort, cells, moments (and groups, unused here); softening is
+    // not used by the lists
+    const double eps = c->eps_given ? 0.0 : (c->eps_all > 0 ? c->eps_all : 1.0);
+    int r = setup_eval(c, theta, n_leaf, kMaxGroup, eps, 0);
+    if (r) return r;
+    ExchangeState *x = state(c);
+    x->built = false;
+    hipStream_t s = c->stream;
+    for (auto &e : x->ev)
+        if (!e) HIPCHK(c, hipEventCreate(&e));
+    HIPCHK(c, hipEventRecord(x->ev[0], s));
+    r = run_tree(c, true);
+    if (r) return r;
+    finish_stats(c);
+    HIPCHK(c, hipEventRecord(x->ev[1], s));
+
+    HIPCHK(c, x->box.ensure(6 * P));
+    HIPCHK(c, x->sys.ensure(P));
+    HIPCHK(c, x->sel.ensure(P));
+    HIPCHK(c, x->ne.ensure(P));
+    HIPCHK(c, x->ns.ensure(P));
+    HIPCHK(c, x->cap.ensure(P));
+    HIPCHK(c, x->seg.ensure(P + 1));
+    HIPCHK(c, x->total.ensure(1));
+    HIPCHK(c, x->np_dev.ensure(1));
+    HIPCHK(c, fill_u32(x->np_dev.p, (uint32_t)P, 1, s));
+    HIPCHK(c, exchange_pairs(c->nsys, c->bbox_u.p, c->cube.p, x->box.p, x->sys.p, x->sel.p, s));
+    Groups pg{};
+    pg.box = x->box.p;
+    pg.sys = x->sys.p;
+    pg.cap = (uint32_t)P;
+    const Cells cv = cells_view(c);
+    const double th2 = c->theta * c->theta;
+    HIPCHK(c, walk(false, P, pg, cv, th2, nullptr, nullptr, 0, nullptr, x->ne.p, x->ns.p, nullptr,
+                   x->sel.p, x->np_dev.p, c->st, s));
+    HIPCHK(c, exchange_caps(P, x->ne.p, x->ns.p, x->cap.p, s));
+    HIPCHK(c, scan_u32_to_u64(x->cap.p, x->seg.p, P, nullptr, nullptr, c->partial.p, x->total.p, s));
+    uint64_t total = 0;
+    HIPCHK(c, hipMemcpyAsync(&total, x->total.p, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (total > x->list_cap || !x->list.p) {
+        HIPCHK(c, x->list.ensure(total + total / 8 + 1024));
+        x->list_cap = total + total / 8 + 1024;
+    }
+    HIPCHK(c, walk(true, P, pg, cv, th2, x->seg.p, x->cap.p, x->list_cap, x->list.p, x->ne.p,
+                   x->ns.p, nullptr, x->sel.p, x->np_dev.p, c->st, s));
+    HIPCHK(c, hipEventRecord(x->ev[2], s));
+    r = read_status(c);
+    if (r) return r;
+    const DevStatus &h = c->hst->st;
+    if (h.walk_error || h.list_overflow)
+        return fail(c, FDX_EHIP, "exchange walk did not complete (stack %u, overflow %u)",
+                    h.walk_error, h.list_overflow);
+    float t0 = 0, t1 = 0;
+    HIPCHK(c, hipEventElapsedTime(&t0, x->ev[0], x->ev[1]));
+    HIPCHK(c, hipEventElapsedTime(&t1, x->ev[1], x->ev[2]));
+    std::vector<uint32_t> ne(P), ns(P);
+    HIPCHK(c, hipMemcpyAsync(ne.data(), x->ne.p, 4 * P, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(ns.data(), x->ns.p, 4 * P, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    x->n_epj = x->n_spj = 0;
+    for (size_t k = 0; k < P; k++) { x->n_epj += ne[k]; x->n_spj += ns[k]; }
+    x->entries = total;
+    x->nsys = c->nsys;
+    x->pairs = P;
+    x->ms_tree = t0;
+    x->ms_lists = t1;
+    x->gen = c->gen;
+    x->built = true;
+    return FDX_OK;
+}
+
+int fdx_get_exchange_counts(fdx_ctx *c, uint32_t *n_epj, uint32_t *n_spj) {
+    if (!c) return FDX_EINVAL;
+    int r = check_built(c);
+    if (r) return r;
+    ExchangeState *x = static_cast<ExchangeState *>(c->ext.exch);
+    const size_t P = x->pairs, S = (size_t)x->nsys;
+    std::vector<uint32_t> ne(P), ns(P);
+    HIPCHK(c, hipMemcpyAsync(ne.data(), x->ne.p, 4 * P, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(ns.data(), x->ns.p, 4 * P, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t s = 0; s < S; s++)
+        for (size_t q = 0; q < S; q++) {
+            const size_t k = s * (S - 1) + (q < s ? q : q - 1);
+            if (n_epj) n_epj[s * S + q] = q == s ? 0u : ne[k];
+            if (n_spj) n_spj[s * S + q] = q == s ? 0u : ns[k];
+        }
+    return FDX_OK;
+}
+
+int fdx_get_exchange_lists(fdx_ctx *c, uint32_t *epj, uint32_t *spj) {
+    if (!c) return FDX_EINVAL;
+    int r = check_built(c);
+    if (r) return r;
+    ExchangeState *x = static_cast<ExchangeState *>(c->ext.exch);
+    const size_t P = x->pairs, n = (size_t)c->n;
+    std::vector<uint32_t> ne(P), ns(P), cap(P), all(std::max<uint64_t>(x->entries, 1)), perm(n);
+    std::vector<uint64_t> seg(P);
+    hipStream_t s = c->stream;
+    HIPCHK(c, hipMemcpyAsync(ne.data(), x->ne.p, 4 * P, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(ns.data(), x->ns.p, 4 * P, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(cap.data(), x->cap.p, 4 * P, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(seg.data(), x->seg.p, 8 * P, hipMemcpyDeviceToHost, s));
+    if (x->entries)
+        HIPCHK(c, hipMemcpyAsync(all.data(), x->list.p, 4 * x->entries, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(perm.data(), c->sperm, 4 * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    size_t oe = 0, os = 0;
+    for (size_t k = 0; k < P; k++) {
+        const uint32_t *g = all.data() + seg[k];
+        if (epj)
+            for (uint32_t i = 0; i < ne[k]; i++) epj[oe + i] = perm[g[i]];
+        if (spj)
+            for (uint32_t i = 0; i < ns[k]; i++) spj[os + i] = g[cap[k] - 1 - i];
+        oe += ne[k];
+        os += ns[k];
+    }
+    return FDX_OK;
+}
+
+int fdx_get_exchange_stats(fdx_ctx *c, fdx_exchange_stats *out) {
+    if (!c || !out) return FDX_EINVAL;
+    int r = check_built(c);
+    if (r) return r;
+    ExchangeState *x = static_cast<ExchangeState *>(c->ext.exch);
+    out->n_domains = x->nsys;
+    out->n_pairs = (int64_t)x->pairs;
+    out->n_epj = (int64_t)x->n_epj;
+    out->n_spj = (int64_t)x->n_spj;
+    out->ms_tree = x->ms_tree;
+    out->ms_lists = x->ms_lists;
+    return FDX_OK;
+}
+
+}  // extern "C"

@@ -124,6 +124,12 @@ hipError_t make_groups(size_t n, int nsys, const int64_t *sys_off, Cells c,
 // A group whose entries do not fit its segment (or whose segment passes list_cap) writes
 // nothing, gets zero counts and is appended to ovf_list (st->list_overflow counts them).
 // sel (optional, with nsel): walk only the listed groups (predictor re-walk).
+// exchange lists: per ordered domain pair, the receiver's box in the sender's grid, the
+// sender's root (= system id) and an identity selection for the walk; then segment sizes
+hipError_t exchange_pairs(int nsys, const uint64_t *bbox_u, const double *cube, uint32_t *box,
+                          uint32_t *sys, uint32_t *sel, hipStream_t s);
+hipError_t exchange_caps(size_t P, const uint32_t *ne, const uint32_t *ns, uint32_t *cap,
+                         hipStream_t s);
 hipError_t walk(bool fill, size_t gmax, const Groups g, const Cells c, double theta2,
                 const uint64_t *seg, const uint32_t *cap, uint64_t list_cap, uint32_t *list,
                 uint32_t *cnt_e, uint32_t *cnt_s, uint32_t *ovf_list, const uint32_t *sel,

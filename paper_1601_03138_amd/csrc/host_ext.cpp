@@ -181,6 +181,7 @@ void ext_release(fdx_ctx *c) {
         c->ext.graph = nullptr;
     }
     predictor_release(c);
+    exchange_release(c);
 }
 
 }  // namespace fdx

@@ -14,6 +14,7 @@ struct HostExt {
     int variant = -1;                 // autotuned force-kernel variant (-1: default)
     void *pred = nullptr;             // predictor state (weights, normalisation)
     void *graph = nullptr;            // captured step (GraphState)
+    void *exch = nullptr;             // exchange lists between domains
     int64_t graph_recoveries = 0;     // replays whose capacities overflowed and were redone
 };
 
@@ -23,5 +24,6 @@ int ext_integrate_graph(fdx_ctx *c, double dt, int n_steps);
 void ext_release(fdx_ctx *c);
 void ext_invalidate(fdx_ctx *c);   // drop any captured graph (particles or buffers changed)
 int ext_predicted_walk(fdx_ctx *c, uint32_t G);
+void exchange_release(fdx_ctx *c);
 
 }  // namespace fdx

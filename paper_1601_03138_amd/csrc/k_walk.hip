@@ -176,6 +176,44 @@ __global__ void k_queue_keys(uint32_t gmax, const uint32_t *ngroups_c, const uin
     }
 }
 
+// Exchange lists between domains (section "Exchange of particles and superparticles",
+// long-range mode): each ordered pair (sender s, receiver r != s), ordered by sender then
+// receiver, becomes one walk of the sender's tree whose "group box" is the exact bounding box
+// of the receiver's particles in the sender's integer grid, q = floor((x - o) * 2^21 / Lr),
+// clamped to [-2^24, 2^24] so half-grid distances stay exact in FP64 (a clamped box is
+// closer, so more cells open and the list stays sufficient).  Boxes are stored as int32 in
+// the u32 box array; the walk reads them back as signed values.
+__device__ __forceinline__ int grid_signed(double x, double o, double Lr) {
+    const double sc = 2097152.0 / Lr;                  // a power of two: exact
+    double f = floor(__dmul_rn(__dsub_rn(x, o), sc));
+    f = fmin(fmax(f, -16777216.0), 16777216.0);
+    return (int)f;
+}
+
+__global__ void k_exchange_pairs(int nsys, const uint64_t *bbox_u, const double *cube,
+                                 uint32_t *box, uint32_t *sys, uint32_t *sel) {
+    const size_t P = (size_t)nsys * (size_t)(nsys - 1);
+    for (size_t k = gtid(); k < P; k += gstride()) {
+        const uint32_t s = (uint32_t)(k / (nsys - 1)), j = (uint32_t)(k % (nsys - 1));
+        const uint32_t r = j < s ? j : j + 1;
+        const double *cb = cube + 4 * (size_t)s;
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            const double lo = ord_to_dbl(bbox_u[6 * (size_t)r + 2 * a]);
+            const double hi = ord_to_dbl(bbox_u[6 * (size_t)r + 2 * a + 1]);
+            box[6 * k + a] = (uint32_t)grid_signed(lo, cb[a], cb[3]);
+            box[6 * k + 3 + a] = (uint32_t)grid_signed(hi, cb[a], cb[3]);
+        }
+        sys[k] = s;
+        sel[k] = (uint32_t)k;
+    }
+}
+
+__global__ void k_exchange_caps(size_t P, const uint32_t *ne, const uint32_t *ns,
+                                uint32_t *cap) {
+    for (size_t k = gtid(); k < P; k += gstride()) cap[k] = ne[k] + ns[k];
+}
+
 inline unsigned grid_waves(size_t gmax) {
     size_t b = (gmax + kWaves - 1) / kWaves;
     if (b < 1) b = 1;
@@ -184,6 +222,26 @@ inline unsigned grid_waves(size_t gmax) {
 }
 
 }  // namespace
+
+hipError_t exchange_pairs(int nsys, const uint64_t *bbox_u, const double *cube, uint32_t *box,
+                          uint32_t *sys, uint32_t *sel, hipStream_t s) {
+    const size_t P = (size_t)nsys * (size_t)(nsys - 1);
+    if (!P) return hipSuccess;
+    size_t b = (P + kThreads - 1) / kThreads;
+    b = b > 4096 ? 4096 : b;
+    hipLaunchKernelGGL(k_exchange_pairs, dim3((unsigned)b), dim3(kThreads), 0, s, nsys, bbox_u,
+                       cube, box, sys, sel);
+    return hipGetLastError();
+}
+
+hipError_t exchange_caps(size_t P, const uint32_t *ne, const uint32_t *ns, uint32_t *cap,
+                         hipStream_t s) {
+    if (!P) return hipSuccess;
+    size_t b = (P + kThreads - 1) / kThreads;
+    b = b > 4096 ? 4096 : b;
+    hipLaunchKernelGGL(k_exchange_caps, dim3((unsigned)b), dim3(kThreads), 0, s, P, ne, ns, cap);
+    return hipGetLastError();
+}
 
 hipError_t walk(bool fill, size_t gmax, const Groups g, const Cells c, double theta2,
                 const uint64_t *seg, const uint32_t *cap, uint64_t list_cap, uint32_t *list,

@@ -24,7 +24,9 @@ EXPORTS = ["fdx_create", "fdx_destroy", "fdx_set_particles", "fdx_build_tree", "
            "fdx_get_tree", "fdx_get_groups", "fdx_get_lists", "fdx_last_error",
            "fdx_autotune_shapes", "fdx_shape_name", "fdx_set_shape", "fdx_autotune", "fdx_mlp_params",
            "fdx_predictor_features", "fdx_mlp_forward", "fdx_mlp_grad", "fdx_predictor_train",
-           "fdx_predictor_margin", "fdx_predictor_save", "fdx_predictor_load"]
+           "fdx_predictor_margin", "fdx_predictor_save", "fdx_predictor_load",
+           "fdx_build_exchange_lists", "fdx_get_exchange_counts", "fdx_get_exchange_lists",
+           "fdx_get_exchange_stats"]
 
 
 class FdxError(RuntimeError):
@@ -41,6 +43,14 @@ class Stats(C.Structure):
         ("shape", C.c_int32), ("theta", C.c_double)] + [(k, C.c_double) for k in (
             "t_keys", "t_sort", "t_tree", "t_moments", "t_groups", "t_walk", "t_force",
             "t_unsort", "t_predict", "t_total")]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ExchangeStats(C.Structure):
+    _fields_ = [("n_domains", C.c_int64), ("n_pairs", C.c_int64), ("n_epj", C.c_int64),
+                ("n_spj", C.c_int64), ("ms_tree", C.c_double), ("ms_lists", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -96,6 +106,10 @@ def _declare(L):
     L.fdx_predictor_margin.argtypes = [vp, f64, vp]
     L.fdx_predictor_save.argtypes = [vp, C.c_char_p]
     L.fdx_predictor_load.argtypes = [vp, C.c_char_p]
+    L.fdx_build_exchange_lists.argtypes = [vp, f64, i32]
+    L.fdx_get_exchange_counts.argtypes = [vp, vp, vp]
+    L.fdx_get_exchange_lists.argtypes = [vp, vp, vp]
+    L.fdx_get_exchange_stats.argtypes = [vp, C.POINTER(ExchangeStats)]
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -275,6 +289,38 @@ class Context:
 
     def set_shape(self, shape: int):
         self._check(self.lib.fdx_set_shape(self.h, int(shape)), "set_shape")
+
+    # -- exchange lists between domains (the systems of the particle set) ----------------
+    def build_exchange_lists(self, theta: float, n_leaf: int = 8):
+        self._check(self.lib.fdx_build_exchange_lists(self.h, float(theta), int(n_leaf)),
+                    "build_exchange_lists")
+
+    def exchange_counts(self):
+        """(n_epj, n_spj) as n_sys x n_sys matrices, row = sender, column = receiver."""
+        S = int(self.stats()["n_sys"])
+        ne, ns = np.empty(S * S, np.uint32), np.empty(S * S, np.uint32)
+        self._check(self.lib.fdx_get_exchange_counts(self.h, _ptr(ne), _ptr(ns)),
+                    "get_exchange_counts")
+        return ne.reshape(S, S), ns.reshape(S, S)
+
+    def exchange_lists(self):
+        """(pairs, n_epj, n_spj, epj, spj): pairs in order (sender, receiver != sender),
+        per-pair counts, and the concatenated entries (caller's particle indices, cell ids)."""
+        ne, ns = self.exchange_counts()
+        S = ne.shape[0]
+        pairs = [(a, b) for a in range(S) for b in range(S) if b != a]
+        pe = np.array([ne[a, b] for a, b in pairs], np.int64)
+        psj = np.array([ns[a, b] for a, b in pairs], np.int64)
+        epj = np.empty(max(1, int(pe.sum())), np.uint32)
+        spj = np.empty(max(1, int(psj.sum())), np.uint32)
+        self._check(self.lib.fdx_get_exchange_lists(self.h, _ptr(epj), _ptr(spj)),
+                    "get_exchange_lists")
+        return pairs, pe, psj, epj[:int(pe.sum())], spj[:int(psj.sum())]
+
+    def exchange_stats(self) -> dict:
+        st = ExchangeStats()
+        self._check(self.lib.fdx_get_exchange_stats(self.h, C.byref(st)), "get_exchange_stats")
+        return st.as_dict()
 
     # -- learned list-length predictor -----------------------------------------------------
     def predictor_features(self) -> np.ndarray:
