@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -44,6 +45,14 @@ WORKLOADS = {
 # trained for (on inputs of other seeds)
 PREDICTOR_WEIGHTS = {("clustered16m", 256, 0.5):
                      os.path.join(ROOT, "paper_1601_03138_amd", "predictor_clustered16m_ng256.bin")}
+
+
+def exchange_list_model(n: float, theta: float, n_p: float) -> float:
+    """Equation n_list_long: total exchange-list length of one of n_p cubic domains of n
+    particles (section "Exchange of particles and superparticles")."""
+    return (14.0 * n ** (2.0 / 3.0) / theta + 21.0 * math.pi * n ** (1.0 / 3.0) / theta ** 2
+            + 28.0 * math.pi / (3.0 * theta ** 3)
+            * math.log2(theta / 2.8 * ((n * n_p) ** (1.0 / 3.0) - n ** (1.0 / 3.0))))
 
 
 def log(*a):
@@ -139,6 +148,9 @@ def main():
                     help="predictor weights (default: the shipped ones for the workload)")
     ap.add_argument("--autotune", action="store_true",
                     help="run the autotuner over n_group x kernel shape first and use its choice")
+    ap.add_argument("--exchange-domains", type=int, default=4,
+                    help="also time the exchange lists of the input cut into k x k x k "
+                         "equal-count domains (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -308,6 +320,40 @@ def main():
         accuracy = {"rms_da_over_a_fp32": e32, "rms_da_over_a_fp64": e64,
                     "subset": "256 particles, seed 102, FP64 direct sum (oracle)"}
 
+    # exchange lists between domains (the same particles as k x k x k virtual processes)
+    exch = None
+    if args.exchange_domains > 0 and ps.n_sys == 1:
+        kd = args.exchange_domains
+        dom, _ = inputs.multisection(ps, kd, kd, kd)
+        cx = fdx.Context(0)
+        cx.set_particles(dom)
+        cx.build_exchange_lists(theta, 8)
+        ts, tl = [], []
+        for _ in range(5):
+            cx.build_exchange_lists(theta, 8)
+            xs = cx.exchange_stats()
+            ts.append(xs["ms_tree"])
+            tl.append(xs["ms_lists"])
+        entries = int(xs["n_epj"] + xs["n_spj"])
+        ms_lists = float(np.median(tl))
+        exch = {"domains": kd ** 3, "theta": theta, "n_leaf": 8,
+                "ms_local_trees": round(float(np.median(ts)), 3), "ms_lists": round(ms_lists, 3),
+                "entries": entries, "epj": int(xs["n_epj"]), "spj": int(xs["n_spj"]),
+                "entries_per_s": round(entries / (ms_lists / 1e3), -6),
+                "mean_entries_per_domain": round(entries / kd ** 3, 1),
+                "model_eq_n_list_long": round(exchange_list_model(ps.n / kd ** 3, theta,
+                                                                  kd ** 3), 1),
+                "paper_s_per_entry_one_cpu_process": 1.12e-7}
+        cx.close()
+        if not args.no_cpu_baseline:
+            import oracle as O
+            ta = time.perf_counter()
+            tr = O.build_tree(dom, 8)
+            O.exchange(tr, theta)
+            exch["cpu_oracle_s"] = round(time.perf_counter() - ta, 2)
+            del tr
+        log(f"[bench] exchange lists: {exch}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
@@ -347,6 +393,7 @@ def main():
         "accuracy": accuracy,
         "phases_ms": phase_ms,
         "phase_gbs": phase_gbs,
+        "exchange": exch,
         "energy_drift": drift,
         "predictor": pred,
         "autotune": tuned,

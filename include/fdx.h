@@ -231,12 +231,16 @@ int fdx_predictor_load(fdx_ctx *ctx, const char *path);
  *   zero on the diagonal; null skips).
  * fdx_get_exchange_lists: all pairs' entries concatenated in pair order (host memory):
  *   epj = caller's particle indices, spj = cell ids of fdx_get_tree (whose mom rows are the
- *   superparticles), each pair's entries in the library's emission order (null skips).
- * fdx_get_exchange_stats: sizes and the device time of the two parts.
+ *   superparticles), each pair's entries in an order of the library's choosing (null
+ *   skips).
+ * fdx_get_exchange_stats: sizes, list memory and the device time of the two parts.
  * The getters return FDX_ESTATE if no lists were built since the last fdx_set_particles. */
 typedef struct {
     int64_t n_domains, n_pairs;
     int64_t n_epj, n_spj;              /* entries over all pairs */
+    int64_t list_capacity;             /* entries allocated: (n_sys - 1) n, the per-sender
+                                          bound, while that fits 16 GiB (one fill walk);
+                                          else the exact total from a count walk */
     double ms_tree;                    /* keys, sort, cells and moments of all local trees */
     double ms_lists;                   /* pair boxes, count walk, offsets, fill walk */
 } fdx_exchange_stats;

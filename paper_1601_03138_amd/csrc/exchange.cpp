@@ -12,13 +12,16 @@ namespace fdx {
 
 namespace {
 
+// largest list buffer sized by the per-sender bound (one fill walk); 16 GiB of the GPU's HBM
+constexpr uint64_t kExchangeBudgetBytes = 16ull << 30;
+
 struct ExchangeState {
     DBuf<uint32_t> box, sys, sel, ne, ns, cap, list, np_dev;
     DBuf<uint64_t> seg, total;
     uint64_t list_cap = 0;
     int nsys = 0;
     size_t pairs = 0;
-    uint64_t entries = 0, n_epj = 0, n_spj = 0;
+    uint64_t entries = 0, n_epj = 0, n_spj = 0, capacity = 0;
     double ms_tree = 0, ms_lists = 0;
     bool built = false;
     uint64_t gen = 0;            // context generation the lists belong to
@@ -99,23 +102,33 @@ int fdx_build_exchange_lists(fdx_ctx *c, double theta, int32_t n_leaf) {
     HIPCHK(c, x->total.ensure(1));
     HIPCHK(c, x->np_dev.ensure(1));
     HIPCHK(c, fill_u32(x->np_dev.p, (uint32_t)P, 1, s));
-    HIPCHK(c, exchange_pairs(c->nsys, c->bbox_u.p, c->cube.p, x->box.p, x->sys.p, x->sel.p, s));
+    // every list of sender s holds at most n_s entries (they cover disjoint sets of its
+    // particles): with room for that bound in every segment, one fill walk does; past the
+    // budget, a count walk sizes the segments first
+    const uint64_t bound = (uint64_t)(c->nsys - 1) * (uint64_t)c->n;
+    const bool one_pass = bound * sizeof(uint32_t) <= kExchangeBudgetBytes;
+    HIPCHK(c, exchange_pairs(c->nsys, c->bbox_u.p, c->cube.p, one_pass ? c->sys_off.p : nullptr,
+                             x->box.p, x->sys.p, x->sel.p, x->cap.p, x->seg.p, s));
     Groups pg{};
     pg.box = x->box.p;
     pg.sys = x->sys.p;
     pg.cap = (uint32_t)P;
     const Cells cv = cells_view(c);
     const double th2 = c->theta * c->theta;
-    HIPCHK(c, walk(false, P, pg, cv, th2, nullptr, nullptr, 0, nullptr, x->ne.p, x->ns.p, nullptr,
-                   x->sel.p, x->np_dev.p, c->st, s));
-    HIPCHK(c, exchange_caps(P, x->ne.p, x->ns.p, x->cap.p, s));
-    HIPCHK(c, scan_u32_to_u64(x->cap.p, x->seg.p, P, nullptr, nullptr, c->partial.p, x->total.p, s));
-    uint64_t total = 0;
-    HIPCHK(c, hipMemcpyAsync(&total, x->total.p, 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
+    uint64_t total = bound;
+    if (!one_pass) {
+        HIPCHK(c, walk(false, P, pg, cv, th2, nullptr, nullptr, 0, nullptr, x->ne.p, x->ns.p,
+                       nullptr, x->sel.p, x->np_dev.p, c->st, s));
+        HIPCHK(c, exchange_caps(P, x->ne.p, x->ns.p, x->cap.p, s));
+        HIPCHK(c, scan_u32_to_u64(x->cap.p, x->seg.p, P, nullptr, nullptr, c->partial.p,
+                                  x->total.p, s));
+        HIPCHK(c, hipMemcpyAsync(&total, x->total.p, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+    }
     if (total > x->list_cap || !x->list.p) {
-        HIPCHK(c, x->list.ensure(total + total / 8 + 1024));
-        x->list_cap = total + total / 8 + 1024;
+        const uint64_t want = one_pass ? total : total + total / 8 + 1024;
+        HIPCHK(c, x->list.ensure(want));
+        x->list_cap = want;
     }
     HIPCHK(c, walk(true, P, pg, cv, th2, x->seg.p, x->cap.p, x->list_cap, x->list.p, x->ne.p,
                    x->ns.p, nullptr, x->sel.p, x->np_dev.p, c->st, s));
@@ -135,7 +148,8 @@ int fdx_build_exchange_lists(fdx_ctx *c, double theta, int32_t n_leaf) {
     HIPCHK(c, hipStreamSynchronize(s));
     x->n_epj = x->n_spj = 0;
     for (size_t k = 0; k < P; k++) { x->n_epj += ne[k]; x->n_spj += ns[k]; }
-    x->entries = total;
+    x->entries = x->n_epj + x->n_spj;
+    x->capacity = total;
     x->nsys = c->nsys;
     x->pairs = P;
     x->ms_tree = t0;
@@ -170,27 +184,33 @@ int fdx_get_exchange_lists(fdx_ctx *c, uint32_t *epj, uint32_t *spj) {
     if (r) return r;
     ExchangeState *x = static_cast<ExchangeState *>(c->ext.exch);
     const size_t P = x->pairs, n = (size_t)c->n;
-    std::vector<uint32_t> ne(P), ns(P), cap(P), all(std::max<uint64_t>(x->entries, 1)), perm(n);
+    std::vector<uint32_t> ne(P), ns(P), cap(P), perm(n);
     std::vector<uint64_t> seg(P);
     hipStream_t s = c->stream;
     HIPCHK(c, hipMemcpyAsync(ne.data(), x->ne.p, 4 * P, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(ns.data(), x->ns.p, 4 * P, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(cap.data(), x->cap.p, 4 * P, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(seg.data(), x->seg.p, 8 * P, hipMemcpyDeviceToHost, s));
-    if (x->entries)
-        HIPCHK(c, hipMemcpyAsync(all.data(), x->list.p, 4 * x->entries, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(perm.data(), c->sperm, 4 * n, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
+    // each segment: particles from its front, cells from its back
+    std::vector<uint32_t> e(std::max<uint64_t>(x->n_epj, 1)), sp(std::max<uint64_t>(x->n_spj, 1));
     size_t oe = 0, os = 0;
     for (size_t k = 0; k < P; k++) {
-        const uint32_t *g = all.data() + seg[k];
-        if (epj)
-            for (uint32_t i = 0; i < ne[k]; i++) epj[oe + i] = perm[g[i]];
-        if (spj)
-            for (uint32_t i = 0; i < ns[k]; i++) spj[os + i] = g[cap[k] - 1 - i];
+        if (epj && ne[k])
+            HIPCHK(c, hipMemcpyAsync(e.data() + oe, x->list.p + seg[k], 4 * (size_t)ne[k],
+                                     hipMemcpyDeviceToHost, s));
+        if (spj && ns[k])
+            HIPCHK(c, hipMemcpyAsync(sp.data() + os, x->list.p + seg[k] + cap[k] - ns[k],
+                                     4 * (size_t)ns[k], hipMemcpyDeviceToHost, s));
         oe += ne[k];
         os += ns[k];
     }
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (epj)
+        for (size_t i = 0; i < oe; i++) epj[i] = perm[e[i]];
+    if (spj)
+        for (size_t i = 0; i < os; i++) spj[i] = sp[i];
     return FDX_OK;
 }
 
@@ -203,6 +223,7 @@ int fdx_get_exchange_stats(fdx_ctx *c, fdx_exchange_stats *out) {
     out->n_pairs = (int64_t)x->pairs;
     out->n_epj = (int64_t)x->n_epj;
     out->n_spj = (int64_t)x->n_spj;
+    out->list_capacity = (int64_t)x->capacity;
     out->ms_tree = x->ms_tree;
     out->ms_lists = x->ms_lists;
     return FDX_OK;

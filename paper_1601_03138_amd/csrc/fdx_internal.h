@@ -125,9 +125,12 @@ hipError_t make_groups(size_t n, int nsys, const int64_t *sys_off, Cells c,
 // nothing, gets zero counts and is appended to ovf_list (st->list_overflow counts them).
 // sel (optional, with nsel): walk only the listed groups (predictor re-walk).
 // exchange lists: per ordered domain pair, the receiver's box in the sender's grid, the
-// sender's root (= system id) and an identity selection for the walk; then segment sizes
-hipError_t exchange_pairs(int nsys, const uint64_t *bbox_u, const double *cube, uint32_t *box,
-                          uint32_t *sys, uint32_t *sel, hipStream_t s);
+// sender's root (= system id) and an identity selection for the walk; with off, also list
+// segments sized by the sender's particle count (an upper bound); else segment sizes from
+// a count pass (exchange_caps)
+hipError_t exchange_pairs(int nsys, const uint64_t *bbox_u, const double *cube,
+                          const int64_t *off, uint32_t *box, uint32_t *sys, uint32_t *sel,
+                          uint32_t *cap, uint64_t *seg, hipStream_t s);
 hipError_t exchange_caps(size_t P, const uint32_t *ne, const uint32_t *ns, uint32_t *cap,
                          hipStream_t s);
 hipError_t walk(bool fill, size_t gmax, const Groups g, const Cells c, double theta2,

@@ -190,8 +190,12 @@ __device__ __forceinline__ int grid_signed(double x, double o, double Lr) {
     return (int)f;
 }
 
+// With off != null also the list segment of every pair sized by the sender's particle count
+// (the entries of one list cover disjoint sets of the sender's particles, so no list is
+// longer): cap = n_s, seg = (nsys - 1) off[s] + j n_s for the j-th receiver of s.
 __global__ void k_exchange_pairs(int nsys, const uint64_t *bbox_u, const double *cube,
-                                 uint32_t *box, uint32_t *sys, uint32_t *sel) {
+                                 const int64_t *off, uint32_t *box, uint32_t *sys,
+                                 uint32_t *sel, uint32_t *cap, uint64_t *seg) {
     const size_t P = (size_t)nsys * (size_t)(nsys - 1);
     for (size_t k = gtid(); k < P; k += gstride()) {
         const uint32_t s = (uint32_t)(k / (nsys - 1)), j = (uint32_t)(k % (nsys - 1));
@@ -206,6 +210,11 @@ __global__ void k_exchange_pairs(int nsys, const uint64_t *bbox_u, const double 
         }
         sys[k] = s;
         sel[k] = (uint32_t)k;
+        if (off) {
+            const uint64_t ns = (uint64_t)(off[s + 1] - off[s]);
+            cap[k] = (uint32_t)ns;
+            seg[k] = (uint64_t)(nsys - 1) * (uint64_t)off[s] + (uint64_t)j * ns;
+        }
     }
 }
 
@@ -223,14 +232,15 @@ inline unsigned grid_waves(size_t gmax) {
 
 }  // namespace
 
-hipError_t exchange_pairs(int nsys, const uint64_t *bbox_u, const double *cube, uint32_t *box,
-                          uint32_t *sys, uint32_t *sel, hipStream_t s) {
+hipError_t exchange_pairs(int nsys, const uint64_t *bbox_u, const double *cube,
+                          const int64_t *off, uint32_t *box, uint32_t *sys, uint32_t *sel,
+                          uint32_t *cap, uint64_t *seg, hipStream_t s) {
     const size_t P = (size_t)nsys * (size_t)(nsys - 1);
     if (!P) return hipSuccess;
     size_t b = (P + kThreads - 1) / kThreads;
     b = b > 4096 ? 4096 : b;
     hipLaunchKernelGGL(k_exchange_pairs, dim3((unsigned)b), dim3(kThreads), 0, s, nsys, bbox_u,
-                       cube, box, sys, sel);
+                       cube, off, box, sys, sel, cap, seg);
     return hipGetLastError();
 }
 

@@ -50,7 +50,8 @@ class Stats(C.Structure):
 
 class ExchangeStats(C.Structure):
     _fields_ = [("n_domains", C.c_int64), ("n_pairs", C.c_int64), ("n_epj", C.c_int64),
-                ("n_spj", C.c_int64), ("ms_tree", C.c_double), ("ms_lists", C.c_double)]
+                ("n_spj", C.c_int64), ("list_capacity", C.c_int64), ("ms_tree", C.c_double),
+                ("ms_lists", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

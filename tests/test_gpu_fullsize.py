@@ -1,7 +1,8 @@
 """GPU parity at the benchmark configurations' full sizes, in the launch configuration bench.py
 times: keys, order, every cell and every group bit-exact against the oracle's full serial
 build; lists and forces on sampled groups; accuracy against FP64 direct summation on seeded
-subsets; the ensemble with graph-captured steps; the predictor path at full size."""
+subsets; the ensemble with graph-captured steps; the predictor path at full size; the
+exchange lists of the benchmark input cut into 64 domains."""
 import os
 import sys
 
@@ -160,3 +161,35 @@ def test_ensemble512_graph_configuration(ctx, fdx):
     for a, b in zip(ctx.particles(), g_state[0]):
         assert np.array_equal(a, b)
     assert np.array_equal(ctx.forces(), g_state[1])
+
+
+def test_clustered16m_exchange_lists_64_domains(fdx):
+    """The benchmark input cut into 4 x 4 x 4 equal-count domains: local trees and the
+    counts of all 4032 pairs bit-exact, entry sets of sampled pairs."""
+    ps = I.workload("clustered16m")
+    dom, _ = I.multisection(ps, 4, 4, 4)
+    _say(f"[fullsize] exchange lists, n={dom.n} domains={dom.n_sys}")
+    t = O.build_tree(dom, 8)
+    L = O.exchange(t, 0.5)
+    c = fdx.Context(0)
+    try:
+        c.set_particles(dom)
+        c.build_exchange_lists(0.5, 8)
+        tree = c.tree()
+        assert np.array_equal(tree["key"], t.skey) and np.array_equal(tree["perm"], t.perm)
+        for k in ("level", "begin", "count", "first_child", "nchild", "parent"):
+            assert np.array_equal(tree[k], getattr(t, k).astype(tree[k].dtype)), k
+        pairs, ne, ns, epj, spj = c.exchange_lists()
+        assert np.array_equal(ne, L.n_epj) and np.array_equal(ns, L.n_spj)
+        oe = np.concatenate([[0], np.cumsum(ne)])
+        os_ = np.concatenate([[0], np.cumsum(ns)])
+        rng = np.random.default_rng(8)
+        for k in rng.choice(len(pairs), 64, replace=False):
+            e_ref, s_ref = L.epj[L.epj_off[k]:L.epj_off[k + 1]], L.spj[L.spj_off[k]:L.spj_off[k + 1]]
+            assert np.array_equal(np.sort(epj[oe[k]:oe[k + 1]]), np.sort(t.perm[e_ref]))
+            assert np.array_equal(np.sort(spj[os_[k]:os_[k + 1]]), np.sort(s_ref))
+        st = c.exchange_stats()
+        _say(f"  entries {int(ne.sum() + ns.sum())}; device ms: trees {st['ms_tree']:.3f}, "
+             f"lists {st['ms_lists']:.3f}")
+    finally:
+        c.close()
