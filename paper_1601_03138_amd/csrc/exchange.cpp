@@ -1,8 +1,8 @@
 // Exchange lists between domains (section "Exchange of particles and superparticles",
 // long-range mode): the domains are the systems of the particle set, each with its own local
-// tree; every ordered pair (sender, receiver) is one walk of the sender's tree against the
-// receiver's particle box, run by the group-walk kernels through their selection arguments
-// (count pass, offsets, one read of the total, fill pass).
+// tree; every ordered pair (sender, receiver) is a walk of the sender's tree against the
+// receiver's particle box, split into sub-walks over the sender's top-level frontier and run
+// by the group-walk kernels through their selection arguments.
 #include <algorithm>
 #include <vector>
 
@@ -16,7 +16,7 @@ namespace {
 constexpr uint64_t kExchangeBudgetBytes = 16ull << 30;
 
 struct ExchangeState {
-    DBuf<uint32_t> box, sys, sel, ne, ns, cap, list, np_dev;
+    DBuf<uint32_t> box, start, sel, ne, ns, cap, list, nsel, front, fcount;
     DBuf<uint64_t> seg, total;
     uint64_t list_cap = 0;
     int nsys = 0;
@@ -28,7 +28,8 @@ struct ExchangeState {
     hipEvent_t ev[3] = {};
 
     void release() {
-        for (auto *b : {&box, &sys, &sel, &ne, &ns, &cap, &list, &np_dev}) b->release();
+        for (auto *b : {&box, &start, &sel, &ne, &ns, &cap, &list, &nsel, &front, &fcount})
+            b->release();
         seg.release();
         total.release();
         for (auto &e : ev)
@@ -92,46 +93,51 @@ int fdx_build_exchange_lists(fdx_ctx *c, double theta, int32_t n_leaf) {
     finish_stats(c);
     HIPCHK(c, hipEventRecord(x->ev[1], s));
 
-    HIPCHK(c, x->box.ensure(6 * P));
-    HIPCHK(c, x->sys.ensure(P));
-    HIPCHK(c, x->sel.ensure(P));
-    HIPCHK(c, x->ne.ensure(P));
-    HIPCHK(c, x->ns.ensure(P));
-    HIPCHK(c, x->cap.ensure(P));
-    HIPCHK(c, x->seg.ensure(P + 1));
+    const size_t G = exchange_subwalks(c->nsys);
+    HIPCHK(c, x->box.ensure(6 * G));
+    HIPCHK(c, x->start.ensure(G));
+    HIPCHK(c, x->sel.ensure(G));
+    HIPCHK(c, x->ne.ensure(G));
+    HIPCHK(c, x->ns.ensure(G));
+    HIPCHK(c, x->cap.ensure(G));
+    HIPCHK(c, x->seg.ensure(G + 1));
     HIPCHK(c, x->total.ensure(1));
-    HIPCHK(c, x->np_dev.ensure(1));
-    HIPCHK(c, fill_u32(x->np_dev.p, (uint32_t)P, 1, s));
-    // every list of sender s holds at most n_s entries (they cover disjoint sets of its
-    // particles): with room for that bound in every segment, one fill walk does; past the
-    // budget, a count walk sizes the segments first
-    const uint64_t bound = (uint64_t)(c->nsys - 1) * (uint64_t)c->n;
-    const bool one_pass = bound * sizeof(uint32_t) <= kExchangeBudgetBytes;
-    HIPCHK(c, exchange_pairs(c->nsys, c->bbox_u.p, c->cube.p, one_pass ? c->sys_off.p : nullptr,
-                             x->box.p, x->sys.p, x->sel.p, x->cap.p, x->seg.p, s));
-    Groups pg{};
-    pg.box = x->box.p;
-    pg.sys = x->sys.p;
-    pg.cap = (uint32_t)P;
+    HIPCHK(c, x->nsel.ensure(1));
+    HIPCHK(c, x->front.ensure((size_t)kExchangeFrontierMax * c->nsys));
+    HIPCHK(c, x->fcount.ensure(c->nsys));
     const Cells cv = cells_view(c);
     const double th2 = c->theta * c->theta;
+    HIPCHK(c, exchange_split(c->nsys, cv, c->bbox_u.p, c->cube.p, th2, x->front.p, x->fcount.p,
+                             x->box.p, x->start.p, x->cap.p, x->sel.p, x->nsel.p, s));
+    HIPCHK(c, fill_u32(x->ne.p, 0u, G, s));
+    HIPCHK(c, fill_u32(x->ns.p, 0u, G, s));
+    Groups pg{};
+    pg.box = x->box.p;
+    pg.sys = x->start.p;
+    pg.cap = (uint32_t)std::min<size_t>(G, 0xFFFFFFFFu);
+    // every list of sender s holds at most n_s entries (they cover disjoint sets of its
+    // particles; so does each sub-walk within its start cell): with room for that bound in
+    // every segment, one fill walk does; past the budget a count walk sizes them first
+    const uint64_t bound = (uint64_t)(c->nsys - 1) * (uint64_t)c->n;
+    const bool one_pass = bound * sizeof(uint32_t) <= kExchangeBudgetBytes;
+    if (!one_pass) {
+        HIPCHK(c, walk(false, G, pg, cv, th2, nullptr, nullptr, 0, nullptr, x->ne.p, x->ns.p,
+                       nullptr, x->sel.p, x->nsel.p, c->st, s));
+        HIPCHK(c, exchange_caps(G, x->sel.p, x->nsel.p, x->ne.p, x->ns.p, x->cap.p, s));
+    }
+    HIPCHK(c, scan_u32_to_u64(x->cap.p, x->seg.p, G, nullptr, nullptr, c->partial.p, x->total.p,
+                              s));
     uint64_t total = bound;
     if (!one_pass) {
-        HIPCHK(c, walk(false, P, pg, cv, th2, nullptr, nullptr, 0, nullptr, x->ne.p, x->ns.p,
-                       nullptr, x->sel.p, x->np_dev.p, c->st, s));
-        HIPCHK(c, exchange_caps(P, x->ne.p, x->ns.p, x->cap.p, s));
-        HIPCHK(c, scan_u32_to_u64(x->cap.p, x->seg.p, P, nullptr, nullptr, c->partial.p,
-                                  x->total.p, s));
         HIPCHK(c, hipMemcpyAsync(&total, x->total.p, 8, hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));
     }
     if (total > x->list_cap || !x->list.p) {
-        const uint64_t want = one_pass ? total : total + total / 8 + 1024;
-        HIPCHK(c, x->list.ensure(want));
-        x->list_cap = want;
+        HIPCHK(c, x->list.ensure(total));
+        x->list_cap = total;
     }
-    HIPCHK(c, walk(true, P, pg, cv, th2, x->seg.p, x->cap.p, x->list_cap, x->list.p, x->ne.p,
-                   x->ns.p, nullptr, x->sel.p, x->np_dev.p, c->st, s));
+    HIPCHK(c, walk(true, G, pg, cv, th2, x->seg.p, x->cap.p, x->list_cap, x->list.p, x->ne.p,
+                   x->ns.p, nullptr, x->sel.p, x->nsel.p, c->st, s));
     HIPCHK(c, hipEventRecord(x->ev[2], s));
     r = read_status(c);
     if (r) return r;
@@ -142,12 +148,12 @@ int fdx_build_exchange_lists(fdx_ctx *c, double theta, int32_t n_leaf) {
     float t0 = 0, t1 = 0;
     HIPCHK(c, hipEventElapsedTime(&t0, x->ev[0], x->ev[1]));
     HIPCHK(c, hipEventElapsedTime(&t1, x->ev[1], x->ev[2]));
-    std::vector<uint32_t> ne(P), ns(P);
-    HIPCHK(c, hipMemcpyAsync(ne.data(), x->ne.p, 4 * P, hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(ns.data(), x->ns.p, 4 * P, hipMemcpyDeviceToHost, s));
+    std::vector<uint32_t> ne(G), ns(G);
+    HIPCHK(c, hipMemcpyAsync(ne.data(), x->ne.p, 4 * G, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(ns.data(), x->ns.p, 4 * G, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     x->n_epj = x->n_spj = 0;
-    for (size_t k = 0; k < P; k++) { x->n_epj += ne[k]; x->n_spj += ns[k]; }
+    for (size_t g = 0; g < G; g++) { x->n_epj += ne[g]; x->n_spj += ns[g]; }
     x->entries = x->n_epj + x->n_spj;
     x->capacity = total;
     x->nsys = c->nsys;
@@ -164,16 +170,23 @@ int fdx_get_exchange_counts(fdx_ctx *c, uint32_t *n_epj, uint32_t *n_spj) {
     int r = check_built(c);
     if (r) return r;
     ExchangeState *x = static_cast<ExchangeState *>(c->ext.exch);
-    const size_t P = x->pairs, S = (size_t)x->nsys;
-    std::vector<uint32_t> ne(P), ns(P);
-    HIPCHK(c, hipMemcpyAsync(ne.data(), x->ne.p, 4 * P, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(ns.data(), x->ns.p, 4 * P, hipMemcpyDeviceToHost, c->stream));
+    const size_t S = (size_t)x->nsys, G = exchange_subwalks(x->nsys);
+    std::vector<uint32_t> ne(G), ns(G);
+    HIPCHK(c, hipMemcpyAsync(ne.data(), x->ne.p, 4 * G, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(ns.data(), x->ns.p, 4 * G, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     for (size_t s = 0; s < S; s++)
         for (size_t q = 0; q < S; q++) {
-            const size_t k = s * (S - 1) + (q < s ? q : q - 1);
-            if (n_epj) n_epj[s * S + q] = q == s ? 0u : ne[k];
-            if (n_spj) n_spj[s * S + q] = q == s ? 0u : ns[k];
+            uint32_t e = 0, sp = 0;
+            if (q != s) {
+                const size_t k = s * (S - 1) + (q < s ? q : q - 1);
+                for (size_t g = k * kExchangeFrontierMax; g < (k + 1) * kExchangeFrontierMax; g++) {
+                    e += ne[g];
+                    sp += ns[g];
+                }
+            }
+            if (n_epj) n_epj[s * S + q] = e;
+            if (n_spj) n_spj[s * S + q] = sp;
         }
     return FDX_OK;
 }
@@ -183,7 +196,7 @@ int fdx_get_exchange_lists(fdx_ctx *c, uint32_t *epj, uint32_t *spj) {
     int r = check_built(c);
     if (r) return r;
     ExchangeState *x = static_cast<ExchangeState *>(c->ext.exch);
-    const size_t P = x->pairs, n = (size_t)c->n;
+    const size_t P = exchange_subwalks(x->nsys), n = (size_t)c->n;   // sub-walks, pair-major
     std::vector<uint32_t> ne(P), ns(P), cap(P), perm(n);
     std::vector<uint64_t> seg(P);
     hipStream_t s = c->stream;
@@ -193,7 +206,8 @@ int fdx_get_exchange_lists(fdx_ctx *c, uint32_t *epj, uint32_t *spj) {
     HIPCHK(c, hipMemcpyAsync(seg.data(), x->seg.p, 8 * P, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(perm.data(), c->sperm, 4 * n, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
-    // each segment: particles from its front, cells from its back
+    // each sub-walk's segment: particles from its front, cells from its back; a pair's
+    // entries are its sub-walks' in slot order
     std::vector<uint32_t> e(std::max<uint64_t>(x->n_epj, 1)), sp(std::max<uint64_t>(x->n_spj, 1));
     size_t oe = 0, os = 0;
     for (size_t k = 0; k < P; k++) {

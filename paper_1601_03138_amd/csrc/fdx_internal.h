@@ -124,15 +124,18 @@ hipError_t make_groups(size_t n, int nsys, const int64_t *sys_off, Cells c,
 // A group whose entries do not fit its segment (or whose segment passes list_cap) writes
 // nothing, gets zero counts and is appended to ovf_list (st->list_overflow counts them).
 // sel (optional, with nsel): walk only the listed groups (predictor re-walk).
-// exchange lists: per ordered domain pair, the receiver's box in the sender's grid, the
-// sender's root (= system id) and an identity selection for the walk; with off, also list
-// segments sized by the sender's particle count (an upper bound); else segment sizes from
-// a count pass (exchange_caps)
-hipError_t exchange_pairs(int nsys, const uint64_t *bbox_u, const double *cube,
-                          const int64_t *off, uint32_t *box, uint32_t *sys, uint32_t *sel,
-                          uint32_t *cap, uint64_t *seg, hipStream_t s);
-hipError_t exchange_caps(size_t P, const uint32_t *ne, const uint32_t *ns, uint32_t *cap,
-                         hipStream_t s);
+// exchange lists: every ordered domain pair's walk split into sub-walks over the sender's
+// frontier (exchange_subwalks(nsys) slots, pair-major); exchange_split writes each slot's
+// receiver box, start cell and segment bound (0 = idle) and appends the active slots to sel
+// (*nsel of them); exchange_caps sets the segment sizes of the active slots from a count walk
+hipError_t exchange_split(int nsys, const Cells c, const uint64_t *bbox_u, const double *cube,
+                          double theta2, uint32_t *front, uint32_t *fcount, uint32_t *box,
+                          uint32_t *start, uint32_t *cap, uint32_t *sel, uint32_t *nsel,
+                          hipStream_t s);
+hipError_t exchange_caps(size_t G, const uint32_t *sel, const uint32_t *nsel, const uint32_t *ne,
+                         const uint32_t *ns, uint32_t *cap, hipStream_t s);
+size_t exchange_subwalks(int nsys);
+constexpr int kExchangeFrontierMax = 64;
 hipError_t walk(bool fill, size_t gmax, const Groups g, const Cells c, double theta2,
                 const uint64_t *seg, const uint32_t *cap, uint64_t list_cap, uint32_t *list,
                 uint32_t *cnt_e, uint32_t *cnt_s, uint32_t *ovf_list, const uint32_t *sel,

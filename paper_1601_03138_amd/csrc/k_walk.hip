@@ -24,6 +24,22 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;
 constexpr int kSlack = 160;     // stack entries kept free for sequential descent
 
+// The opening test: a cell of side S (level l: S = 2^(22-l) half-grid units) whose centre
+// lies at distance D from the box [bmin, bmax] (half-grid units) is accepted iff
+// S^2 < theta^2 D^2; D^2 is an exact integer in FP64 and the product is rounded once.
+__device__ __forceinline__ bool cell_accepted(const uint4 nd, int bminx, int bminy, int bminz,
+                                              int bmaxx, int bmaxy, int bmaxz, double theta2) {
+    const int lv = (int)(nd.w & 0xFFu);
+    const int cx = (int)nd.x, cy = (int)nd.y, cz = (int)nd.z;
+    const int dx = max(0, max(bminx - cx, cx - bmaxx));
+    const int dy = max(0, max(bminy - cy, cy - bmaxy));
+    const int dz = max(0, max(bminz - cz, cz - bmaxz));
+    const double D2 = (double)dx * (double)dx + (double)dy * (double)dy +
+                      (double)dz * (double)dz;                         // exact integers
+    const double S2 = __longlong_as_double((long long)(1023 + 2 * (22 - lv)) << 52);
+    return S2 < __dmul_rn(theta2, D2);
+}
+
 template <bool FILL>
 __global__ void __launch_bounds__(kThreads)
 k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, uint32_t ccap,
@@ -62,16 +78,9 @@ k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, 
             // branches, so both loads are issued together and nothing is loaded later
             const uint4 nd = node[cid];
             const uint2 lk = link[cid];
-            const int lv = (int)(nd.w & 0xFFu);
             const uint32_t nch = nd.w >> 8;
-            const int cx = (int)nd.x, cy = (int)nd.y, cz = (int)nd.z;
-            const int dx = max(0, max(bminx - cx, cx - bmaxx));
-            const int dy = max(0, max(bminy - cy, cy - bmaxy));
-            const int dz = max(0, max(bminz - cz, cz - bmaxz));
-            const double D2 = (double)dx * (double)dx + (double)dy * (double)dy +
-                              (double)dz * (double)dz;                 // exact integers
-            const double S2 = __longlong_as_double((long long)(1023 + 2 * (22 - lv)) << 52);
-            const bool accept = act && S2 < __dmul_rn(theta2, D2);
+            const bool accept =
+                act && cell_accepted(nd, bminx, bminy, bminz, bmaxx, bmaxy, bmaxz, theta2);
             const bool open = act && !accept;
             const bool leaf = open && nch == 0 && lk.y > 0;
             const bool inner = open && nch != 0;
@@ -177,12 +186,24 @@ __global__ void k_queue_keys(uint32_t gmax, const uint32_t *ngroups_c, const uin
 }
 
 // Exchange lists between domains (section "Exchange of particles and superparticles",
-// long-range mode): each ordered pair (sender s, receiver r != s), ordered by sender then
-// receiver, becomes one walk of the sender's tree whose "group box" is the exact bounding box
-// of the receiver's particles in the sender's integer grid, q = floor((x - o) * 2^21 / Lr),
-// clamped to [-2^24, 2^24] so half-grid distances stay exact in FP64 (a clamped box is
-// closer, so more cells open and the list stays sufficient).  Boxes are stored as int32 in
-// the u32 box array; the walk reads them back as signed values.
+// long-range mode).  The list of the ordered pair (sender s, receiver r != s) is the walk of
+// s's tree against the exact bounding box of r's particles in s's integer grid,
+// q = floor((x - o) * 2^21 / Lr), clamped to [-2^24, 2^24] so half-grid distances stay exact
+// in FP64 (a clamped box is closer, so more cells open and the list stays sufficient).  Boxes
+// are stored as int32 in the u32 box array; the walk reads them back as signed values.
+//
+// Each pair's walk is split over the sender's frontier at level kFrontier (its cells of that
+// level and its leaves above it; at most 8^kFrontier cells, covering every particle once).
+// Every cell is decided from itself and the box alone, so the full walk equals, for each
+// frontier cell c: nothing if an ancestor of c is accepted, except that the frontier cell
+// sharing the first particle of the highest accepted ancestor a emits a; otherwise the walk
+// of c's subtree.  A sub-walk is one "group" of the walk kernel whose start cell is c (or a,
+// which the kernel then accepts at once).
+__global__ void k_fill_one(uint32_t *p) { *p = 0u; }
+
+constexpr int kFrontier = 2;
+constexpr int kFrontierMax = 64;                    // 8^kFrontier
+
 __device__ __forceinline__ int grid_signed(double x, double o, double Lr) {
     const double sc = 2097152.0 / Lr;                  // a power of two: exact
     double f = floor(__dmul_rn(__dsub_rn(x, o), sc));
@@ -190,37 +211,77 @@ __device__ __forceinline__ int grid_signed(double x, double o, double Lr) {
     return (int)f;
 }
 
-// With off != null also the list segment of every pair sized by the sender's particle count
-// (the entries of one list cover disjoint sets of the sender's particles, so no list is
-// longer): cap = n_s, seg = (nsys - 1) off[s] + j n_s for the j-th receiver of s.
-__global__ void k_exchange_pairs(int nsys, const uint64_t *bbox_u, const double *cube,
-                                 const int64_t *off, uint32_t *box, uint32_t *sys,
-                                 uint32_t *sel, uint32_t *cap, uint64_t *seg) {
-    const size_t P = (size_t)nsys * (size_t)(nsys - 1);
-    for (size_t k = gtid(); k < P; k += gstride()) {
-        const uint32_t s = (uint32_t)(k / (nsys - 1)), j = (uint32_t)(k % (nsys - 1));
-        const uint32_t r = j < s ? j : j + 1;
-        const double *cb = cube + 4 * (size_t)s;
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-            const double lo = ord_to_dbl(bbox_u[6 * (size_t)r + 2 * a]);
-            const double hi = ord_to_dbl(bbox_u[6 * (size_t)r + 2 * a + 1]);
-            box[6 * k + a] = (uint32_t)grid_signed(lo, cb[a], cb[3]);
-            box[6 * k + 3 + a] = (uint32_t)grid_signed(hi, cb[a], cb[3]);
+// frontier cells of every system (depth-first, child order): front[kFrontierMax s + f]
+__global__ void k_exchange_frontier(int nsys, Cells c, uint32_t *front, uint32_t *fcount) {
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < nsys; s += gridDim.x * blockDim.x) {
+        uint32_t stk[1 + 7 * kFrontier], sp = 0, nf = 0;
+        stk[sp++] = (uint32_t)s;
+        while (sp) {
+            const uint32_t cid = stk[--sp];
+            const uint32_t nch = c.nchild[cid];
+            if (c.level[cid] >= (uint32_t)kFrontier || nch == 0) {
+                front[kFrontierMax * (size_t)s + nf++] = cid;
+            } else {
+                const uint32_t f = c.first[cid];
+                for (uint32_t k = nch; k-- > 0;) stk[sp++] = f + k;
+            }
         }
-        sys[k] = s;
-        sel[k] = (uint32_t)k;
-        if (off) {
-            const uint64_t ns = (uint64_t)(off[s + 1] - off[s]);
-            cap[k] = (uint32_t)ns;
-            seg[k] = (uint64_t)(nsys - 1) * (uint64_t)off[s] + (uint64_t)j * ns;
-        }
+        fcount[s] = nf;
     }
 }
 
-__global__ void k_exchange_caps(size_t P, const uint32_t *ne, const uint32_t *ns,
-                                uint32_t *cap) {
-    for (size_t k = gtid(); k < P; k += gstride()) cap[k] = ne[k] + ns[k];
+// one sub-walk per (pair k, frontier slot f): box, start cell and segment size (0 = idle);
+// the active sub-walks are appended to sel.  With by_bound the segment is sized by the start
+// cell's particle count (a sub-walk's entries cover disjoint sets of its particles), else
+// the count walk sizes it afterwards.
+__global__ void k_exchange_split(int nsys, Cells c, const uint32_t *front, const uint32_t *fcount,
+                                 const uint64_t *bbox_u, const double *cube, double theta2,
+                                 uint32_t *box, uint32_t *start, uint32_t *cap, uint32_t *sel,
+                                 uint32_t *nsel) {
+    const size_t P = (size_t)nsys * (size_t)(nsys - 1);
+    for (size_t g = gtid(); g < P * kFrontierMax; g += gstride()) {
+        const size_t k = g / kFrontierMax;
+        const uint32_t f = (uint32_t)(g % kFrontierMax);
+        const uint32_t s = (uint32_t)(k / (nsys - 1)), j = (uint32_t)(k % (nsys - 1));
+        const uint32_t r = j < s ? j : j + 1;
+        cap[g] = 0;
+        if (f >= fcount[s]) continue;
+        const double *cb = cube + 4 * (size_t)s;
+        int q[6];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            q[a] = grid_signed(ord_to_dbl(bbox_u[6 * (size_t)r + 2 * a]), cb[a], cb[3]);
+            q[3 + a] = grid_signed(ord_to_dbl(bbox_u[6 * (size_t)r + 2 * a + 1]), cb[a], cb[3]);
+            box[6 * g + a] = (uint32_t)q[a];
+            box[6 * g + 3 + a] = (uint32_t)q[3 + a];
+        }
+        const uint32_t cell = front[kFrontierMax * (size_t)s + f];
+        // the ancestors of the frontier cell, root first
+        uint32_t anc[kFrontier];
+        int na = 0;
+        for (uint32_t a = c.parent[cell]; a != kNone && na < kFrontier; a = c.parent[a]) anc[na++] = a;
+        uint32_t st = cell, sz = c.count[cell];
+        for (int i = na - 1; i >= 0; i--) {
+            if (cell_accepted(c.node[anc[i]], 2 * q[0], 2 * q[1], 2 * q[2], 2 * q[3] + 2,
+                              2 * q[4] + 2, 2 * q[5] + 2, theta2)) {
+                st = anc[i];
+                sz = c.begin[cell] == c.begin[st] ? 1u : 0u;
+                break;
+            }
+        }
+        start[g] = st;
+        cap[g] = sz;
+        if (sz) sel[atomicAdd(nsel, 1u)] = (uint32_t)g;
+    }
+}
+
+__global__ void k_exchange_caps(size_t G, const uint32_t *sel, const uint32_t *nsel,
+                                const uint32_t *ne, const uint32_t *ns, uint32_t *cap) {
+    const uint32_t n = *nsel;
+    for (size_t i = gtid(); i < n; i += gstride()) {
+        const uint32_t g = sel[i];
+        if (g < G) cap[g] = ne[g] + ns[g];
+    }
 }
 
 inline unsigned grid_waves(size_t gmax) {
@@ -232,24 +293,33 @@ inline unsigned grid_waves(size_t gmax) {
 
 }  // namespace
 
-hipError_t exchange_pairs(int nsys, const uint64_t *bbox_u, const double *cube,
-                          const int64_t *off, uint32_t *box, uint32_t *sys, uint32_t *sel,
-                          uint32_t *cap, uint64_t *seg, hipStream_t s) {
-    const size_t P = (size_t)nsys * (size_t)(nsys - 1);
-    if (!P) return hipSuccess;
-    size_t b = (P + kThreads - 1) / kThreads;
-    b = b > 4096 ? 4096 : b;
-    hipLaunchKernelGGL(k_exchange_pairs, dim3((unsigned)b), dim3(kThreads), 0, s, nsys, bbox_u,
-                       cube, off, box, sys, sel, cap, seg);
+size_t exchange_subwalks(int nsys) {
+    return (size_t)nsys * (size_t)(nsys - 1) * kFrontierMax;
+}
+
+hipError_t exchange_split(int nsys, const Cells c, const uint64_t *bbox_u, const double *cube,
+                          double theta2, uint32_t *front, uint32_t *fcount, uint32_t *box,
+                          uint32_t *start, uint32_t *cap, uint32_t *sel, uint32_t *nsel,
+                          hipStream_t s) {
+    const size_t G = exchange_subwalks(nsys);
+    if (!G) return hipSuccess;
+    hipLaunchKernelGGL(k_exchange_frontier, dim3((nsys + 63) / 64), dim3(64), 0, s, nsys, c, front,
+                       fcount);
+    hipLaunchKernelGGL(k_fill_one, dim3(1), dim3(1), 0, s, nsel);
+    size_t b = (G + kThreads - 1) / kThreads;
+    b = b > 8192 ? 8192 : b;
+    hipLaunchKernelGGL(k_exchange_split, dim3((unsigned)b), dim3(kThreads), 0, s, nsys, c, front,
+                       fcount, bbox_u, cube, theta2, box, start, cap, sel, nsel);
     return hipGetLastError();
 }
 
-hipError_t exchange_caps(size_t P, const uint32_t *ne, const uint32_t *ns, uint32_t *cap,
-                         hipStream_t s) {
-    if (!P) return hipSuccess;
-    size_t b = (P + kThreads - 1) / kThreads;
+hipError_t exchange_caps(size_t G, const uint32_t *sel, const uint32_t *nsel, const uint32_t *ne,
+                         const uint32_t *ns, uint32_t *cap, hipStream_t s) {
+    if (!G) return hipSuccess;
+    size_t b = (G + kThreads - 1) / kThreads;
     b = b > 4096 ? 4096 : b;
-    hipLaunchKernelGGL(k_exchange_caps, dim3((unsigned)b), dim3(kThreads), 0, s, P, ne, ns, cap);
+    hipLaunchKernelGGL(k_exchange_caps, dim3((unsigned)b), dim3(kThreads), 0, s, G, sel, nsel, ne,
+                       ns, cap);
     return hipGetLastError();
 }
 
