@@ -72,6 +72,13 @@ def _declare(L):
     L.or_force.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp]
     L.or_exchange.argtypes = [vp, i64, vp, vp, vp, f64, vp]
     L.or_exchange.restype = vp
+    L.or_wendland_c6.argtypes = [f64, f64]
+    L.or_wendland_c6.restype = f64
+    L.or_density_brute.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, f64, vp, vp]
+    L.or_cell_hmax.argtypes = [vp, vp, vp]
+    L.or_short_walk.argtypes = [vp, i64, vp, vp, vp, i32, vp, vp, vp, vp]
+    L.or_short_walk.restype = vp
+    L.or_density_lists.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i32, f64, vp, vp]
 
 
 def _c(a, dt):
@@ -394,6 +401,85 @@ def list_force(x, y, z, eps, jx, jy, jz, jm, mom, quad: bool = True, self_mask=N
         out[:, 2] += az.sum(axis=1)
         out[:, 3] += ph.sum(axis=1)
     return out
+
+
+# ----------------------------------------------------------------------------------------
+# Short-range neighbour lists and SPH density (readings at or_density_brute in oracle.c)
+
+CUT_FIXED, CUT_SCATTER, CUT_GATHER, CUT_SYMMETRIC = 0, 1, 2, 3
+
+
+def wendland_c6(r: float, H: float) -> float:
+    return lib().or_wendland_c6(float(r), float(H))
+
+
+def density_brute(ps, h, mode: int, r_cut: float = 0.0):
+    """(rho, n_ngb) of every particle by all pairs of its system, caller's order."""
+    rho = np.zeros(ps.n)
+    n = np.zeros(ps.n, np.uint32)
+    hh = None if h is None else _c(h, np.float64)
+    lib().or_density_brute(ps.n_sys, _p(_c(ps.offsets(), np.int64)), _p(_c(ps.x, np.float64)),
+                           _p(_c(ps.y, np.float64)), _p(_c(ps.z, np.float64)),
+                           _p(_c(ps.m, np.float64)), None if hh is None else _p(hh), int(mode),
+                           float(r_cut), _p(rho), _p(n))
+    return rho, n
+
+
+class ShortLists:
+    """Candidate neighbour lists of every group (sorted particle positions) for one cutoff
+    mode, and the density / neighbour count they give."""
+
+    def __init__(self, tree: Tree, grp: Groups, h, mode: int, r_cut: float = 0.0):
+        L = lib()
+        self.tree, self.grp, self.mode, self.r_cut = tree, grp, int(mode), float(r_cut)
+        self.sh = None if h is None else _c(np.asarray(h)[tree.perm.astype(np.int64)], np.float64)
+        self.hmax = None
+        if mode in (CUT_SCATTER, CUT_SYMMETRIC):
+            self.hmax = np.zeros(tree.n_cells)
+            L.or_cell_hmax(tree._h, _p(self.sh), _p(self.hmax))
+        rg = np.full(grp.n, self.r_cut)
+        if mode in (CUT_GATHER, CUT_SYMMETRIC):
+            rg = np.array([self.sh[b:b + c].max() for b, c in zip(grp.begin, grp.count)])
+        self.rg = _c(rg, np.float64)
+        counts = np.zeros(grp.n, np.int64)
+        self._h = L.or_short_walk(tree._h, grp.n, _p(grp.root), _p(grp.qmin), _p(grp.qmax),
+                                  self.mode, _p(self.rg),
+                                  None if self.hmax is None else _p(self.hmax),
+                                  _p(_c(tree.cube, np.float64)), _p(counts))
+        self.n_epj = counts
+        self.epj_off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+        self.epj = np.zeros(int(self.epj_off[-1]), np.uint32)
+        dummy = np.zeros(1, np.uint32)
+        L.or_walk_export(self._h, _p(self.epj), _p(dummy))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().or_walk_free(h)
+            self._h = None
+
+    def group_list(self, k: int):
+        return self.epj[self.epj_off[k]:self.epj_off[k + 1]]
+
+    def density(self):
+        """(rho, n_ngb) at sorted positions."""
+        t, g = self.tree, self.grp
+        rho = np.full(t.ps.n, np.nan)
+        n = np.zeros(t.ps.n, np.uint32)
+        lib().or_density_lists(self._h, _p(g.begin), _p(g.count), _p(t.sx), _p(t.sy), _p(t.sz),
+                               _p(t.sm), None if self.sh is None else _p(self.sh), self.mode,
+                               self.r_cut, _p(rho), _p(n))
+        return rho, n
+
+
+def short_lists(tree: Tree, grp: Groups, h, mode: int, r_cut: float = 0.0) -> ShortLists:
+    return ShortLists(tree, grp, h, mode, r_cut)
+
+
+def nlist_short_model(n_grp: float, r_cut: float, mean_spacing: float) -> float:
+    """Short-range interaction-list length, equation nlist_short of section "Tree traverse
+    and interaction calculation"."""
+    return (n_grp ** (1.0 / 3.0) - 1.0 + 2.0 * r_cut / mean_spacing) ** 3
 
 
 def exchange_list_model(n: float, theta: float, n_p: float) -> float:

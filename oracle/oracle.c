@@ -555,3 +555,158 @@ void or_force(void *wh, const int64_t *gsel, const uint32_t *gbegin, const uint3
         }
     }
 }
+
+/* ------------------------------------------------------------------------------------ */
+/* Short-range neighbour lists and SPH density.  The same tree is traversed for short-range
+ * interactions, with four kinds of cutoff length: fixed, j-dependent, i-dependent and
+ * symmetric (section "Interaction calculation"); the paper's SPH application uses the
+ * Wendland C6 kernel with a cutoff of 4.2 mean interparticle distances, about 300
+ * neighbours (section "Giant impact simulation"), and models the list length by equation
+ * nlist_short.  Readings:
+ *   mode 0 fixed (a pair interacts if r < r_cut), 1 j-dependent "scatter" (r < h_j),
+ *   2 i-dependent "gather" (r < h_i), 3 symmetric (r < max(h_i, h_j));
+ *   candidate list of a group = the particles of every leaf the walk opens, where a cell is
+ *   opened iff the distance between the group's integer box [2 qmin, 2 qmax + 2] and the
+ *   cell's cube [C - 2^(21-l), C + 2^(21-l)] (half-grid units, exact integers) satisfies
+ *   D^2 <= R^2, R = r * (2^22 / Lr) the search radius in half-grid units (an exact scaling of
+ *   the physical radius r, one rounding in R * R); r = r_cut (fixed), the largest h of the
+ *   group (gather), the largest h in the cell (scatter), the larger of the two (symmetric);
+ *   rho_i = sum_j m_j W(|r_ij|, H) over pairs with |r_ij| < H, j = i included, H = r_cut
+ *   (fixed), h_i (gather), h_j (scatter); symmetric: the mean of the gather and the scatter
+ *   sums; n_i = number of j (i included) with |r_ij| < H, symmetric H = max(h_i, h_j);
+ *   |r_ij|^2 = dx*dx + dy*dy + dz*dz rounded as written, compared with H*H.
+ * Wendland C6 kernel (Dehnen & Aly 2012) in three dimensions, q = r / H < 1:
+ *   W = 1365 / (64 pi H^3) (1 - q)^8 (1 + 8 q + 25 q^2 + 32 q^3). */
+double or_wendland_c6(double r, double H) {
+    double q = r / H;
+    if (q >= 1.0) return 0.0;
+    double u = 1.0 - q, u2 = u * u, u4 = u2 * u2, u8 = u4 * u4;
+    const double pi = 3.14159265358979323846;
+    return 1365.0 / (64.0 * pi * H * H * H) * u8 * (1.0 + 8.0 * q + 25.0 * q * q + 32.0 * q * q * q);
+}
+
+static double pair_r2(double dx, double dy, double dz) { return dx * dx + dy * dy + dz * dz; }
+
+/* one pair's contribution: adds to rho and counts the neighbour */
+static void sph_pair(int32_t mode, double r_cut, double r2, double mj, double hi, double hj,
+                     nsum *rho, uint32_t *n) {
+    double r = sqrt(r2);
+    if (mode == 0) {
+        if (r2 < r_cut * r_cut) { nadd(rho, mj * or_wendland_c6(r, r_cut)); (*n)++; }
+    } else if (mode == 1) {
+        if (r2 < hj * hj) { nadd(rho, mj * or_wendland_c6(r, hj)); (*n)++; }
+    } else if (mode == 2) {
+        if (r2 < hi * hi) { nadd(rho, mj * or_wendland_c6(r, hi)); (*n)++; }
+    } else {
+        double w = 0.0;
+        if (r2 < hi * hi) w += or_wendland_c6(r, hi);
+        if (r2 < hj * hj) w += or_wendland_c6(r, hj);
+        if (w > 0.0) nadd(rho, 0.5 * mj * w);
+        double H = hi > hj ? hi : hj;
+        if (r2 < H * H) (*n)++;
+    }
+}
+
+/* brute force over all pairs of each system (inputs in any order, per system contiguous) */
+void or_density_brute(int64_t nsys, const int64_t *off, const double *x, const double *y,
+                      const double *z, const double *m, const double *h, int32_t mode,
+                      double r_cut, double *rho, uint32_t *nngb) {
+    for (int64_t s = 0; s < nsys; s++) {
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t i = off[s]; i < off[s + 1]; i++) {
+            nsum acc = {0, 0};
+            uint32_t n = 0;
+            double hi = h ? h[i] : r_cut;
+            for (int64_t j = off[s]; j < off[s + 1]; j++) {
+                double hj = h ? h[j] : r_cut;
+                sph_pair(mode, r_cut, pair_r2(x[j] - x[i], y[j] - y[i], z[j] - z[i]), m[j], hi, hj,
+                         &acc, &n);
+            }
+            rho[i] = nval(&acc);
+            nngb[i] = n;
+        }
+    }
+}
+
+/* largest h of every cell's particles (sorted order) */
+void or_cell_hmax(void *h, const double *sh, double *hmax) {
+    const or_cells *t = (const or_cells *)h;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t c = 0; c < t->ncell; c++) {
+        double v = 0.0;
+        for (uint32_t i = t->begin[c]; i < t->begin[c] + t->count[c]; i++) v = sh[i] > v ? sh[i] : v;
+        hmax[c] = v;
+    }
+}
+
+static void short_visit(const or_cells *t, uint32_t c, const int64_t *lo, const int64_t *hi,
+                        int32_t mode, double rg, const double *hmax, double scale, u32vec *epj) {
+    if (t->count[c] == 0) return;
+    uint32_t cq[3];
+    int32_t l = t->level[c];
+    deinterleave(t->prefix[c] << (3 * (OR_LEVELS - l)), &cq[0], &cq[1], &cq[2]);
+    double D2 = 0.0;
+    int64_t half = (int64_t)1 << (OR_LEVELS - l);
+    for (int a = 0; a < 3; a++) {
+        int64_t C = 2 * (int64_t)cq[a] + half;
+        int64_t bmin = 2 * lo[a], bmax = 2 * hi[a] + 2;
+        int64_t d = 0;
+        if (bmin - (C + half) > d) d = bmin - (C + half);
+        if ((C - half) - bmax > d) d = (C - half) - bmax;
+        D2 += (double)(d * d);
+    }
+    double r = mode == 1 ? hmax[c] : (mode == 3 && hmax[c] > rg ? hmax[c] : rg);
+    double R = r * scale;
+    if (D2 > R * R) return;
+    if (t->nchild[c] == 0) {
+        for (uint32_t i = t->begin[c]; i < t->begin[c] + t->count[c]; i++) vpush(epj, i);
+        return;
+    }
+    for (uint32_t k = 0; k < t->nchild[c]; k++)
+        short_visit(t, t->first_child[c] + k, lo, hi, mode, rg, hmax, scale, epj);
+}
+
+/* Candidate lists of all groups (counts[g] = length); rg[g] = the group's search radius for
+ * modes 0, 2, 3 (r_cut, or its largest h); hmax per cell for modes 1, 3; cube per system. */
+void *or_short_walk(void *h, int64_t ng, const uint32_t *groot, const uint32_t *qmin,
+                    const uint32_t *qmax, int32_t mode, const double *rg, const double *hmax,
+                    const double *cube, int64_t *counts) {
+    const or_cells *t = (const or_cells *)h;
+    walk_res *w = (walk_res *)calloc(1, sizeof(walk_res));
+    w->nsel = ng;
+    w->epj = (u32vec *)calloc((size_t)(ng > 0 ? ng : 1), sizeof(u32vec));
+    w->spj = (u32vec *)calloc((size_t)(ng > 0 ? ng : 1), sizeof(u32vec));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t g = 0; g < ng; g++) {
+        int64_t lo[3], hi[3];
+        for (int a = 0; a < 3; a++) { lo[a] = qmin[3 * g + a]; hi[a] = qmax[3 * g + a]; }
+        double scale = 4194304.0 / cube[4 * (size_t)groot[g] + 3];
+        short_visit(t, groot[g], lo, hi, mode, rg ? rg[g] : 0.0, hmax, scale, &w->epj[g]);
+        counts[g] = w->epj[g].n;
+    }
+    return w;
+}
+
+/* Density and neighbour count of every particle of every group from its candidate list
+ * (inputs in sorted order, outputs at sorted positions). */
+void or_density_lists(void *wh, const uint32_t *gbegin, const uint32_t *gcount, const double *sx,
+                      const double *sy, const double *sz, const double *sm, const double *sh,
+                      int32_t mode, double r_cut, double *rho, uint32_t *nngb) {
+    walk_res *w = (walk_res *)wh;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t g = 0; g < w->nsel; g++) {
+        for (uint32_t i = gbegin[g]; i < gbegin[g] + gcount[g]; i++) {
+            nsum acc = {0, 0};
+            uint32_t n = 0;
+            double hi = sh ? sh[i] : r_cut;
+            for (int64_t t = 0; t < w->epj[g].n; t++) {
+                uint32_t j = w->epj[g].v[t];
+                double hj = sh ? sh[j] : r_cut;
+                sph_pair(mode, r_cut, pair_r2(sx[j] - sx[i], sy[j] - sy[i], sz[j] - sz[i]), sm[j], hi,
+                         hj, &acc, &n);
+            }
+            rho[i] = nval(&acc);
+            nngb[i] = n;
+        }
+    }
+}
