@@ -250,6 +250,36 @@ int fdx_get_exchange_counts(fdx_ctx *ctx, uint32_t *n_epj, uint32_t *n_spj);
 int fdx_get_exchange_lists(fdx_ctx *ctx, uint32_t *epj, uint32_t *spj);
 int fdx_get_exchange_stats(fdx_ctx *ctx, fdx_exchange_stats *out);
 
+/* ---- Short-range neighbour lists and SPH density ---------------------------------------
+ * The same tree is traversed for short-range interactions with four kinds of cutoff
+ * (section "Interaction calculation"): fixed (pairs with r < r_cut), j-dependent
+ * (FDX_CUT_SCATTER: r < h_j), i-dependent (FDX_CUT_GATHER: r < h_i) and symmetric
+ * (r < max(h_i, h_j)); equation nlist_short models the list length.  For every group the walk
+ * keeps the particles of each leaf whose cube lies within the search radius of the group's
+ * box (r_cut, the group's largest h, the cell's largest h, or the larger of the two), and the
+ * density kernel evaluates, for every particle,
+ *   rho_i = sum_j m_j W(|r_ij|, H) over pairs with |r_ij| < H (j = i included),
+ *   H = r_cut (fixed), h_j (scatter), h_i (gather); symmetric: the mean of the gather and
+ *   the scatter sums; n_ngb_i = number of such j (symmetric: |r_ij| < max(h_i, h_j)),
+ * with the Wendland C6 kernel of the paper's SPH application (section "Giant impact
+ * simulation"), q = r/H < 1: W = 1365/(64 pi H^3) (1-q)^8 (1 + 8q + 25q^2 + 32q^3).  FP64;
+ * neighbour counts are exact.
+ * fdx_calc_density: mode FDX_CUT_*; r_cut (fixed mode, finite > 0); h = support radius of
+ *   every particle, caller's order, length n, in host or device memory (mem_kind; ignored in
+ *   fixed mode); n_leaf, n_group as for the tree; flags: FDX_TIMING (phase times in
+ *   fdx_get_stats: t_walk = walk, t_force = density).  The candidate lists stay readable with
+ *   fdx_get_lists (no superparticles).  FDX_EINVAL: bad mode, r_cut, h (null, non-positive or
+ *   non-finite), n_leaf or n_group; FDX_ESTATE: no particles.
+ * fdx_get_density: rho and n_ngb (length n each, caller's order, null skips).  FDX_ESTATE if
+ *   none was computed since the last fdx_set_particles. */
+#define FDX_CUT_FIXED 0
+#define FDX_CUT_SCATTER 1
+#define FDX_CUT_GATHER 2
+#define FDX_CUT_SYMMETRIC 3
+int fdx_calc_density(fdx_ctx *ctx, int32_t mode, double r_cut, const double *h, int32_t mem_kind,
+                     int32_t n_leaf, int32_t n_group, int32_t flags);
+int fdx_get_density(fdx_ctx *ctx, double *rho, uint32_t *n_ngb, int32_t mem_kind);
+
 /* Message of the last failed call on ctx (never null; "" when none). */
 const char *fdx_last_error(const fdx_ctx *ctx);
 

@@ -158,6 +158,7 @@ int enqueue_tree_groups(fdx_ctx *c) {
 // Tree part of one evaluation with host checks: retries with larger cell / group capacity
 // when the device reports an overflow.  Leaves the status (group count, levels) in c->hst.
 int run_tree(fdx_ctx *c, bool sync) {
+    c->have_lists = false;
     int r = enqueue_keys_sort(c);
     if (r) return r;
     for (int attempt = 0;; attempt++) {
@@ -269,6 +270,7 @@ int run_force(fdx_ctx *c) {
         c->stats.list_capacity = (int64_t)total;
         c->stats.overflow_groups = 0;
     }
+    c->have_lists = true;
     r = enqueue_force(c, G);
     if (r) return r;
     c->have_force = true;
@@ -431,6 +433,7 @@ int fdx_set_particles(fdx_ctx *c, int64_t n, const double *x, const double *y, c
     }
     c->have_particles = false;
     c->have_force = false;
+    c->have_lists = false;
     c->gen++;
     ext_invalidate(c);
     c->n = n;
@@ -624,7 +627,7 @@ int fdx_get_groups(fdx_ctx *c, uint32_t *cell, uint32_t *begin, uint32_t *count,
 
 int fdx_get_lists(fdx_ctx *c, uint32_t *n_epj, uint32_t *n_spj, uint32_t *epj, uint32_t *spj) {
     if (!c) return FDX_EINVAL;
-    if (!c->have_force) return fail(c, FDX_ESTATE, "no walk done");
+    if (!c->have_lists) return fail(c, FDX_ESTATE, "no walk done on the current groups");
     hipStream_t s = c->stream;
     const size_t G = (size_t)c->stats.n_groups;
     std::vector<uint32_t> ce(G), cs(G), cap(G);

@@ -93,6 +93,7 @@ struct fdx_ctx {
     fdx::DBuf<double4> fs;
     fdx::DBuf<double> ax, ay, az, pot;
     bool have_force = false;
+    bool have_lists = false;       // the lists belong to the current groups (last walk)
 
     // status
     fdx::DevStatus *st = nullptr;

@@ -136,10 +136,38 @@ hipError_t exchange_caps(size_t G, const uint32_t *sel, const uint32_t *nsel, co
                          const uint32_t *ns, uint32_t *cap, hipStream_t s);
 size_t exchange_subwalks(int nsys);
 constexpr int kExchangeFrontierMax = 64;
+// short-range walks: search radius per group (rg, or r_fixed for every group when rg is
+// null), largest support radius per cell (hmax), root cube per system (cube)
+struct ShortArgs {
+    const double *rg = nullptr;
+    const double *hmax = nullptr;
+    const double *cube = nullptr;
+    double r_fixed = 0.0;
+};
 hipError_t walk(bool fill, size_t gmax, const Groups g, const Cells c, double theta2,
                 const uint64_t *seg, const uint32_t *cap, uint64_t list_cap, uint32_t *list,
                 uint32_t *cnt_e, uint32_t *cnt_s, uint32_t *ovf_list, const uint32_t *sel,
                 const uint32_t *nsel, DevStatus *st, hipStream_t s);
+// short-range walk (kind 1: group radius, 2: cell radius, 3: the larger), no superparticles
+hipError_t walk_short(bool fill, int kind, size_t gmax, const Groups g, const Cells c,
+                      const ShortArgs sa, const uint64_t *seg, const uint32_t *cap,
+                      uint64_t list_cap, uint32_t *list, uint32_t *cnt_e, uint32_t *cnt_s,
+                      uint32_t *ovf_list, DevStatus *st, hipStream_t s);
+// SPH density on short-range lists (k_sph.hip): support radii in sorted order (h given, else
+// r_fixed; a non-positive or non-finite radius sets bad_input), largest radius per cell
+// (bottom-up) and per group, density and neighbour count per sorted particle (mode 0 fixed,
+// 1 scatter, 2 gather, 3 symmetric), and their return to the caller's order
+hipError_t sph_radius(size_t n, const uint32_t *perm, const double *h, double r_fixed,
+                      double *sh, DevStatus *st, hipStream_t s);
+hipError_t sph_cell_hmax(const Cells c, const double *sh, double *hmax, hipStream_t s);
+hipError_t sph_group_hmax(size_t gmax, const Groups g, const double *sh, double *rg,
+                          DevStatus *st, hipStream_t s);
+hipError_t sph_density(int mode, size_t gmax, const Groups g, const uint64_t *seg,
+                       const uint32_t *cnt_e, const uint32_t *list, const double4 *jp,
+                       const double *sh, double *rho_s, uint32_t *n_s, DevStatus *st,
+                       hipStream_t s);
+hipError_t sph_unsort(size_t n, const uint32_t *inv, const double *rho_s, const uint32_t *n_s,
+                      double *rho, uint32_t *nngb, hipStream_t s);
 // queue order for the persistent force kernel: groups by decreasing estimated cost
 hipError_t queue_keys(size_t gmax, const Groups g, const uint32_t *cnt_e, const uint32_t *cnt_s,
                       uint64_t *key, uint32_t *val, DevStatus *st, hipStream_t s);

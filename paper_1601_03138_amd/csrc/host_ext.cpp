@@ -182,6 +182,7 @@ void ext_release(fdx_ctx *c) {
     }
     predictor_release(c);
     exchange_release(c);
+    sph_release(c);
 }
 
 }  // namespace fdx

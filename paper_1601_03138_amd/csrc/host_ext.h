@@ -15,6 +15,7 @@ struct HostExt {
     void *pred = nullptr;             // predictor state (weights, normalisation)
     void *graph = nullptr;            // captured step (GraphState)
     void *exch = nullptr;             // exchange lists between domains
+    void *sph = nullptr;              // SPH density state
     int64_t graph_recoveries = 0;     // replays whose capacities overflowed and were redone
 };
 
@@ -25,5 +26,6 @@ void ext_release(fdx_ctx *c);
 void ext_invalidate(fdx_ctx *c);   // drop any captured graph (particles or buffers changed)
 int ext_predicted_walk(fdx_ctx *c, uint32_t G);
 void exchange_release(fdx_ctx *c);
+void sph_release(fdx_ctx *c);
 
 }  // namespace fdx

@@ -40,13 +40,33 @@ __device__ __forceinline__ bool cell_accepted(const uint4 nd, int bminx, int bmi
     return S2 < __dmul_rn(theta2, D2);
 }
 
-template <bool FILL>
+// Short-range walks (the same tree traversed with a cutoff instead of an opening angle): a
+// cell is dropped iff the distance between the box and the cell's cube exceeds the search
+// radius, in half-grid units D^2 > R^2 with R = r * 2^22 / Lr (an exact scaling of the
+// physical radius r, one rounding in R * R); kept cells are opened and kept leaves give
+// their particles as candidates.
+__device__ __forceinline__ bool cell_far(const uint4 nd, int bminx, int bminy, int bminz,
+                                         int bmaxx, int bmaxy, int bmaxz, double R2) {
+    const int half = 1 << (kLevels - (int)(nd.w & 0xFFu));
+    const int cx = (int)nd.x, cy = (int)nd.y, cz = (int)nd.z;
+    const int dx = max(0, max(bminx - (cx + half), (cx - half) - bmaxx));
+    const int dy = max(0, max(bminy - (cy + half), (cy - half) - bmaxy));
+    const int dz = max(0, max(bminz - (cz + half), (cz - half) - bmaxz));
+    const double D2 = (double)dx * (double)dx + (double)dy * (double)dy +
+                      (double)dz * (double)dz;
+    return D2 > R2;
+}
+
+// KIND 0: gravity (opening angle; accepted cells are superparticles).  Short range, search
+// radius r: 1 the group's radius (fixed cutoff or the group's largest h), 2 the cell's largest
+// h (scatter), 3 the larger of the two (symmetric).
+template <bool FILL, int KIND>
 __global__ void __launch_bounds__(kThreads)
 k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, uint32_t ccap,
        double theta2,
        const uint64_t *seg, const uint32_t *cap, uint64_t list_cap, uint32_t *list,
        uint32_t *cnt_e, uint32_t *cnt_s, uint32_t *ovf_list, const uint32_t *sel,
-       const uint32_t *nsel, DevStatus *st) {
+       const uint32_t *nsel, DevStatus *st, ShortArgs sa) {
     __shared__ uint32_t stack_all[kWaves][kWalkStack];
     const int w = threadIdx.x / kWave, lane = lane_id();
     const uint64_t lt = lanemask_lt();
@@ -62,6 +82,13 @@ k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, 
         const uint32_t capg = FILL && seg_ok ? cap[gi] : 0;
         uint32_t ne = 0, ns = 0, sp = 1;
         bool err = false;
+        double scale = 0.0, rg = 0.0, Rg2 = 0.0;
+        if (KIND != 0) {
+            scale = 4194304.0 / sa.cube[4 * (size_t)g.sys[gi] + 3];    // exact: Lr = 2^k
+            rg = sa.rg ? sa.rg[gi] : sa.r_fixed;
+            const double R = __dmul_rn(rg, scale);
+            Rg2 = __dmul_rn(R, R);
+        }
         if (lane == 0) stk[0] = g.sys[gi];          // roots are cells 0..nsys-1
         wave_barrier();
         while (sp > 0) {
@@ -79,18 +106,31 @@ k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, 
             const uint4 nd = node[cid];
             const uint2 lk = link[cid];
             const uint32_t nch = nd.w >> 8;
-            const bool accept =
-                act && cell_accepted(nd, bminx, bminy, bminz, bmaxx, bmaxy, bmaxz, theta2);
+            bool accept;
+            if (KIND == 0) {
+                accept = act && cell_accepted(nd, bminx, bminy, bminz, bmaxx, bmaxy, bmaxz, theta2);
+            } else {
+                double R2 = Rg2;
+                if (KIND != 1) {
+                    const double hm = sa.hmax[cid];
+                    const double r = (KIND == 2 || hm > rg) ? hm : rg;
+                    const double R = __dmul_rn(r, scale);
+                    R2 = __dmul_rn(R, R);
+                }
+                accept = act && cell_far(nd, bminx, bminy, bminz, bmaxx, bmaxy, bmaxz, R2);
+            }
             const bool open = act && !accept;
             const bool leaf = open && nch == 0 && lk.y > 0;
             const bool inner = open && nch != 0;
             // superparticles, from the back of the segment
-            const uint64_t bs = __ballot(accept);
-            if (FILL && accept) {
-                const uint32_t j = ns + (uint32_t)__popcll(bs & lt);
-                if (j < capg) list[base + capg - 1 - j] = cid;
+            if (KIND == 0) {
+                const uint64_t bs = __ballot(accept);
+                if (FILL && accept) {
+                    const uint32_t j = ns + (uint32_t)__popcll(bs & lt);
+                    if (j < capg) list[base + capg - 1 - j] = cid;
+                }
+                ns += (uint32_t)__popcll(bs);
             }
-            ns += (uint32_t)__popcll(bs);
             // particles of opened leaves (front of the segment) and children of opened
             // internal cells (stack): offsets from one prefix sum of both counts packed in a
             // word (children, at most 8 per lane, in bits 22-31), unless a leaf holds 2^16
@@ -323,18 +363,43 @@ hipError_t exchange_caps(size_t G, const uint32_t *sel, const uint32_t *nsel, co
     return hipGetLastError();
 }
 
+template <int KIND>
+static void launch_walk(bool fill, size_t gmax, const Groups &g, const Cells &c, double theta2,
+                        const uint64_t *seg, const uint32_t *cap, uint64_t list_cap,
+                        uint32_t *list, uint32_t *cnt_e, uint32_t *cnt_s, uint32_t *ovf_list,
+                        const uint32_t *sel, const uint32_t *nsel, DevStatus *st,
+                        const ShortArgs &sa, hipStream_t s) {
+    if (fill)
+        hipLaunchKernelGGL((k_walk<true, KIND>), dim3(grid_waves(gmax)), dim3(kThreads), 0, s,
+                           &st->n_groups, g, c.node, c.link, c.cap, theta2, seg, cap, list_cap,
+                           list, cnt_e, cnt_s, ovf_list, sel, nsel, st, sa);
+    else
+        hipLaunchKernelGGL((k_walk<false, KIND>), dim3(grid_waves(gmax)), dim3(kThreads), 0, s,
+                           &st->n_groups, g, c.node, c.link, c.cap, theta2, seg, cap, list_cap,
+                           list, cnt_e, cnt_s, ovf_list, sel, nsel, st, sa);
+}
+
 hipError_t walk(bool fill, size_t gmax, const Groups g, const Cells c, double theta2,
                 const uint64_t *seg, const uint32_t *cap, uint64_t list_cap, uint32_t *list,
                 uint32_t *cnt_e, uint32_t *cnt_s, uint32_t *ovf_list, const uint32_t *sel,
                 const uint32_t *nsel, DevStatus *st, hipStream_t s) {
-    if (fill)
-        hipLaunchKernelGGL(k_walk<true>, dim3(grid_waves(gmax)), dim3(kThreads), 0, s,
-                           &st->n_groups, g, c.node, c.link, c.cap, theta2, seg, cap, list_cap, list,
-                           cnt_e, cnt_s, ovf_list, sel, nsel, st);
-    else
-        hipLaunchKernelGGL(k_walk<false>, dim3(grid_waves(gmax)), dim3(kThreads), 0, s,
-                           &st->n_groups, g, c.node, c.link, c.cap, theta2, seg, cap, list_cap, list,
-                           cnt_e, cnt_s, ovf_list, sel, nsel, st);
+    launch_walk<0>(fill, gmax, g, c, theta2, seg, cap, list_cap, list, cnt_e, cnt_s, ovf_list,
+                   sel, nsel, st, ShortArgs{}, s);
+    return hipGetLastError();
+}
+
+hipError_t walk_short(bool fill, int kind, size_t gmax, const Groups g, const Cells c,
+                      const ShortArgs sa, const uint64_t *seg, const uint32_t *cap,
+                      uint64_t list_cap, uint32_t *list, uint32_t *cnt_e, uint32_t *cnt_s,
+                      uint32_t *ovf_list, DevStatus *st, hipStream_t s) {
+    switch (kind) {
+        case 1: launch_walk<1>(fill, gmax, g, c, 0.0, seg, cap, list_cap, list, cnt_e, cnt_s,
+                               ovf_list, nullptr, nullptr, st, sa, s); break;
+        case 2: launch_walk<2>(fill, gmax, g, c, 0.0, seg, cap, list_cap, list, cnt_e, cnt_s,
+                               ovf_list, nullptr, nullptr, st, sa, s); break;
+        default: launch_walk<3>(fill, gmax, g, c, 0.0, seg, cap, list_cap, list, cnt_e, cnt_s,
+                                ovf_list, nullptr, nullptr, st, sa, s); break;
+    }
     return hipGetLastError();
 }
 

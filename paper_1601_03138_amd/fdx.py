@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libfdx.so")
 OK, EINVAL, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4
 MEM_HOST, MEM_DEVICE = 0, 1
 QUAD, FP32REL, PREDICTOR, PERSISTENT, GRAPH, TIMING = 1, 2, 4, 8, 16, 32
+CUT_FIXED, CUT_SCATTER, CUT_GATHER, CUT_SYMMETRIC = 0, 1, 2, 3
 
 EXPORTS = ["fdx_create", "fdx_destroy", "fdx_set_particles", "fdx_build_tree", "fdx_calc_force",
            "fdx_integrate", "fdx_get_particles", "fdx_get_forces", "fdx_get_stats",
@@ -26,7 +27,7 @@ EXPORTS = ["fdx_create", "fdx_destroy", "fdx_set_particles", "fdx_build_tree", "
            "fdx_predictor_features", "fdx_mlp_forward", "fdx_mlp_grad", "fdx_predictor_train",
            "fdx_predictor_margin", "fdx_predictor_save", "fdx_predictor_load",
            "fdx_build_exchange_lists", "fdx_get_exchange_counts", "fdx_get_exchange_lists",
-           "fdx_get_exchange_stats"]
+           "fdx_get_exchange_stats", "fdx_calc_density", "fdx_get_density"]
 
 
 class FdxError(RuntimeError):
@@ -111,6 +112,8 @@ def _declare(L):
     L.fdx_get_exchange_counts.argtypes = [vp, vp, vp]
     L.fdx_get_exchange_lists.argtypes = [vp, vp, vp]
     L.fdx_get_exchange_stats.argtypes = [vp, C.POINTER(ExchangeStats)]
+    L.fdx_calc_density.argtypes = [vp, i32, f64, vp, i32, i32, i32, i32]
+    L.fdx_get_density.argtypes = [vp, vp, vp, i32]
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -322,6 +325,30 @@ class Context:
         st = ExchangeStats()
         self._check(self.lib.fdx_get_exchange_stats(self.h, C.byref(st)), "get_exchange_stats")
         return st.as_dict()
+
+    # -- short-range neighbour lists and SPH density -------------------------------------
+    def calc_density(self, mode: int, r_cut: float = 0.0, h=None, n_leaf: int = 8,
+                     n_group: int = 64, timing: bool = False):
+        """h: per-particle support radius (numpy array, caller's order) or a device tensor."""
+        hp, kind = None, MEM_HOST
+        if h is not None:
+            if hasattr(h, "data_ptr"):
+                hp, kind = _dptr(h), MEM_DEVICE
+                self._keep = [h]
+            else:
+                hh = _f64(h)
+                self._keep = [hh]
+                hp = _ptr(hh)
+        self._check(self.lib.fdx_calc_density(self.h, int(mode), float(r_cut), hp, kind,
+                                              int(n_leaf), int(n_group),
+                                              TIMING if timing else 0), "calc_density")
+
+    def density(self):
+        """(rho, n_ngb) in the caller's order."""
+        rho = np.empty(self.n)
+        n = np.empty(self.n, np.uint32)
+        self._check(self.lib.fdx_get_density(self.h, _ptr(rho), _ptr(n), MEM_HOST), "get_density")
+        return rho, n
 
     # -- learned list-length predictor -----------------------------------------------------
     def predictor_features(self) -> np.ndarray:
