@@ -151,6 +151,9 @@ def main():
     ap.add_argument("--exchange-domains", type=int, default=4,
                     help="also time the exchange lists of the input cut into k x k x k "
                          "equal-count domains (0: skip)")
+    ap.add_argument("--sph-log2n", type=int, default=24,
+                    help="also time the SPH density (fixed cutoff of 4.2 mean spacings, uniform "
+                         "cube of 2^k particles; 0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -354,6 +357,35 @@ def main():
             del tr
         log(f"[bench] exchange lists: {exch}")
 
+    # SPH density: short-range neighbour lists (fixed cutoff) + Wendland C6 density, FP64
+    sph = None
+    if args.sph_log2n > 0:
+        from paper_1601_03138_amd import sph_timing
+        sps, r_cut, _ = sph_timing.workload(args.sph_log2n, 4.2, fdx.CUT_FIXED)
+        cs = fdx.Context(0)
+        cs.set_particles(sps)
+        cs.calc_density(fdx.CUT_FIXED, r_cut, n_group=64, timing=True)
+        rows = []
+        for _ in range(3):
+            cs.calc_density(fdx.CUT_FIXED, r_cut, n_group=64, timing=True)
+            ss = cs.stats()
+            rows.append((ss["t_walk"], ss["t_force"], ss["t_total"]))
+        _, nngb = cs.density()
+        med = np.median(np.array(rows), axis=0)
+        spacing = sps.n ** (-1.0 / 3.0)
+        n_grp = sps.n / max(1, int(ss["n_groups"]))
+        sph = {"n": sps.n, "cutoff": "fixed, 4.2 mean spacings", "n_group": 64,
+               "ms_walk": round(float(med[0]), 3), "ms_density": round(float(med[1]), 3),
+               "ms_total": round(float(med[2]), 3),
+               "particles_per_s": float(round(sps.n / (med[2] / 1e3), -5)),
+               "pair_tests_per_s": float(round(int(ss["n_interactions_pp"]) / (med[1] / 1e3), -8)),
+               "mean_neighbours": round(float(nngb.mean()), 1),
+               "mean_candidates_per_group": round(int(ss["n_epj"]) / int(ss["n_groups"]), 1),
+               "model_eq_nlist_short": round((n_grp ** (1 / 3) - 1 + 2 * r_cut / spacing) ** 3, 1)}
+        cs.close()
+        del sps
+        log(f"[bench] sph: {sph}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
@@ -394,6 +426,7 @@ def main():
         "phases_ms": phase_ms,
         "phase_gbs": phase_gbs,
         "exchange": exch,
+        "sph": sph,
         "energy_drift": drift,
         "predictor": pred,
         "autotune": tuned,
