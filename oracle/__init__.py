@@ -79,6 +79,12 @@ def _declare(L):
     L.or_short_walk.argtypes = [vp, i64, vp, vp, vp, i32, vp, vp, vp, vp]
     L.or_short_walk.restype = vp
     L.or_density_lists.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i32, f64, vp, vp]
+    L.or_s2_cutoff.argtypes = [f64]
+    L.or_s2_cutoff.restype = f64
+    L.or_direct_cutoff.argtypes = [i64, vp, vp, vp, vp, vp, vp, f64, vp]
+    L.or_walk_cutoff.argtypes = [vp, i64, vp, vp, vp, f64, f64, vp, vp]
+    L.or_walk_cutoff.restype = vp
+    L.or_force_cutoff.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, f64, vp]
 
 
 def _c(a, dt):
@@ -480,6 +486,67 @@ def nlist_short_model(n_grp: float, r_cut: float, mean_spacing: float) -> float:
     """Short-range interaction-list length, equation nlist_short of section "Tree traverse
     and interaction calculation"."""
     return (n_grp ** (1.0 / 3.0) - 1.0 + 2.0 * r_cut / mean_spacing) ** 3
+
+
+# ----------------------------------------------------------------------------------------
+# Tree part of TreePM: monopole tree force with the S2 cutoff (readings at or_s2_cutoff)
+
+def s2_cutoff(xi: float) -> float:
+    return lib().or_s2_cutoff(float(xi))
+
+
+def direct_cutoff(ps, r_cut: float) -> np.ndarray:
+    """Acceleration of every particle (caller's order, n x 3) from all pairs of its system."""
+    acc = np.zeros((ps.n, 3))
+    lib().or_direct_cutoff(ps.n_sys, _p(_c(ps.offsets(), np.int64)), _p(_c(ps.x, np.float64)),
+                           _p(_c(ps.y, np.float64)), _p(_c(ps.z, np.float64)),
+                           _p(_c(ps.m, np.float64)), _p(_c(ps.eps, np.float64)), float(r_cut),
+                           _p(acc))
+    return acc
+
+
+class CutoffLists:
+    """Lists of every group for the cutoff walk (EPJ sorted positions, SPJ cell ids) and the
+    monopole cutoff force they give."""
+
+    def __init__(self, tree: Tree, grp: Groups, theta: float, r_cut: float):
+        L = lib()
+        self.tree, self.grp, self.r_cut = tree, grp, float(r_cut)
+        counts = np.zeros(2 * grp.n, np.int64)
+        self._h = L.or_walk_cutoff(tree._h, grp.n, _p(grp.root), _p(grp.qmin), _p(grp.qmax),
+                                   float(theta), self.r_cut, _p(_c(tree.cube, np.float64)),
+                                   _p(counts))
+        self.n_epj = counts[0::2].copy()
+        self.n_spj = counts[1::2].copy()
+        self.epj_off = np.concatenate([[0], np.cumsum(self.n_epj)]).astype(np.int64)
+        self.spj_off = np.concatenate([[0], np.cumsum(self.n_spj)]).astype(np.int64)
+        self.epj = np.zeros(int(self.epj_off[-1]), np.uint32)
+        self.spj = np.zeros(int(self.spj_off[-1]), np.uint32)
+        L.or_walk_export(self._h, _p(self.epj), _p(self.spj))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().or_walk_free(h)
+            self._h = None
+
+    def group_lists(self, k: int):
+        return (self.epj[self.epj_off[k]:self.epj_off[k + 1]],
+                self.spj[self.spj_off[k]:self.spj_off[k + 1]])
+
+    def force(self) -> np.ndarray:
+        """Acceleration at sorted positions (n x 3)."""
+        t, g = self.tree, self.grp
+        if t.mom is None:
+            t.compute_moments()
+        acc = np.zeros((t.ps.n, 3))
+        lib().or_force_cutoff(self._h, _p(g.begin), _p(g.count), _p(t.sx), _p(t.sy), _p(t.sz),
+                              _p(t.sm), _p(t.seps), _p(t.mom), self.r_cut, _p(acc))
+        return acc
+
+
+def cutoff_lists(tree: Tree, grp: Groups, theta: float, r_cut: float) -> CutoffLists:
+    return CutoffLists(tree, grp, theta, r_cut)
 
 
 def exchange_list_model(n: float, theta: float, n_p: float) -> float:

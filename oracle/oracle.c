@@ -710,3 +710,133 @@ void or_density_lists(void *wh, const uint32_t *gbegin, const uint32_t *gcount, 
         }
     }
 }
+
+/* ------------------------------------------------------------------------------------ */
+/* Tree part of TreePM (section "Cosmological simulation": a monopole-only tree kernel with
+ * a cutoff of three mesh widths, theta 0.5, the long-range part on a mesh with the S2 cloud
+ * profile of Hockney & Eastwood).  The tree part is Newton's force minus the force between
+ * two S2 clouds of diameter r_cut (uniform-gradient spheres: density proportional to
+ * r_cut/2 - r), i.e. 1/r^2 times g(xi), xi = 2 r / r_cut:
+ *   g = 1 - (224 xi^3 - 224 xi^5 + 70 xi^6 + 48 xi^7 - 21 xi^8) / 140,           xi <= 1
+ *   g = 1 - (12 - 224 xi^2 + 896 xi^3 - 840 xi^4 + 224 xi^5 + 70 xi^6 - 48 xi^7 + 7 xi^8) / 140,
+ *                                                                                1 <= xi <= 2
+ *   g = 0,                                                                       xi >= 2.
+ * Readings: softening enters the Newtonian factor only, a = m (r_j - r_i) g(2 r / r_cut) /
+ * (r^2 + eps_i^2)^{3/2} with r unsoftened; a superparticle is its monopole at the centre of
+ * mass; the walk drops a cell whose cube lies farther than r_cut from the group's box (every
+ * pair in it has g = 0; test as for the short-range walk, R = r_cut * 2^22 / Lr) and applies
+ * the opening test to the others; no potential. */
+double or_s2_cutoff(double xi) {
+    if (xi >= 2.0) return 0.0;
+    double x2 = xi * xi, x3 = x2 * xi, x4 = x2 * x2, x5 = x4 * xi, x6 = x3 * x3, x7 = x6 * xi,
+           x8 = x4 * x4;
+    if (xi <= 1.0) return 1.0 - (224.0 * x3 - 224.0 * x5 + 70.0 * x6 + 48.0 * x7 - 21.0 * x8) / 140.0;
+    return 1.0 - (12.0 - 224.0 * x2 + 896.0 * x3 - 840.0 * x4 + 224.0 * x5 + 70.0 * x6 - 48.0 * x7 +
+                  7.0 * x8) / 140.0;
+}
+
+/* all pairs of each system, caller's order, acc[3 i] */
+void or_direct_cutoff(int64_t nsys, const int64_t *off, const double *x, const double *y,
+                      const double *z, const double *m, const double *eps, double r_cut,
+                      double *acc) {
+    for (int64_t s = 0; s < nsys; s++) {
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t i = off[s]; i < off[s + 1]; i++) {
+            nsum ax = {0, 0}, ay = {0, 0}, az = {0, 0};
+            double e2 = eps[i] * eps[i];
+            for (int64_t j = off[s]; j < off[s + 1]; j++) {
+                if (j == i) continue;
+                double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
+                double r2 = dx * dx + dy * dy + dz * dz;
+                double g = or_s2_cutoff(2.0 * sqrt(r2) / r_cut);
+                if (g == 0.0) continue;
+                double rinv = 1.0 / sqrt(r2 + e2);
+                double f = m[j] * rinv * rinv * rinv * g;
+                nadd(&ax, f * dx); nadd(&ay, f * dy); nadd(&az, f * dz);
+            }
+            acc[3 * i] = nval(&ax); acc[3 * i + 1] = nval(&ay); acc[3 * i + 2] = nval(&az);
+        }
+    }
+}
+
+static void cutoff_visit(const or_cells *t, uint32_t c, const int64_t *lo, const int64_t *hi,
+                         double th2, double R2, u32vec *epj, u32vec *spj) {
+    if (t->count[c] == 0) return;
+    uint32_t cq[3];
+    int32_t l = t->level[c];
+    deinterleave(t->prefix[c] << (3 * (OR_LEVELS - l)), &cq[0], &cq[1], &cq[2]);
+    double D2 = 0.0;
+    int64_t half = (int64_t)1 << (OR_LEVELS - l);
+    for (int a = 0; a < 3; a++) {
+        int64_t C = 2 * (int64_t)cq[a] + half;
+        int64_t bmin = 2 * lo[a], bmax = 2 * hi[a] + 2;
+        int64_t d = 0;
+        if (bmin - (C + half) > d) d = bmin - (C + half);
+        if ((C - half) - bmax > d) d = (C - half) - bmax;
+        D2 += (double)(d * d);
+    }
+    if (D2 > R2) return;
+    if (accept_cell(l, t->prefix[c], lo, hi, th2)) { vpush(spj, c); return; }
+    if (t->nchild[c] == 0) {
+        for (uint32_t i = t->begin[c]; i < t->begin[c] + t->count[c]; i++) vpush(epj, i);
+        return;
+    }
+    for (uint32_t k = 0; k < t->nchild[c]; k++)
+        cutoff_visit(t, t->first_child[c] + k, lo, hi, th2, R2, epj, spj);
+}
+
+void *or_walk_cutoff(void *h, int64_t ng, const uint32_t *groot, const uint32_t *qmin,
+                     const uint32_t *qmax, double theta, double r_cut, const double *cube,
+                     int64_t *counts) {
+    const or_cells *t = (const or_cells *)h;
+    walk_res *w = (walk_res *)calloc(1, sizeof(walk_res));
+    w->nsel = ng;
+    w->epj = (u32vec *)calloc((size_t)(ng > 0 ? ng : 1), sizeof(u32vec));
+    w->spj = (u32vec *)calloc((size_t)(ng > 0 ? ng : 1), sizeof(u32vec));
+    double th2 = theta * theta;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t g = 0; g < ng; g++) {
+        int64_t lo[3], hi[3];
+        for (int a = 0; a < 3; a++) { lo[a] = qmin[3 * g + a]; hi[a] = qmax[3 * g + a]; }
+        double R = r_cut * (4194304.0 / cube[4 * (size_t)groot[g] + 3]);
+        cutoff_visit(t, groot[g], lo, hi, th2, R * R, &w->epj[g], &w->spj[g]);
+        counts[2 * g] = w->epj[g].n;
+        counts[2 * g + 1] = w->spj[g].n;
+    }
+    return w;
+}
+
+/* acceleration of every group member from its lists (sorted order, acc[3 i]) */
+void or_force_cutoff(void *wh, const uint32_t *gbegin, const uint32_t *gcount, const double *sx,
+                     const double *sy, const double *sz, const double *sm, const double *seps,
+                     const double *mom, double r_cut, double *acc) {
+    walk_res *w = (walk_res *)wh;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t g = 0; g < w->nsel; g++) {
+        for (uint32_t i = gbegin[g]; i < gbegin[g] + gcount[g]; i++) {
+            double e2 = seps[i] * seps[i];
+            nsum ax = {0, 0}, ay = {0, 0}, az = {0, 0};
+            for (int64_t t = 0; t < w->epj[g].n; t++) {
+                uint32_t j = w->epj[g].v[t];
+                if (j == i) continue;
+                double dx = sx[j] - sx[i], dy = sy[j] - sy[i], dz = sz[j] - sz[i];
+                double r2 = dx * dx + dy * dy + dz * dz;
+                double gc = or_s2_cutoff(2.0 * sqrt(r2) / r_cut);
+                double rinv = 1.0 / sqrt(r2 + e2);
+                double f = sm[j] * rinv * rinv * rinv * gc;
+                nadd(&ax, f * dx); nadd(&ay, f * dy); nadd(&az, f * dz);
+            }
+            for (int64_t t = 0; t < w->spj[g].n; t++) {
+                const double *o = mom + 10 * (size_t)w->spj[g].v[t];
+                double dx = o[1] - sx[i], dy = o[2] - sy[i], dz = o[3] - sz[i];
+                double r2 = dx * dx + dy * dy + dz * dz;
+                double gc = or_s2_cutoff(2.0 * sqrt(r2) / r_cut);
+                double rinv = 1.0 / sqrt(r2 + e2);
+                double f = o[0] * rinv * rinv * rinv * gc;
+                nadd(&ax, f * dx); nadd(&ay, f * dy); nadd(&az, f * dz);
+            }
+            acc[3 * (size_t)i] = nval(&ax); acc[3 * (size_t)i + 1] = nval(&ay);
+            acc[3 * (size_t)i + 2] = nval(&az);
+        }
+    }
+}
