@@ -212,6 +212,21 @@ int fdx_predictor_margin(fdx_ctx *ctx, double margin, double *out);
 int fdx_predictor_save(fdx_ctx *ctx, const char *path);
 int fdx_predictor_load(fdx_ctx *ctx, const char *path);
 
+/* ---- Tree part of TreePM -----------------------------------------------------------------
+ * The paper's cosmological run splits gravity into a mesh part and a tree part with a
+ * monopole-only kernel and a cutoff of three mesh widths, with the S2 cloud profile of
+ * Hockney & Eastwood (section "Cosmological simulation").  fdx_calc_force_cutoff evaluates
+ * the tree part: cells whose cube lies farther than r_cut from a group's box are dropped, the
+ * rest follow the opening angle theta, superparticles are monopoles, and every pair force is
+ * Newton's times g(2 r / r_cut), the complement of the force between two S2 clouds of
+ * diameter r_cut (g = 1 at r = 0, 0 for r >= r_cut; r unsoftened, eps_i in the Newtonian
+ * factor).  The potential is not computed (returned as 0).  Same arguments as fdx_calc_force
+ * plus r_cut (finite > 0); flags: FDX_FP32REL, FDX_PERSISTENT, FDX_TIMING.  fdx_integrate then
+ * steps with this force (not with FDX_GRAPH).  FDX_EINVAL: r_cut, FDX_QUAD, FDX_PREDICTOR or
+ * FDX_GRAPH, or a parameter fdx_calc_force rejects. */
+int fdx_calc_force_cutoff(fdx_ctx *ctx, double theta, int32_t n_leaf, int32_t n_group, double eps,
+                          double r_cut, int32_t flags);
+
 /* ---- Exchange lists between domains ----------------------------------------------------
  * Before the force step every process sends every other process the particles and
  * superparticles it needs, found by the usual tree traversal of its own local tree with the

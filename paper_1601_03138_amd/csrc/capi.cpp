@@ -191,11 +191,23 @@ int run_tree(fdx_ctx *c, bool sync) {
 
 // Exact walk, first half: count pass, segment sizes and offsets (device total in
 // st->list_total).  gmax bounds the groups (the host count, or the capacity when captured).
+static ShortArgs cutoff_args(fdx_ctx *c) {
+    ShortArgs sa;
+    sa.cube = c->cube.p;
+    sa.r_fixed = c->cutoff;
+    return sa;
+}
+
 int enqueue_count(fdx_ctx *c, size_t gmax) {
     hipStream_t s = c->stream;
     Groups gv = groups_view(c);
-    HIPCHK(c, walk(false, gmax, gv, cells_view(c), c->theta * c->theta, nullptr, nullptr, 0,
-                   nullptr, c->cnt_e.p, c->cnt_s.p, c->ovf_list.p, nullptr, nullptr, c->st, s));
+    if (c->cutoff > 0)
+        HIPCHK(c, walk_short(false, 4, gmax, gv, cells_view(c), cutoff_args(c), c->theta * c->theta,
+                             nullptr, nullptr, 0, nullptr, c->cnt_e.p, c->cnt_s.p, c->ovf_list.p,
+                             c->st, s));
+    else
+        HIPCHK(c, walk(false, gmax, gv, cells_view(c), c->theta * c->theta, nullptr, nullptr, 0,
+                       nullptr, c->cnt_e.p, c->cnt_s.p, c->ovf_list.p, nullptr, nullptr, c->st, s));
     HIPCHK(c, list_caps(gmax, c->cnt_e.p, c->cnt_s.p, c->lcap.p, c->st, s));
     HIPCHK(c, scan_u32_to_u64(c->lcap.p, c->seg.p, 0, nullptr, &c->st->n_groups_c, c->partial.p,
                               &c->st->list_total, s));
@@ -206,9 +218,14 @@ int enqueue_count(fdx_ctx *c, size_t gmax) {
 int enqueue_fill(fdx_ctx *c, size_t gmax) {
     hipStream_t s = c->stream;
     Groups gv = groups_view(c);
-    HIPCHK(c, walk(true, gmax, gv, cells_view(c), c->theta * c->theta, c->seg.p, c->lcap.p,
-                   c->list_cap, c->list.p, c->cnt_e.p, c->cnt_s.p, c->ovf_list.p, nullptr,
-                   nullptr, c->st, s));
+    if (c->cutoff > 0)
+        HIPCHK(c, walk_short(true, 4, gmax, gv, cells_view(c), cutoff_args(c), c->theta * c->theta,
+                             c->seg.p, c->lcap.p, c->list_cap, c->list.p, c->cnt_e.p, c->cnt_s.p,
+                             c->ovf_list.p, c->st, s));
+    else
+        HIPCHK(c, walk(true, gmax, gv, cells_view(c), c->theta * c->theta, c->seg.p, c->lcap.p,
+                       c->list_cap, c->list.p, c->cnt_e.p, c->cnt_s.p, c->ovf_list.p, nullptr,
+                       nullptr, c->st, s));
     return FDX_OK;
 }
 
@@ -228,6 +245,7 @@ int enqueue_force(fdx_ctx *c, size_t gmax) {
     fa.fp32 = (c->flags & FDX_FP32REL) != 0;
     fa.persistent = (c->flags & FDX_PERSISTENT) != 0;
     fa.variant = ext_force_variant(c);
+    fa.r_cut = c->cutoff;
     if (fa.persistent) {
         int r = ext_queue_order(c, gmax, &fa.order);
         if (r) return r;
@@ -505,8 +523,29 @@ int fdx_calc_force(fdx_ctx *c, double theta, int32_t n_leaf, int32_t n_group, do
                    int32_t flags) {
     if (!c) return FDX_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, FDX_EHIP, "hipSetDevice failed");
+    c->cutoff = 0.0;
     int r = setup_eval(c, theta, n_leaf, n_group, eps, flags);
     if (r) return r;
+    r = run_tree(c, true);
+    if (r) return r;
+    r = run_force(c);
+    if (r) return r;
+    finish_stats(c);
+    r = sync_timing(c);
+    if (r) return r;
+    return read_counters(c);
+}
+
+int fdx_calc_force_cutoff(fdx_ctx *c, double theta, int32_t n_leaf, int32_t n_group, double eps,
+                          double r_cut, int32_t flags) {
+    if (!c) return FDX_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, FDX_EHIP, "hipSetDevice failed");
+    if (!(std::isfinite(r_cut) && r_cut > 0.0)) return fail(c, FDX_EINVAL, "r_cut must be finite and > 0");
+    if (flags & (FDX_QUAD | FDX_PREDICTOR | FDX_GRAPH))
+        return fail(c, FDX_EINVAL, "the cutoff kernel is monopole only, without predictor or graph");
+    int r = setup_eval(c, theta, n_leaf, n_group, eps, flags);
+    if (r) return r;
+    c->cutoff = r_cut;
     r = run_tree(c, true);
     if (r) return r;
     r = run_force(c);
@@ -522,6 +561,8 @@ int fdx_integrate(fdx_ctx *c, double dt, int32_t n_steps, int32_t flags) {
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, FDX_EHIP, "hipSetDevice failed");
     if (!c->have_force) return fail(c, FDX_ESTATE, "evaluate the force once before integrating");
     if (!std::isfinite(dt) || n_steps < 0) return fail(c, FDX_EINVAL, "bad dt or n_steps");
+    if ((flags & FDX_GRAPH) && c->cutoff > 0)
+        return fail(c, FDX_EINVAL, "graph capture is not available with the cutoff kernel");
     if (flags & FDX_GRAPH) return ext_integrate_graph(c, dt, n_steps);
     const size_t n = (size_t)c->n;
     for (int k = 0; k < n_steps; k++) {

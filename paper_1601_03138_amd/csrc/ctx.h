@@ -102,6 +102,7 @@ struct fdx_ctx {
     // last parameters
     double theta = 0.5, eps_all = 0.0;
     int n_leaf = 8, n_group = 64, flags = 0, variant = -1;
+    double cutoff = 0.0;           // > 0: the last evaluation was the TreePM cutoff kernel
     fdx_stats stats{};
     hipEvent_t ev[12] = {};
 

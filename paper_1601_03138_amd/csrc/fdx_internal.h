@@ -148,9 +148,11 @@ hipError_t walk(bool fill, size_t gmax, const Groups g, const Cells c, double th
                 const uint64_t *seg, const uint32_t *cap, uint64_t list_cap, uint32_t *list,
                 uint32_t *cnt_e, uint32_t *cnt_s, uint32_t *ovf_list, const uint32_t *sel,
                 const uint32_t *nsel, DevStatus *st, hipStream_t s);
-// short-range walk (kind 1: group radius, 2: cell radius, 3: the larger), no superparticles
+// short-range walk (kind 1: group radius, 2: cell radius, 3: the larger; no superparticles)
+// or the TreePM cutoff walk (kind 4: cells beyond sa.r_fixed dropped, opening angle theta
+// for the rest)
 hipError_t walk_short(bool fill, int kind, size_t gmax, const Groups g, const Cells c,
-                      const ShortArgs sa, const uint64_t *seg, const uint32_t *cap,
+                      const ShortArgs sa, double theta2, const uint64_t *seg, const uint32_t *cap,
                       uint64_t list_cap, uint32_t *list, uint32_t *cnt_e, uint32_t *cnt_s,
                       uint32_t *ovf_list, DevStatus *st, hipStream_t s);
 // SPH density on short-range lists (k_sph.hip): support radii in sorted order (h given, else
@@ -190,6 +192,7 @@ struct ForceArgs {
     DevStatus *st;
     bool quad, fp32, persistent;
     int variant;            // kernel shape chosen by the autotuner
+    double r_cut = 0.0;     // > 0: tree part of TreePM (monopole, S2 cutoff), no potential
 };
 // G = number of groups (direct launch: one workgroup per group; persistent launch: G bounds
 // the grid and the kernel reads the true count from the device status).

@@ -46,6 +46,7 @@ struct KArgs {
     double4 *fs;
     DevStatus *st;
     uint32_t G;              // groups (direct launch); persistent kernels read *ngroups
+    double cut_s;            // cutoff kernel: 2 / r_cut
 };
 
 template <class T> struct V4;
@@ -81,10 +82,39 @@ __device__ __forceinline__ double rsqrt_t(double x) {
     return y;
 }
 
+// Tree part of TreePM (cutoff kernel, monopole): the Newtonian pair force times
+// g(xi), xi = 2 r / r_cut, the complement of the force between two S2 clouds of diameter
+// r_cut (Hockney & Eastwood):
+//   g = 1 - xi^3 (224 - 224 xi^2 + 70 xi^3 + 48 xi^4 - 21 xi^5) / 140,              xi <= 1
+//   g = 1 - (12 - 224 xi^2 + 896 xi^3 - 840 xi^4 + 224 xi^5 + 70 xi^6 - 48 xi^7 + 7 xi^8)/140,
+//                                                                            1 < xi < 2
+//   g = 0 beyond; r unsoftened, softening in the Newtonian factor only; no potential.
 template <class T>
+__device__ __forceinline__ T s2_cutoff(T xi) {
+    if (xi >= (T)2) return (T)0;
+    if (xi <= (T)1) {
+        const T p = fma(xi, fma(xi, fma(xi, fma(xi, (T)-21, (T)48), (T)70), (T)-224), (T)0);
+        return (T)1 - xi * xi * xi * fma(xi, p, (T)224) / (T)140;
+    }
+    const T q = fma(xi, fma(xi, fma(xi, fma(xi, fma(xi, fma(xi, fma(xi, (T)7, (T)-48), (T)70),
+                                                         (T)224), (T)-840), (T)896), (T)-224),
+                    (T)0);
+    return (T)1 - fma(xi, q, (T)12) / (T)140;
+}
+
+template <class T, bool CUT = false>
 __device__ __forceinline__ void pp(const typename V4<T>::t &J, T xi, T yi, T zi, T e2, T &ax,
-                                   T &ay, T &az, T &ph) {
+                                   T &ay, T &az, T &ph, T cut_s = (T)0) {
     const T dx = J.x - xi, dy = J.y - yi, dz = J.z - zi;
+    if (CUT) {
+        const T r2u = fma(dz, dz, fma(dy, dy, dx * dx));
+        const T ri = rsqrt_t(r2u + e2);
+        const T f = J.w * ri * ri * ri * s2_cutoff<T>(sqrt(r2u) * cut_s);
+        ax = fma(f, dx, ax);
+        ay = fma(f, dy, ay);
+        az = fma(f, dz, az);
+        return;
+    }
     const T r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
     const T ri = rsqrt_t(r2);
     const T mri = J.w * ri;
@@ -95,11 +125,20 @@ __device__ __forceinline__ void pp(const typename V4<T>::t &J, T xi, T yi, T zi,
     ph -= mri;
 }
 
-template <class T, bool QUAD>
+template <class T, bool QUAD, bool CUT = false>
 __device__ __forceinline__ void pc(const typename V4<T>::t &A, const typename V4<T>::t &B,
                                    const typename V4<T>::t &C, T xi, T yi, T zi, T e2, T &ax,
-                                   T &ay, T &az, T &ph) {
+                                   T &ay, T &az, T &ph, T cut_s = (T)0) {
     const T rx = xi - A.x, ry = yi - A.y, rz = zi - A.z;
+    if (CUT) {                                       // monopole with cutoff
+        const T r2u = fma(rz, rz, fma(ry, ry, rx * rx));
+        const T Ri = rsqrt_t(r2u + e2);
+        const T f = A.w * Ri * Ri * Ri * s2_cutoff<T>(sqrt(r2u) * cut_s);
+        ax = fma(-f, rx, ax);
+        ay = fma(-f, ry, ay);
+        az = fma(-f, rz, az);
+        return;
+    }
     const T R2 = fma(rz, rz, fma(ry, ry, fma(rx, rx, e2)));
     const T Ri = rsqrt_t(R2);
     const T Ri2 = Ri * Ri;
@@ -137,7 +176,7 @@ struct Smem {
     uint32_t slot;
 };
 
-template <class T, bool QUAD, int NT, int IPL, bool PF>
+template <class T, bool QUAD, int NT, int IPL, bool PF, bool CUT = false>
 __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T, NT, IPL> &sm) {
     using V = typename V4<T>::t;
     const int tid = threadIdx.x;
@@ -148,6 +187,7 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
     const bool fp32 = sizeof(T) == 4;
     const double cx = fp32 ? a.gcentre[3 * gi] : 0.0, cy = fp32 ? a.gcentre[3 * gi + 1] : 0.0,
                  cz = fp32 ? a.gcentre[3 * gi + 2] : 0.0;
+    const T cut_s = (T)a.cut_s;
 
     uint32_t tps = (ni + IPL - 1) / IPL;
     tps = tps < 1 ? 1 : (tps > (uint32_t)NT ? (uint32_t)NT : tps);
@@ -196,14 +236,14 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
                     const V J = run[q];
 #pragma unroll
                     for (int k = 0; k < IPL; k++)
-                        pp<T>(J, xi[k], yi[k], zi[k], e2[k], tx[k], ty[k], tz[k], tp[k]);
+                        pp<T, CUT>(J, xi[k], yi[k], zi[k], e2[k], tx[k], ty[k], tz[k], tp[k], cut_s);
                 }
                 const uint32_t j = kmain * nslice + slice;
                 if (j < nt) {
                     const V J = sm.e[j];
 #pragma unroll
                     for (int k = 0; k < IPL; k++)
-                        pp<T>(J, xi[k], yi[k], zi[k], e2[k], tx[k], ty[k], tz[k], tp[k]);
+                        pp<T, CUT>(J, xi[k], yi[k], zi[k], e2[k], tx[k], ty[k], tz[k], tp[k], cut_s);
                 }
 #pragma unroll
                 for (int k = 0; k < IPL; k++) {
@@ -254,7 +294,8 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
                     if (QUAD) { B = run[3 * q + 1]; C = run[3 * q + 2]; } else { B = A; C = A; }
 #pragma unroll
                     for (int k = 0; k < IPL; k++)
-                        pc<T, QUAD>(A, B, C, xi[k], yi[k], zi[k], e2[k], tx[k], ty[k], tz[k], tp[k]);
+                        pc<T, QUAD, CUT>(A, B, C, xi[k], yi[k], zi[k], e2[k], tx[k], ty[k], tz[k], tp[k],
+                                         cut_s);
                 }
                 const uint32_t j = kmain * nslice + slice;
                 if (j < nt) {
@@ -263,7 +304,8 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
                     if (QUAD) { B = sm.s[3 * j + 1]; C = sm.s[3 * j + 2]; } else { B = A; C = A; }
 #pragma unroll
                     for (int k = 0; k < IPL; k++)
-                        pc<T, QUAD>(A, B, C, xi[k], yi[k], zi[k], e2[k], tx[k], ty[k], tz[k], tp[k]);
+                        pc<T, QUAD, CUT>(A, B, C, xi[k], yi[k], zi[k], e2[k], tx[k], ty[k], tz[k], tp[k],
+                                         cut_s);
                 }
 #pragma unroll
                 for (int k = 0; k < IPL; k++) {
@@ -295,15 +337,15 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
             }
             const uint32_t r = gb + i;
             const T mi = (T)a.jp[r].w;
-            const T self = mi * rsqrt_t(e2[k]);
-            a.fs[r] = make_double4(s[0], s[1], s[2], s[3] + (double)self);
+            const T self = CUT ? (T)0 : mi * rsqrt_t(e2[k]);
+            a.fs[r] = make_double4(s[0], s[1], s[2], CUT ? 0.0 : s[3] + (double)self);
         }
     }
     __syncthreads();
 }
 
 // OCC: minimum waves per SIMD the register allocation must allow (1 = no constraint).
-template <class T, bool QUAD, int NT, int IPL, bool PF, int OCC>
+template <class T, bool QUAD, int NT, int IPL, bool PF, int OCC, bool CUT>
 __global__ void __launch_bounds__(NT, OCC)
 k_force_direct(KArgs a) {
     __shared__ Smem<T, NT, IPL> sm;
@@ -313,12 +355,12 @@ k_force_direct(KArgs a) {
     const uint32_t chunk = (G + 7) / 8;
     const uint32_t q = (blockIdx.x % 8) * chunk + blockIdx.x / 8;
     if (q >= G) return;
-    force_group<T, QUAD, NT, IPL, PF>(a, a.order ? a.order[q] : q, sm);
+    force_group<T, QUAD, NT, IPL, PF, CUT>(a, a.order ? a.order[q] : q, sm);
 }
 
 // Persistent variant: a fixed grid pops queue slots from a device counter (the queue order
 // lists the groups by decreasing cost, so the longest work starts first).
-template <class T, bool QUAD, int NT, int IPL, bool PF, int OCC>
+template <class T, bool QUAD, int NT, int IPL, bool PF, int OCC, bool CUT>
 __global__ void __launch_bounds__(NT, OCC)
 k_force_persistent(KArgs a) {
     __shared__ Smem<T, NT, IPL> sm;
@@ -329,11 +371,11 @@ k_force_persistent(KArgs a) {
         const uint32_t slot = sm.slot;
         __syncthreads();
         if (slot >= G) break;
-        force_group<T, QUAD, NT, IPL, PF>(a, a.order ? a.order[slot] : slot, sm);
+        force_group<T, QUAD, NT, IPL, PF, CUT>(a, a.order ? a.order[slot] : slot, sm);
     }
 }
 
-template <class T, bool QUAD, int NT, int IPL, bool PF, int OCC = 1>
+template <class T, bool QUAD, int NT, int IPL, bool PF, int OCC = 1, bool CUT = false>
 hipError_t launch(const KArgs &k, bool persistent, hipStream_t s) {
     if (persistent) {
         int dev = 0, ncu = 256;
@@ -341,16 +383,16 @@ hipError_t launch(const KArgs &k, bool persistent, hipStream_t s) {
         (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
         int per_cu = 0;
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(k_force_persistent<T, QUAD, NT, IPL, PF, OCC>), NT, 0);
+            &per_cu, reinterpret_cast<const void *>(k_force_persistent<T, QUAD, NT, IPL, PF, OCC, CUT>), NT, 0);
         if (per_cu < 1) per_cu = 1;
         size_t grid = (size_t)ncu * per_cu;
         if (k.G && grid > k.G) grid = k.G;
-        hipLaunchKernelGGL((k_force_persistent<T, QUAD, NT, IPL, PF, OCC>), dim3((unsigned)grid), dim3(NT),
+        hipLaunchKernelGGL((k_force_persistent<T, QUAD, NT, IPL, PF, OCC, CUT>), dim3((unsigned)grid), dim3(NT),
                            0, s, k);
     } else {
         if (k.G == 0) return hipSuccess;
         const uint32_t chunk = (k.G + 7) / 8;
-        hipLaunchKernelGGL((k_force_direct<T, QUAD, NT, IPL, PF, OCC>), dim3(8 * chunk), dim3(NT), 0, s, k);
+        hipLaunchKernelGGL((k_force_direct<T, QUAD, NT, IPL, PF, OCC, CUT>), dim3(8 * chunk), dim3(NT), 0, s, k);
     }
     return hipGetLastError();
 }
@@ -400,6 +442,10 @@ hipError_t force(size_t G, const ForceArgs &fa, hipStream_t s) {
     k.list = fa.list;
     k.order = fa.order; k.ngroups = &fa.st->n_groups_c; k.fs = fa.fs; k.st = fa.st;
     k.G = (uint32_t)G;
+    k.cut_s = fa.r_cut > 0 ? 2.0 / fa.r_cut : 0.0;
+    if (fa.r_cut > 0)                  // tree part of TreePM: monopole with the S2 cutoff
+        return fa.fp32 ? launch<float, false, 512, 1, true, 8, true>(k, fa.persistent, s)
+                       : launch<double, false, 256, 2, false, 1, true>(k, fa.persistent, s);
     const int v = fa.variant;
     if (fa.fp32) return fa.quad ? launch_v<float, true>(k, fa.persistent, v, s)
                                 : launch_v<float, false>(k, fa.persistent, v, s);

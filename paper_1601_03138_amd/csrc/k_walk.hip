@@ -59,7 +59,8 @@ __device__ __forceinline__ bool cell_far(const uint4 nd, int bminx, int bminy, i
 
 // KIND 0: gravity (opening angle; accepted cells are superparticles).  Short range, search
 // radius r: 1 the group's radius (fixed cutoff or the group's largest h), 2 the cell's largest
-// h (scatter), 3 the larger of the two (symmetric).
+// h (scatter), 3 the larger of the two (symmetric).  4: tree part of TreePM, cells beyond the
+// cutoff (sa.r_fixed) dropped, the opening angle for the rest.
 template <bool FILL, int KIND>
 __global__ void __launch_bounds__(kThreads)
 k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, uint32_t ccap,
@@ -106,9 +107,15 @@ k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, 
             const uint4 nd = node[cid];
             const uint2 lk = link[cid];
             const uint32_t nch = nd.w >> 8;
-            bool accept;
+            // accept: emitted as a superparticle (gravity); drop: out of range (short range,
+            // cutoff); otherwise opened
+            bool accept = false, drop = false;
             if (KIND == 0) {
                 accept = act && cell_accepted(nd, bminx, bminy, bminz, bmaxx, bmaxy, bmaxz, theta2);
+            } else if (KIND == 4) {
+                drop = act && cell_far(nd, bminx, bminy, bminz, bmaxx, bmaxy, bmaxz, Rg2);
+                accept = act && !drop &&
+                         cell_accepted(nd, bminx, bminy, bminz, bmaxx, bmaxy, bmaxz, theta2);
             } else {
                 double R2 = Rg2;
                 if (KIND != 1) {
@@ -117,13 +124,13 @@ k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, 
                     const double R = __dmul_rn(r, scale);
                     R2 = __dmul_rn(R, R);
                 }
-                accept = act && cell_far(nd, bminx, bminy, bminz, bmaxx, bmaxy, bmaxz, R2);
+                drop = act && cell_far(nd, bminx, bminy, bminz, bmaxx, bmaxy, bmaxz, R2);
             }
-            const bool open = act && !accept;
+            const bool open = act && !accept && !drop;
             const bool leaf = open && nch == 0 && lk.y > 0;
             const bool inner = open && nch != 0;
             // superparticles, from the back of the segment
-            if (KIND == 0) {
+            if (KIND == 0 || KIND == 4) {
                 const uint64_t bs = __ballot(accept);
                 if (FILL && accept) {
                     const uint32_t j = ns + (uint32_t)__popcll(bs & lt);
@@ -389,7 +396,7 @@ hipError_t walk(bool fill, size_t gmax, const Groups g, const Cells c, double th
 }
 
 hipError_t walk_short(bool fill, int kind, size_t gmax, const Groups g, const Cells c,
-                      const ShortArgs sa, const uint64_t *seg, const uint32_t *cap,
+                      const ShortArgs sa, double theta2, const uint64_t *seg, const uint32_t *cap,
                       uint64_t list_cap, uint32_t *list, uint32_t *cnt_e, uint32_t *cnt_s,
                       uint32_t *ovf_list, DevStatus *st, hipStream_t s) {
     switch (kind) {
@@ -397,7 +404,9 @@ hipError_t walk_short(bool fill, int kind, size_t gmax, const Groups g, const Ce
                                ovf_list, nullptr, nullptr, st, sa, s); break;
         case 2: launch_walk<2>(fill, gmax, g, c, 0.0, seg, cap, list_cap, list, cnt_e, cnt_s,
                                ovf_list, nullptr, nullptr, st, sa, s); break;
-        default: launch_walk<3>(fill, gmax, g, c, 0.0, seg, cap, list_cap, list, cnt_e, cnt_s,
+        case 3: launch_walk<3>(fill, gmax, g, c, 0.0, seg, cap, list_cap, list, cnt_e, cnt_s,
+                               ovf_list, nullptr, nullptr, st, sa, s); break;
+        default: launch_walk<4>(fill, gmax, g, c, theta2, seg, cap, list_cap, list, cnt_e, cnt_s,
                                 ovf_list, nullptr, nullptr, st, sa, s); break;
     }
     return hipGetLastError();

@@ -97,7 +97,7 @@ int fdx_calc_density(fdx_ctx *c, int32_t mode, double r_cut, const double *h, in
     }
     const int kind = mode == FDX_CUT_SCATTER ? 2 : (mode == FDX_CUT_SYMMETRIC ? 3 : 1);
     // count pass, segment sizes and offsets (total in st->list_total), one read, fill pass
-    HIPCHK(c, walk_short(false, kind, G, gv, cv, sa, nullptr, nullptr, 0, nullptr, c->cnt_e.p,
+    HIPCHK(c, walk_short(false, kind, G, gv, cv, sa, 0.0, nullptr, nullptr, 0, nullptr, c->cnt_e.p,
                          c->cnt_s.p, nullptr, c->st, s));
     HIPCHK(c, list_caps(G, c->cnt_e.p, c->cnt_s.p, c->lcap.p, c->st, s));
     HIPCHK(c, scan_u32_to_u64(c->lcap.p, c->seg.p, 0, nullptr, &c->st->n_groups_c, c->partial.p,
@@ -109,7 +109,7 @@ int fdx_calc_density(fdx_ctx *c, int32_t mode, double r_cut, const double *h, in
     if (hs.walk_error) return fail(c, FDX_EHIP, "walk stack exhausted");
     r = ensure_list_capacity(c, hs.list_total);
     if (r) return r;
-    HIPCHK(c, walk_short(true, kind, G, gv, cv, sa, c->seg.p, c->lcap.p, c->list_cap, c->list.p,
+    HIPCHK(c, walk_short(true, kind, G, gv, cv, sa, 0.0, c->seg.p, c->lcap.p, c->list_cap, c->list.p,
                          c->cnt_e.p, c->cnt_s.p, nullptr, c->st, s));
     c->have_lists = true;
     c->stats.list_capacity = (int64_t)hs.list_total;

@@ -27,7 +27,8 @@ EXPORTS = ["fdx_create", "fdx_destroy", "fdx_set_particles", "fdx_build_tree", "
            "fdx_predictor_features", "fdx_mlp_forward", "fdx_mlp_grad", "fdx_predictor_train",
            "fdx_predictor_margin", "fdx_predictor_save", "fdx_predictor_load",
            "fdx_build_exchange_lists", "fdx_get_exchange_counts", "fdx_get_exchange_lists",
-           "fdx_get_exchange_stats", "fdx_calc_density", "fdx_get_density"]
+           "fdx_get_exchange_stats", "fdx_calc_density", "fdx_get_density",
+           "fdx_calc_force_cutoff"]
 
 
 class FdxError(RuntimeError):
@@ -113,6 +114,7 @@ def _declare(L):
     L.fdx_get_exchange_lists.argtypes = [vp, vp, vp]
     L.fdx_get_exchange_stats.argtypes = [vp, C.POINTER(ExchangeStats)]
     L.fdx_calc_density.argtypes = [vp, i32, f64, vp, i32, i32, i32, i32]
+    L.fdx_calc_force_cutoff.argtypes = [vp, f64, i32, i32, f64, f64, i32]
     L.fdx_get_density.argtypes = [vp, vp, vp, i32]
 
 
@@ -325,6 +327,16 @@ class Context:
         st = ExchangeStats()
         self._check(self.lib.fdx_get_exchange_stats(self.h, C.byref(st)), "get_exchange_stats")
         return st.as_dict()
+
+    # -- tree part of TreePM ----------------------------------------------------------------
+    def calc_force_cutoff(self, theta: float, n_leaf: int, n_group: int, eps: float,
+                          r_cut: float, fp32: bool = False, persistent: bool = False,
+                          timing: bool = False):
+        flags = ((FP32REL if fp32 else 0) | (PERSISTENT if persistent else 0)
+                 | (TIMING if timing else 0))
+        self._check(self.lib.fdx_calc_force_cutoff(self.h, float(theta), int(n_leaf),
+                                                   int(n_group), float(eps), float(r_cut), flags),
+                    "calc_force_cutoff")
 
     # -- short-range neighbour lists and SPH density -------------------------------------
     def calc_density(self, mode: int, r_cut: float = 0.0, h=None, n_leaf: int = 8,
