@@ -154,6 +154,9 @@ def main():
     ap.add_argument("--sph-log2n", type=int, default=24,
                     help="also time the SPH density (fixed cutoff of 4.2 mean spacings, uniform "
                          "cube of 2^k particles; 0: skip)")
+    ap.add_argument("--treepm-log2n", type=int, default=24,
+                    help="also time the tree part of TreePM (uniform cube of 2^k particles, cutoff "
+                         "of three mesh widths; 0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -386,6 +389,30 @@ def main():
         del sps
         log(f"[bench] sph: {sph}")
 
+    # tree part of TreePM: monopole tree with the S2 cutoff, FP32 group-relative
+    treepm = None
+    if args.treepm_log2n > 0:
+        from paper_1601_03138_amd import treepm_timing
+        tps, r_cut = treepm_timing.workload(args.treepm_log2n)
+        ct = fdx.Context(0)
+        ct.set_particles(tps)
+        ct.calc_force_cutoff(0.5, 8, 256, 0.0, r_cut, fp32=True, timing=True)
+        rows = []
+        for _ in range(3):
+            ct.calc_force_cutoff(0.5, 8, 256, 0.0, r_cut, fp32=True, timing=True)
+            ts_ = ct.stats()
+            rows.append((ts_["t_walk"], ts_["t_force"], ts_["t_total"]))
+        med = np.median(np.array(rows), axis=0)
+        inter = int(ts_["n_interactions_pp"] + ts_["n_interactions_pc"])
+        treepm = {"n": tps.n, "r_cut": r_cut, "theta": 0.5, "n_group": 256, "dtype": "f32",
+                  "ms_walk": round(float(med[0]), 3), "ms_force": round(float(med[1]), 3),
+                  "ms_total": round(float(med[2]), 3),
+                  "particles_per_s": float(round(tps.n / (med[2] / 1e3), -5)),
+                  "interactions_per_s": float(round(inter / (med[1] / 1e3), -8))}
+        ct.close()
+        del tps
+        log(f"[bench] treepm tree part: {treepm}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
@@ -427,6 +454,7 @@ def main():
         "phase_gbs": phase_gbs,
         "exchange": exch,
         "sph": sph,
+        "treepm_tree": treepm,
         "energy_drift": drift,
         "predictor": pred,
         "autotune": tuned,
