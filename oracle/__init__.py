@@ -10,7 +10,8 @@ Two parts:
   O-T  `build_tree`, `make_groups`, `walk`, `tree_force`
                      a plain serial tree that fixes keys, order, cells, groups and lists
                      (the readings are documented in oracle.c next to each step).
-Plus the exchange lists between domains (`exchange`, section "Exchange of particles and
+Plus the multisection domain decomposition with cost-weighted sampling (`decompose`,
+section "Domain decomposition"), the exchange lists between domains (`exchange`, section "Exchange of particles and
 superparticles") with the force from received lists (`list_force`), the leapfrog of the
 sample program (`kdk`), energy and error diagnostics, and the list-length models (equations
 nlist_long and n_list_long).
@@ -85,6 +86,12 @@ def _declare(L):
     L.or_walk_cutoff.argtypes = [vp, i64, vp, vp, vp, f64, f64, vp, vp]
     L.or_walk_cutoff.restype = vp
     L.or_force_cutoff.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, f64, vp]
+    L.or_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+    L.or_splitmix64.restype = C.c_uint64
+    L.or_dd_sample.argtypes = [i64, vp, vp, C.c_uint64, vp]
+    L.or_dd_multisection.argtypes = [i64, vp, vp, vp, i32, i32, i32, vp, vp, vp, vp]
+    L.or_dd_multisection.restype = i32
+    L.or_dd_assign.argtypes = [i64, vp, vp, vp, i32, i32, i32, vp, vp, vp, vp]
 
 
 def _c(a, dt):
@@ -555,6 +562,112 @@ def exchange_list_model(n: float, theta: float, n_p: float) -> float:
     return (14.0 * n ** (2.0 / 3.0) / theta + 21.0 * math.pi * n ** (1.0 / 3.0) / theta ** 2
             + 28.0 * math.pi / (3.0 * theta ** 3)
             * math.log2(theta / 2.8 * ((n * n_p) ** (1.0 / 3.0) - n ** (1.0 / 3.0))))
+
+
+# ----------------------------------------------------------------------------------------
+# Domain decomposition (section "Domain decomposition"): multisection with sampling
+def splitmix64(seed: int, ctr: int) -> int:
+    """Output number ctr (0-based) of SplitMix64 seeded with seed."""
+    return int(lib().or_splitmix64(seed & (2 ** 64 - 1), ctr))
+
+
+def dd_factor(n: int):
+    """(n_x, n_y, n_z) for n domains: integers close to n^(1/3) -- among the factorisations
+    n_x >= n_y >= n_z, the one with the smallest n_x - n_z, then the smallest n_x - n_y."""
+    best = None
+    for nz in range(1, n + 1):
+        if n % nz:
+            continue
+        for ny in range(nz, n // nz + 1):
+            if (n // nz) % ny:
+                continue
+            nx = n // nz // ny
+            if nx < ny:
+                continue
+            k = (nx - nz, nx - ny)
+            if best is None or k < best[0]:
+                best = (k, (nx, ny, nz))
+    return best[1]
+
+
+def dd_sample_counts(n_p, cost, n_sample: int) -> np.ndarray:
+    """Samples drawn by each current domain: proportional to its cost, so that a sample
+    stands for the same work everywhere (the sampling rate is the cost per particle).
+    k_p = floor(n_sample * T_p / sum T) in FP64 (the sum taken in domain order), 0 for an
+    empty domain; T_p = cost[p], or the particle count when cost is None."""
+    n_p = [int(v) for v in n_p]
+    T = [float(v) for v in (n_p if cost is None else cost)]
+    total = 0.0
+    for t in T:
+        total += t
+    return np.array([0 if n_p[p] == 0 else int(math.floor(float(n_sample) * T[p] / total))
+                     for p in range(len(n_p))], dtype=np.int64)
+
+
+def dd_sample(off, k, seed: int) -> np.ndarray:
+    """Particle index of every sample (domains in order, k[p] samples each)."""
+    off = _c(off, np.int64)
+    k = _c(k, np.int64)
+    idx = np.zeros(max(int(k.sum()), 1), np.uint32)
+    lib().or_dd_sample(len(k), _p(off), _p(k), seed & (2 ** 64 - 1), _p(idx))
+    return idx[:int(k.sum())]
+
+
+def dd_multisection(sx, sy, sz, nx: int, ny: int, nz: int):
+    """Faces (bx [nx+1], by [nx, ny+1], bz [nx, ny, nz+1]) and the domain of every sample."""
+    K = len(sx)
+    bx = np.zeros(nx + 1)
+    by = np.zeros((nx, ny + 1))
+    bz = np.zeros((nx, ny, nz + 1))
+    cell = np.zeros(max(K, 1), np.uint32)
+    r = lib().or_dd_multisection(K, _p(_c(sx, np.float64)), _p(_c(sy, np.float64)),
+                                 _p(_c(sz, np.float64)), nx, ny, nz, _p(bx), _p(by), _p(bz),
+                                 _p(cell))
+    if r != 0:
+        raise ValueError("fewer samples than domains")
+    return bx, by, bz, cell[:K]
+
+
+def dd_assign(x, y, z, nx: int, ny: int, nz: int, bx, by, bz) -> np.ndarray:
+    """Destination domain of every particle."""
+    n = len(x)
+    dest = np.zeros(max(n, 1), np.uint32)
+    lib().or_dd_assign(n, _p(_c(x, np.float64)), _p(_c(y, np.float64)), _p(_c(z, np.float64)),
+                       nx, ny, nz, _p(_c(bx, np.float64)), _p(_c(by, np.float64)),
+                       _p(_c(bz, np.float64)), _p(dest))
+    return dest[:n]
+
+
+def dd_exchange(dest, src, n_dom: int, n_src: int):
+    """The exchange of particles: the new order (particles grouped by destination; within a
+    destination by source domain, then by position, i.e. a stable grouping), the send
+    counts [source, destination] and the offsets of the new domains."""
+    dest = np.asarray(dest, np.int64)
+    order = np.argsort(dest, kind="stable").astype(np.uint32)
+    counts = np.zeros((n_src, n_dom), np.int64)
+    np.add.at(counts, (np.asarray(src, np.int64), dest), 1)
+    dom_off = np.concatenate([[0], np.cumsum(counts.sum(axis=0))]).astype(np.int64)
+    return order, counts, dom_off
+
+
+class Decomposition:
+    def __init__(self, **kw):
+        self.__dict__.update(kw)
+
+
+def decompose(ps, nx: int, ny: int, nz: int, n_sample: int, cost=None, seed: int = 0):
+    """The whole decomposition of a particle set whose systems are the current domains:
+    sample counts, samples, multisection, destinations and the exchange."""
+    off = ps.offsets()
+    n_p = np.diff(off)
+    k = dd_sample_counts(n_p, cost, n_sample)
+    idx = dd_sample(off, k, seed)
+    bx, by, bz, cell = dd_multisection(ps.x[idx], ps.y[idx], ps.z[idx], nx, ny, nz)
+    dest = dd_assign(ps.x, ps.y, ps.z, nx, ny, nz, bx, by, bz)
+    src = np.repeat(np.arange(len(n_p)), n_p)
+    order, counts, dom_off = dd_exchange(dest, src, nx * ny * nz, len(n_p))
+    return Decomposition(k=k, idx=idx, bx=bx, by=by, bz=bz, cell=cell, dest=dest, order=order,
+                         counts=counts, dom_off=dom_off)
 
 
 def rms_rel_error(a: np.ndarray, a_ref: np.ndarray) -> float:

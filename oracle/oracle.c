@@ -16,6 +16,9 @@
  *     angle (section "Exchange of particles and superparticles"), and the particle /
  *     superparticle force of equations (ParticleParticleNbody) and
  *     (ParticleSuperparticleNbody).
+ *   - the exchange lists between domains, the short-range neighbour walk with the SPH
+ *     density, the cutoff tree of TreePM, and the multisection domain decomposition with
+ *     cost-weighted sampling (section "Domain decomposition"), each at its own section below.
  * Where the paper is silent (how keys and cells are formed, the opening test, group shape,
  * quadrupole formula) the oracle implements one fixed reading; each is stated at the
  * function that implements it.
@@ -838,5 +841,132 @@ void or_force_cutoff(void *wh, const uint32_t *gbegin, const uint32_t *gcount, c
             acc[3 * (size_t)i] = nval(&ax); acc[3 * (size_t)i + 1] = nval(&ay);
             acc[3 * (size_t)i + 2] = nval(&az);
         }
+    }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Domain decomposition (section "Domain decomposition"): the multisection method with
+ * the sampling method.  The domains are n_x n_y n_z boxes; the division is applied once
+ * per axis -- n_x slabs in x, each slab cut into n_y columns in y, each column into n_z
+ * domains in z -- so that the sample particles are equally divided.  The current domains
+ * (the systems of the particle set) each draw a number of samples proportional to their
+ * cost, so that every sample stands for the same amount of work.
+ * Readings (the paper does not fix them):
+ *   - samples are drawn with replacement, uniformly over the domain's particles: sample s
+ *     of a domain with n_p particles starting at off_p is particle
+ *     off_p + floor(r * n_p / 2^64), r = SplitMix64 output number s for the seed;
+ *   - a division sorts the samples of a segment by coordinate (ties by sample number) and
+ *     cuts them into runs of equal count, run i being the sorted ranks
+ *     [floor(i K / n), floor((i + 1) K / n)); each cut lies at the midpoint of the two
+ *     samples on either side of it, the outer faces are -inf and +inf;
+ *   - a particle belongs to the domain whose box holds it, lower faces closed and upper
+ *     faces open. */
+
+/* SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number generators",
+ * OOPSLA 2014): a Weyl sequence with increment 0x9E3779B97F4A7C15 followed by a 64-bit
+ * finaliser.  Output number ctr (0-based) of the generator seeded with seed. */
+uint64_t or_splitmix64(uint64_t seed, uint64_t ctr) {
+    uint64_t z = seed + (ctr + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* particle index of every sample: k[p] samples of current domain p (particles
+ * [off[p], off[p+1])), numbered consecutively over the domains in order */
+void or_dd_sample(int64_t nsys, const int64_t *off, const int64_t *k, uint64_t seed,
+                  uint32_t *idx) {
+    uint64_t s = 0;
+    for (int64_t p = 0; p < nsys; p++) {
+        uint64_t np = (uint64_t)(off[p + 1] - off[p]);
+        for (int64_t j = 0; j < k[p]; j++, s++) {
+            unsigned __int128 prod = (unsigned __int128)or_splitmix64(seed, s) * np;
+            idx[s] = (uint32_t)(off[p] + (int64_t)(uint64_t)(prod >> 64));
+        }
+    }
+}
+
+typedef struct { double v; uint32_t s; } dd_item;
+
+static int dd_cmp(const void *a, const void *b) {
+    const dd_item *x = (const dd_item *)a, *y = (const dd_item *)b;
+    if (x->v < y->v) return -1;
+    if (x->v > y->v) return 1;
+    return (x->s > y->s) - (x->s < y->s);
+}
+
+/* Divide the samples listed in items[0..K) (sorted here in place by coordinate v, ties by
+ * sample number) into n runs of equal count: run i of the sorted ranks is
+ * [floor(i K / n), floor((i + 1) K / n)).  b[0..n] receives the faces (b[0] = -inf,
+ * b[n] = +inf, b[i] = midpoint of the samples at ranks floor(i K / n) - 1 and floor(i K / n))
+ * and run[t] the run of the t-th sorted sample. */
+static void dd_divide(dd_item *items, int64_t K, int n, double *b, int *run) {
+    qsort(items, (size_t)K, sizeof(dd_item), dd_cmp);
+    b[0] = -INFINITY;
+    b[n] = INFINITY;
+    for (int i = 1; i < n; i++) {
+        int64_t r = (int64_t)i * K / n;
+        b[i] = (items[r - 1].v + items[r].v) * 0.5;
+    }
+    for (int i = 0; i < n; i++)
+        for (int64_t t = (int64_t)i * K / n; t < (int64_t)(i + 1) * K / n; t++) run[t] = i;
+}
+
+/* The multisection of K samples (coordinates sx, sy, sz; sample number = position) into
+ * nx x ny x nz domains.  Needs K >= nx ny nz so that every run holds a sample.  Outputs the
+ * faces bx[nx+1], by[nx][ny+1], bz[nx][ny][nz+1] and the domain (ix ny + iy) nz + iz of
+ * every sample.  Returns 0, or -1 when K is too small. */
+int or_dd_multisection(int64_t K, const double *sx, const double *sy, const double *sz, int nx,
+                       int ny, int nz, double *bx, double *by, double *bz, uint32_t *cell) {
+    if (K < (int64_t)nx * ny * nz) return -1;
+    dd_item *it = (dd_item *)malloc(sizeof(dd_item) * (size_t)(K > 0 ? K : 1));
+    dd_item *sub = (dd_item *)malloc(sizeof(dd_item) * (size_t)(K > 0 ? K : 1));
+    int *run = (int *)malloc(sizeof(int) * (size_t)(K > 0 ? K : 1));
+    int *ix = (int *)malloc(sizeof(int) * (size_t)(K > 0 ? K : 1));
+    int *iy = (int *)malloc(sizeof(int) * (size_t)(K > 0 ? K : 1));
+    /* x: all samples */
+    for (int64_t s = 0; s < K; s++) { it[s].v = sx[s]; it[s].s = (uint32_t)s; }
+    dd_divide(it, K, nx, bx, run);
+    for (int64_t t = 0; t < K; t++) ix[it[t].s] = run[t];
+    /* y: the samples of each slab */
+    for (int a = 0; a < nx; a++) {
+        int64_t m = 0;
+        for (int64_t s = 0; s < K; s++)
+            if (ix[s] == a) { sub[m].v = sy[s]; sub[m].s = (uint32_t)s; m++; }
+        dd_divide(sub, m, ny, by + (size_t)a * (ny + 1), run);
+        for (int64_t t = 0; t < m; t++) iy[sub[t].s] = run[t];
+    }
+    /* z: the samples of each column */
+    for (int a = 0; a < nx; a++)
+        for (int c = 0; c < ny; c++) {
+            int64_t m = 0;
+            for (int64_t s = 0; s < K; s++)
+                if (ix[s] == a && iy[s] == c) { sub[m].v = sz[s]; sub[m].s = (uint32_t)s; m++; }
+            int col = a * ny + c;
+            dd_divide(sub, m, nz, bz + (size_t)col * (nz + 1), run);
+            for (int64_t t = 0; t < m; t++) cell[sub[t].s] = (uint32_t)(col * nz + run[t]);
+        }
+    free(it); free(sub); free(run); free(ix); free(iy);
+    return 0;
+}
+
+/* number of faces b[1..n-1] at or below v: the run of [b[i], b[i+1]) that holds v */
+static int dd_run_of(const double *b, int n, double v) {
+    int i = 0;
+    for (int j = 1; j < n; j++)
+        if (b[j] <= v) i = j;
+    return i;
+}
+
+/* destination domain of every particle: the box of the multisection that holds it */
+void or_dd_assign(int64_t n, const double *x, const double *y, const double *z, int nx, int ny,
+                  int nz, const double *bx, const double *by, const double *bz, uint32_t *dest) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++) {
+        int a = dd_run_of(bx, nx, x[i]);
+        int c = dd_run_of(by + (size_t)a * (ny + 1), ny, y[i]);
+        int col = a * ny + c;
+        int e = dd_run_of(bz + (size_t)col * (nz + 1), nz, z[i]);
+        dest[i] = (uint32_t)(col * nz + e);
     }
 }
