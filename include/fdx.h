@@ -295,6 +295,75 @@ int fdx_calc_density(fdx_ctx *ctx, int32_t mode, double r_cut, const double *h, 
                      int32_t n_leaf, int32_t n_group, int32_t flags);
 int fdx_get_density(fdx_ctx *ctx, double *rho, uint32_t *n_ngb, int32_t mem_kind);
 
+/* ---- Domain decomposition: multisection with cost-weighted sampling ---------------------
+ * Section "Domain decomposition": the domains are n_x n_y n_z boxes found by dividing once
+ * per axis -- n_x slabs along x, each slab into n_y columns along y, each column into n_z
+ * domains along z -- so that sample particles are equally divided; each current domain (a
+ * system of the particle set, standing in for a process) samples its own particles at a rate
+ * proportional to its cost per particle, so that every sample stands for the same work.
+ * Then every particle is sent to the domain whose box holds it (the exchange of particles).
+ *   Samples: current domain p with n_p particles draws
+ *     k_p = floor(n_sample * T_p / sum_q T_q)   (FP64, the sum in domain order; 0 if n_p = 0)
+ *   samples; T_p = cost[p] when given, else the count of members times list length summed
+ *   over p's groups in the last walk (FDX_DD_COST_LISTS), else n_p (uniform sampling).
+ *   Sample s (numbered over the domains in order) is particle
+ *   off_p + floor(r_s n_p / 2^64), r_s = output number s of SplitMix64 seeded with seed.
+ *   Division: each segment's samples sorted by coordinate (ties by sample number) are cut
+ *   into n runs, run i = sorted ranks [floor(i m / n), floor((i+1) m / n)) of its m samples;
+ *   a cut lies at the midpoint (a + b) * 0.5 of the samples on either side; the outer faces
+ *   are -inf and +inf.  Domain (ix, iy, iz) is number (ix n_y + iy) n_z + iz and holds the
+ *   particles with bx[ix] <= x < bx[ix+1], by[ix][iy] <= y < by[ix][iy+1],
+ *   bz[ix][iy][iz] <= z < bz[ix][iy][iz+1].
+ *   Exchange: the new order lists the particles grouped by destination, within one
+ *   destination in their current order (that is, by source domain, then position).
+ * fdx_dd_factor: (n_x, n_y, n_z) for n domains, integers close to n^(1/3): among the
+ *   factorisations n_x >= n_y >= n_z, the smallest n_x - n_z, then the smallest n_x - n_y.
+ *   Host only.  FDX_EINVAL: n < 1 or a null pointer.
+ * fdx_decompose: n_x, n_y, n_z >= 1; n_sample in [1, 2^31); cost = host array of n_sys
+ *   finite non-negative values or null; flags FDX_DD_COST_LISTS (needs cost == null and a walk
+ *   on the current particles).  Work is enqueued on the stream (FDX_DD_COST_LISTS reads the
+ *   costs back first).  FDX_EINVAL: a size out of range, more than 2^24 (source, destination)
+ *   pairs, a bad cost, a zero total cost, or fewer samples than domains; FDX_ESTATE: no
+ *   particles, or no walk for FDX_DD_COST_LISTS.
+ * fdx_get_decomposition: faces bx[n_x+1], by[n_x][n_y+1], bz[n_x][n_y][n_z+1], the send
+ *   counts [source p][destination d] (n_sys x n_domains) and the new domain offsets
+ *   dom_off[n_domains+1]; host memory, null skips.
+ * fdx_get_dd_samples: k_p per current domain (n_sys), the particle of every sample and the
+ *   domain its division put it in (K = sum k_p each; fdx_get_dd_stats gives K); host, null
+ *   skips.
+ * fdx_get_dd_destinations: dest[i] for every particle (current order) and order[r] = the
+ *   current index of the particle at new position r (length n each), host or device memory.
+ * fdx_exchange_particles: applies the last decomposition: the context's particles are
+ *   reordered into the new order on the device (into library-owned memory, also when they
+ *   were borrowed) and the domains become the systems (n_sys = n_domains, sys_off =
+ *   dom_off).  Afterwards every getter's "caller's order" is the new order; earlier forces
+ *   and lists are dropped.
+ * fdx_get_dd_stats: sizes, n_moved = particles whose destination number differs from their
+ *   current domain number, and the device time of each part.
+ * The getters and fdx_exchange_particles return FDX_ESTATE without a decomposition of the
+ * current particles (fdx_set_particles drops it; the exchange keeps it readable). */
+#define FDX_DD_COST_LISTS 1
+typedef struct {
+    int32_t nx, ny, nz, n_domains, n_src;
+    int64_t n_samples;                 /* K */
+    int64_t n_moved;
+    double ms_sample;                  /* costs (if from lists), samples */
+    double ms_divide;                  /* three sorts of the samples and their cuts */
+    double ms_assign;                  /* destinations, partition sort, send counts */
+    double ms_exchange;                /* reorder of the particle arrays (0 if not applied) */
+} fdx_dd_stats;
+
+int fdx_dd_factor(int32_t n, int32_t *nx, int32_t *ny, int32_t *nz);
+int fdx_decompose(fdx_ctx *ctx, int32_t nx, int32_t ny, int32_t nz, int64_t n_sample,
+                  const double *cost, uint64_t seed, int32_t flags);
+int fdx_get_decomposition(fdx_ctx *ctx, double *bx, double *by, double *bz,
+                          int64_t *send_counts, int64_t *dom_off);
+int fdx_get_dd_samples(fdx_ctx *ctx, int64_t *k_per_domain, uint32_t *sample_idx,
+                       uint32_t *sample_domain);
+int fdx_get_dd_destinations(fdx_ctx *ctx, uint32_t *dest, uint32_t *order, int32_t mem_kind);
+int fdx_exchange_particles(fdx_ctx *ctx);
+int fdx_get_dd_stats(fdx_ctx *ctx, fdx_dd_stats *out);
+
 /* Message of the last failed call on ctx (never null; "" when none). */
 const char *fdx_last_error(const fdx_ctx *ctx);
 

@@ -170,6 +170,33 @@ hipError_t sph_density(int mode, size_t gmax, const Groups g, const uint64_t *se
                        hipStream_t s);
 hipError_t sph_unsort(size_t n, const uint32_t *inv, const double *rho_s, const uint32_t *n_s,
                       double *rho, uint32_t *nngb, hipStream_t s);
+// domain decomposition (k_dd.hip): cost of each current domain from the last walk (sum of
+// members x list length over its groups, added to cost), samples of the current domains,
+// one division pass over samples sorted by (segment, coordinate), destination and partition
+// key (destination * nsrc + current domain) of every particle, the (destination, source) runs
+// of the sorted keys, and the gather of up to 8 FP64 arrays into the new order
+struct DdArrays {
+    double *p[8];
+};
+hipError_t dd_cost(uint32_t G, const uint32_t *g_sys, const uint32_t *g_count,
+                   const uint32_t *cnt_e, const uint32_t *cnt_s, uint64_t *cost, hipStream_t s);
+hipError_t dd_sample(uint32_t K, uint32_t nsys, const int64_t *kofs, const int64_t *off,
+                     uint64_t seed, const double *x, const double *y, const double *z,
+                     uint32_t *idx, double *sx, double *sy, double *sz, uint64_t *key,
+                     uint32_t *val, hipStream_t s);
+hipError_t dd_cut(uint32_t K, uint32_t nseg, const uint32_t *start, uint32_t n,
+                  const uint32_t *val, const double *coord, const double *next, uint32_t *cell,
+                  uint32_t *new_start, double *face, uint64_t *key_next, uint32_t *val_next,
+                  hipStream_t s);
+hipError_t dd_assign(uint32_t n, const double *x, const double *y, const double *z,
+                     const uint32_t *sysid, uint32_t nsrc, uint32_t nx, uint32_t ny, uint32_t nz,
+                     const double *bx, const double *by, const double *bz, uint32_t *dest,
+                     uint64_t *key, uint32_t *val, hipStream_t s);
+hipError_t dd_runs(uint32_t n, const uint64_t *key, uint32_t *run_lo, uint32_t *run_hi,
+                   hipStream_t s);
+hipError_t dd_gather(uint32_t n, const uint32_t *order, int narr, const DdArrays &src,
+                     const DdArrays &dst, hipStream_t s);
+
 // queue order for the persistent force kernel: groups by decreasing estimated cost
 hipError_t queue_keys(size_t gmax, const Groups g, const uint32_t *cnt_e, const uint32_t *cnt_s,
                       uint64_t *key, uint32_t *val, DevStatus *st, hipStream_t s);

@@ -183,6 +183,7 @@ void ext_release(fdx_ctx *c) {
     predictor_release(c);
     exchange_release(c);
     sph_release(c);
+    dd_release(c);
 }
 
 }  // namespace fdx

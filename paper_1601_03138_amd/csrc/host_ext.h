@@ -16,6 +16,7 @@ struct HostExt {
     void *graph = nullptr;            // captured step (GraphState)
     void *exch = nullptr;             // exchange lists between domains
     void *sph = nullptr;              // SPH density state
+    void *dd = nullptr;               // domain decomposition state
     int64_t graph_recoveries = 0;     // replays whose capacities overflowed and were redone
 };
 
@@ -27,5 +28,6 @@ void ext_invalidate(fdx_ctx *c);   // drop any captured graph (particles or buff
 int ext_predicted_walk(fdx_ctx *c, uint32_t G);
 void exchange_release(fdx_ctx *c);
 void sph_release(fdx_ctx *c);
+void dd_release(fdx_ctx *c);
 
 }  // namespace fdx

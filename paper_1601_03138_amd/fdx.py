@@ -19,6 +19,7 @@ OK, EINVAL, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4
 MEM_HOST, MEM_DEVICE = 0, 1
 QUAD, FP32REL, PREDICTOR, PERSISTENT, GRAPH, TIMING = 1, 2, 4, 8, 16, 32
 CUT_FIXED, CUT_SCATTER, CUT_GATHER, CUT_SYMMETRIC = 0, 1, 2, 3
+DD_COST_LISTS = 1
 
 EXPORTS = ["fdx_create", "fdx_destroy", "fdx_set_particles", "fdx_build_tree", "fdx_calc_force",
            "fdx_integrate", "fdx_get_particles", "fdx_get_forces", "fdx_get_stats",
@@ -28,7 +29,9 @@ EXPORTS = ["fdx_create", "fdx_destroy", "fdx_set_particles", "fdx_build_tree", "
            "fdx_predictor_margin", "fdx_predictor_save", "fdx_predictor_load",
            "fdx_build_exchange_lists", "fdx_get_exchange_counts", "fdx_get_exchange_lists",
            "fdx_get_exchange_stats", "fdx_calc_density", "fdx_get_density",
-           "fdx_calc_force_cutoff"]
+           "fdx_calc_force_cutoff", "fdx_dd_factor", "fdx_decompose", "fdx_get_decomposition",
+           "fdx_get_dd_samples", "fdx_get_dd_destinations", "fdx_exchange_particles",
+           "fdx_get_dd_stats"]
 
 
 class FdxError(RuntimeError):
@@ -54,6 +57,16 @@ class ExchangeStats(C.Structure):
     _fields_ = [("n_domains", C.c_int64), ("n_pairs", C.c_int64), ("n_epj", C.c_int64),
                 ("n_spj", C.c_int64), ("list_capacity", C.c_int64), ("ms_tree", C.c_double),
                 ("ms_lists", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class DdStats(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("n_domains", C.c_int32), ("n_src", C.c_int32), ("n_samples", C.c_int64),
+                ("n_moved", C.c_int64), ("ms_sample", C.c_double), ("ms_divide", C.c_double),
+                ("ms_assign", C.c_double), ("ms_exchange", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -116,6 +129,13 @@ def _declare(L):
     L.fdx_calc_density.argtypes = [vp, i32, f64, vp, i32, i32, i32, i32]
     L.fdx_calc_force_cutoff.argtypes = [vp, f64, i32, i32, f64, f64, i32]
     L.fdx_get_density.argtypes = [vp, vp, vp, i32]
+    L.fdx_dd_factor.argtypes = [i32, vp, vp, vp]
+    L.fdx_decompose.argtypes = [vp, i32, i32, i32, i64, vp, C.c_uint64, i32]
+    L.fdx_get_decomposition.argtypes = [vp] + [vp] * 5
+    L.fdx_get_dd_samples.argtypes = [vp] + [vp] * 3
+    L.fdx_get_dd_destinations.argtypes = [vp, vp, vp, i32]
+    L.fdx_exchange_particles.argtypes = [vp]
+    L.fdx_get_dd_stats.argtypes = [vp, C.POINTER(DdStats)]
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -328,6 +348,56 @@ class Context:
         self._check(self.lib.fdx_get_exchange_stats(self.h, C.byref(st)), "get_exchange_stats")
         return st.as_dict()
 
+    # -- domain decomposition: multisection with cost-weighted sampling --------------------
+    def decompose(self, nx: int, ny: int, nz: int, n_sample: int, cost=None, seed: int = 0,
+                  cost_lists: bool = False):
+        """cost: one value per current domain (system), or None (particle counts, or the
+        list lengths of the last walk with cost_lists)."""
+        cp = None
+        if cost is not None:
+            self._keep = [_f64(cost)]
+            cp = _ptr(self._keep[0])
+        self._check(self.lib.fdx_decompose(self.h, int(nx), int(ny), int(nz), int(n_sample), cp,
+                                           int(seed) & (2 ** 64 - 1),
+                                           DD_COST_LISTS if cost_lists else 0), "decompose")
+
+    def dd_stats(self) -> dict:
+        st = DdStats()
+        self._check(self.lib.fdx_get_dd_stats(self.h, C.byref(st)), "get_dd_stats")
+        return st.as_dict()
+
+    def decomposition(self) -> dict:
+        """faces bx [nx+1], by [nx, ny+1], bz [nx, ny, nz+1]; send counts [source, destination];
+        dom_off [n_domains+1]."""
+        st = self.dd_stats()
+        nx, ny, nz, D, S = st["nx"], st["ny"], st["nz"], st["n_domains"], st["n_src"]
+        bx, by, bz = np.empty(nx + 1), np.empty((nx, ny + 1)), np.empty((nx, ny, nz + 1))
+        counts, off = np.empty((S, D), np.int64), np.empty(D + 1, np.int64)
+        self._check(self.lib.fdx_get_decomposition(self.h, _ptr(bx), _ptr(by), _ptr(bz),
+                                                   _ptr(counts), _ptr(off)), "get_decomposition")
+        return {"bx": bx, "by": by, "bz": bz, "counts": counts, "dom_off": off}
+
+    def dd_samples(self):
+        """(k per current domain, particle index of every sample, domain of every sample)."""
+        st = self.dd_stats()
+        K = int(st["n_samples"])
+        k = np.empty(st["n_src"], np.int64)
+        idx, cell = np.empty(max(K, 1), np.uint32), np.empty(max(K, 1), np.uint32)
+        self._check(self.lib.fdx_get_dd_samples(self.h, _ptr(k), _ptr(idx), _ptr(cell)),
+                    "get_dd_samples")
+        return k, idx[:K], cell[:K]
+
+    def dd_destinations(self):
+        """(dest per particle in the current order, order[r] = current index at new position r)
+        as numpy arrays."""
+        dest, order = np.empty(max(self.n, 1), np.uint32), np.empty(max(self.n, 1), np.uint32)
+        self._check(self.lib.fdx_get_dd_destinations(self.h, _ptr(dest), _ptr(order), MEM_HOST),
+                    "get_dd_destinations")
+        return dest[:self.n], order[:self.n]
+
+    def exchange_particles(self):
+        self._check(self.lib.fdx_exchange_particles(self.h), "exchange_particles")
+
     # -- tree part of TreePM ----------------------------------------------------------------
     def calc_force_cutoff(self, theta: float, n_leaf: int, n_group: int, eps: float,
                           r_cut: float, fp32: bool = False, persistent: bool = False,
@@ -407,3 +477,12 @@ class Context:
 
     def predictor_load(self, path: str):
         self._check(self.lib.fdx_predictor_load(self.h, path.encode()), "predictor_load")
+
+
+def dd_factor(n: int):
+    """(n_x, n_y, n_z) for n domains, integers close to n^(1/3)."""
+    a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+    r = load().fdx_dd_factor(int(n), C.byref(a), C.byref(b), C.byref(c))
+    if r != 0:
+        raise FdxError(r, "dd_factor: n must be >= 1")
+    return a.value, b.value, c.value

@@ -49,3 +49,13 @@ def test_null_context_calls_fail_cleanly(lib):
     assert lib.fdx_destroy(None) == 0
     lib.fdx_create.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
     assert lib.fdx_create(None, 0, None) == -1
+
+
+def test_domain_factorisation_matches_the_oracle():
+    # fdx_dd_factor is host-only logic: no GPU needed
+    import oracle as O
+    from paper_1601_03138_amd import fdx
+    for n in range(1, 400):
+        assert fdx.dd_factor(n) == O.dd_factor(n), n
+    with pytest.raises(fdx.FdxError):
+        fdx.dd_factor(0)
