@@ -154,6 +154,10 @@ def main():
     ap.add_argument("--sph-log2n", type=int, default=24,
                     help="also time the SPH density (fixed cutoff of 4.2 mean spacings, uniform "
                          "cube of 2^k particles; 0: skip)")
+    ap.add_argument("--dd-k", type=int, default=4,
+                    help="domain decomposition of the clustered workload from k^3 current "
+                         "domains into k^3 new ones (0: skip)")
+    ap.add_argument("--dd-samples", type=int, default=1 << 20)
     ap.add_argument("--treepm-log2n", type=int, default=24,
                     help="also time the tree part of TreePM (uniform cube of 2^k particles, cutoff "
                          "of three mesh widths; 0: skip)")
@@ -360,6 +364,22 @@ def main():
             del tr
         log(f"[bench] exchange lists: {exch}")
 
+    # multisection domain decomposition with cost-weighted sampling + exchange of particles
+    dd = None
+    if args.dd_k > 0 and ps.n_sys == 1:
+        from paper_1601_03138_amd import dd_timing
+        kd = args.dd_k
+        ddom = dom if exch is not None and kd == args.exchange_domains else \
+            inputs.multisection(ps, kd, kd, kd)[0]
+        dd = dd_timing.run(ddom, kd, args.dd_samples, 3, theta, log=log)
+        if not args.no_cpu_baseline:
+            import oracle as O
+            ta = time.perf_counter()
+            O.decompose(ddom, kd, kd, kd, args.dd_samples, seed=1)
+            dd["cpu_oracle_s_uniform_cost"] = round(time.perf_counter() - ta, 2)
+        del ddom
+        log(f"[bench] domain decomposition: {dd}")
+
     # SPH density: short-range neighbour lists (fixed cutoff) + Wendland C6 density, FP64
     sph = None
     if args.sph_log2n > 0:
@@ -453,6 +473,7 @@ def main():
         "phases_ms": phase_ms,
         "phase_gbs": phase_gbs,
         "exchange": exch,
+        "domain_decomposition": dd,
         "sph": sph,
         "treepm_tree": treepm,
         "energy_drift": drift,

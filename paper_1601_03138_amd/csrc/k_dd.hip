@@ -44,14 +44,26 @@ __device__ __forceinline__ uint32_t last_le(const T *a, uint32_t n, T v) {
     return lo;
 }
 
+// groups come in system order, so a wave's groups belong to few systems: each wave sums its
+// weights per system and issues one atomic per system it holds
 __global__ void __launch_bounds__(kThreads)
 k_dd_cost(uint32_t G, const uint32_t *g_sys, const uint32_t *g_count, const uint32_t *cnt_e,
           const uint32_t *cnt_s, unsigned long long *cost) {
     const uint32_t g = blockIdx.x * kThreads + threadIdx.x;
-    if (g >= G) return;
+    const bool valid = g < G;
+    const uint32_t sys = valid ? g_sys[g] : 0xFFFFFFFFu;
     const unsigned long long w =
-        (unsigned long long)g_count[g] * ((unsigned long long)cnt_e[g] + cnt_s[g]);
-    atomicAdd(&cost[g_sys[g]], w);
+        valid ? (unsigned long long)g_count[g] * ((unsigned long long)cnt_e[g] + cnt_s[g]) : 0ull;
+    uint64_t pending = __ballot(valid);
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const uint32_t s0 = __shfl(sys, leader);
+        const bool mine = valid && sys == s0;
+        pending &= ~__ballot(mine);
+        unsigned long long v = mine ? w : 0ull;
+        for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane_id() == leader) atomicAdd(&cost[s0], v);
+    }
 }
 
 // sample s of the domain p with kofs[p] <= s < kofs[p+1]: particle

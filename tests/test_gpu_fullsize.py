@@ -2,7 +2,7 @@
 times: keys, order, every cell and every group bit-exact against the oracle's full serial
 build; lists and forces on sampled groups; accuracy against FP64 direct summation on seeded
 subsets; the ensemble with graph-captured steps; the predictor path at full size; the
-exchange lists of the benchmark input cut into 64 domains."""
+exchange lists of the benchmark input cut into 64 domains; its multisection domain decomposition."""
 import os
 import sys
 
@@ -191,5 +191,41 @@ def test_clustered16m_exchange_lists_64_domains(fdx):
         st = c.exchange_stats()
         _say(f"  entries {int(ne.sum() + ns.sum())}; device ms: trees {st['ms_tree']:.3f}, "
              f"lists {st['ms_lists']:.3f}")
+    finally:
+        c.close()
+
+
+def test_clustered16m_domain_decomposition_64_domains(fdx):
+    """The benchmark input in 4 x 4 x 4 current domains decomposed again into 4 x 4 x 4 from
+    2^20 samples drawn in proportion to a cost per domain: samples, faces, destinations,
+    exchange order and send counts bit-exact; the exchange of particles applied."""
+    ps = I.workload("clustered16m")
+    dom, _ = I.multisection(ps, 4, 4, 4)
+    n_p = np.diff(dom.offsets())
+    cost = n_p * (1.0 + np.arange(dom.n_sys) % 5)
+    _say(f"[fullsize] domain decomposition, n={dom.n} current domains={dom.n_sys}")
+    ref = O.decompose(dom, 4, 4, 4, 1 << 20, cost=cost, seed=1)
+    c = fdx.Context(0)
+    try:
+        c.set_particles(dom)
+        c.decompose(4, 4, 4, 1 << 20, cost=cost, seed=1)
+        k, idx, cell = c.dd_samples()
+        assert np.array_equal(k, ref.k) and np.array_equal(idx, ref.idx)
+        assert np.array_equal(cell, ref.cell)
+        d = c.decomposition()
+        for f in ("bx", "by", "bz"):
+            assert np.array_equal(d[f], getattr(ref, f)), f
+        dest, order = c.dd_destinations()
+        assert np.array_equal(dest, ref.dest) and np.array_equal(order, ref.order)
+        assert np.array_equal(d["counts"], ref.counts)
+        assert np.array_equal(d["dom_off"], ref.dom_off)
+        c.exchange_particles()
+        x, y, z, vx, vy, vz = c.particles()
+        o = ref.order.astype(np.int64)
+        assert np.array_equal(x, dom.x[o]) and np.array_equal(vz, dom.vz[o])
+        st = c.dd_stats()
+        _say(f"  samples {st['n_samples']}, moved {st['n_moved']}; device ms: sample "
+             f"{st['ms_sample']:.3f}, divide {st['ms_divide']:.3f}, assign "
+             f"{st['ms_assign']:.3f}, exchange {st['ms_exchange']:.3f}")
     finally:
         c.close()
