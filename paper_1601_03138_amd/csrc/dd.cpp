@@ -244,17 +244,18 @@ int fdx_decompose(fdx_ctx *c, int32_t nx, int32_t ny, int32_t nz, int64_t n_samp
     }
     HIPCHK(c, hipEventRecord(d->ev[2], s));
 
-    // destinations, grouping by (destination, source), send-count runs
-    HIPCHK(c, dd_assign((uint32_t)N, c->x, c->y, c->z, c->sysid.p, (uint32_t)nsrc, nx, ny, nz,
-                        bx, by, bz, d->dest.p, d->pkey.p, d->pval.p, s));
+    // destinations, stable grouping by destination, send-count runs
+    HIPCHK(c, dd_assign((uint32_t)N, c->x, c->y, c->z, nx, ny, nz, bx, by, bz, d->dest.p,
+                        d->pkey.p, d->pval.p, s));
     bool palt = false;
     HIPCHK(c, radix_sort(N, d->pkey.p, d->pkey_alt.p, d->pval.p, d->pval_alt.p, nullptr, 1,
-                         bits_for(D * (uint64_t)nsrc - 1), c->rs_scratch.p, c->partial.p, &palt, s));
+                         bits_for(D - 1), c->rs_scratch.p, c->partial.p, &palt, s));
     d->order = palt ? d->pval_alt.p : d->pval.p;
     const uint64_t *psorted = palt ? d->pkey_alt.p : d->pkey.p;
     HIPCHK(c, hipMemsetAsync(d->run_lo.p, 0, 4 * D * nsrc, s));
     HIPCHK(c, hipMemsetAsync(d->run_hi.p, 0, 4 * D * nsrc, s));
-    HIPCHK(c, dd_runs((uint32_t)N, psorted, d->run_lo.p, d->run_hi.p, s));
+    HIPCHK(c, dd_runs((uint32_t)N, psorted, d->order, c->sysid.p, (uint32_t)nsrc, d->run_lo.p,
+                      d->run_hi.p, s));
     HIPCHK(c, hipEventRecord(d->ev[3], s));
 
     d->nx = nx; d->ny = ny; d->nz = nz; d->nsrc = nsrc;

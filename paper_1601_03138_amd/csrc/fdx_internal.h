@@ -172,9 +172,9 @@ hipError_t sph_unsort(size_t n, const uint32_t *inv, const double *rho_s, const 
                       double *rho, uint32_t *nngb, hipStream_t s);
 // domain decomposition (k_dd.hip): cost of each current domain from the last walk (sum of
 // members x list length over its groups, added to cost), samples of the current domains,
-// one division pass over samples sorted by (segment, coordinate), destination and partition
-// key (destination * nsrc + current domain) of every particle, the (destination, source) runs
-// of the sorted keys, and the gather of up to 8 FP64 arrays into the new order
+// one division pass over samples sorted by (segment, coordinate), destination (the grouping
+// key) of every particle, the (destination, source) runs of the grouped order, and the
+// gather of up to 8 FP64 arrays into the new order
 struct DdArrays {
     double *p[8];
 };
@@ -188,11 +188,12 @@ hipError_t dd_cut(uint32_t K, uint32_t nseg, const uint32_t *start, uint32_t n,
                   const uint32_t *val, const double *coord, const double *next, uint32_t *cell,
                   uint32_t *new_start, double *face, uint64_t *key_next, uint32_t *val_next,
                   hipStream_t s);
-hipError_t dd_assign(uint32_t n, const double *x, const double *y, const double *z,
-                     const uint32_t *sysid, uint32_t nsrc, uint32_t nx, uint32_t ny, uint32_t nz,
-                     const double *bx, const double *by, const double *bz, uint32_t *dest,
-                     uint64_t *key, uint32_t *val, hipStream_t s);
-hipError_t dd_runs(uint32_t n, const uint64_t *key, uint32_t *run_lo, uint32_t *run_hi,
+hipError_t dd_assign(uint32_t n, const double *x, const double *y, const double *z, uint32_t nx,
+                     uint32_t ny, uint32_t nz, const double *bx, const double *by,
+                     const double *bz, uint32_t *dest, uint64_t *key, uint32_t *val,
+                     hipStream_t s);
+hipError_t dd_runs(uint32_t n, const uint64_t *dest, const uint32_t *order,
+                   const uint32_t *sysid, uint32_t nsrc, uint32_t *run_lo, uint32_t *run_hi,
                    hipStream_t s);
 hipError_t dd_gather(uint32_t n, const uint32_t *order, int narr, const DdArrays &src,
                      const DdArrays &dst, hipStream_t s);

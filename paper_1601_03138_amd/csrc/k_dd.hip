@@ -117,12 +117,12 @@ k_dd_cut(uint32_t K, uint32_t nseg, const uint32_t *start, uint32_t n, const uin
     }
 }
 
-// destination of every particle; partition key (destination, current domain) and index
+// destination of every particle; it is also the grouping key (the current domains are
+// contiguous and in order, so a stable grouping by destination keeps (source, position) order)
 __global__ void __launch_bounds__(kThreads)
-k_dd_assign(uint32_t n, const double *x, const double *y, const double *z,
-            const uint32_t *sysid, uint32_t nsrc, uint32_t nx, uint32_t ny, uint32_t nz,
-            const double *bx, const double *by, const double *bz, uint32_t *dest,
-            uint64_t *key, uint32_t *val) {
+k_dd_assign(uint32_t n, const double *x, const double *y, const double *z, uint32_t nx,
+            uint32_t ny, uint32_t nz, const double *bx, const double *by, const double *bz,
+            uint32_t *dest, uint64_t *key, uint32_t *val) {
     const uint32_t i = blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
     // the run [b[k], b[k+1]) holding the coordinate: last face at or below it (b[0] = -inf)
@@ -132,18 +132,21 @@ k_dd_assign(uint32_t n, const double *x, const double *y, const double *z,
     const uint32_t e = last_le<double>(bz + (size_t)col * (nz + 1), nz, z[i]);
     const uint32_t d = col * nz + e;
     dest[i] = d;
-    key[i] = (uint64_t)d * nsrc + (sysid ? sysid[i] : 0u);
+    key[i] = d;
     val[i] = i;
 }
 
-// first and one-past-last sorted position of every (destination, source) run
+// first and one-past-last grouped position of every (destination, source) run; the source of
+// position r is the current domain of particle order[r]
 __global__ void __launch_bounds__(kThreads)
-k_dd_runs(uint32_t n, const uint64_t *key, uint32_t *run_lo, uint32_t *run_hi) {
+k_dd_runs(uint32_t n, const uint64_t *dest, const uint32_t *order, const uint32_t *sysid,
+          uint32_t nsrc, uint32_t *run_lo, uint32_t *run_hi) {
     const uint32_t r = blockIdx.x * kThreads + threadIdx.x;
     if (r >= n) return;
-    const uint64_t k = key[r];
-    if (r == 0 || key[r - 1] != k) run_lo[k] = r;
-    if (r == n - 1 || key[r + 1] != k) run_hi[k] = r + 1;
+    auto pair = [&](uint32_t q) { return dest[q] * nsrc + sysid[order[q]]; };
+    const uint64_t k = pair(r);
+    if (r == 0 || pair(r - 1) != k) run_lo[k] = r;
+    if (r == n - 1 || pair(r + 1) != k) run_hi[k] = r + 1;
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -186,20 +189,22 @@ hipError_t dd_cut(uint32_t K, uint32_t nseg, const uint32_t *start, uint32_t n,
     return hipGetLastError();
 }
 
-hipError_t dd_assign(uint32_t n, const double *x, const double *y, const double *z,
-                     const uint32_t *sysid, uint32_t nsrc, uint32_t nx, uint32_t ny, uint32_t nz,
-                     const double *bx, const double *by, const double *bz, uint32_t *dest,
-                     uint64_t *key, uint32_t *val, hipStream_t s) {
+hipError_t dd_assign(uint32_t n, const double *x, const double *y, const double *z, uint32_t nx,
+                     uint32_t ny, uint32_t nz, const double *bx, const double *by,
+                     const double *bz, uint32_t *dest, uint64_t *key, uint32_t *val,
+                     hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_dd_assign, grid_of(n), dim3(kThreads), 0, s, n, x, y, z, sysid, nsrc,
-                       nx, ny, nz, bx, by, bz, dest, key, val);
+    hipLaunchKernelGGL(k_dd_assign, grid_of(n), dim3(kThreads), 0, s, n, x, y, z, nx, ny, nz, bx,
+                       by, bz, dest, key, val);
     return hipGetLastError();
 }
 
-hipError_t dd_runs(uint32_t n, const uint64_t *key, uint32_t *run_lo, uint32_t *run_hi,
+hipError_t dd_runs(uint32_t n, const uint64_t *dest, const uint32_t *order,
+                   const uint32_t *sysid, uint32_t nsrc, uint32_t *run_lo, uint32_t *run_hi,
                    hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_dd_runs, grid_of(n), dim3(kThreads), 0, s, n, key, run_lo, run_hi);
+    hipLaunchKernelGGL(k_dd_runs, grid_of(n), dim3(kThreads), 0, s, n, dest, order, sysid, nsrc,
+                       run_lo, run_hi);
     return hipGetLastError();
 }
 

@@ -16,12 +16,16 @@ import numpy as np
 
 from . import fdx, inputs
 
-# algorithmic HBM bytes per particle: destinations (read x, y, z and the current domain,
-# write destination, partition key and index) 44 + partition sort, 2 passes of 8 bits over
-# the (destination, source) key (histogram reads the key, scatter reads and writes key and
-# index) 64 + run bounds (read the key) 8; exchange: read the order and 8 FP64 arrays
-# (x, y, z, vx, vy, vz, m, eps), write the 8 arrays
-BYTES_ASSIGN = 44 + 64 + 8
+# algorithmic HBM bytes per particle: destinations (read x, y, z, write destination, grouping
+# key and index) 40 + grouping sort, one 8-bit pass per byte of the destination (histogram
+# reads the key, scatter reads and writes key and index) 32 each + run bounds (read key, order
+# and the source domain) 16; exchange: read the order and 8 FP64 arrays (x, y, z, vx, vy, vz,
+# m, eps), write the 8 arrays
+def bytes_assign(domains: int) -> int:
+    passes = max(1, ((domains - 1).bit_length() + 7) // 8) if domains > 1 else 0
+    return 40 + 32 * passes + 16
+
+
 BYTES_EXCHANGE = 4 + 64 + 64
 
 
@@ -65,7 +69,7 @@ def run(dom, k: int, n_sample: int, reps: int, theta: float = 0.5, log=print) ->
             "ms_assign": round(float(med[2]), 3), "ms_exchange": round(float(med[3]), 3),
             "ms_device_total": round(dev, 3), "ms_wall": round(float(med[4]), 3),
             "particles_per_s": float(round(n / (dev / 1e3), -5)),
-            "assign_gbs": gbs(BYTES_ASSIGN * n, med[2]),
+            "assign_gbs": gbs(bytes_assign(k ** 3) * n, med[2]),
             "exchange_gbs": gbs(BYTES_EXCHANGE * n, med[3]),
             "moved": int(st["n_moved"]),
             "particles_per_domain_min_max": [int(n_d.min()), int(n_d.max())]}
