@@ -1,7 +1,8 @@
-// Instruction-throughput ceilings of gfx950 for the force kernel's arithmetic (packed FP32
-// disabled, as in the library): FP32 FMA rate, v_rsq_f32 rate, and the quadrupole
-// particle-cell interaction with its j-record broadcast from LDS (no global memory in the
-// loop).  Prints one line per measurement; used to derive the force kernel's roofline.
+// Instruction-throughput ceilings of gfx950 for the force kernels' arithmetic (packed FP32
+// disabled, as in the library): FP32 and FP64 FMA rates, v_rsq_f32 and v_rsq_f64 rates, and
+// the quadrupole particle-cell interaction with its j-record broadcast from LDS (no global
+// memory in the loop), in FP32 and in FP64 (hardware estimate + two Newton steps, as in the
+// library).  Prints one line per measurement; used to derive the force kernels' rooflines.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -66,10 +67,77 @@ __global__ void __launch_bounds__(256) k_pc(float *out, int iters, const float4 
     out[blockIdx.x * blockDim.x + threadIdx.x] = ax + ay + az + ph;
 }
 
+__global__ void __launch_bounds__(256) k_fma64(double *out, int iters, double a, double b) {
+    double x[8];
+    for (int k = 0; k < 8; k++) x[k] = threadIdx.x * 0.001 + k;
+    for (int i = 0; i < iters; i++) {
+#pragma unroll
+        for (int k = 0; k < 8; k++) x[k] = fma(x[k], a, b);
+    }
+    double s = 0;
+    for (int k = 0; k < 8; k++) s += x[k];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) k_rsq64(double *out, int iters, double a) {
+    double x[8];
+    for (int k = 0; k < 8; k++) x[k] = 1.0 + threadIdx.x * 0.001 + k;
+    for (int i = 0; i < iters; i++) {
+#pragma unroll
+        for (int k = 0; k < 8; k++) x[k] = __builtin_amdgcn_rsq(x[k]) + a;
+    }
+    double s = 0;
+    for (int k = 0; k < 8; k++) s += x[k];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+__device__ __forceinline__ double rsqrt_nr2(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    for (int k = 0; k < 2; k++) {
+        const double r = fma(-(x * y), y, 1.0);
+        y = fma(y * r, 0.5, y);
+    }
+    return y;
+}
+
+// the library's FP64 quadrupole particle-cell interaction, j from a 64-entry LDS table
+__global__ void __launch_bounds__(256) k_pc64(double *out, int iters, const double4 *tab) {
+    __shared__ double4 t[3 * 64];
+    for (int k = threadIdx.x; k < 3 * 64; k += blockDim.x) t[k] = tab[k];
+    __syncthreads();
+    const double xi = threadIdx.x * 1e-3, yi = 0.5 - xi, zi = 0.25 + xi, e2 = 1e-6;
+    double ax = 0, ay = 0, az = 0, ph = 0;
+    for (int i = 0; i < iters; i++) {
+        const int j = i & 63;
+        const double4 A = t[3 * j], B = t[3 * j + 1], C = t[3 * j + 2];
+        const double rx = xi - A.x, ry = yi - A.y, rz = zi - A.z;
+        const double R2 = fma(rz, rz, fma(ry, ry, fma(rx, rx, e2)));
+        const double Ri = rsqrt_nr2(R2), Ri2 = Ri * Ri, MRi = A.w * Ri;
+        const double qx = fma(B.w, ry, fma(C.x, rz, B.x * rx));
+        const double qy = fma(B.w, rx, fma(C.y, rz, B.y * ry));
+        const double qz = fma(C.x, rx, fma(C.y, ry, B.z * rz));
+        const double rqr = fma(rx, qx, fma(ry, qy, rz * qz));
+        const double Ri5 = Ri * Ri2 * Ri2, tt = rqr * Ri5, u = Ri2 * fma(2.5, tt, MRi);
+        ax = fma(-u, rx, fma(Ri5, qx, ax));
+        ay = fma(-u, ry, fma(Ri5, qy, ay));
+        az = fma(-u, rz, fma(Ri5, qz, az));
+        ph -= fma(0.5, tt, MRi);
+    }
+    out[blockIdx.x * blockDim.x + threadIdx.x] = ax + ay + az + ph;
+}
+
 int main() {
     const int blocks = 256 * 16, threads = 256, iters = 4096;
     float *out = nullptr;
     float4 *tab = nullptr;
+    double *out64 = nullptr;
+    double4 *tab64 = nullptr;
+    CK(hipMalloc(&out64, sizeof(double) * blocks * threads));
+    CK(hipMalloc(&tab64, sizeof(double4) * 3 * 64));
+    std::vector<double4> h64(3 * 64);
+    for (int k = 0; k < 3 * 64; k++)
+        h64[k] = make_double4(0.1 * (k % 7) + 1, 0.2 * (k % 5) + 1, 0.3 * (k % 3) + 1, 1e-3);
+    CK(hipMemcpy(tab64, h64.data(), sizeof(double4) * h64.size(), hipMemcpyHostToDevice));
     CK(hipMalloc(&out, sizeof(float) * blocks * threads));
     CK(hipMalloc(&tab, sizeof(float4) * 3 * 64));
     std::vector<float4> h(3 * 64);
@@ -103,7 +171,29 @@ int main() {
         const double pcs = (double)blocks * threads * iters * 4;
         std::printf("rep %d quadrupole pc (LDS j): %.3f ms, %.3e interactions/s, %.1f TFLOP/s at 54\n",
                     rep, ms, pcs / (ms * 1e-3), pcs * 54 / (ms * 1e-3) / 1e12);
+        CK(hipEventRecord(a));
+        hipLaunchKernelGGL(k_fma64, dim3(blocks), dim3(threads), 0, 0, out64, iters, 1.0001, 0.5);
+        CK(hipEventRecord(b));
+        CK(hipEventSynchronize(b));
+        CK(hipEventElapsedTime(&ms, a, b));
+        std::printf("rep %d fma f64: %.3f ms, %.2f TFLOP/s (FMA = 2)\n", rep, ms, 2 * fmas / ms / 1e9);
+        CK(hipEventRecord(a));
+        hipLaunchKernelGGL(k_rsq64, dim3(blocks), dim3(threads), 0, 0, out64, iters, 0.25);
+        CK(hipEventRecord(b));
+        CK(hipEventSynchronize(b));
+        CK(hipEventElapsedTime(&ms, a, b));
+        std::printf("rep %d rsq f64+add: %.3f ms, %.2f T rsq/s\n", rep, ms, rs / ms / 1e9);
+        CK(hipEventRecord(a));
+        hipLaunchKernelGGL(k_pc64, dim3(blocks), dim3(threads), 0, 0, out64, iters, tab64);
+        CK(hipEventRecord(b));
+        CK(hipEventSynchronize(b));
+        CK(hipEventElapsedTime(&ms, a, b));
+        const double pcs64 = (double)blocks * threads * iters;
+        std::printf("rep %d quadrupole pc f64 (LDS j): %.3f ms, %.3e interactions/s, %.1f TFLOP/s at 54\n",
+                    rep, ms, pcs64 / (ms * 1e-3), pcs64 * 54 / (ms * 1e-3) / 1e12);
     }
+    CK(hipFree(out64));
+    CK(hipFree(tab64));
     CK(hipFree(out));
     CK(hipFree(tab));
     return 0;
