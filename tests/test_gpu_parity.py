@@ -45,6 +45,10 @@ CASES = {
                         8, 64, 0.6, True),
     "leaf1_group5": (lambda: I.plummer(3000, seed=22, eps=0.01), 1, 5, 0.4, True),
     "group512": (lambda: I.plummer(12000, seed=23, eps=0.01), 16, 512, 0.7, True),
+    # the ends of the opening-angle range: theta = 1 with 64-particle leaves, and theta = 0.1
+    # (lists close to the whole system)
+    "theta1_leaf64": (lambda: I.plummer(8000, seed=24, eps=0.01), 64, 256, 1.0, True),
+    "theta01": (lambda: I.plummer(3000, seed=25, eps=0.01), 8, 64, 0.1, True),
 }
 
 
