@@ -38,8 +38,11 @@ def main():
             rows.append((st["ms_tree"], st["ms_lists"]))
     med = np.median(np.array(rows), axis=0)
     print(json.dumps({"workload": args.workload, "domains": args.k ** 3, "theta": args.theta,
-                      "entries": int(st["n_epj"] + st["n_spj"]), "ms_trees": round(med[0], 3),
-                      "ms_lists": round(med[1], 3)}), flush=True)
+                      "entries": int(st["n_epj"] + st["n_spj"]),
+                      "list_capacity": int(st["list_capacity"]),
+                      "ms_trees": round(float(med[0]), 3), "ms_lists": round(float(med[1]), 3),
+                      "entries_per_s": float(round((st["n_epj"] + st["n_spj"])
+                                                   / (med[1] / 1e3), -6))}), flush=True)
     ctx.close()
 
 

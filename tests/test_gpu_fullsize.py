@@ -229,3 +229,33 @@ def test_clustered16m_domain_decomposition_64_domains(fdx):
              f"{st['ms_assign']:.3f}, exchange {st['ms_exchange']:.3f}")
     finally:
         c.close()
+
+
+def test_clustered16m_exchange_lists_512_domains_two_pass(fdx):
+    """8 x 8 x 8 domains: the per-sender bound (511 n entries) exceeds the one-pass budget, so
+    a count walk sizes every segment before the fill walk; counts of all 261,632 pairs and
+    the entry sets of sampled pairs bit-exact, capacity = the exact total."""
+    ps = I.workload("clustered16m")
+    dom, _ = I.multisection(ps, 8, 8, 8)
+    _say(f"[fullsize] exchange lists, n={dom.n} domains={dom.n_sys}")
+    t = O.build_tree(dom, 8)
+    L = O.exchange(t, 0.5)
+    c = fdx.Context(0)
+    try:
+        c.set_particles(dom)
+        c.build_exchange_lists(0.5, 8)
+        pairs, ne, ns, epj, spj = c.exchange_lists()
+        assert np.array_equal(ne, L.n_epj) and np.array_equal(ns, L.n_spj)
+        oe = np.concatenate([[0], np.cumsum(ne)])
+        os_ = np.concatenate([[0], np.cumsum(ns)])
+        rng = np.random.default_rng(9)
+        for k in rng.choice(len(pairs), 256, replace=False):
+            e_ref, s_ref = L.epj[L.epj_off[k]:L.epj_off[k + 1]], L.spj[L.spj_off[k]:L.spj_off[k + 1]]
+            assert np.array_equal(np.sort(epj[oe[k]:oe[k + 1]]), np.sort(t.perm[e_ref]))
+            assert np.array_equal(np.sort(spj[os_[k]:os_[k + 1]]), np.sort(s_ref))
+        st = c.exchange_stats()
+        assert st["list_capacity"] == int(ne.sum() + ns.sum())     # sized by the count walk
+        _say(f"  entries {int(ne.sum() + ns.sum())}; device ms: trees {st['ms_tree']:.3f}, "
+             f"lists {st['ms_lists']:.3f}")
+    finally:
+        c.close()
