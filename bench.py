@@ -87,6 +87,13 @@ def read_traffic(kernel_tag: str, shape: str):
         return None
 
 
+def rms_rel_error(a, a_ref) -> float:
+    """sqrt(mean_i |a_i - a_ref_i|^2 / |a_ref_i|^2) over the rows given (3 components)."""
+    d = np.sum((a[:, :3] - a_ref[:, :3]) ** 2, axis=1)
+    r = np.sum(a_ref[:, :3] ** 2, axis=1)
+    return float(math.sqrt(np.mean(d / r)))
+
+
 def cpu_baseline(ps, n_group, theta, quad, n_sample_groups, seed=7):
     """The oracle as it stands (FP64 serial tree, OpenMP over groups): the full tree build of
     the workload plus the walk and force of a random sample of groups, scaled to one whole
@@ -318,17 +325,14 @@ def main():
     # accuracy of both paths against FP64 direct summation at the current positions
     accuracy = None
     if not args.no_accuracy:
-        import oracle as O
-        x, y, z, vx, vy, vz = ctx.particles()
-        cur = inputs.ParticleSet(x, y, z, vx, vy, vz, ps.m, ps.eps, ps.sys_off)
         sub = inputs.subset(ps.n, 256, seed=102)
-        d = O.direct(cur, sub)
+        d = ctx.direct_forces(sub)                  # FP64 direct sum on the GPU
         ctx.calc_force_flags(theta, 8, n_group, 0.0, fdx.Context.flags(quad=quad, fp32=False))
-        e64 = O.rms_rel_error(ctx.forces()[sub], d)
+        e64 = rms_rel_error(ctx.forces()[sub], d)
         ctx.calc_force_flags(theta, 8, n_group, 0.0, fdx.Context.flags(quad=quad, fp32=True))
-        e32 = O.rms_rel_error(ctx.forces()[sub], d)
+        e32 = rms_rel_error(ctx.forces()[sub], d)
         accuracy = {"rms_da_over_a_fp32": e32, "rms_da_over_a_fp64": e64,
-                    "subset": "256 particles, seed 102, FP64 direct sum (oracle)"}
+                    "subset": "256 particles, seed 102, FP64 direct sum (fdx_direct_forces)"}
 
     # exchange lists between domains (the same particles as k x k x k virtual processes)
     exch = None
@@ -355,13 +359,6 @@ def main():
                                                                   kd ** 3), 1),
                 "paper_s_per_entry_one_cpu_process": 1.12e-7}
         cx.close()
-        if not args.no_cpu_baseline:
-            import oracle as O
-            ta = time.perf_counter()
-            tr = O.build_tree(dom, 8)
-            O.exchange(tr, theta)
-            exch["cpu_oracle_s"] = round(time.perf_counter() - ta, 2)
-            del tr
         log(f"[bench] exchange lists: {exch}")
 
     # multisection domain decomposition with cost-weighted sampling + exchange of particles
@@ -372,12 +369,6 @@ def main():
         ddom = dom if exch is not None and kd == args.exchange_domains else \
             inputs.multisection(ps, kd, kd, kd)[0]
         dd = dd_timing.run(ddom, kd, args.dd_samples, 3, theta, log=log)
-        if not args.no_cpu_baseline:
-            import oracle as O
-            ta = time.perf_counter()
-            O.decompose(ddom, kd, kd, kd, args.dd_samples, seed=1)
-            dd["cpu_oracle_s_uniform_cost"] = round(time.perf_counter() - ta, 2)
-        del ddom
         log(f"[bench] domain decomposition: {dd}")
 
     # SPH density: short-range neighbour lists (fixed cutoff) + Wendland C6 density, FP64
@@ -437,6 +428,18 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         cpu = cpu_baseline(ps, n_group, theta, quad, args.cpu_sample_groups)
+        # the oracle on the "next" rows' workloads, for the same comparison
+        import oracle as O
+        nxt = {}
+        if exch is not None:
+            ta = time.perf_counter()
+            O.exchange(O.build_tree(dom, 8), theta)
+            nxt["exchange_lists_s"] = round(time.perf_counter() - ta, 2)
+        if dd is not None:
+            ta = time.perf_counter()
+            O.decompose(ddom, args.dd_k, args.dd_k, args.dd_k, args.dd_samples, seed=1)
+            nxt["domain_decomposition_s_uniform_cost"] = round(time.perf_counter() - ta, 2)
+        cpu["next_rows"] = nxt
 
     out = {
         "metric": "particles/s per force eval at N=2^24, theta=0.5; FP32 vs FP64 at rms da/a<=1e-3",

@@ -364,6 +364,21 @@ int fdx_get_dd_destinations(fdx_ctx *ctx, uint32_t *dest, uint32_t *order, int32
 int fdx_exchange_particles(fdx_ctx *ctx);
 int fdx_get_dd_stats(fdx_ctx *ctx, fdx_dd_stats *out);
 
+/* ---- Direct summation (the reference for the tree's error) -----------------------------
+ * The exact quantity the tree approximates, equation ParticleParticleNbody (section "An
+ * example -- gravitational N-body problem") with G = 1, for selected target particles:
+ *   a_i   =  sum_{j != i} m_j (x_j - x_i) / (|x_j - x_i|^2 + eps_i^2)^{3/2}
+ *   phi_i = -sum_{j != i} m_j / (|x_j - x_i|^2 + eps_i^2)^{1/2}
+ * over the particles j of i's system, at the context's current positions, in FP64 with
+ * compensated sums; O(n_targets x system size) work.
+ * fdx_direct_forces: targets = host array of n_targets indices in [0, n) (caller's order);
+ *   out = host array of 4 n_targets values (ax, ay, az, phi per target); eps = the softening
+ *   when the particles carry none (finite, > 0; ignored otherwise).  Synchronous.
+ *   FDX_EINVAL: n_targets outside [0, 2^24], a null pointer, an index out of range or a bad
+ *   eps; FDX_ESTATE: no particles. */
+int fdx_direct_forces(fdx_ctx *ctx, const int64_t *targets, int64_t n_targets, double eps,
+                      double *out);
+
 /* Message of the last failed call on ctx (never null; "" when none). */
 const char *fdx_last_error(const fdx_ctx *ctx);
 

@@ -198,6 +198,13 @@ hipError_t dd_runs(uint32_t n, const uint64_t *dest, const uint32_t *order,
 hipError_t dd_gather(uint32_t n, const uint32_t *order, int narr, const DdArrays &src,
                      const DdArrays &dst, hipStream_t s);
 
+// FP64 direct summation for nt target particles (caller's order indices) over their
+// systems; out = 4 per target (ax, ay, az, phi)
+hipError_t direct_forces(uint32_t nt, const uint32_t *targets, const double *x, const double *y,
+                         const double *z, const double *m, const double *eps, double eps_all,
+                         const uint32_t *sysid, const int64_t *sys_off, double *out,
+                         hipStream_t s);
+
 // queue order for the persistent force kernel: groups by decreasing estimated cost
 hipError_t queue_keys(size_t gmax, const Groups g, const uint32_t *cnt_e, const uint32_t *cnt_s,
                       uint64_t *key, uint32_t *val, DevStatus *st, hipStream_t s);

@@ -31,7 +31,7 @@ EXPORTS = ["fdx_create", "fdx_destroy", "fdx_set_particles", "fdx_build_tree", "
            "fdx_get_exchange_stats", "fdx_calc_density", "fdx_get_density",
            "fdx_calc_force_cutoff", "fdx_dd_factor", "fdx_decompose", "fdx_get_decomposition",
            "fdx_get_dd_samples", "fdx_get_dd_destinations", "fdx_exchange_particles",
-           "fdx_get_dd_stats"]
+           "fdx_get_dd_stats", "fdx_direct_forces"]
 
 
 class FdxError(RuntimeError):
@@ -136,6 +136,7 @@ def _declare(L):
     L.fdx_get_dd_destinations.argtypes = [vp, vp, vp, i32]
     L.fdx_exchange_particles.argtypes = [vp]
     L.fdx_get_dd_stats.argtypes = [vp, C.POINTER(DdStats)]
+    L.fdx_direct_forces.argtypes = [vp, vp, i64, f64, vp]
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -347,6 +348,16 @@ class Context:
         st = ExchangeStats()
         self._check(self.lib.fdx_get_exchange_stats(self.h, C.byref(st)), "get_exchange_stats")
         return st.as_dict()
+
+    # -- FP64 direct summation (reference) ------------------------------------------------
+    def direct_forces(self, targets, eps: float = 0.0) -> np.ndarray:
+        """[len(targets), 4] = (ax, ay, az, phi) by FP64 direct summation over each target's
+        system at the current positions."""
+        t = np.ascontiguousarray(targets, dtype=np.int64)
+        out = np.empty((max(len(t), 1), 4))
+        self._check(self.lib.fdx_direct_forces(self.h, _ptr(t), len(t), float(eps), _ptr(out)),
+                    "direct_forces")
+        return out[:len(t)]
 
     # -- domain decomposition: multisection with cost-weighted sampling --------------------
     def decompose(self, nx: int, ny: int, nz: int, n_sample: int, cost=None, seed: int = 0,

@@ -251,3 +251,30 @@ def test_leapfrog_step_matches_oracle(ctx):
     e = O.rms_rel_error(a0, d)
     _say(f"[plummer4k] monopole rms vs direct {e:.3e}")
     assert e < 2e-3
+
+
+def test_direct_sum_reference_matches_the_oracle(ctx, fdx):
+    """fdx_direct_forces (the bench's accuracy reference) against the oracle's direct sum:
+    per-particle and global softening, several systems (sums stay inside each), argument
+    errors."""
+    ps = I.concat([I.plummer(n, seed=60 + k, eps=0.01 * (k + 1)) for k, n in
+                   enumerate([3000, 1, 700, 20011])])
+    ps.eps = ps.eps * (1.0 + 0.1 * np.sin(np.arange(ps.n)))          # per-particle values
+    sub = np.concatenate([I.subset(ps.n, 400, seed=61), [3000, ps.n - 1]])
+    ref = O.direct(ps, sub)
+    ctx.set_particles(ps)
+    d = ctx.direct_forces(sub)
+    rel = np.abs(d - ref) / np.maximum(np.abs(ref), 1e-300)
+    rel[sub == 3000, :3] = np.abs(d[sub == 3000, :3] - ref[sub == 3000, :3])   # alone: a = 0
+    _say(f"[direct] max rel vs oracle {rel.max():.2e}")
+    assert rel.max() <= 1e-12
+    # one global softening
+    ctx.set_particles(ps, per_particle_eps=False)
+    g = I.ParticleSet(ps.x, ps.y, ps.z, ps.vx, ps.vy, ps.vz, ps.m, np.full(ps.n, 0.02),
+                      ps.sys_off)
+    d2 = ctx.direct_forces(sub[:50], eps=0.02)
+    assert np.allclose(d2, O.direct(g, sub[:50]), rtol=1e-12, atol=0)
+    with pytest.raises(fdx.FdxError):
+        ctx.direct_forces([ps.n])
+    with pytest.raises(fdx.FdxError):
+        ctx.direct_forces([0], eps=0.0)
