@@ -72,3 +72,37 @@ def rel_err(a, ref):
 
 def pot_rel_err(a, ref):
     return np.abs(a[:, 3] - ref[:, 3]) / np.abs(ref[:, 3])
+
+
+def fp32_error_bound(t, g, lists, ref_sorted):
+    """Per-particle bound (sorted order) on the relative error of the FP32 group-relative
+    kernel against the FP64 kernel on the same lists.  Coordinates relative to the group
+    centre c are rounded to FP32 (unit roundoff u = 2^-24), so a pair separation d = x_j - x_i
+    is off by at most sqrt(3) u (|x_i - c| + |x_j - c|); the pair force m d / r_eff^3 then
+    moves by at most 3 |dd| / r_eff of its size, plus a few u of arithmetic:
+        |da_i| <= sum_j m_j / r_eff^2 (3 sqrt(3) u (|x_i - c| + |x_j - c|) / r_eff + 8 u),
+    superparticles taken as point masses at their centre of mass.  Returned as |da_i| / |a_i|
+    (inf where a_i = 0).  It grows with the group's extent over its pair separations."""
+    u = 2.0 ** -24
+    pos = np.stack([t.sx, t.sy, t.sz], axis=1)
+    out = np.full(t.sx.shape[0], np.inf)
+    for k in range(g.n):
+        b, n = int(g.begin[k]), int(g.count[k])
+        c = g.centre[k]
+        xi = pos[b:b + n] - c
+        ni = np.linalg.norm(xi, axis=1)
+        e, s = lists.group_lists(k)
+        xj = np.concatenate([pos[e.astype(np.int64)], t.mom[s.astype(np.int64), 1:4]]) - c
+        mj = np.concatenate([t.sm[e.astype(np.int64)], t.mom[s.astype(np.int64), 0]])
+        nj = np.linalg.norm(xj, axis=1)
+        d = xj[None, :, :] - xi[:, None, :]
+        reff = np.sqrt(np.sum(d * d, axis=2) + (t.seps[b:b + n] ** 2)[:, None])
+        dd = np.sqrt(3.0) * u * (ni[:, None] + nj[None, :])
+        term = mj[None, :] / reff ** 2 * (3.0 * dd / reff + 8.0 * u)
+        self_pair = np.zeros_like(term, dtype=bool)
+        self_pair[:, :len(e)] = (e.astype(np.int64)[None, :] == np.arange(b, b + n)[:, None])
+        term[self_pair] = 0.0
+        amag = np.linalg.norm(ref_sorted[b:b + n, :3], axis=1)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            out[b:b + n] = np.where(amag > 0, term.sum(axis=1) / amag, np.inf)
+    return out
