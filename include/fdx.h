@@ -182,6 +182,18 @@ int fdx_set_shape(fdx_ctx *ctx, int32_t shape);
 int fdx_autotune(fdx_ctx *ctx, double theta, int32_t n_leaf, double eps, int32_t flags,
                  const int32_t *n_group_cand, int32_t n_cand, int32_t reps, double *times_ms,
                  int32_t *best_n_group, int32_t *best_shape);
+/* fdx_autotune_cached: the same search, with its result recorded in the text file `path`
+ * (one JSON object per line: {"key": "...", "n_group": g, "shape": v}); the key holds the
+ * device architecture, floor(log2 n), floor(log2 n_sys), theta, n_leaf, the QUAD / FP32REL /
+ * PERSISTENT flags, the candidate list and reps.  A recorded key is applied without timing
+ * (*from_cache = 1: the shape is kept for later calls and the group size returned); otherwise
+ * fdx_autotune runs and one line is appended (*from_cache = 0).  Lines that do not parse, or
+ * name a shape that cannot hold their group size, are ignored.  FDX_EINVAL: null path, no
+ * candidates, reps < 1, or the file cannot be written; FDX_ESTATE: no particles. */
+int fdx_autotune_cached(fdx_ctx *ctx, const char *path, double theta, int32_t n_leaf,
+                        double eps, int32_t flags, const int32_t *n_group_cand, int32_t n_cand,
+                        int32_t reps, int32_t *best_n_group, int32_t *best_shape,
+                        int32_t *from_cache);
 
 /* ---- Learned interaction-list length predictor -----------------------------------------
  * A small network (8 inputs -> 64 -> 64 -> 1, SiLU, FP32; fdx_mlp_params() = 4801 weights)

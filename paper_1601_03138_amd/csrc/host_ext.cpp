@@ -3,6 +3,9 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
 #include <vector>
 
 #include "ctx.h"
@@ -238,6 +241,66 @@ int fdx_autotune(fdx_ctx *c, double theta, int32_t n_leaf, double eps, int32_t f
         }
     }
     c->ext.variant = bv;
+    if (best_n_group) *best_n_group = bg;
+    if (best_shape) *best_shape = bv;
+    return FDX_OK;
+}
+
+// Autotuner results recorded in a text file, one JSON object per line:
+//   {"key": "<arch>|n2^<k>|sys2^<k>|theta=<g>|leaf=<n>|flags=<f>|cand=<a,b,..>|reps=<r>",
+//    "n_group": <g>, "shape": <v>}
+// The last line with the same key wins; lines that do not parse are ignored.
+int fdx_autotune_cached(fdx_ctx *c, const char *path, double theta, int32_t n_leaf, double eps,
+                        int32_t flags, const int32_t *n_group_cand, int32_t n_cand, int32_t reps,
+                        int32_t *best_n_group, int32_t *best_shape, int32_t *from_cache) {
+    if (!c) return FDX_EINVAL;
+    if (!path || !n_group_cand || n_cand < 1 || reps < 1)
+        return fail(c, FDX_EINVAL, "null path or no candidates");
+    if (!c->have_particles) return fail(c, FDX_ESTATE, "no particles: call fdx_set_particles first");
+    hipDeviceProp_t prop;
+    HIPCHK(c, hipGetDeviceProperties(&prop, c->device));
+    auto lg = [](int64_t v) { int k = 0; while (v > 1) { v >>= 1; k++; } return k; };
+    const int32_t fkey = flags & (FDX_QUAD | FDX_FP32REL | FDX_PERSISTENT);
+    char head[256];
+    snprintf(head, sizeof(head), "%s|n2^%d|sys2^%d|theta=%.9g|leaf=%d|flags=%d|cand=",
+             prop.gcnArchName, lg(c->n), lg(c->nsys), theta, n_leaf, fkey);
+    std::string key = head;
+    for (int k = 0; k < n_cand; k++) key += (k ? "," : "") + std::to_string(n_group_cand[k]);
+    key += "|reps=" + std::to_string(reps);
+    if (from_cache) *from_cache = 0;
+    // look the key up
+    int g_hit = -1, v_hit = -1;
+    if (FILE *f = fopen(path, "r")) {
+        char line[1024];
+        const std::string want = "{\"key\": \"" + key + "\", ";
+        while (fgets(line, sizeof(line), f)) {
+            if (strncmp(line, want.c_str(), want.size()) != 0) continue;
+            int g = -1, v = -1;
+            if (sscanf(line + want.size(), "\"n_group\": %d, \"shape\": %d}", &g, &v) == 2 &&
+                g >= 1 && g <= kMaxGroup && v >= 0 && v < force_variants() &&
+                force_variant_capacity(v) >= g) {
+                g_hit = g;
+                v_hit = v;
+            }
+        }
+        fclose(f);
+    }
+    if (g_hit > 0) {
+        c->ext.variant = v_hit;
+        if (best_n_group) *best_n_group = g_hit;
+        if (best_shape) *best_shape = v_hit;
+        if (from_cache) *from_cache = 1;
+        return FDX_OK;
+    }
+    int32_t bg = -1, bv = -1;
+    int r = fdx_autotune(c, theta, n_leaf, eps, flags, n_group_cand, n_cand, reps, nullptr, &bg,
+                         &bv);
+    if (r) return r;
+    FILE *f = fopen(path, "a");
+    if (!f) return fail(c, FDX_EINVAL, "cannot append to %s", path);
+    fprintf(f, "{\"key\": \"%s\", \"n_group\": %d, \"shape\": %d}\n", key.c_str(), bg, bv);
+    const bool ok = fclose(f) == 0;
+    if (!ok) return fail(c, FDX_EINVAL, "cannot write %s", path);
     if (best_n_group) *best_n_group = bg;
     if (best_shape) *best_shape = bv;
     return FDX_OK;

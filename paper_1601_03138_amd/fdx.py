@@ -31,7 +31,7 @@ EXPORTS = ["fdx_create", "fdx_destroy", "fdx_set_particles", "fdx_build_tree", "
            "fdx_get_exchange_stats", "fdx_calc_density", "fdx_get_density",
            "fdx_calc_force_cutoff", "fdx_dd_factor", "fdx_decompose", "fdx_get_decomposition",
            "fdx_get_dd_samples", "fdx_get_dd_destinations", "fdx_exchange_particles",
-           "fdx_get_dd_stats", "fdx_direct_forces"]
+           "fdx_get_dd_stats", "fdx_direct_forces", "fdx_autotune_cached"]
 
 
 class FdxError(RuntimeError):
@@ -137,6 +137,8 @@ def _declare(L):
     L.fdx_exchange_particles.argtypes = [vp]
     L.fdx_get_dd_stats.argtypes = [vp, C.POINTER(DdStats)]
     L.fdx_direct_forces.argtypes = [vp, vp, i64, f64, vp]
+    L.fdx_autotune_cached.argtypes = [vp, C.c_char_p, f64, i32, f64, i32, vp, i32, i32, vp, vp,
+                                      vp]
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -310,6 +312,16 @@ class Context:
                                           _ptr(cand), cand.shape[0], reps, _ptr(times),
                                           C.byref(bg), C.byref(bv)), "autotune")
         return int(bg.value), int(bv.value), times.reshape(cand.shape[0], nv)
+
+    def autotune_cached(self, path, theta, n_leaf, eps, flags, n_group_candidates, reps=2):
+        """(n_group, shape, from_cache): fdx_autotune with its result recorded in `path`."""
+        cand = np.ascontiguousarray(n_group_candidates, dtype=np.int32)
+        bg, bv, fc = C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(self.lib.fdx_autotune_cached(self.h, os.fsencode(str(path)), float(theta),
+                                                 n_leaf, float(eps), int(flags), _ptr(cand),
+                                                 cand.shape[0], reps, C.byref(bg), C.byref(bv),
+                                                 C.byref(fc)), "autotune_cached")
+        return int(bg.value), int(bv.value), bool(fc.value)
 
     def shape_name(self, shape: int) -> str:
         return self.lib.fdx_shape_name(int(shape)).decode()

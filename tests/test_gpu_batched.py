@@ -74,6 +74,29 @@ def test_autotuner_picks_a_measured_candidate(ctx, fdx):
     ctx.set_shape(-1)
 
 
+def test_autotuner_records_and_reuses_its_choice(ctx, fdx, tmp_path):
+    ps = I.plummer(20000, seed=14, eps=1 / 256)
+    ctx.set_particles(ps)
+    flags = fdx.Context.flags(quad=True, fp32=True)
+    path = tmp_path / "autotune.jsonl"
+    path.write_text("not a record\n")                  # unparsable lines are ignored
+    bg, bv, hit = ctx.autotune_cached(path, 0.5, 8, 0.0, flags, [64, 256], reps=1)
+    assert not hit and bg in (64, 256)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 2 and f'"n_group": {bg}, "shape": {bv}}}' in lines[1]
+    ctx.set_shape(-1)
+    bg2, bv2, hit2 = ctx.autotune_cached(path, 0.5, 8, 0.0, flags, [64, 256], reps=1)
+    assert hit2 and (bg2, bv2) == (bg, bv)
+    ctx.calc_force(0.5, 8, bg2, 0.0, quad=True, fp32=True)
+    assert ctx.stats()["shape"] == bv2                   # the recorded shape is in use
+    # another opening angle is another key: measured and appended
+    _, _, hit3 = ctx.autotune_cached(path, 0.7, 8, 0.0, flags, [64, 256], reps=1)
+    assert not hit3 and len(path.read_text().splitlines()) == 3
+    with pytest.raises(fdx.FdxError):
+        ctx.autotune_cached(tmp_path / "missing_dir" / "x.jsonl", 0.4, 8, 0.0, flags, [64])
+    ctx.set_shape(-1)
+
+
 def test_graph_steps_match_eager_steps_on_an_ensemble(ctx, fdx):
     ens = I.ensemble(n_sys=24, seed=40, nmin=256, nmax=4096)
     _say(f"[graph] ensemble n={ens.n} systems={ens.n_sys}")
