@@ -75,6 +75,13 @@ k_group_hmax(const uint32_t *ngroups, Groups g, const double *sh, double *rg) {
     }
 }
 
+// |r|^2 rounded as written, ((dx dx + dy dy) + dz dz), with no fused multiply-add, so the
+// comparison with H^2 decides exactly as the plain definition does
+__device__ __forceinline__ double dist2_as_written(double dx, double dy, double dz) {
+#pragma clang fp contract(off)
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
 __device__ __forceinline__ double wendland(double r2, double invh, double norm) {
     const double q = __dmul_rn(sqrt(r2), invh);
     const double u = 1.0 - q, u2 = u * u, u4 = u2 * u2, u8 = u4 * u4;
@@ -132,8 +139,7 @@ __global__ void __launch_bounds__(kThreads) k_density(DensArgs a) {
                         const double4 pj = tj[jj];
                         const double dx = __dsub_rn(pj.x, pi.x), dy = __dsub_rn(pj.y, pi.y),
                                      dz = __dsub_rn(pj.z, pi.z);
-                        const double r2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
-                                                    __dmul_rn(dz, dz));
+                        const double r2 = dist2_as_written(dx, dy, dz);
                         if (MODE == 0 || MODE == 2) {
                             if (r2 < hi2) { acc += pj.w * wendland(r2, invhi, normi); cnt++; }
                         } else if (MODE == 1) {
