@@ -50,7 +50,10 @@ typedef struct fdx_ctx fdx_ctx;
 /* fdx_calc_force / fdx_integrate flags (bitwise or) */
 #define FDX_QUAD 1        /* superparticles carry the quadrupole moment (else monopole) */
 #define FDX_FP32REL 2     /* FP32 force kernels on group-relative coordinates with
-                             compensated accumulation (else FP64 kernels) */
+                             compensated accumulation (else FP64 kernels); a group too wide
+                             for that -- 9 u min(S / eps_min, 2^d) > 1e-4 with u = 2^-24,
+                             S its cell side, eps_min its smallest softening, d the depth of
+                             its deepest leaf below its cell -- is evaluated in FP64 */
 #define FDX_PREDICTOR 4   /* size interaction lists from the learned list-length predictor
                              (single walk; overflowing groups are re-walked exactly, so
                              forces never depend on it) */
@@ -142,6 +145,10 @@ typedef struct {
        force, unsort, predict (feature + MLP), total */
     double t_keys, t_sort, t_tree, t_moments, t_groups, t_walk, t_force, t_unsort, t_predict,
         t_total;
+    /* FP32 evaluations: groups evaluated by the FP64 kernel instead, because FP32 rounding of
+       coordinates relative to the group centre could move a close pair's force by more than
+       1e-4 of itself (see FDX_FP32REL) */
+    int64_t fp64_groups;
 } fdx_stats;
 
 int fdx_get_stats(fdx_ctx *ctx, fdx_stats *out);

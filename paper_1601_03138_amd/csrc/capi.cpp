@@ -69,6 +69,8 @@ int ensure_tree_buffers(fdx_ctx *c, uint32_t cell_cap, uint32_t group_cap) {
         HIPCHK(c, c->g_sys.ensure(group_cap));
         HIPCHK(c, c->g_box.ensure(6 * (size_t)group_cap));
         HIPCHK(c, c->g_centre.ensure(3 * (size_t)group_cap));
+        HIPCHK(c, c->g_wide.ensure(group_cap));
+        HIPCHK(c, c->wide_list.ensure(group_cap));
         HIPCHK(c, c->cnt_e.ensure(group_cap));
         HIPCHK(c, c->cnt_s.ensure(group_cap));
         HIPCHK(c, c->lcap.ensure(group_cap));
@@ -96,7 +98,7 @@ Cells cells_view(fdx_ctx *c) {
 Groups groups_view(fdx_ctx *c) {
     Groups g;
     g.cell = c->g_cell.p; g.begin = c->g_begin.p; g.count = c->g_count.p; g.sys = c->g_sys.p;
-    g.box = c->g_box.p; g.centre = c->g_centre.p; g.cap = c->group_cap;
+    g.box = c->g_box.p; g.centre = c->g_centre.p; g.wide = c->g_wide.p; g.cap = c->group_cap;
     return g;
 }
 
@@ -148,9 +150,9 @@ int enqueue_tree_groups(fdx_ctx *c) {
     mark(c, 3);
     HIPCHK(c, tree_moments(cells_view(c), c->jp.p, s));
     mark(c, 4);
-    HIPCHK(c, make_groups(n, S, c->sys_off.p, cells_view(c), c->skey, c->cube.p, c->n_group,
-                          groups_view(c), c->flag.p, c->gcell_at.p, c->gpos.p, c->partial.p,
-                          c->st, s));
+    HIPCHK(c, make_groups(n, S, c->sys_off.p, cells_view(c), c->skey, c->cube.p, c->seps.p,
+                          c->n_group, groups_view(c), c->flag.p, c->gcell_at.p, c->gpos.p,
+                          c->leaf_lev.p, c->partial.p, c->st, s));
     mark(c, 5);
     return FDX_OK;
 }
@@ -251,6 +253,19 @@ int enqueue_force(fdx_ctx *c, size_t gmax) {
         if (r) return r;
     }
     HIPCHK(c, force(gmax, fa, s));
+    if (fa.fp32) {
+        // groups too wide for group-relative FP32: evaluated again by the FP64 kernel, which
+        // overwrites their rows (one persistent pass over the device-side list; empty when no
+        // group is wide)
+        HIPCHK(c, wide_group_list(gmax, gv, c->wide_list.p, c->st, s));
+        ForceArgs fw = fa;
+        fw.fp32 = false;
+        fw.persistent = true;
+        fw.order = c->wide_list.p;
+        fw.count = &c->st->wide_groups;
+        fw.variant = 5;                    // the FP64 default shape
+        HIPCHK(c, force(gmax, fw, s));
+    }
     mark(c, 7);
     HIPCHK(c, unsort_forces(n, c->fs.p, c->inv.p, c->ax.p, c->ay.p, c->az.p, c->pot.p, s));
     mark(c, 8);
@@ -351,6 +366,7 @@ int read_counters(fdx_ctx *c) {
     c->stats.n_spj = (int64_t)h.n_spj;
     c->stats.n_interactions_pp = (int64_t)h.inter_pp;
     c->stats.n_interactions_pc = (int64_t)h.inter_pc;
+    c->stats.fp64_groups = (c->flags & FDX_FP32REL) ? (int64_t)h.wide_groups : 0;
     return FDX_OK;
 }
 
@@ -398,8 +414,9 @@ int fdx_destroy(fdx_ctx *c) {
                     &c->c_begin, &c->c_count, &c->c_first, &c->c_nchild, &c->c_parent, &c->c_lvl,
                     &c->tmp_n, &c->tmp_off, &c->g_cell, &c->g_begin, &c->g_count, &c->g_sys,
                     &c->g_box, &c->flag, &c->gcell_at, &c->gpos, &c->cnt_e, &c->cnt_s, &c->lcap,
-                    &c->list, &c->ovf_list, &c->order, &c->q_val_alt})
+                    &c->list, &c->ovf_list, &c->order, &c->q_val_alt, &c->g_wide, &c->wide_list})
         b->release();
+    c->leaf_lev.release();
     for (auto *b : {&c->bbox_u, &c->key, &c->key_alt, &c->partial, &c->c_prefix, &c->seg,
                     &c->q_key, &c->q_key_alt})
         b->release();
@@ -496,6 +513,7 @@ int fdx_set_particles(fdx_ctx *c, int64_t n, const double *x, const double *y, c
     HIPCHK(c, c->flag.ensure(N));
     HIPCHK(c, c->gcell_at.ensure(N));
     HIPCHK(c, c->gpos.ensure(N));
+    HIPCHK(c, c->leaf_lev.ensure(N));
     HIPCHK(c, c->fs.ensure(N));
     HIPCHK(c, c->ax.ensure(N));
     HIPCHK(c, c->ay.ensure(N));

@@ -80,6 +80,8 @@ struct fdx_ctx {
 
     // groups
     fdx::DBuf<uint32_t> g_cell, g_begin, g_count, g_sys, g_box, flag, gcell_at, gpos;
+    fdx::DBuf<uint32_t> g_wide, wide_list;     // groups evaluated in FP64 by the FP32 path
+    fdx::DBuf<uint8_t> leaf_lev;               // level of every sorted particle's leaf
     fdx::DBuf<double> g_centre;
     uint32_t group_cap = 0;
 

@@ -29,6 +29,8 @@ struct DevStatus {
     uint64_t inter_pp, inter_pc;
     uint32_t group_overflow;  // more groups than the group arrays hold
     uint32_t top_level;       // deepest tree level whose cells fit the cell capacity
+    uint32_t wide_groups;     // FP32 evaluation: groups too wide for group-relative FP32
+    uint32_t pad_;
 };
 
 // any device-reported condition that makes this evaluation's forces incomplete
@@ -51,6 +53,7 @@ struct Groups {
     uint32_t *cell, *begin, *count, *sys;
     uint32_t *box;    // 6 per group: qmin x y z, qmax x y z (grid units)
     double *centre;   // 3 per group: geometric centre of the group's cell
+    uint32_t *wide;   // 1 where group-relative FP32 would be too coarse (evaluated in FP64)
     uint32_t cap;
 };
 
@@ -113,10 +116,19 @@ hipError_t tree_build(size_t n, int nsys, const int64_t *sys_off, const uint64_t
                       int n_leaf, Cells c, uint8_t *bytes, uint32_t *scratch,
                       uint64_t *partial, DevStatus *st, hipStream_t s);
 hipError_t tree_moments(Cells c, const double4 *jp, hipStream_t s);
+// groups, their boxes and centres, and the wide flag: with d = depth of the group's deepest
+// leaf below its cell, S the cell side and eps_min the smallest softening among its members,
+// a group is wide iff 9 u min(S / eps_min, 2^d) > 1e-4 (u = 2^-24), i.e. FP32 rounding of
+// coordinates taken relative to the group's centre could move a close pair's force by more
+// than 1e-4 of itself.  plev (n bytes) receives the level of every particle's leaf.
 hipError_t make_groups(size_t n, int nsys, const int64_t *sys_off, Cells c,
-                       const uint64_t *skey, const double *cube, int n_group, Groups g,
-                       uint32_t *flag, uint32_t *gcell_at, uint32_t *gpos, uint64_t *partial,
-                       DevStatus *st, hipStream_t s);
+                       const uint64_t *skey, const double *cube, const double *seps,
+                       int n_group, Groups g, uint32_t *flag, uint32_t *gcell_at, uint32_t *gpos,
+                       uint8_t *plev, uint64_t *partial, DevStatus *st, hipStream_t s);
+// list of the wide groups (any order; count in st->wide_groups) and a reset of the persistent
+// queue head for the pass that evaluates them
+hipError_t wide_group_list(size_t gmax, const Groups g, uint32_t *list, DevStatus *st,
+                           hipStream_t s);
 
 // walk: count (fill = false) or fill (fill = true) the interaction lists.
 // seg[g]/cap[g] = start and capacity of group g's segment in `list`; EPJ entries grow from
@@ -228,6 +240,7 @@ struct ForceArgs {
     bool quad, fp32, persistent;
     int variant;            // kernel shape chosen by the autotuner
     double r_cut = 0.0;     // > 0: tree part of TreePM (monopole, S2 cutoff), no potential
+    const uint32_t *count = nullptr;   // persistent launch: device group count (default: all)
 };
 // G = number of groups (direct launch: one workgroup per group; persistent launch: G bounds
 // the grid and the kernel reads the true count from the device status).

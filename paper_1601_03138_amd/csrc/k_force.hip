@@ -440,7 +440,8 @@ hipError_t force(size_t G, const ForceArgs &fa, hipStream_t s) {
     k.jp = fa.jp; k.seps = fa.seps; k.mom = fa.mom;
     k.seg = fa.seg; k.cap = fa.cap; k.cnt_e = fa.cnt_e; k.cnt_s = fa.cnt_s;
     k.list = fa.list;
-    k.order = fa.order; k.ngroups = &fa.st->n_groups_c; k.fs = fa.fs; k.st = fa.st;
+    k.order = fa.order; k.ngroups = fa.count ? fa.count : &fa.st->n_groups_c;
+    k.fs = fa.fs; k.st = fa.st;
     k.G = (uint32_t)G;
     k.cut_s = fa.r_cut > 0 ? 2.0 / fa.r_cut : 0.0;
     if (fa.r_cut > 0)                  // tree part of TreePM: monopole with the S2 cutoff

@@ -364,9 +364,29 @@ __global__ void k_group_emit(size_t n, int n_group, Cells c, const uint32_t *fla
 
 // One wave per group: integer box of the members' grid cells, centre of the group's cell,
 // and the group's system.
+// level of every particle's leaf (leaves partition the particles)
+__global__ void k_leaf_level(Cells c, uint8_t *plev) {
+    const uint32_t nc = min(c.lvl[kLevels + 1], c.cap);
+    for (size_t k = gtid(); k < nc; k += gstride()) {
+        if (c.nchild[k] != 0) continue;
+        const uint32_t b = c.begin[k], e = b + c.count[k];
+        const uint8_t l = (uint8_t)c.level[k];
+        for (uint32_t r = b; r < e; r++) plev[r] = l;
+    }
+}
+
+// groups flagged wide, appended in any order (each is evaluated on its own); the counter
+// starts from zero
+__global__ void k_wide_list(const uint32_t *ngroups_c, Groups g, uint32_t *list, DevStatus *st) {
+    const uint32_t G = *ngroups_c;
+    for (size_t gi = gtid(); gi < G; gi += gstride())
+        if (g.wide[gi]) list[atomicAdd(&st->wide_groups, 1u)] = (uint32_t)gi;
+}
+
 __global__ void __launch_bounds__(kThreads)
 k_group_geom(const uint32_t *ngroups, int nsys, const int64_t *off, Cells c,
-             const uint64_t *skey, const double *cube, Groups g, DevStatus *st) {
+             const uint64_t *skey, const double *cube, const double *seps, const uint8_t *plev,
+             Groups g, DevStatus *st) {
     const uint32_t G = min(*ngroups, g.cap);
     if (gtid() == 0) {
         st->n_groups_c = G;
@@ -377,14 +397,21 @@ k_group_geom(const uint32_t *ngroups, int nsys, const int64_t *off, Cells c,
     for (size_t gi = wave0; gi < G; gi += nwaves) {
         const uint32_t b = g.begin[gi], e = b + g.count[gi];
         uint32_t lo[3] = {kNone, kNone, kNone}, hi[3] = {0, 0, 0};
+        uint32_t deep = 0;
+        double emin = INFINITY;
         for (uint32_t r = b + lane; r < e; r += kWave) {
             const uint64_t k = skey[r];
             const uint32_t q[3] = {compact3(k >> 2), compact3(k >> 1), compact3(k)};
 #pragma unroll
             for (int a = 0; a < 3; a++) { lo[a] = min(lo[a], q[a]); hi[a] = max(hi[a], q[a]); }
+            deep = max(deep, (uint32_t)plev[r]);
+            emin = fmin(emin, seps[r]);
         }
 #pragma unroll
         for (int a = 0; a < 3; a++) { lo[a] = wave_min_u32(lo[a]); hi[a] = wave_max_u32(hi[a]); }
+        deep = wave_max_u32(deep);
+#pragma unroll
+        for (int d = kWave / 2; d >= 1; d >>= 1) emin = fmin(emin, __shfl_xor(emin, d, kWave));
         if (lane == 0) {
             int slo = 0, shi = nsys - 1;               // last s with off[s] <= b
             while (slo < shi) {
@@ -405,6 +432,11 @@ k_group_geom(const uint32_t *ngroups, int nsys, const int64_t *off, Cells c,
                 const double hg = (double)(2u * cq[a] + (1u << (kLevels - l)));
                 g.centre[3 * gi + a] = __dadd_rn(cb[a], __dmul_rn(hg, h));
             }
+            // wide: 9 u min(S / eps_min, 2^d) > 1e-4 with u = 2^-24
+            const double side = ldexp(cb[3], -(int)l);
+            const double span = ldexp(1.0, (int)deep - (int)l);
+            const double m = fmin(side / emin, span);
+            g.wide[gi] = (9.0 * 5.9604644775390625e-8) * m > 1e-4 ? 1u : 0u;
         }
     }
 }
@@ -468,9 +500,9 @@ hipError_t tree_moments(Cells c, const double4 *jp, hipStream_t s) {
 }
 
 hipError_t make_groups(size_t n, int nsys, const int64_t *sys_off, Cells c,
-                       const uint64_t *skey, const double *cube, int n_group, Groups g,
-                       uint32_t *flag, uint32_t *gcell_at, uint32_t *gpos, uint64_t *partial,
-                       DevStatus *st, hipStream_t s) {
+                       const uint64_t *skey, const double *cube, const double *seps,
+                       int n_group, Groups g, uint32_t *flag, uint32_t *gcell_at, uint32_t *gpos,
+                       uint8_t *plev, uint64_t *partial, DevStatus *st, hipStream_t s) {
     hipError_t e = fill_u32(flag, 0u, n, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_group_flags, dim3(grid_for(c.cap, 8192)), dim3(kThreads), 0, s, c,
@@ -479,8 +511,19 @@ hipError_t make_groups(size_t n, int nsys, const int64_t *sys_off, Cells c,
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_group_emit, dim3(grid_for(n)), dim3(kThreads), 0, s, n, n_group, c, flag,
                        gcell_at, gpos, g);
+    hipLaunchKernelGGL(k_leaf_level, dim3(grid_for(c.cap, 8192)), dim3(kThreads), 0, s, c, plev);
     hipLaunchKernelGGL(k_group_geom, dim3(grid_for(n / 16 + 64, 4096)), dim3(kThreads), 0, s,
-                       &st->n_groups, nsys, sys_off, c, skey, cube, g, st);
+                       &st->n_groups, nsys, sys_off, c, skey, cube, seps, plev, g, st);
+    return hipGetLastError();
+}
+
+hipError_t wide_group_list(size_t gmax, const Groups g, uint32_t *list, DevStatus *st,
+                           hipStream_t s) {
+    hipError_t e = fill_u32(&st->wide_groups, 0u, 1, s);
+    if (e == hipSuccess) e = fill_u32(&st->queue_head, 0u, 1, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_wide_list, dim3(grid_for(gmax + 1, 4096)), dim3(kThreads), 0, s,
+                       &st->n_groups_c, g, list, st);
     return hipGetLastError();
 }
 

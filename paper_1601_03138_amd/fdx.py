@@ -47,7 +47,7 @@ class Stats(C.Structure):
         ("n_leaf", C.c_int32), ("n_group", C.c_int32), ("flags", C.c_int32),
         ("shape", C.c_int32), ("theta", C.c_double)] + [(k, C.c_double) for k in (
             "t_keys", "t_sort", "t_tree", "t_moments", "t_groups", "t_walk", "t_force",
-            "t_unsort", "t_predict", "t_total")]
+            "t_unsort", "t_predict", "t_total")] + [("fp64_groups", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -278,3 +278,49 @@ def test_direct_sum_reference_matches_the_oracle(ctx, fdx):
         ctx.direct_forces([ps.n])
     with pytest.raises(fdx.FdxError):
         ctx.direct_forces([0], eps=0.0)
+
+
+def _wide_groups_reference(t, g):
+    """Groups the FP32 path must hand to the FP64 kernel: 9 u min(S / eps_min, 2^d) > 1e-4."""
+    leaf = t.nchild == 0
+    plev = np.zeros(t.sx.shape[0], np.int64)
+    for b, c, l in zip(t.begin[leaf], t.count[leaf], t.level[leaf]):
+        plev[int(b):int(b) + int(c)] = int(l)
+    b = g.begin.astype(np.int64)
+    deep = np.maximum.reduceat(plev, b)
+    emin = np.minimum.reduceat(t.seps, b)
+    lvl = t.level[g.cell].astype(np.int64)
+    side = np.ldexp(t.cube.reshape(-1, 4)[t.csys[g.cell], 3], -lvl)
+    m = np.minimum(side / emin, np.ldexp(1.0, deep - lvl))
+    return (9.0 * 2.0 ** -24) * m > 1e-4
+
+
+def test_fp32_path_hands_wide_groups_to_fp64(ctx):
+    """A small system of two tight clumps 10^4 apart is one group: group-relative FP32 would
+    lose ~1e-3 of its close-pair forces, so that group is evaluated in FP64 (its rows equal the
+    FP64 evaluation bit for bit); compact groups stay FP32."""
+    a = I.plummer(200, seed=81, eps=0.01)
+    a.x[100:] += 1.0e4
+    b = I.plummer(3000, seed=82, eps=0.01)
+    ps = I.concat([a, b])
+    t, g, lists = tree_ref(ps, 1, 200, 0.76)
+    wide = _wide_groups_reference(t, g)
+    assert wide.sum() >= 1 and not wide.all()
+    ctx.set_particles(ps)
+    ctx.calc_force(0.76, 1, 200, 0.0, quad=True, fp32=False)
+    a64 = ctx.forces()
+    ctx.calc_force(0.76, 1, 200, 0.0, quad=True, fp32=True)
+    a32 = ctx.forces()
+    assert ctx.stats()["fp64_groups"] == int(wide.sum())
+    rows = np.concatenate([np.arange(g.begin[k], g.begin[k] + g.count[k]) for k in np.nonzero(wide)[0]])
+    user = t.perm[rows].astype(np.int64)
+    assert np.array_equal(a32[user], a64[user])
+    other = np.setdiff1d(np.arange(ps.n), user)
+    assert not np.array_equal(a32[other], a64[other])
+    ref_sorted = lists.force(True)
+    ref = np.empty_like(ref_sorted)
+    ref[t.perm.astype(np.int64)] = ref_sorted
+    ok = np.linalg.norm(ref[:, :3], axis=1) > 0
+    e = rel_err(a32[ok], ref[ok])
+    _say(f"[wide] fp64 groups {int(wide.sum())} of {g.n}; fp32-path rms vs tree {np.sqrt(np.mean(e ** 2)):.2e}")
+    assert np.sqrt(np.mean(e ** 2)) <= F32_RMS_REL_VS_TREE

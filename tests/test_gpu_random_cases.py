@@ -5,7 +5,8 @@ and moment order.  Keys, order, cells, groups and every list bit-exact; FP64 for
 the FP64 tolerance of the oracle's forces on the same lists; FP32 group-relative forces within
 the per-particle bound that FP32 rounding of group-relative coordinates allows (it grows with
 a group's extent over its pair separations: a small system of two far-apart clumps forms one
-wide group), and within the FP32 tolerance wherever that bound is small."""
+wide group) and within the FP32 tolerance (groups too wide for FP32 are handed to the FP64
+kernel)."""
 import sys
 
 import numpy as np
@@ -98,4 +99,4 @@ def test_random_configuration(ctx, seed):
         _say(f"  fp32 rms {rms:.2e} (bound rms {brms:.2e}), max ratio to bound "
              f"{np.max(e32 / bound):.2e}")
         assert np.all(e32 <= 1.5 * bound + 1e-6)
-        assert rms <= max(F32_RMS_REL_VS_TREE, brms)
+        assert rms <= F32_RMS_REL_VS_TREE      # groups too wide for FP32 run in FP64
