@@ -2,7 +2,8 @@
 times: keys, order, every cell and every group bit-exact against the oracle's full serial
 build; lists and forces on sampled groups; accuracy against FP64 direct summation on seeded
 subsets; the ensemble with graph-captured steps; the predictor path at full size; the
-exchange lists of the benchmark input cut into 64 domains; its multisection domain decomposition."""
+exchange lists of the benchmark input cut into 64 and 512 domains; its multisection domain
+decomposition; the whole path at 4x the benchmark size."""
 import os
 import sys
 
@@ -257,5 +258,41 @@ def test_clustered16m_exchange_lists_512_domains_two_pass(fdx):
         assert st["list_capacity"] == int(ne.sum() + ns.sum())     # sized by the count walk
         _say(f"  entries {int(ne.sum() + ns.sum())}; device ms: trees {st['ms_tree']:.3f}, "
              f"lists {st['ms_lists']:.3f}")
+    finally:
+        c.close()
+
+
+def test_clustered64m_beyond_the_benchmark_size(fdx):
+    """N = 2^26 clustered (4x the benchmark): 3.5e9 list entries, past signed 32-bit offsets.  Keys,
+    order, every cell and group bit-exact; sampled lists exact; FP32 forces against the tree
+    and against direct summation on the GPU."""
+    ps = I.clustered(n_background=1 << 25, n_clusters=64, n_per_cluster=1 << 19, seed=26)
+    _say(f"[fullsize] clustered n={ps.n}")
+    c = fdx.Context(0)
+    try:
+        c.set_particles(ps)
+        c.calc_force(0.5, 8, 256, 0.0, quad=True, fp32=True)
+        st = c.stats()
+        assert st["n_epj"] + st["n_spj"] > (1 << 31)          # past signed 32-bit offsets
+        t = O.build_tree(ps, 8)
+        g = O.make_groups(t, 256)
+        tree = c.tree()
+        assert np.array_equal(tree["key"], t.skey) and np.array_equal(tree["perm"], t.perm)
+        for k in ("level", "prefix", "begin", "count", "first_child", "nchild", "parent"):
+            assert np.array_equal(tree[k], getattr(t, k).astype(tree[k].dtype)), k
+        check_moments(tree["mom"], t)
+        check_groups(c.groups(), g)
+        rng = np.random.default_rng(3)
+        sel = np.sort(rng.choice(g.n, 32, replace=False))
+        lists = O.walk(t, g, 0.5, sel)
+        ne, ns = c.list_counts()
+        assert np.array_equal(ne[sel].astype(np.int64), lists.n_epj)
+        assert np.array_equal(ns[sel].astype(np.int64), lists.n_spj)
+        e_tree = _sampled_force_check(c, t, g, sel, lists, True)
+        sub = I.subset(ps.n, 256, seed=102)
+        e_direct = O.rms_rel_error(c.forces()[sub], c.direct_forces(sub))
+        _say(f"  entries {st['n_epj'] + st['n_spj']}; fp32 vs tree {e_tree:.2e}, vs direct "
+             f"{e_direct:.2e}")
+        assert e_tree <= F32_RMS_REL_VS_TREE and e_direct <= BAR_RMS_VS_DIRECT
     finally:
         c.close()
