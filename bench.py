@@ -168,6 +168,9 @@ def main():
     ap.add_argument("--treepm-log2n", type=int, default=24,
                     help="also time the tree part of TreePM (uniform cube of 2^k particles, cutoff "
                          "of three mesh widths; 0: skip)")
+    ap.add_argument("--ensemble-steps", type=int, default=10,
+                    help="also time the batched ensemble (512 Plummer systems, persistent force, "
+                         "graph-captured steps) for this many steps (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -263,8 +266,15 @@ def main():
     # + 8 eps + 4 inverse); walk = the 4-byte list entries written by the fill pass
     passes = 8 + (0 if ps.n_sys <= 1 else (int(np.ceil(np.log2(ps.n_sys))) + 7) // 8)
     gbs = lambda b, ms: round(b / (ms / 1e3) / 1e9, 1) if ms > 0 else None
+    # tree = 30 B per particle (keys read by the level, count and emit passes) + 60 B per
+    # cell written; moments = 80 B per cell written + 80 B per child read; groups = 16 B per
+    # particle + 1 B leaf level written and read
+    ncell = int(st["n_cells"])
     phase_gbs = {"keys": gbs(124 * ps.n, phase_ms["keys"]),
                  "sort": gbs((32 * passes + 80) * ps.n, phase_ms["sort"]),
+                 "tree": gbs(30 * ps.n + 60 * ncell, phase_ms["tree"]),
+                 "moments": gbs(160 * ncell, phase_ms["moments"]),
+                 "groups": gbs(18 * ps.n, phase_ms["groups"]),
                  "walk_list_write": gbs(4 * (int(st["n_epj"]) + int(st["n_spj"])),
                                         phase_ms["walk"])}
     traffic = read_traffic(f"force_fp32_quad_{args.workload}" if quad else
@@ -400,6 +410,45 @@ def main():
         del sps
         log(f"[bench] sph: {sph}")
 
+    # batched ensemble: 512 independent Plummer systems in one persistent force launch, steps
+    # captured as a HIP graph; FP32 group-relative and FP64 against direct summation
+    ens = None
+    if args.ensemble_steps > 0 and args.workload != "ensemble512":
+        eg, eth, equad, edt = WORKLOADS["ensemble512"]
+        eps_ = inputs.workload("ensemble512")
+        ce = fdx.Context(0)
+        ce.set_particles(eps_)
+        f32 = fdx.Context.flags(quad=equad, fp32=True, persistent=True)
+        ce.calc_force_flags(eth, 8, eg, 0.0, f32)
+        for _ in range(2):
+            ce.integrate(edt, 1, graph=True)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(args.ensemble_steps):
+            ce.integrate(edt, 1, graph=True)
+        torch.cuda.synchronize()
+        ms_graph = (time.perf_counter() - ta) * 1e3 / args.ensemble_steps
+        sub = inputs.subset(eps_.n, 256, seed=103)
+        d = ce.direct_forces(sub)
+        ce.calc_force_flags(eth, 8, eg, 0.0, f32 | fdx.TIMING)
+        e32 = rms_rel_error(ce.forces()[sub], d)
+        t32 = ce.stats()["t_total"]
+        f64 = fdx.Context.flags(quad=equad, fp32=False, persistent=True, timing=True)
+        ce.calc_force_flags(eth, 8, eg, 0.0, f64)
+        ce.calc_force_flags(eth, 8, eg, 0.0, f64)
+        t64 = ce.stats()["t_total"]
+        e64 = rms_rel_error(ce.forces()[sub], d)
+        ens = {"n": eps_.n, "systems": eps_.n_sys, "theta": eth, "n_group": eg,
+               "steps_graph": args.ensemble_steps, "ms_per_step_graph": round(ms_graph, 3),
+               "particles_per_s_graph": float(round(eps_.n / (ms_graph / 1e3), -5)),
+               "ms_per_eval_fp32": round(float(t32), 3), "ms_per_eval_fp64": round(float(t64), 3),
+               "particles_per_s_fp64": float(round(eps_.n / (t64 / 1e3), -5)),
+               "rms_da_over_a_fp32": e32, "rms_da_over_a_fp64": e64,
+               "accuracy_subset": "256 particles, seed 103, FP64 direct sum within each system"}
+        ce.close()
+        del eps_
+        log(f"[bench] ensemble: {ens}")
+
     # tree part of TreePM: monopole tree with the S2 cutoff, FP32 group-relative
     treepm = None
     if args.treepm_log2n > 0:
@@ -477,6 +526,7 @@ def main():
         "phase_gbs": phase_gbs,
         "exchange": exch,
         "domain_decomposition": dd,
+        "ensemble": ens,
         "sph": sph,
         "treepm_tree": treepm,
         "energy_drift": drift,
