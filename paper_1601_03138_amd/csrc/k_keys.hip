@@ -21,7 +21,8 @@ constexpr int kBboxChunk = 4096;
 
 // Per-system min/max of x, y, z as order-preserving u64 (bbox_u[6 s + 2 a] = min of axis a,
 // bbox_u[6 s + 2 a + 1] = max).  A block reduces a contiguous chunk; elements of a system
-// other than the chunk's first take the (rare) per-element atomic path.
+// other than the chunk's first (systems are contiguous, so a wave's 64 consecutive elements
+// hold few of them) are reduced per wave and system and issue one set of atomics each.
 __global__ void __launch_bounds__(kThreads)
 k_bbox(size_t n, const double *x, const double *y, const double *z, const uint32_t *sysid,
        uint64_t *bbox_u) {
@@ -30,18 +31,45 @@ k_bbox(size_t n, const double *x, const double *y, const double *z, const uint32
     if (b0 >= n) return;
     const size_t b1 = min(n, b0 + kBboxChunk);
     const uint32_t s0 = sysid[b0];
+    const int lane = lane_id();
     uint64_t mn[3] = {~0ull, ~0ull, ~0ull}, mx[3] = {0, 0, 0};
-    for (size_t i = b0 + threadIdx.x; i < b1; i += kThreads) {
-        uint64_t v[3] = {dbl_to_ord(x[i]), dbl_to_ord(y[i]), dbl_to_ord(z[i])};
-        uint32_t s = sysid[i];
-        if (s == s0) {
+    // wave-uniform trip count: every lane of a wave takes part in the ballots below
+    for (size_t base = b0 + (threadIdx.x - lane); base < b1; base += kThreads) {
+        const size_t i = base + lane;
+        const bool valid = i < b1;
+        uint64_t v[3] = {0, 0, 0};
+        uint32_t s = s0;
+        if (valid) {
+            v[0] = dbl_to_ord(x[i]); v[1] = dbl_to_ord(y[i]); v[2] = dbl_to_ord(z[i]);
+            s = sysid[i];
+            if (s == s0) {
 #pragma unroll
-            for (int a = 0; a < 3; a++) { mn[a] = min(mn[a], v[a]); mx[a] = max(mx[a], v[a]); }
-        } else {
+                for (int a = 0; a < 3; a++) { mn[a] = min(mn[a], v[a]); mx[a] = max(mx[a], v[a]); }
+            }
+        }
+        uint64_t pending = __ballot(valid && s != s0);
+        while (pending) {
+            const int leader = __ffsll((long long)pending) - 1;
+            const uint32_t s1 = __shfl(s, leader);
+            const bool mine = valid && s == s1;
+            pending &= ~__ballot(mine);
+            uint64_t lo[3], hi[3];
+#pragma unroll
+            for (int a = 0; a < 3; a++) { lo[a] = mine ? v[a] : ~0ull; hi[a] = mine ? v[a] : 0ull; }
 #pragma unroll
             for (int a = 0; a < 3; a++) {
-                atomicMin((unsigned long long *)&bbox_u[6 * s + 2 * a], (unsigned long long)v[a]);
-                atomicMax((unsigned long long *)&bbox_u[6 * s + 2 * a + 1], (unsigned long long)v[a]);
+#pragma unroll
+                for (int d = 32; d >= 1; d >>= 1) {
+                    lo[a] = min(lo[a], (uint64_t)__shfl_xor((unsigned long long)lo[a], d, kWave));
+                    hi[a] = max(hi[a], (uint64_t)__shfl_xor((unsigned long long)hi[a], d, kWave));
+                }
+            }
+            if (lane == leader) {
+#pragma unroll
+                for (int a = 0; a < 3; a++) {
+                    atomicMin((unsigned long long *)&bbox_u[6 * s1 + 2 * a], (unsigned long long)lo[a]);
+                    atomicMax((unsigned long long *)&bbox_u[6 * s1 + 2 * a + 1], (unsigned long long)hi[a]);
+                }
             }
         }
     }
