@@ -64,7 +64,7 @@ def force_flops(st, quad):
         FLOPS_PC_QUAD if quad else FLOPS_PC_MONO)
 
 
-def read_traffic(kernel_tag: str, shape: str):
+def read_traffic(kernel_tag: str, shape: str, launch: str):
     """HBM bytes per launch of the force kernel measured by rocprofv3 counters, if a summary
     for the current kernel source is committed under profiles/ (else None)."""
     path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.txt")
@@ -80,7 +80,7 @@ def read_traffic(kernel_tag: str, shape: str):
         src = open(os.path.join(ROOT, "paper_1601_03138_amd", "csrc", "k_force.hip"), "rb").read()
         if vals.get("k_force.hip sha256") != hashlib.sha256(src).hexdigest():
             return None
-        if vals.get("shape") != shape:
+        if vals.get("shape") != shape or vals.get("launch") != launch:
             return None
         return float(vals["hbm bytes per launch"])
     except (KeyError, ValueError, OSError):
@@ -144,8 +144,9 @@ def main():
     ap.add_argument("--cpu-sample-groups", type=int, default=512)
     ap.add_argument("--graph", action="store_true",
                     help="replay each leapfrog step as a captured HIP graph (persistent force)")
-    ap.add_argument("--persistent", action="store_true",
-                    help="persistent force kernel over the cost-ordered group queue")
+    ap.add_argument("--direct", action="store_true",
+                    help="one workgroup per group in group order (XCD-aware) instead of the "
+                         "default persistent force kernel over the cost-ordered group queue")
     ap.add_argument("--walk", default="auto", choices=["auto", "exact", "predicted"],
                     help="exact: count pass + fill pass; predicted: the learned list-length "
                          "predictor sizes the lists for a single fill pass (groups that do not "
@@ -196,7 +197,7 @@ def main():
     ps = inputs.workload(args.workload)
     ctx = fdx.Context(0)
     ctx.set_particles(ps)
-    persistent = args.persistent or args.graph
+    persistent = not args.direct or args.graph
     flags = fdx.Context.flags(quad=quad, fp32=True, timing=True, persistent=persistent)
     tuned = None
     if args.autotune:
@@ -278,7 +279,8 @@ def main():
                  "walk_list_write": gbs(4 * (int(st["n_epj"]) + int(st["n_spj"])),
                                         phase_ms["walk"])}
     traffic = read_traffic(f"force_fp32_quad_{args.workload}" if quad else
-                           f"force_fp32_mono_{args.workload}", shape)
+                           f"force_fp32_mono_{args.workload}", shape,
+                           "persistent" if persistent else "direct")
 
     # the same evaluation with the exact and the predicted walk
     pred = None
@@ -314,7 +316,7 @@ def main():
     # FP64 force path on the same (current) particles
     fp64 = None
     if args.fp64_evals > 0:
-        f64flags = fdx.Context.flags(quad=quad, fp32=False, timing=True)
+        f64flags = fdx.Context.flags(quad=quad, fp32=False, timing=True, persistent=persistent)
         ctx.calc_force_flags(theta, 8, n_group, 0.0, f64flags)
         torch.cuda.synchronize()
         ta = time.perf_counter()
@@ -512,7 +514,8 @@ def main():
                    "step": "leapfrog kick-drift, full force evaluation, kick"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                     "traffic": traffic, "kernel": f"k_force_direct<float, quad> {shape}",
+                     "traffic": traffic, "kernel": (f"k_force_persistent<float, quad> {shape}" if persistent
+                                else f"k_force_direct<float, quad> {shape}"),
                      "kernel_ms": round(mean_force_ms, 3),
                      "interactions_per_launch": int(st["n_interactions_pp"] + st["n_interactions_pc"]),
                      "interactions_per_s": round((st["n_interactions_pp"] + st["n_interactions_pc"])

@@ -57,8 +57,9 @@ typedef struct fdx_ctx fdx_ctx;
 #define FDX_PREDICTOR 4   /* size interaction lists from the learned list-length predictor
                              (single walk; overflowing groups are re-walked exactly, so
                              forces never depend on it) */
-#define FDX_PERSISTENT 8  /* one persistent force launch that pops groups from a
-                             cost-ordered global queue */
+#define FDX_PERSISTENT 8  /* one persistent force launch: the groups, in tree order, are cut
+                             into one contiguous queue per XCD; a workgroup pops its own
+                             XCD's queue, then takes slots from the others' */
 #define FDX_GRAPH 16      /* fdx_integrate: capture one step as a HIP graph and replay it */
 #define FDX_TIMING 32     /* record per-phase times (fdx_get_stats) */
 

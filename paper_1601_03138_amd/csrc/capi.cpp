@@ -76,10 +76,6 @@ int ensure_tree_buffers(fdx_ctx *c, uint32_t cell_cap, uint32_t group_cap) {
         HIPCHK(c, c->lcap.ensure(group_cap));
         HIPCHK(c, c->seg.ensure((size_t)group_cap + 1));
         HIPCHK(c, c->ovf_list.ensure(group_cap));
-        HIPCHK(c, c->order.ensure(group_cap));
-        HIPCHK(c, c->q_val_alt.ensure(group_cap));
-        HIPCHK(c, c->q_key.ensure(group_cap));
-        HIPCHK(c, c->q_key_alt.ensure(group_cap));
         HIPCHK(c, c->rs_scratch.ensure(radix_scratch_u32(std::max<size_t>(n, group_cap))));
         c->group_cap = group_cap;
     }
@@ -248,10 +244,6 @@ int enqueue_force(fdx_ctx *c, size_t gmax) {
     fa.persistent = (c->flags & FDX_PERSISTENT) != 0;
     fa.variant = ext_force_variant(c);
     fa.r_cut = c->cutoff;
-    if (fa.persistent) {
-        int r = ext_queue_order(c, gmax, &fa.order);
-        if (r) return r;
-    }
     HIPCHK(c, force(gmax, fa, s));
     if (fa.fp32) {
         // groups too wide for group-relative FP32: evaluated again by the FP64 kernel, which
@@ -414,11 +406,10 @@ int fdx_destroy(fdx_ctx *c) {
                     &c->c_begin, &c->c_count, &c->c_first, &c->c_nchild, &c->c_parent, &c->c_lvl,
                     &c->tmp_n, &c->tmp_off, &c->g_cell, &c->g_begin, &c->g_count, &c->g_sys,
                     &c->g_box, &c->flag, &c->gcell_at, &c->gpos, &c->cnt_e, &c->cnt_s, &c->lcap,
-                    &c->list, &c->ovf_list, &c->order, &c->q_val_alt, &c->g_wide, &c->wide_list})
+                    &c->list, &c->ovf_list, &c->g_wide, &c->wide_list})
         b->release();
     c->leaf_lev.release();
-    for (auto *b : {&c->bbox_u, &c->key, &c->key_alt, &c->partial, &c->c_prefix, &c->seg,
-                    &c->q_key, &c->q_key_alt})
+    for (auto *b : {&c->bbox_u, &c->key, &c->key_alt, &c->partial, &c->c_prefix, &c->seg})
         b->release();
     c->sys_off.release();
     c->jp.release();

@@ -86,8 +86,7 @@ struct fdx_ctx {
     uint32_t group_cap = 0;
 
     // lists
-    fdx::DBuf<uint32_t> cnt_e, cnt_s, lcap, list, ovf_list, order, q_val_alt;
-    fdx::DBuf<uint64_t> q_key, q_key_alt;
+    fdx::DBuf<uint32_t> cnt_e, cnt_s, lcap, list, ovf_list;
     fdx::DBuf<uint64_t> seg;
     uint64_t list_cap = 0;
 

@@ -31,6 +31,7 @@ struct DevStatus {
     uint32_t top_level;       // deepest tree level whose cells fit the cell capacity
     uint32_t wide_groups;     // FP32 evaluation: groups too wide for group-relative FP32
     uint32_t pad_;
+    uint32_t xcd_head[8];     // persistent force kernel: next slot of each XCD's queue
 };
 
 // any device-reported condition that makes this evaluation's forces incomplete
@@ -217,9 +218,6 @@ hipError_t direct_forces(uint32_t nt, const uint32_t *targets, const double *x, 
                          const uint32_t *sysid, const int64_t *sys_off, double *out,
                          hipStream_t s);
 
-// queue order for the persistent force kernel: groups by decreasing estimated cost
-hipError_t queue_keys(size_t gmax, const Groups g, const uint32_t *cnt_e, const uint32_t *cnt_s,
-                      uint64_t *key, uint32_t *val, DevStatus *st, hipStream_t s);
 hipError_t list_caps(size_t gmax, const uint32_t *cnt_e, const uint32_t *cnt_s, uint32_t *cap,
                      DevStatus *st, hipStream_t s);
 hipError_t list_stats(size_t gmax, const Groups g, const uint32_t *cnt_e,

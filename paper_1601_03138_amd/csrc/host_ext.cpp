@@ -1,5 +1,5 @@
-// Host extensions of the force path: force-kernel shape choice and autotuner, the
-// cost-ordered queue of the persistent force kernel, and HIP-graph capture of leapfrog steps.
+// Host extensions of the force path: force-kernel shape choice and autotuner, and HIP-graph
+// capture of leapfrog steps.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -19,19 +19,6 @@ int ext_force_variant(fdx_ctx *c) {
     int v = c->ext.variant >= 0 ? c->ext.variant : dflt;
     if (force_variant_capacity(v) < c->n_group) v = 3;
     return v;
-}
-
-// Groups by decreasing estimated cost (stable radix sort of complemented 32-bit costs), so
-// the persistent kernel starts the longest work first (longest-processing-time order).
-int ext_queue_order(fdx_ctx *c, size_t gmax, const uint32_t **order) {
-    hipStream_t s = c->stream;
-    HIPCHK(c, queue_keys(gmax, groups_view(c), c->cnt_e.p, c->cnt_s.p, c->q_key.p, c->order.p,
-                         c->st, s));
-    bool alt = false;
-    HIPCHK(c, radix_sort(gmax, c->q_key.p, c->q_key_alt.p, c->order.p, c->q_val_alt.p, nullptr,
-                         1, 32, c->rs_scratch.p, c->partial.p, &alt, s));
-    *order = alt ? c->q_val_alt.p : c->order.p;
-    return FDX_OK;
 }
 
 // ---------------------------------------------------------------------------------------

@@ -1,5 +1,5 @@
 // Host-side extensions of the force path: learned list-length predictor, force-kernel
-// autotuner, persistent-queue ordering and HIP-graph capture of leapfrog steps.
+// autotuner and HIP-graph capture of leapfrog steps.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -21,7 +21,6 @@ struct HostExt {
 };
 
 int ext_force_variant(fdx_ctx *c);
-int ext_queue_order(fdx_ctx *c, size_t gmax, const uint32_t **order);
 int ext_integrate_graph(fdx_ctx *c, double dt, int n_steps);
 void ext_release(fdx_ctx *c);
 void ext_invalidate(fdx_ctx *c);   // drop any captured graph (particles or buffers changed)

@@ -358,15 +358,35 @@ k_force_direct(KArgs a) {
     force_group<T, QUAD, NT, IPL, PF, CUT>(a, a.order ? a.order[q] : q, sm);
 }
 
-// Persistent variant: a fixed grid pops queue slots from a device counter (the queue order
-// lists the groups by decreasing cost, so the longest work starts first).
+// Persistent variant: a fixed grid pops work from device counters.  Without an explicit list
+// the groups are split into eight contiguous runs in tree order, one queue per XCD
+// (consecutive workgroups are dispatched round-robin over the 8 XCDs, so workgroup b runs on
+// XCD b % 8); a workgroup pops from its own XCD's queue, keeping neighbouring groups -- which
+// share most of their lists -- in one L2, and once that queue is empty takes slots from the
+// other XCDs' queues, which balances the load.  With an explicit list (order + device count)
+// it pops one shared queue.
 template <class T, bool QUAD, int NT, int IPL, bool PF, int OCC, bool CUT>
 __global__ void __launch_bounds__(NT, OCC)
 k_force_persistent(KArgs a) {
     __shared__ Smem<T, NT, IPL> sm;
     const uint32_t G = *a.ngroups;
+    const uint32_t x = blockIdx.x % 8u, chunk = (G + 7u) / 8u;
     for (;;) {
-        if (threadIdx.x == 0) sm.slot = atomicAdd(&a.st->queue_head, 1u);
+        if (threadIdx.x == 0) {
+            uint32_t slot = kNone;
+            if (a.order) {
+                slot = atomicAdd(&a.st->queue_head, 1u);
+            } else {
+                for (uint32_t t = 0; t < 8u && slot == kNone; t++) {
+                    const uint32_t q = (x + t) & 7u;
+                    const uint32_t lo = q * chunk, hi = min(G, lo + chunk);
+                    if (lo >= hi) continue;
+                    const uint32_t k = atomicAdd(&a.st->xcd_head[q], 1u);
+                    if (k < hi - lo) slot = lo + k;
+                }
+            }
+            sm.slot = slot;
+        }
         __syncthreads();
         const uint32_t slot = sm.slot;
         __syncthreads();

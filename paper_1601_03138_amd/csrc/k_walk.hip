@@ -216,22 +216,6 @@ k_list_stats(const uint32_t *ngroups, uint32_t gmax, const uint32_t *gcount,
     }
 }
 
-// Persistent-queue keys: estimated cost n_i * (|EPJ| + 2 |SPJ|) (a superparticle costs about
-// twice a particle), complemented so an ascending sort lists the costliest group first;
-// slots past the group count sort last.
-__global__ void k_queue_keys(uint32_t gmax, const uint32_t *ngroups_c, const uint32_t *gcount,
-                             const uint32_t *cnt_e, const uint32_t *cnt_s, uint64_t *key,
-                             uint32_t *val) {
-    const uint32_t G = *ngroups_c;
-    for (size_t gi = gtid(); gi < gmax; gi += gstride()) {
-        uint64_t cost = 0;
-        if (gi < G) cost = (uint64_t)gcount[gi] * ((uint64_t)cnt_e[gi] + 2ull * cnt_s[gi]);
-        cost = cost > 0xFFFFFFFEull ? 0xFFFFFFFEull : cost;
-        key[gi] = gi < G ? (uint64_t)(0xFFFFFFFEu - (uint32_t)cost) : 0xFFFFFFFFull;
-        val[gi] = (uint32_t)gi;
-    }
-}
-
 // Exchange lists between domains (section "Exchange of particles and superparticles",
 // long-range mode).  The list of the ordered pair (sender s, receiver r != s) is the walk of
 // s's tree against the exact bounding box of r's particles in s's integer grid,
@@ -409,15 +393,6 @@ hipError_t walk_short(bool fill, int kind, size_t gmax, const Groups g, const Ce
         default: launch_walk<4>(fill, gmax, g, c, theta2, seg, cap, list_cap, list, cnt_e, cnt_s,
                                 ovf_list, nullptr, nullptr, st, sa, s); break;
     }
-    return hipGetLastError();
-}
-
-hipError_t queue_keys(size_t gmax, const Groups g, const uint32_t *cnt_e, const uint32_t *cnt_s,
-                      uint64_t *key, uint32_t *val, DevStatus *st, hipStream_t s) {
-    size_t b = (gmax + kThreads - 1) / kThreads;
-    b = b < 1 ? 1 : (b > 8192 ? 8192 : b);
-    hipLaunchKernelGGL(k_queue_keys, dim3((unsigned)b), dim3(kThreads), 0, s, (uint32_t)gmax,
-                       &st->n_groups_c, g.count, cnt_e, cnt_s, key, val);
     return hipGetLastError();
 }
 
