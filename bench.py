@@ -5,6 +5,10 @@ keys, sort, tree, moments, groups, walk, force, unsort; kick) on the N = 2^24 cl
 workload, theta = 0.5, quadrupole superparticles, FP32 group-relative force kernels.
 Inputs are resident in device memory before the timed region.  Prints one JSON line.
 
+n_group and the force kernel's workgroup shape are chosen first by the library's autotuner
+(n_group in {64, 128, 256, 512} x every shape, full evaluations timed; --no-autotune keeps the
+workload default), for the headline workload and for the batched ensemble.
+
 Also reported: the FP64 force path on the same input, the force-kernel roofline (measured with
 HIP events on the library's stream), accuracy against FP64 direct summation on a seeded
 subset, and the CPU oracle timed on a bounded sample of the same workload.
@@ -66,25 +70,29 @@ def force_flops(st, quad):
 
 def read_traffic(kernel_tag: str, shape: str, launch: str):
     """HBM bytes per launch of the force kernel measured by rocprofv3 counters, if a summary
-    for the current kernel source is committed under profiles/ (else None)."""
-    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.txt")
-    if not os.path.exists(path):
-        return None
-    vals = {}
-    for line in open(path):
-        if ":" in line:
-            k, v = line.split(":", 1)
-            vals[k.strip()] = v.strip()
+    for the current kernel source, this shape and this launch is committed under profiles/
+    (files <kernel_tag>_<shape>_traffic.txt; else None)."""
+    import glob
+    import hashlib
     try:
-        import hashlib
         src = open(os.path.join(ROOT, "paper_1601_03138_amd", "csrc", "k_force.hip"), "rb").read()
-        if vals.get("k_force.hip sha256") != hashlib.sha256(src).hexdigest():
-            return None
-        if vals.get("shape") != shape or vals.get("launch") != launch:
-            return None
-        return float(vals["hbm bytes per launch"])
-    except (KeyError, ValueError, OSError):
+    except OSError:
         return None
+    sha = hashlib.sha256(src).hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"{kernel_tag}_*traffic.txt"))):
+        vals = {}
+        for line in open(path):
+            if ":" in line:
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+        if (vals.get("k_force.hip sha256") != sha or vals.get("shape") != shape
+                or vals.get("launch") != launch):
+            continue
+        try:
+            return float(vals["hbm bytes per launch"])
+        except (KeyError, ValueError):
+            return None
+    return None
 
 
 def rms_rel_error(a, a_ref) -> float:
@@ -92,6 +100,18 @@ def rms_rel_error(a, a_ref) -> float:
     d = np.sum((a[:, :3] - a_ref[:, :3]) ** 2, axis=1)
     r = np.sum(a_ref[:, :3] ** 2, axis=1)
     return float(math.sqrt(np.mean(d / r)))
+
+
+def autotune(ctx, theta, quad, persistent):
+    """n_group in {64, 128, 256, 512} x every force-kernel shape, full evaluations timed by the
+    library's autotuner (the median of 2 after one untimed); its choice stays set in ctx."""
+    from paper_1601_03138_amd import fdx
+    cand = [64, 128, 256, 512]
+    bg, bv, times = ctx.autotune(theta, 8, 0.0,
+                                 fdx.Context.flags(quad=quad, fp32=True, persistent=persistent),
+                                 cand, reps=2)
+    return {"n_group": bg, "shape": bv, "shape_name": ctx.shape_name(bv), "candidates": cand,
+            "ms": [[None if np.isnan(v) else round(float(v), 3) for v in row] for row in times]}
 
 
 def cpu_baseline(ps, n_group, theta, quad, n_sample_groups, seed=7):
@@ -154,8 +174,11 @@ def main():
                          "when weights for the workload exist")
     ap.add_argument("--predictor", default="",
                     help="predictor weights (default: the shipped ones for the workload)")
-    ap.add_argument("--autotune", action="store_true",
-                    help="run the autotuner over n_group x kernel shape first and use its choice")
+    ap.add_argument("--shape", default="",
+                    help="force-kernel shape by name (e.g. nt512_ipl1_w8); skips the autotuner")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the autotuner (n_group x kernel shape) and use the workload's "
+                         "default n_group and shape")
     ap.add_argument("--exchange-domains", type=int, default=4,
                     help="also time the exchange lists of the input cut into k x k x k "
                          "equal-count domains (0: skip)")
@@ -200,14 +223,16 @@ def main():
     persistent = not args.direct or args.graph
     flags = fdx.Context.flags(quad=quad, fp32=True, timing=True, persistent=persistent)
     tuned = None
-    if args.autotune:
-        cand = [64, 128, 256, 512]
-        bg, bv, times = ctx.autotune(theta, 8, 0.0, fdx.Context.flags(quad=quad, fp32=True), cand,
-                                     reps=2)
-        n_group = bg
-        tuned = {"n_group": bg, "shape": bv, "candidates": cand,
-                 "ms": [[None if np.isnan(v) else round(float(v), 3) for v in row] for row in times]}
-        log(f"[bench] autotune: n_group={bg} shape={bv} times={tuned['ms']}")
+    if args.shape:
+        names = [ctx.shape_name(v) for v in range(ctx.lib.fdx_autotune_shapes())]
+        if args.shape not in names:
+            print(f"bench.py: unknown shape {args.shape}; shapes: {names}", file=sys.stderr)
+            sys.exit(2)
+        ctx.set_shape(names.index(args.shape))
+    elif not args.no_autotune and not args.n_group:
+        tuned = autotune(ctx, theta, quad, persistent)
+        n_group = tuned["n_group"]
+        log(f"[bench] autotune: n_group={n_group} shape={tuned['shape_name']} times={tuned['ms']}")
 
     weights = args.predictor or PREDICTOR_WEIGHTS.get((args.workload, n_group, theta), "")
     if weights and not os.path.exists(weights):
@@ -420,6 +445,11 @@ def main():
         eps_ = inputs.workload("ensemble512")
         ce = fdx.Context(0)
         ce.set_particles(eps_)
+        etuned = None
+        if not args.no_autotune:
+            etuned = autotune(ce, eth, equad, True)
+            eg = etuned["n_group"]
+            log(f"[bench] ensemble autotune: n_group={eg} shape={etuned['shape_name']}")
         f32 = fdx.Context.flags(quad=equad, fp32=True, persistent=True)
         ce.calc_force_flags(eth, 8, eg, 0.0, f32)
         for _ in range(2):
@@ -446,7 +476,8 @@ def main():
                "ms_per_eval_fp32": round(float(t32), 3), "ms_per_eval_fp64": round(float(t64), 3),
                "particles_per_s_fp64": float(round(eps_.n / (t64 / 1e3), -5)),
                "rms_da_over_a_fp32": e32, "rms_da_over_a_fp64": e64,
-               "accuracy_subset": "256 particles, seed 103, FP64 direct sum within each system"}
+               "accuracy_subset": "256 particles, seed 103, FP64 direct sum within each system",
+               "autotune": etuned and {k: etuned[k] for k in ("n_group", "shape_name")}}
         ce.close()
         del eps_
         log(f"[bench] ensemble: {ens}")

@@ -180,9 +180,10 @@ int fdx_get_lists(fdx_ctx *ctx, uint32_t *n_epj, uint32_t *n_spj, uint32_t *epj,
  * it instead.  fdx_autotune_shapes() = number of force-kernel shapes (threads per workgroup x
  * i-particles per thread).  fdx_autotune times fdx_calc_force (median of `reps` calls after
  * one warm-up) for each of the n_cand candidate group sizes and every shape that can hold
- * them, keeps the fastest shape for later calls and returns it with its group size;
+ * them, keeps the fastest shape for later calls of the same precision (FDX_FP32REL set or
+ * not in `flags`; the other precision keeps its shape) and returns it with its group size;
  * times_ms[k * shapes + v] receives each time (NaN where the shape cannot hold the group
- * size; null skips).  fdx_set_shape fixes the shape (-1 = default).
+ * size; null skips).  fdx_set_shape fixes the shape of both precisions (-1 = default).
  * FDX_EINVAL: no candidates, reps < 1, or a shape out of range. */
 int fdx_autotune_shapes(void);
 const char *fdx_shape_name(int32_t shape);   /* e.g. "nt512_ipl1_pf"; "" if out of range */

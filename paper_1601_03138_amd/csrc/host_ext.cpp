@@ -14,9 +14,12 @@
 namespace fdx {
 
 int ext_force_variant(fdx_ctx *c) {
-    // defaults measured at N = 2^24: FP32 nt512_ipl1_pf_w8, FP64 nt256_ipl2 (no prefetch)
-    const int dflt = (c->flags & FDX_FP32REL) ? 8 : 5;
-    int v = c->ext.variant >= 0 ? c->ext.variant : dflt;
+    // defaults measured at N = 2^24: FP32 nt512_ipl1_pf_w8 for the direct launch and
+    // nt512_ipl1_w8 (no register prefetch: no spills in the persistent loop) for the
+    // persistent launch, FP64 nt256_ipl2 (no prefetch)
+    const bool f32 = (c->flags & FDX_FP32REL) != 0;
+    const int dflt = f32 ? ((c->flags & FDX_PERSISTENT) ? 9 : 8) : 5;
+    int v = c->ext.variant[f32] >= 0 ? c->ext.variant[f32] : dflt;
     if (force_variant_capacity(v) < c->n_group) v = 3;
     return v;
 }
@@ -191,7 +194,7 @@ const char *fdx_shape_name(int32_t shape) {
 int fdx_set_shape(fdx_ctx *c, int32_t shape) {
     if (!c) return FDX_EINVAL;
     if (shape < -1 || shape >= force_variants()) return fail(c, FDX_EINVAL, "shape out of range");
-    c->ext.variant = shape;
+    c->ext.variant[0] = c->ext.variant[1] = shape;
     return FDX_OK;
 }
 
@@ -203,20 +206,23 @@ int fdx_autotune(fdx_ctx *c, double theta, int32_t n_leaf, double eps, int32_t f
     const int nv = force_variants();
     double best = 1e300;
     int bg = -1, bv = -1;
-    const int saved = c->ext.variant;
+    // the search sets the shape of the precision it times; the other keeps its own
+    const bool f32 = (flags & FDX_FP32REL) != 0;
+    int &slot = c->ext.variant[f32];
+    const int saved = slot;
     flags &= ~(FDX_TIMING | FDX_PREDICTOR);
     for (int k = 0; k < n_cand; k++) {
         for (int v = 0; v < nv; v++) {
             double t = NAN;
             if (force_variant_capacity(v) >= n_group_cand[k]) {
-                c->ext.variant = v;
+                slot = v;
                 int r = fdx_calc_force(c, theta, n_leaf, n_group_cand[k], eps, flags);
-                if (r) { c->ext.variant = saved; return r; }
+                if (r) { slot = saved; return r; }
                 std::vector<double> ts;
                 for (int q = 0; q < reps; q++) {
                     auto t0 = std::chrono::steady_clock::now();
                     r = fdx_calc_force(c, theta, n_leaf, n_group_cand[k], eps, flags);
-                    if (r) { c->ext.variant = saved; return r; }
+                    if (r) { slot = saved; return r; }
                     auto t1 = std::chrono::steady_clock::now();
                     ts.push_back(std::chrono::duration<double, std::milli>(t1 - t0).count());
                 }
@@ -227,7 +233,7 @@ int fdx_autotune(fdx_ctx *c, double theta, int32_t n_leaf, double eps, int32_t f
             if (times_ms) times_ms[(size_t)k * nv + v] = t;
         }
     }
-    c->ext.variant = bv;
+    slot = bv;
     if (best_n_group) *best_n_group = bg;
     if (best_shape) *best_shape = bv;
     return FDX_OK;
@@ -273,7 +279,7 @@ int fdx_autotune_cached(fdx_ctx *c, const char *path, double theta, int32_t n_le
         fclose(f);
     }
     if (g_hit > 0) {
-        c->ext.variant = v_hit;
+        c->ext.variant[(flags & FDX_FP32REL) != 0] = v_hit;
         if (best_n_group) *best_n_group = g_hit;
         if (best_shape) *best_shape = v_hit;
         if (from_cache) *from_cache = 1;

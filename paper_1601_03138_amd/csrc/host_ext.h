@@ -11,7 +11,7 @@ struct fdx_ctx;
 namespace fdx {
 
 struct HostExt {
-    int variant = -1;                 // autotuned force-kernel variant (-1: default)
+    int variant[2] = {-1, -1};        // autotuned force-kernel variant, [FP64, FP32] (-1: default)
     void *pred = nullptr;             // predictor state (weights, normalisation)
     void *graph = nullptr;            // captured step (GraphState)
     void *exch = nullptr;             // exchange lists between domains

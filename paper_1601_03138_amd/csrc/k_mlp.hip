@@ -66,14 +66,22 @@ __global__ void k_features(const uint32_t *ngroups_c, Groups g, Cells c, const i
     }
 }
 
-// inference: one thread per sample; parameters staged in LDS
-__global__ void __launch_bounds__(256)
+// inference: one thread per sample; parameters staged in LDS.  The second layer runs over
+// blocks of 8 units (8 accumulators, their weights read as vectors), which keeps the register
+// budget near 100 and several waves per SIMD; every sum is taken in the same order as a
+// plain unit-by-unit evaluation (bias first, then inputs ascending; the output over units
+// ascending).  At least 4 waves per SIMD (128 registers).
+__global__ void __launch_bounds__(256, 4)
 k_mlp_infer(size_t n, const uint32_t *n_dev, const float *X, const float *P, float *y) {
     __shared__ float w[kMlpParams];
     for (int k = threadIdx.x; k < kMlpParams; k += blockDim.x) w[k] = P[k];
     __syncthreads();
     const size_t nn = n_dev ? *n_dev : n;
     for (size_t s = gtid(); s < nn; s += gstride()) {
+        // the weights are read from LDS where they are used: without this compiler barrier
+        // the first layer's 576 loop-invariant reads are hoisted out of the sample loop and
+        // spill
+        __asm__ volatile("" ::: "memory");
         float x[kIn], h1[kH];
 #pragma unroll
         for (int k = 0; k < kIn; k++) x[k] = X[s * kIn + k];
@@ -85,11 +93,18 @@ k_mlp_infer(size_t n, const uint32_t *n_dev, const float *X, const float *P, flo
             h1[u] = silu(z);
         }
         float out = w[OB3];
-        for (int u = 0; u < kH; u++) {
-            float z = w[OB2 + u];
+#pragma unroll 1
+        for (int u0 = 0; u0 < kH; u0 += 8) {
+            float z[8];
 #pragma unroll
-            for (int k = 0; k < kH; k++) z = fmaf(h1[k], w[OW2 + k * kH + u], z);
-            out = fmaf(silu(z), w[OW3 + u], out);
+            for (int j = 0; j < 8; j++) z[j] = w[OB2 + u0 + j];
+#pragma unroll
+            for (int k = 0; k < kH; k++) {
+#pragma unroll
+                for (int j = 0; j < 8; j++) z[j] = fmaf(h1[k], w[OW2 + k * kH + u0 + j], z[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < 8; j++) out = fmaf(silu(z[j]), w[OW3 + u0 + j], out);
         }
         y[s] = out;
     }

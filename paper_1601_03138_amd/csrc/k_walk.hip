@@ -158,17 +158,27 @@ k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, 
                 ctot = (uint32_t)__builtin_amdgcn_readlane((int)ci, kWave - 1);
                 lex = li - lc; cex = ci - cc;
             }
+            // the stores of a lane run in unrolled chunks of 8 with immediate offsets (the
+            // capacity bound hoisted out of the chunk), so a wave spends a few instructions
+            // per slot instead of a masked loop iteration
             if (FILL && leaf) {
                 const uint32_t e0 = ne + lex;
-                for (uint32_t k = 0; k < lc; k++)
-                    if (e0 + k < capg) list[base + e0 + k] = lk.x + k;
+                const uint32_t nw = e0 < capg ? min(lc, capg - e0) : 0u;
+                uint32_t *dst = list + base + e0;
+                for (uint32_t k0 = 0; k0 < nw; k0 += 8) {
+#pragma unroll
+                    for (uint32_t k = 0; k < 8; k++)
+                        if (k0 + k < nw) dst[k0 + k] = lk.x + k0 + k;
+                }
             }
             ne += ltot;
-            // children of opened internal cells onto the stack
+            // children of opened internal cells onto the stack (at most 8 per cell)
             if (sp + ctot > (uint32_t)kWalkStack) { err = true; break; }
             if (inner) {
-                const uint32_t s0 = sp + cex;
-                for (uint32_t k = 0; k < cc; k++) stk[s0 + k] = lk.x + k;
+                uint32_t *d = stk + sp + cex;
+#pragma unroll
+                for (uint32_t k = 0; k < 8; k++)
+                    if (k < cc) d[k] = lk.x + k;
             }
             sp += ctot;
             wave_barrier();
@@ -207,12 +217,22 @@ k_list_stats(const uint32_t *ngroups, uint32_t gmax, const uint32_t *gcount,
         e += cnt_e[gi]; s += cnt_s[gi];
         pp += ni * cnt_e[gi]; pc += ni * cnt_s[gi];
     }
+    // wave sums, then the block's waves through LDS: one set of atomics per block (a few
+    // dozen blocks), not per wave
+    __shared__ uint64_t part[kWaves][4];
     e = wave_sum_u64(e); s = wave_sum_u64(s); pp = wave_sum_u64(pp); pc = wave_sum_u64(pc);
-    if (lane_id() == 0 && (e | s)) {
-        atomicAdd((unsigned long long *)&st->n_epj, (unsigned long long)e);
-        atomicAdd((unsigned long long *)&st->n_spj, (unsigned long long)s);
-        atomicAdd((unsigned long long *)&st->inter_pp, (unsigned long long)pp);
-        atomicAdd((unsigned long long *)&st->inter_pc, (unsigned long long)pc);
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) { part[w][0] = e; part[w][1] = s; part[w][2] = pp; part[w][3] = pc; }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        uint64_t v = 0;
+#pragma unroll
+        for (int k = 0; k < kWaves; k++) v += part[k][threadIdx.x];
+        unsigned long long *dst[4] = {(unsigned long long *)&st->n_epj,
+                                      (unsigned long long *)&st->n_spj,
+                                      (unsigned long long *)&st->inter_pp,
+                                      (unsigned long long *)&st->inter_pc};
+        if (v) atomicAdd(dst[threadIdx.x], (unsigned long long)v);
     }
 }
 
@@ -408,7 +428,7 @@ hipError_t list_caps(size_t gmax, const uint32_t *cnt_e, const uint32_t *cnt_s, 
 hipError_t list_stats(size_t gmax, const Groups g, const uint32_t *cnt_e, const uint32_t *cnt_s,
                       DevStatus *st, hipStream_t s) {
     size_t b = (gmax + kThreads - 1) / kThreads;
-    b = b < 1 ? 1 : (b > 2048 ? 2048 : b);
+    b = b < 1 ? 1 : (b > 64 ? 64 : b);
     hipLaunchKernelGGL(k_list_stats, dim3((unsigned)b), dim3(kThreads), 0, s, &st->n_groups_c,
                        (uint32_t)gmax, g.count, cnt_e, cnt_s, st);
     return hipGetLastError();

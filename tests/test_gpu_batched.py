@@ -71,6 +71,14 @@ def test_autotuner_picks_a_measured_candidate(ctx, fdx):
     assert bg in cand and 0 <= bv < times.shape[1]
     assert np.nanmin(times) == times[cand.index(bg), bv]
     assert np.isnan(times[cand.index(512), 0])           # shape 0 holds at most 256
+    ctx.calc_force(0.5, 8, bg, 0.0, quad=True, fp32=True)
+    assert ctx.stats()["shape"] == bv                     # the FP32 choice is in use
+    # tuning the FP32 kernel leaves the FP64 kernel's shape at its default
+    ctx.calc_force(0.5, 8, 256, 0.0, quad=True, fp32=False)
+    s64 = ctx.stats()["shape"]
+    ctx.set_shape(-1)
+    ctx.calc_force(0.5, 8, 256, 0.0, quad=True, fp32=False)
+    assert ctx.stats()["shape"] == s64
     ctx.set_shape(-1)
 
 
