@@ -37,12 +37,15 @@ FLOPS_PC_MONO = 20
 FLOPS_PC_QUAD = 54
 
 WORKLOADS = {
-    # name: (n_group, theta, quad, dt)
+    # name: (n_group, theta, quad, dt); the clustered and ensemble workloads are defined with
+    # an autotuned n_group (the value here is the default without the autotuner), the two
+    # Plummer spheres with a fixed one
     "clustered16m": (256, 0.5, True, 1.0 / 1024.0),
     "ensemble512": (128, 0.6, True, 1.0 / 256.0),
     "plummer1m": (256, 0.5, True, 1.0 / 256.0),
     "plummer4k": (64, 0.5, False, 1.0 / 128.0),
 }
+AUTOTUNED = {"clustered16m", "ensemble512"}
 
 
 # list-length predictor weights shipped with the package: (workload, n_group, theta) they were
@@ -160,6 +163,8 @@ def main():
     ap.add_argument("--n-group", type=int, default=0, help="0: workload default")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--accuracy-subset", type=int, default=4096,
+                    help="particles whose forces are checked against FP64 direct summation")
     ap.add_argument("--fp64-evals", type=int, default=3)
     ap.add_argument("--cpu-sample-groups", type=int, default=512)
     ap.add_argument("--graph", action="store_true",
@@ -229,7 +234,7 @@ def main():
             print(f"bench.py: unknown shape {args.shape}; shapes: {names}", file=sys.stderr)
             sys.exit(2)
         ctx.set_shape(names.index(args.shape))
-    elif not args.no_autotune and not args.n_group:
+    elif not args.no_autotune and not args.n_group and args.workload in AUTOTUNED:
         tuned = autotune(ctx, theta, quad, persistent)
         n_group = tuned["n_group"]
         log(f"[bench] autotune: n_group={n_group} shape={tuned['shape_name']} times={tuned['ms']}")
@@ -249,7 +254,7 @@ def main():
     # initial force (its flags, walk included, are those of every step), then warm-up steps
     step_flags = flags | (fdx.PREDICTOR if walk == "predicted" else 0)
     ctx.calc_force_flags(theta, 8, n_group, 0.0, step_flags)
-    energy0 = system_energies(ps, ctx) if ps.n_sys > 1 else None
+    energy0 = system_energies(ps, ctx)
     for _ in range(args.warmup):
         ctx.integrate(dt, 1, graph=args.graph)
     torch.cuda.synchronize()
@@ -362,14 +367,14 @@ def main():
     # accuracy of both paths against FP64 direct summation at the current positions
     accuracy = None
     if not args.no_accuracy:
-        sub = inputs.subset(ps.n, 256, seed=102)
+        sub = inputs.subset(ps.n, min(args.accuracy_subset, ps.n), seed=102)
         d = ctx.direct_forces(sub)                  # FP64 direct sum on the GPU
         ctx.calc_force_flags(theta, 8, n_group, 0.0, fdx.Context.flags(quad=quad, fp32=False))
         e64 = rms_rel_error(ctx.forces()[sub], d)
         ctx.calc_force_flags(theta, 8, n_group, 0.0, fdx.Context.flags(quad=quad, fp32=True))
         e32 = rms_rel_error(ctx.forces()[sub], d)
         accuracy = {"rms_da_over_a_fp32": e32, "rms_da_over_a_fp64": e64,
-                    "subset": "256 particles, seed 102, FP64 direct sum (fdx_direct_forces)"}
+                    "subset": f"{len(sub)} particles, seed 102, FP64 direct sum (fdx_direct_forces)"}
 
     # exchange lists between domains (the same particles as k x k x k virtual processes)
     exch = None
@@ -460,7 +465,7 @@ def main():
             ce.integrate(edt, 1, graph=True)
         torch.cuda.synchronize()
         ms_graph = (time.perf_counter() - ta) * 1e3 / args.ensemble_steps
-        sub = inputs.subset(eps_.n, 256, seed=103)
+        sub = inputs.subset(eps_.n, min(args.accuracy_subset, eps_.n), seed=103)
         d = ce.direct_forces(sub)
         ce.calc_force_flags(eth, 8, eg, 0.0, f32 | fdx.TIMING)
         e32 = rms_rel_error(ce.forces()[sub], d)
@@ -476,7 +481,8 @@ def main():
                "ms_per_eval_fp32": round(float(t32), 3), "ms_per_eval_fp64": round(float(t64), 3),
                "particles_per_s_fp64": float(round(eps_.n / (t64 / 1e3), -5)),
                "rms_da_over_a_fp32": e32, "rms_da_over_a_fp64": e64,
-               "accuracy_subset": "256 particles, seed 103, FP64 direct sum within each system",
+               "accuracy_subset": f"{len(sub)} particles, seed 103, FP64 direct sum within each "
+                                  "system",
                "autotune": etuned and {k: etuned[k] for k in ("n_group", "shape_name")}}
         ce.close()
         del eps_
