@@ -89,18 +89,31 @@ __device__ __forceinline__ double rsqrt_t(double x) {
 //   g = 1 - (12 - 224 xi^2 + 896 xi^3 - 840 xi^4 + 224 xi^5 + 70 xi^6 - 48 xi^7 + 7 xi^8)/140,
 //                                                                            1 < xi < 2
 //   g = 0 beyond; r unsoftened, softening in the Newtonian factor only; no potential.
+// The division by 140 is folded into the coefficients (Horner form), so no divide is issued.
 template <class T>
 __device__ __forceinline__ T s2_cutoff(T xi) {
     if (xi >= (T)2) return (T)0;
     if (xi <= (T)1) {
-        const T p = fma(xi, fma(xi, fma(xi, fma(xi, (T)-21, (T)48), (T)70), (T)-224), (T)0);
-        return (T)1 - xi * xi * xi * fma(xi, p, (T)224) / (T)140;
+        // (224 - 224 xi^2 + 70 xi^3 + 48 xi^4 - 21 xi^5) / 140
+        const T p = fma(xi, fma(xi, fma(xi, fma(xi, (T)(-21.0 / 140.0), (T)(48.0 / 140.0)),
+                                        (T)0.5), (T)-1.6), (T)0);
+        return (T)1 - xi * xi * xi * fma(xi, p, (T)1.6);
     }
-    const T q = fma(xi, fma(xi, fma(xi, fma(xi, fma(xi, fma(xi, fma(xi, (T)7, (T)-48), (T)70),
-                                                         (T)224), (T)-840), (T)896), (T)-224),
-                    (T)0);
-    return (T)1 - fma(xi, q, (T)12) / (T)140;
+    // (12 - 224 xi^2 + 896 xi^3 - 840 xi^4 + 224 xi^5 + 70 xi^6 - 48 xi^7 + 7 xi^8) / 140
+    const T q = fma(xi, fma(xi, fma(xi, fma(xi, fma(xi, fma(xi, fma(xi, (T)0.05,
+                                                                     (T)(-48.0 / 140.0)),
+                                                             (T)0.5), (T)1.6), (T)-6.0),
+                                    (T)6.4), (T)-1.6), (T)0);
+    return (T)1 - fma(xi, q, (T)(12.0 / 140.0));
 }
+
+// unsoftened |r| for the cutoff argument: FP32 from the hardware reciprocal square root
+// (a separation whose square is below the smallest normal float gives g = 1 either way);
+// FP64 the correctly rounded square root
+__device__ __forceinline__ float cut_dist(float r2) {
+    return r2 >= 1.17549435e-38f ? r2 * __builtin_amdgcn_rsqf(r2) : 0.0f;
+}
+__device__ __forceinline__ double cut_dist(double r2) { return sqrt(r2); }
 
 template <class T, bool CUT = false>
 __device__ __forceinline__ void pp(const typename V4<T>::t &J, T xi, T yi, T zi, T e2, T &ax,
@@ -109,7 +122,7 @@ __device__ __forceinline__ void pp(const typename V4<T>::t &J, T xi, T yi, T zi,
     if (CUT) {
         const T r2u = fma(dz, dz, fma(dy, dy, dx * dx));
         const T ri = rsqrt_t(r2u + e2);
-        const T f = J.w * ri * ri * ri * s2_cutoff<T>(sqrt(r2u) * cut_s);
+        const T f = J.w * ri * ri * ri * s2_cutoff<T>(cut_dist(r2u) * cut_s);
         ax = fma(f, dx, ax);
         ay = fma(f, dy, ay);
         az = fma(f, dz, az);
@@ -133,7 +146,7 @@ __device__ __forceinline__ void pc(const typename V4<T>::t &A, const typename V4
     if (CUT) {                                       // monopole with cutoff
         const T r2u = fma(rz, rz, fma(ry, ry, rx * rx));
         const T Ri = rsqrt_t(r2u + e2);
-        const T f = A.w * Ri * Ri * Ri * s2_cutoff<T>(sqrt(r2u) * cut_s);
+        const T f = A.w * Ri * Ri * Ri * s2_cutoff<T>(cut_dist(r2u) * cut_s);
         ax = fma(-f, rx, ax);
         ay = fma(-f, ry, ay);
         az = fma(-f, rz, az);
@@ -464,9 +477,12 @@ hipError_t force(size_t G, const ForceArgs &fa, hipStream_t s) {
     k.fs = fa.fs; k.st = fa.st;
     k.G = (uint32_t)G;
     k.cut_s = fa.r_cut > 0 ? 2.0 / fa.r_cut : 0.0;
-    if (fa.r_cut > 0)                  // tree part of TreePM: monopole with the S2 cutoff
-        return fa.fp32 ? launch<float, false, 512, 1, true, 8, true>(k, fa.persistent, s)
-                       : launch<double, false, 256, 2, false, 1, true>(k, fa.persistent, s);
+    if (fa.r_cut > 0) {                // tree part of TreePM: monopole with the S2 cutoff
+        if (!fa.fp32) return launch<double, false, 256, 2, false, 1, true>(k, fa.persistent, s);
+        // the persistent loop holds the 64-register budget only without the register prefetch
+        return fa.persistent ? launch<float, false, 512, 1, false, 8, true>(k, true, s)
+                             : launch<float, false, 512, 1, true, 8, true>(k, false, s);
+    }
     const int v = fa.variant;
     if (fa.fp32) return fa.quad ? launch_v<float, true>(k, fa.persistent, v, s)
                                 : launch_v<float, false>(k, fa.persistent, v, s);

@@ -3,6 +3,7 @@
 cells per side, theta 0.5, monopole kernel with the S2 cutoff, FP32 group-relative.
 
   python -m paper_1601_03138_amd.treepm_timing [--log2n 24] [--n-group 256] [--reps 5]
+                                                [--persistent] [--fp64]
 """
 from __future__ import annotations
 
@@ -28,6 +29,9 @@ def main():
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--fp64", action="store_true")
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--persistent", action="store_true",
+                    help="persistent force kernel over per-XCD queues (default: one workgroup "
+                         "per group)")
     args = ap.parse_args()
     ps, r_cut = workload(args.log2n)
     ctx = fdx.Context(0)
@@ -35,7 +39,7 @@ def main():
     rows = []
     for r in range(args.reps + 1):
         ctx.calc_force_cutoff(args.theta, 8, args.n_group, 0.0, r_cut, fp32=not args.fp64,
-                              timing=True)
+                              persistent=args.persistent, timing=True)
         st = ctx.stats()
         print(f"[treepm] call {r}: walk {st['t_walk']:.3f} ms, force {st['t_force']:.3f} ms, "
               f"total {st['t_total']:.3f} ms", flush=True)
@@ -44,7 +48,7 @@ def main():
     med = np.median(np.array(rows), axis=0)
     inter = int(st["n_interactions_pp"] + st["n_interactions_pc"])
     print(json.dumps({"n": ps.n, "r_cut": r_cut, "theta": args.theta, "n_group": args.n_group,
-                      "fp32": not args.fp64, "ms_walk": round(med[0], 3),
+                      "fp32": not args.fp64, "persistent": args.persistent, "ms_walk": round(med[0], 3),
                       "ms_force": round(med[1], 3), "ms_total": round(med[2], 3),
                       "interactions": inter, "epj": int(st["n_epj"]), "spj": int(st["n_spj"]),
                       "particles_per_s": round(ps.n / (med[2] / 1e3), -5)}), flush=True)
