@@ -2,7 +2,6 @@
 committed counter summary to the kernel source, shape and launch it was taken for, the flop
 accounting of the roofline and the error metric of reading R14."""
 import os
-import shutil
 import subprocess
 import sys
 
@@ -21,29 +20,38 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr or "1 GPU" in r.stderr or "--gpus 1" in r.stderr
 
 
+def _summary(shape, launch, hbm, sha):
+    return (f"HBM traffic of a force kernel\n"
+            f"fetch bytes per launch (scaled): 1.0e+09\n"
+            f"hbm bytes per launch: {hbm:.6e}\n"
+            f"shape: {shape}\nlaunch: {launch}\nk_force.hip sha256: {sha}\n")
+
+
 def test_traffic_lookup_matches_source_shape_and_launch(tmp_path, monkeypatch):
+    import hashlib
     tag = "force_fp32_quad_clustered16m"
-    shapes = {}
-    for f in os.listdir(os.path.join(ROOT, "profiles")):
-        if f.startswith(tag) and f.endswith("traffic.txt"):
-            vals = dict(line.split(":", 1) for line in open(os.path.join(ROOT, "profiles", f))
-                        if ":" in line)
-            shapes[vals["shape"].strip()] = (vals["launch"].strip(),
-                                             float(vals["hbm bytes per launch"]))
-    assert shapes, "no committed traffic summary"
-    for shape, (launch, hbm) in shapes.items():
-        assert bench.read_traffic(tag, shape, launch) == hbm
-        assert bench.read_traffic(tag, shape, "direct" if launch != "direct" else "x") is None
+    root = tmp_path / "root"
+    (root / "paper_1601_03138_amd" / "csrc").mkdir(parents=True)
+    (root / "profiles").mkdir()
+    src = root / "paper_1601_03138_amd" / "csrc" / "k_force.hip"
+    src.write_text("// kernel source as profiled\n")
+    sha = hashlib.sha256(src.read_bytes()).hexdigest()
+    (root / "profiles" / f"{tag}_nt512_ipl1_w8_traffic.txt").write_text(
+        _summary("nt512_ipl1_w8", "persistent", 8.3e9, sha))
+    (root / "profiles" / f"{tag}_nt512_ipl1_pf_w8_traffic.txt").write_text(
+        _summary("nt512_ipl1_pf_w8", "persistent", 1.36e10, sha))
+    (root / "profiles" / f"{tag}_nt256_ipl1_traffic.txt").write_text(
+        _summary("nt256_ipl1", "direct", 7.0e9, "0" * 64))          # another source
+    monkeypatch.setattr(bench, "ROOT", str(root))
+    assert bench.read_traffic(tag, "nt512_ipl1_w8", "persistent") == 8.3e9
+    assert bench.read_traffic(tag, "nt512_ipl1_pf_w8", "persistent") == 1.36e10
+    assert bench.read_traffic(tag, "nt512_ipl1_w8", "direct") is None       # other launch
+    assert bench.read_traffic(tag, "nt256_ipl1", "direct") is None          # stale source
     assert bench.read_traffic(tag, "no_such_shape", "persistent") is None
-    # a kernel source that differs from the one the counters were taken on: no traffic
-    fake = tmp_path / "root"
-    (fake / "paper_1601_03138_amd" / "csrc").mkdir(parents=True)
-    shutil.copytree(os.path.join(ROOT, "profiles"), fake / "profiles")
-    src = open(os.path.join(ROOT, "paper_1601_03138_amd", "csrc", "k_force.hip")).read()
-    (fake / "paper_1601_03138_amd" / "csrc" / "k_force.hip").write_text(src + "\n// changed\n")
-    monkeypatch.setattr(bench, "ROOT", str(fake))
-    for shape, (launch, _) in shapes.items():
-        assert bench.read_traffic(tag, shape, launch) is None
+    assert bench.read_traffic("force_fp32_quad_other", "nt512_ipl1_w8", "persistent") is None
+    # the kernel source changes after the counters were taken: no traffic is reported
+    src.write_text("// kernel source as profiled\n// changed\n")
+    assert bench.read_traffic(tag, "nt512_ipl1_w8", "persistent") is None
 
 
 def test_flop_accounting():
