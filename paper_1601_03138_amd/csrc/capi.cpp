@@ -127,7 +127,9 @@ int enqueue_keys_sort(fdx_ctx *c) {
     mark(c, 1);
     bool alt = false;
     HIPCHK(c, radix_sort(n, c->key.p, c->key_alt.p, c->perm.p, c->perm_alt.p, c->sysid.p, S, 64,
-                         c->rs_scratch.p, c->partial.p, &alt, s));
+                         c->rs_scratch.p, c->partial.p, &alt, s,
+                         S > 1 && S <= 65536 && c->sys_carry.cap >= 2 * n ? c->sys_carry.p
+                                                                           : nullptr));
     c->skey = alt ? c->key_alt.p : c->key.p;
     c->sperm = alt ? c->perm_alt.p : c->perm.p;
     HIPCHK(c, gather_sorted(n, c->sperm, c->packed.p, c->eps_given ? c->eps : nullptr,
@@ -409,6 +411,7 @@ int fdx_destroy(fdx_ctx *c) {
                     &c->list, &c->ovf_list, &c->g_wide, &c->wide_list})
         b->release();
     c->leaf_lev.release();
+    c->sys_carry.release();
     for (auto *b : {&c->bbox_u, &c->key, &c->key_alt, &c->partial, &c->c_prefix, &c->seg})
         b->release();
     c->sys_off.release();
@@ -498,6 +501,7 @@ int fdx_set_particles(fdx_ctx *c, int64_t n, const double *x, const double *y, c
     HIPCHK(c, c->perm_alt.ensure(N));
     HIPCHK(c, c->inv.ensure(N));
     HIPCHK(c, c->rs_scratch.ensure(radix_scratch_u32(N)));
+    if (n_sys > 1 && n_sys <= 65536) HIPCHK(c, c->sys_carry.ensure(2 * N));
     HIPCHK(c, c->jp.ensure(N));
     HIPCHK(c, c->packed.ensure(N));
     HIPCHK(c, c->seps.ensure(N));

@@ -63,6 +63,7 @@ struct fdx_ctx {
     fdx::DBuf<uint64_t> bbox_u, key, key_alt;
     fdx::DBuf<double> cube;
     fdx::DBuf<uint32_t> perm, perm_alt, inv, rs_scratch;
+    fdx::DBuf<uint16_t> sys_carry;                               // 2n: sort carry (several systems)
     fdx::DBuf<uint64_t> partial;
     uint64_t *skey = nullptr;
     uint32_t *sperm = nullptr;

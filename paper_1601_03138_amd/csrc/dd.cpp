@@ -359,6 +359,7 @@ int fdx_exchange_particles(fdx_ctx *c) {
     HIPCHK(c, sysid_fill(c->sys_off.p, D, c->sysid.p, N, s));
     HIPCHK(c, c->bbox_u.ensure(6 * (size_t)D));
     HIPCHK(c, c->cube.ensure(4 * (size_t)D));
+    if (D > 1 && D <= 65536) HIPCHK(c, c->sys_carry.ensure(2 * N));
     HIPCHK(c, hipStreamSynchronize(s));        // dom_off is a host vector
     c->nsys = D;
     c->sys_off_h = d->dom_off;

@@ -98,10 +98,14 @@ hipError_t morton_keys(size_t n, const double *x, const double *y, const double 
 
 // radix sort of (key, perm) pairs by key, then (stable) by system id of the original index.
 size_t radix_scratch_u32(size_t n);
-// key_bits = significant low bits of the keys (passes of 8 bits over them).
+// key_bits = significant low bits of the keys (passes of 8 bits over them).  carry: optional
+// 2n 16-bit scratch; with 2..65536 systems their ids then travel with the elements instead of
+// being gathered through the index in the system-id passes (the val array must start as the
+// identity, and sysid be indexed by the original index).
 hipError_t radix_sort(size_t n, uint64_t *key, uint64_t *key_alt, uint32_t *val,
                       uint32_t *val_alt, const uint32_t *sysid, int nsys, int key_bits,
-                      uint32_t *scratch, uint64_t *partial, bool *result_in_alt, hipStream_t s);
+                      uint32_t *scratch, uint64_t *partial, bool *result_in_alt, hipStream_t s,
+                      uint16_t *carry = nullptr);
 
 // sorted particle data
 hipError_t pack_particles(size_t n, const double *x, const double *y, const double *z,
