@@ -214,6 +214,14 @@ int enqueue_count(fdx_ctx *c, size_t gmax) {
     return FDX_OK;
 }
 
+int enqueue_bound(fdx_ctx *c, size_t gmax) {
+    hipStream_t s = c->stream;
+    HIPCHK(c, bound_caps(gmax, c->g_sys.p, c->sys_off.p, c->lcap.p, c->st, s));
+    HIPCHK(c, scan_u32_to_u64(c->lcap.p, c->seg.p, 0, nullptr, &c->st->n_groups_c, c->partial.p,
+                              &c->st->list_total, s));
+    return FDX_OK;
+}
+
 // Fill pass into the list buffer (its capacity guards every write), then counters.
 int enqueue_fill(fdx_ctx *c, size_t gmax) {
     hipStream_t s = c->stream;
@@ -691,21 +699,38 @@ int fdx_get_lists(fdx_ctx *c, uint32_t *n_epj, uint32_t *n_spj, uint32_t *epj, u
     HIPCHK(c, hipMemcpyAsync(cap.data(), c->lcap.p, 4 * G, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(seg.data(), c->seg.p, 8 * G, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
-    uint64_t end = 0;
-    for (size_t g = 0; g < G; g++) end = std::max<uint64_t>(end, seg[g] + cap[g]);
-    std::vector<uint32_t> all;
-    if (epj || spj) {
-        all.resize(end ? end : 1);
-        if (end) HIPCHK(c, hipMemcpy(all.data(), c->list.p, 4 * end, hipMemcpyDeviceToHost));
-    }
-    uint64_t oe = 0, os = 0;
+    // entries compacted on the device (segments may be far longer than their lists)
+    std::vector<uint64_t> oe(G + 1, 0), os(G + 1, 0);
     for (size_t g = 0; g < G; g++) {
+        oe[g + 1] = oe[g] + ce[g];
+        os[g + 1] = os[g] + cs[g];
         if (n_epj) n_epj[g] = ce[g];
         if (n_spj) n_spj[g] = cs[g];
-        if (epj) memcpy(epj + oe, all.data() + seg[g], 4ull * ce[g]);
-        if (spj) memcpy(spj + os, all.data() + seg[g] + cap[g] - cs[g], 4ull * cs[g]);
-        oe += ce[g];
-        os += cs[g];
+    }
+    if ((epj || spj) && G && (oe[G] || os[G])) {
+        DBuf<uint64_t> doe, dos;
+        DBuf<uint32_t> de, ds;
+        auto run = [&]() -> hipError_t {
+            hipError_t e = doe.ensure(G + 1);
+            if (e == hipSuccess) e = dos.ensure(G + 1);
+            if (e == hipSuccess) e = de.ensure(std::max<uint64_t>(oe[G], 1));
+            if (e == hipSuccess) e = ds.ensure(std::max<uint64_t>(os[G], 1));
+            if (e == hipSuccess) e = hipMemcpyAsync(doe.p, oe.data(), 8 * (G + 1),
+                                                    hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = hipMemcpyAsync(dos.p, os.data(), 8 * (G + 1),
+                                                    hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = compact_lists(G, c->seg.p, c->lcap.p, c->cnt_e.p, c->cnt_s.p,
+                                                   doe.p, dos.p, c->list.p, de.p, ds.p, s);
+            if (e == hipSuccess && epj && oe[G])
+                e = hipMemcpyAsync(epj, de.p, 4 * oe[G], hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess && spj && os[G])
+                e = hipMemcpyAsync(spj, ds.p, 4 * os[G], hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            return e;
+        };
+        const hipError_t e = run();
+        doe.release(); dos.release(); de.release(); ds.release();
+        if (e != hipSuccess) return fail(c, FDX_EHIP, "get_lists: %s", hipGetErrorString(e));
     }
     return FDX_OK;
 }

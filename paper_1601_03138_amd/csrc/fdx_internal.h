@@ -224,6 +224,14 @@ hipError_t direct_forces(uint32_t nt, const uint32_t *targets, const double *x, 
 
 hipError_t list_caps(size_t gmax, const uint32_t *cnt_e, const uint32_t *cnt_s, uint32_t *cap,
                      DevStatus *st, hipStream_t s);
+// lists out of their segments: epj[oe[g] ...] and spj[os[g] ...] (offsets exclusive sums)
+hipError_t compact_lists(size_t G, const uint64_t *seg, const uint32_t *cap,
+                         const uint32_t *cnt_e, const uint32_t *cnt_s, const uint64_t *oe,
+                         const uint64_t *os, const uint32_t *list, uint32_t *epj, uint32_t *spj,
+                         hipStream_t s);
+// cap[g] = size of the group's system (an upper bound on its list length)
+hipError_t bound_caps(size_t gmax, const uint32_t *gsys, const int64_t *sys_off, uint32_t *cap,
+                      DevStatus *st, hipStream_t s);
 hipError_t list_stats(size_t gmax, const Groups g, const uint32_t *cnt_e,
                       const uint32_t *cnt_s, DevStatus *st, hipStream_t s);
 

@@ -26,10 +26,13 @@ int ext_force_variant(fdx_ctx *c) {
 
 // ---------------------------------------------------------------------------------------
 // Graph-captured leapfrog step: kick + drift, the whole force evaluation (exact walk into a
-// fixed-capacity list buffer, persistent force kernel over the cost-ordered queue), kick.
-// Capacities are fixed at capture time with a margin; a step whose tree, groups or lists do
-// not fit is reported by the device status: its final kick is skipped, the host redoes force
-// and kick eagerly with larger buffers and captures again.
+// fixed-capacity list buffer, persistent force kernel over per-XCD queues), kick.  With
+// several systems whose list bound (every group's segment as long as its system, see
+// bound_caps) fits the list budget, the segments are sized by that bound and one fill walk
+// builds the lists; otherwise a count walk sizes them first.  Capacities are fixed at capture
+// time with a margin; a step whose tree, groups or lists do not fit is reported by the device
+// status: its final kick is skipped, the host redoes force and kick eagerly with larger
+// buffers and captures again.
 struct GraphState {
     hipStream_t gs = nullptr;
     hipGraph_t graph = nullptr;
@@ -39,6 +42,7 @@ struct GraphState {
     double dt = 0, theta = 0, eps_all = 0;
     int flags = 0, n_leaf = 0, n_group = 0, variant = 0, nsys = 0;
     int64_t n = -1;
+    bool bound = false;           // segments sized by the system-size bound (no count walk)
     void drop() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -57,7 +61,7 @@ static int capture_step(fdx_ctx *c, GraphState *g, double dt) {
                              dt, g->gs));
         int q = enqueue_keys_sort(c);
         if (!q) q = enqueue_tree_groups(c);
-        if (!q) q = enqueue_count(c, c->group_cap);
+        if (!q) q = g->bound ? enqueue_bound(c, c->group_cap) : enqueue_count(c, c->group_cap);
         if (!q) q = enqueue_fill(c, c->group_cap);
         if (!q) q = enqueue_force(c, c->group_cap);
         if (q) return q;
@@ -103,15 +107,33 @@ void ext_invalidate(fdx_ctx *c) {
     if (g) g->drop();
 }
 
-// capacities with headroom for the drift of one step
-static int graph_headroom(fdx_ctx *c) {
-    const DevStatus &h = c->hst->st;
+// list entries (4 B each) the bound-sized segments may take: 16 GiB
+constexpr uint64_t kBoundBudget = 1ull << 32;
+
+// capacities with headroom for the drift of one step; chooses the segment sizing
+static int graph_headroom(fdx_ctx *c, GraphState *g) {
+    const DevStatus h = c->hst->st;         // the last eager evaluation's tree and lists
     const uint32_t ncell = c->hst->lvl[kLevels + 1];
     uint32_t ccap = std::max<uint32_t>(c->cell_cap, ncell + ncell / 4 + 1024);
     uint32_t gcap = std::max<uint32_t>(c->group_cap, h.n_groups + h.n_groups / 4 + 1024);
     int r = ensure_tree_buffers(c, ccap, gcap);
     if (r) return r;
-    return ensure_list_capacity(c, h.list_total + h.list_total / 4 + 4096);
+    uint64_t need = h.list_total;
+    g->bound = false;
+    if (c->nsys > 1 && c->have_lists) {
+        // the bound of the current groups (their segments are re-sized by the next count or
+        // fill pass anyway)
+        r = enqueue_bound(c, gcap);
+        c->have_lists = false;              // seg / cap no longer describe the stored lists
+        if (!r) r = read_status(c);
+        if (r) return r;
+        const uint64_t bound = c->hst->st.list_total;
+        if (bound + bound / 4 + 4096 <= kBoundBudget) {
+            g->bound = true;
+            need = bound;
+        }
+    }
+    return ensure_list_capacity(c, need + need / 4 + 4096);
 }
 
 int ext_integrate_graph(fdx_ctx *c, double dt, int n_steps) {
@@ -130,7 +152,7 @@ int ext_integrate_graph(fdx_ctx *c, double dt, int n_steps) {
     int r = FDX_OK;
     for (int k = 0; k < n_steps && !r; k++) {
         if (graph_stale(c, g, dt)) {
-            r = graph_headroom(c);
+            r = graph_headroom(c, g);
             if (!r) r = capture_step(c, g, dt);
             if (r) break;
         }
@@ -140,6 +162,7 @@ int ext_integrate_graph(fdx_ctx *c, double dt, int n_steps) {
         if (r) break;
         const DevStatus h = c->hst->st;
         if (h.bad_input) { r = fail(c, FDX_EINVAL, "non-finite particle data"); break; }
+        c->have_lists = true;                // the replay's lists (or the eager redo's)
         if (status_incomplete(h)) {
             // positions and velocities hold kick + drift; redo force and kick eagerly
             r = run_tree(c, true);

@@ -207,6 +207,32 @@ __global__ void k_list_caps(const uint32_t *ngroups, uint32_t gmax, const uint32
     for (size_t gi = gtid(); gi < G; gi += gstride()) cap[gi] = cnt_e[gi] + cnt_s[gi];
 }
 
+// cap[g] = particles of the group's system: a bound on |EPJ| + |SPJ|, since a list's entries
+// (opened leaves' particles, accepted cells) cover disjoint sets of the system's particles
+__global__ void k_bound_caps(const uint32_t *ngroups, uint32_t gmax, const uint32_t *gsys,
+                             const int64_t *sys_off, uint32_t *cap) {
+    const uint32_t G = min(*ngroups, gmax);
+    for (size_t gi = gtid(); gi < G; gi += gstride()) {
+        const uint32_t s = gsys[gi];
+        cap[gi] = (uint32_t)(sys_off[s + 1] - sys_off[s]);
+    }
+}
+
+// every group's entries out of its segment into contiguous per-kind arrays (one workgroup per
+// group): EPJ from the front of the segment, SPJ from its back
+__global__ void __launch_bounds__(kThreads)
+k_compact_lists(size_t G, const uint64_t *seg, const uint32_t *cap, const uint32_t *cnt_e,
+                const uint32_t *cnt_s, const uint64_t *oe, const uint64_t *os,
+                const uint32_t *list, uint32_t *epj, uint32_t *spj) {
+    for (size_t g = blockIdx.x; g < G; g += gridDim.x) {
+        const uint64_t b = seg[g], e0 = oe[g], s0 = os[g];
+        const uint32_t ne = cnt_e[g], ns = cnt_s[g];
+        const uint64_t sb = b + cap[g] - ns;
+        for (uint32_t k = threadIdx.x; k < ne; k += kThreads) epj[e0 + k] = list[b + k];
+        for (uint32_t k = threadIdx.x; k < ns; k += kThreads) spj[s0 + k] = list[sb + k];
+    }
+}
+
 __global__ void __launch_bounds__(kThreads)
 k_list_stats(const uint32_t *ngroups, uint32_t gmax, const uint32_t *gcount,
              const uint32_t *cnt_e, const uint32_t *cnt_s, DevStatus *st) {
@@ -422,6 +448,25 @@ hipError_t list_caps(size_t gmax, const uint32_t *cnt_e, const uint32_t *cnt_s, 
     b = b < 1 ? 1 : (b > 8192 ? 8192 : b);
     hipLaunchKernelGGL(k_list_caps, dim3((unsigned)b), dim3(kThreads), 0, s, &st->n_groups_c,
                        (uint32_t)gmax, cnt_e, cnt_s, cap);
+    return hipGetLastError();
+}
+
+hipError_t bound_caps(size_t gmax, const uint32_t *gsys, const int64_t *sys_off, uint32_t *cap,
+                      DevStatus *st, hipStream_t s) {
+    size_t b = (gmax + kThreads - 1) / kThreads;
+    b = b < 1 ? 1 : (b > 8192 ? 8192 : b);
+    hipLaunchKernelGGL(k_bound_caps, dim3((unsigned)b), dim3(kThreads), 0, s, &st->n_groups_c,
+                       (uint32_t)gmax, gsys, sys_off, cap);
+    return hipGetLastError();
+}
+
+hipError_t compact_lists(size_t G, const uint64_t *seg, const uint32_t *cap,
+                         const uint32_t *cnt_e, const uint32_t *cnt_s, const uint64_t *oe,
+                         const uint64_t *os, const uint32_t *list, uint32_t *epj, uint32_t *spj,
+                         hipStream_t s) {
+    if (!G) return hipSuccess;
+    hipLaunchKernelGGL(k_compact_lists, dim3((unsigned)(G < 65536 ? G : 65536)), dim3(kThreads),
+                       0, s, G, seg, cap, cnt_e, cnt_s, oe, os, list, epj, spj);
     return hipGetLastError();
 }
 

@@ -105,7 +105,18 @@ def test_autotuner_records_and_reuses_its_choice(ctx, fdx, tmp_path):
     ctx.set_shape(-1)
 
 
+def _list_sets(lists):
+    ne, ns, epj, spj = lists
+    oe = np.concatenate([[0], np.cumsum(ne.astype(np.int64))])
+    os_ = np.concatenate([[0], np.cumsum(ns.astype(np.int64))])
+    return ne, ns, [np.sort(epj[oe[k]:oe[k + 1]]) for k in range(len(ne))], \
+        [np.sort(spj[os_[k]:os_[k + 1]]) for k in range(len(ns))]
+
+
 def test_graph_steps_match_eager_steps_on_an_ensemble(ctx, fdx):
+    """Several systems: the captured step sizes list segments by the system-size bound and
+    fills them in one walk; particles, forces and every list equal the eager steps' (count
+    walk, then fill)."""
     ens = I.ensemble(n_sys=24, seed=40, nmin=256, nmax=4096)
     _say(f"[graph] ensemble n={ens.n} systems={ens.n_sys}")
     dt, steps = 1.0 / 256.0, 6
@@ -114,10 +125,14 @@ def test_graph_steps_match_eager_steps_on_an_ensemble(ctx, fdx):
         ctx.set_particles(ens)
         ctx.calc_force(0.6, 8, 128, 0.0, quad=True, fp32=True, persistent=True)
         ctx.integrate(dt, steps, graph=graph)
-        runs[graph] = (ctx.particles(), ctx.forces())
+        runs[graph] = (ctx.particles(), ctx.forces(), _list_sets(ctx.lists()))
     for a, b in zip(runs[False][0], runs[True][0]):
         assert np.array_equal(a, b)
     assert np.array_equal(runs[False][1], runs[True][1])
+    (ne0, ns0, e0, s0), (ne1, ns1, e1, s1) = runs[False][2], runs[True][2]
+    assert np.array_equal(ne0, ne1) and np.array_equal(ns0, ns1)
+    assert all(np.array_equal(a, b) for a, b in zip(e0, e1))
+    assert all(np.array_equal(a, b) for a, b in zip(s0, s1))
 
 
 def test_ensemble_energy_and_force_error(ctx, fdx):
