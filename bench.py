@@ -465,6 +465,7 @@ def main():
             ce.integrate(edt, 1, graph=True)
         torch.cuda.synchronize()
         ms_graph = (time.perf_counter() - ta) * 1e3 / args.ensemble_steps
+        recoveries = int(ce.stats()["graph_recoveries"])
         sub = inputs.subset(eps_.n, min(args.accuracy_subset, eps_.n), seed=103)
         d = ce.direct_forces(sub)
         ce.calc_force_flags(eth, 8, eg, 0.0, f32 | fdx.TIMING)
@@ -483,6 +484,7 @@ def main():
                "rms_da_over_a_fp32": e32, "rms_da_over_a_fp64": e64,
                "accuracy_subset": f"{len(sub)} particles, seed 103, FP64 direct sum within each "
                                   "system",
+               "graph_recoveries": recoveries,
                "autotune": etuned and {k: etuned[k] for k in ("n_group", "shape_name")}}
         ce.close()
         del eps_
@@ -572,6 +574,7 @@ def main():
         "sph": sph,
         "treepm_tree": treepm,
         "energy_drift": drift,
+        "graph_recoveries": int(ctx.stats()["graph_recoveries"]) if args.graph else None,
         "predictor": pred,
         "autotune": tuned,
         "tree": {"cells": int(st["n_cells"]), "groups": int(st["n_groups"]),

@@ -120,6 +120,16 @@ int fdx_calc_force(fdx_ctx *ctx, double theta, int32_t n_leaf, int32_t n_group, 
  * n_steps < 0. */
 int fdx_integrate(fdx_ctx *ctx, double dt, int32_t n_steps, int32_t flags);
 
+/* List sizing of FDX_GRAPH steps with several systems.  A group's list has at most as many
+ * entries as its system has particles (its entries cover disjoint sets of them), so the
+ * captured step can size every group's list segment by its system, min(particles of the
+ * system, percent / 100 x the longest list the system had in the evaluation before the
+ * capture + 64), and fill the lists in one walk, without a count walk, when all segments fit
+ * a 16 GiB budget.  A replay whose list outgrew its segment is redone eagerly (counted in
+ * fdx_stats.graph_recoveries) and the percentage doubles for the next capture.  percent = 0
+ * sizes the segments by a count walk in every step.  Default 200.  FDX_EINVAL: percent < 0. */
+int fdx_set_graph_list_margin(fdx_ctx *ctx, int32_t percent);
+
 /* Copy positions and velocities (caller's order) into x..vz (length n each, memory of
  * kind mem_kind).  Any pointer may be null to skip that array. */
 int fdx_get_particles(fdx_ctx *ctx, double *x, double *y, double *z, double *vx, double *vy,
@@ -150,6 +160,7 @@ typedef struct {
        coordinates relative to the group centre could move a close pair's force by more than
        1e-4 of itself (see FDX_FP32REL) */
     int64_t fp64_groups;
+    int64_t graph_recoveries;   /* graph-replayed steps redone eagerly (a capacity overflowed) */
 } fdx_stats;
 
 int fdx_get_stats(fdx_ctx *ctx, fdx_stats *out);

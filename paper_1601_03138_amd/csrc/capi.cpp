@@ -214,9 +214,9 @@ int enqueue_count(fdx_ctx *c, size_t gmax) {
     return FDX_OK;
 }
 
-int enqueue_bound(fdx_ctx *c, size_t gmax) {
+int enqueue_sys_caps(fdx_ctx *c, size_t gmax, const uint32_t *sys_cap) {
     hipStream_t s = c->stream;
-    HIPCHK(c, bound_caps(gmax, c->g_sys.p, c->sys_off.p, c->lcap.p, c->st, s));
+    HIPCHK(c, sys_caps(gmax, c->g_sys.p, sys_cap, c->lcap.p, c->st, s));
     HIPCHK(c, scan_u32_to_u64(c->lcap.p, c->seg.p, 0, nullptr, &c->st->n_groups_c, c->partial.p,
                               &c->st->list_total, s));
     return FDX_OK;
@@ -344,6 +344,7 @@ void finish_stats(fdx_ctx *c) {
     o.depth = depth;
     o.n_leaf = c->n_leaf; o.n_group = c->n_group; o.flags = c->flags; o.theta = c->theta;
     o.shape = ext_force_variant(c);
+    o.graph_recoveries = c->ext.graph_recoveries;
 }
 
 int sync_timing(fdx_ctx *c) {

@@ -136,8 +136,8 @@ int enqueue_keys_sort(fdx_ctx *c);
 int enqueue_tree_groups(fdx_ctx *c);
 int enqueue_count(fdx_ctx *c, size_t gmax);
 int enqueue_fill(fdx_ctx *c, size_t gmax);
-// segments sized by the bound |list| <= particles of the group's system (no count walk)
-int enqueue_bound(fdx_ctx *c, size_t gmax);
+// segments sized per system (sys_cap, device array indexed by system), no count walk
+int enqueue_sys_caps(fdx_ctx *c, size_t gmax, const uint32_t *sys_cap);
 int enqueue_force(fdx_ctx *c, size_t gmax);
 int ensure_list_capacity(fdx_ctx *c, uint64_t total);
 int setup_eval(fdx_ctx *c, double theta, int n_leaf, int n_group, double eps, int flags);

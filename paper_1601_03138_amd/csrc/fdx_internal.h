@@ -229,9 +229,12 @@ hipError_t compact_lists(size_t G, const uint64_t *seg, const uint32_t *cap,
                          const uint32_t *cnt_e, const uint32_t *cnt_s, const uint64_t *oe,
                          const uint64_t *os, const uint32_t *list, uint32_t *epj, uint32_t *spj,
                          hipStream_t s);
-// cap[g] = size of the group's system (an upper bound on its list length)
-hipError_t bound_caps(size_t gmax, const uint32_t *gsys, const int64_t *sys_off, uint32_t *cap,
-                      DevStatus *st, hipStream_t s);
+// cap[g] = sys_cap[system of g]
+hipError_t sys_caps(size_t gmax, const uint32_t *gsys, const uint32_t *sys_cap, uint32_t *cap,
+                    DevStatus *st, hipStream_t s);
+// lmax[s] = max over the groups of system s of |EPJ| + |SPJ| (lmax zeroed by the caller)
+hipError_t sys_lmax(size_t gmax, const uint32_t *gsys, const uint32_t *cnt_e,
+                    const uint32_t *cnt_s, uint32_t *lmax, DevStatus *st, hipStream_t s);
 hipError_t list_stats(size_t gmax, const Groups g, const uint32_t *cnt_e,
                       const uint32_t *cnt_s, DevStatus *st, hipStream_t s);
 

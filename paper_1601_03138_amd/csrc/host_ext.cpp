@@ -25,14 +25,16 @@ int ext_force_variant(fdx_ctx *c) {
 }
 
 // ---------------------------------------------------------------------------------------
-// Graph-captured leapfrog step: kick + drift, the whole force evaluation (exact walk into a
+// Graph-captured leapfrog step: kick + drift, the whole force evaluation (walk into a
 // fixed-capacity list buffer, persistent force kernel over per-XCD queues), kick.  With
-// several systems whose list bound (every group's segment as long as its system, see
-// bound_caps) fits the list budget, the segments are sized by that bound and one fill walk
-// builds the lists; otherwise a count walk sizes them first.  Capacities are fixed at capture
-// time with a margin; a step whose tree, groups or lists do not fit is reported by the device
-// status: its final kick is skipped, the host redoes force and kick eagerly with larger
-// buffers and captures again.
+// several systems every group's segment is sized by its system: min(particles of the system,
+// percent / 100 x the longest list the system had in the evaluation before the capture + 64),
+// and one
+// fill walk builds the lists, if the segments fit the list budget; otherwise a count walk
+// sizes them first.  Capacities are fixed at capture time with a margin; a step whose tree,
+// groups or lists do not fit is reported by the device status: its final kick is skipped, the
+// host redoes force and kick eagerly with larger buffers (and a doubled list percentage) and
+// captures again.
 struct GraphState {
     hipStream_t gs = nullptr;
     hipGraph_t graph = nullptr;
@@ -42,7 +44,8 @@ struct GraphState {
     double dt = 0, theta = 0, eps_all = 0;
     int flags = 0, n_leaf = 0, n_group = 0, variant = 0, nsys = 0;
     int64_t n = -1;
-    bool bound = false;           // segments sized by the system-size bound (no count walk)
+    bool sized = false;           // segments sized per system (no count walk)
+    DBuf<uint32_t> sys_cap, lmax;
     void drop() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -61,7 +64,8 @@ static int capture_step(fdx_ctx *c, GraphState *g, double dt) {
                              dt, g->gs));
         int q = enqueue_keys_sort(c);
         if (!q) q = enqueue_tree_groups(c);
-        if (!q) q = g->bound ? enqueue_bound(c, c->group_cap) : enqueue_count(c, c->group_cap);
+        if (!q) q = g->sized ? enqueue_sys_caps(c, c->group_cap, g->sys_cap.p)
+                             : enqueue_count(c, c->group_cap);
         if (!q) q = enqueue_fill(c, c->group_cap);
         if (!q) q = enqueue_force(c, c->group_cap);
         if (q) return q;
@@ -107,8 +111,8 @@ void ext_invalidate(fdx_ctx *c) {
     if (g) g->drop();
 }
 
-// list entries (4 B each) the bound-sized segments may take: 16 GiB
-constexpr uint64_t kBoundBudget = 1ull << 32;
+// list entries (4 B each) the per-system segments may take: 16 GiB
+constexpr uint64_t kSizedBudget = 1ull << 32;
 
 // capacities with headroom for the drift of one step; chooses the segment sizing
 static int graph_headroom(fdx_ctx *c, GraphState *g) {
@@ -119,18 +123,34 @@ static int graph_headroom(fdx_ctx *c, GraphState *g) {
     int r = ensure_tree_buffers(c, ccap, gcap);
     if (r) return r;
     uint64_t need = h.list_total;
-    g->bound = false;
-    if (c->nsys > 1 && c->have_lists) {
-        // the bound of the current groups (their segments are re-sized by the next count or
-        // fill pass anyway)
-        r = enqueue_bound(c, gcap);
+    g->sized = false;
+    const int S = c->nsys;
+    const uint64_t pct = c->ext.graph_margin_pct;
+    if (S > 1 && c->have_lists && pct > 0) {
+        // per-system segment sizes from the current lists' longest entry per system
+        HIPCHK(c, g->lmax.ensure(S));
+        HIPCHK(c, g->sys_cap.ensure(S));
+        HIPCHK(c, fill_u32(g->lmax.p, 0u, S, c->stream));
+        HIPCHK(c, sys_lmax(gcap, c->g_sys.p, c->cnt_e.p, c->cnt_s.p, g->lmax.p, c->st, c->stream));
+        std::vector<uint32_t> lm(S), cap(S);
+        HIPCHK(c, hipMemcpyAsync(lm.data(), g->lmax.p, 4 * (size_t)S, hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int s = 0; s < S; s++) {
+            const uint64_t ns = (uint64_t)(c->sys_off_h[s + 1] - c->sys_off_h[s]);
+            cap[s] = (uint32_t)std::min<uint64_t>(ns, pct * lm[s] / 100 + 64);
+        }
+        HIPCHK(c, hipMemcpyAsync(g->sys_cap.p, cap.data(), 4 * (size_t)S, hipMemcpyHostToDevice,
+                                 c->stream));
+        // the segments of the current groups (re-sized by the next count or fill pass anyway)
+        r = enqueue_sys_caps(c, gcap, g->sys_cap.p);
         c->have_lists = false;              // seg / cap no longer describe the stored lists
         if (!r) r = read_status(c);
         if (r) return r;
-        const uint64_t bound = c->hst->st.list_total;
-        if (bound + bound / 4 + 4096 <= kBoundBudget) {
-            g->bound = true;
-            need = bound;
+        const uint64_t total = c->hst->st.list_total;
+        if (total + total / 4 + 4096 <= kSizedBudget) {
+            g->sized = true;
+            need = total;
         }
     }
     return ensure_list_capacity(c, need + need / 4 + 4096);
@@ -174,6 +194,8 @@ int ext_integrate_graph(fdx_ctx *c, double dt, int n_steps) {
             r = read_status(c);
             if (r) break;
             c->ext.graph_recoveries++;
+            if (g->sized && h.list_overflow && c->ext.graph_margin_pct < (1u << 20))
+                c->ext.graph_margin_pct *= 2;
             g->drop();
         }
     }
@@ -192,6 +214,8 @@ void ext_release(fdx_ctx *c) {
     GraphState *g = static_cast<GraphState *>(c->ext.graph);
     if (g) {
         g->drop();
+        g->sys_cap.release();
+        g->lmax.release();
         if (g->gs) (void)hipStreamDestroy(g->gs);
         delete g;
         c->ext.graph = nullptr;
@@ -212,6 +236,14 @@ int fdx_autotune_shapes(void) { return force_variants(); }
 
 const char *fdx_shape_name(int32_t shape) {
     return shape < 0 || shape >= force_variants() ? "" : force_variant_name(shape);
+}
+
+int fdx_set_graph_list_margin(fdx_ctx *c, int32_t percent) {
+    if (!c) return FDX_EINVAL;
+    if (percent < 0) return fail(c, FDX_EINVAL, "percent must be >= 0");
+    c->ext.graph_margin_pct = (uint32_t)percent;
+    ext_invalidate(c);
+    return FDX_OK;
 }
 
 int fdx_set_shape(fdx_ctx *c, int32_t shape) {

@@ -18,6 +18,7 @@ struct HostExt {
     void *sph = nullptr;              // SPH density state
     void *dd = nullptr;               // domain decomposition state
     int64_t graph_recoveries = 0;     // replays whose capacities overflowed and were redone
+    uint32_t graph_margin_pct = 200;  // graph list segments: percent of each system's longest
 };
 
 int ext_force_variant(fdx_ctx *c);

@@ -207,15 +207,21 @@ __global__ void k_list_caps(const uint32_t *ngroups, uint32_t gmax, const uint32
     for (size_t gi = gtid(); gi < G; gi += gstride()) cap[gi] = cnt_e[gi] + cnt_s[gi];
 }
 
-// cap[g] = particles of the group's system: a bound on |EPJ| + |SPJ|, since a list's entries
-// (opened leaves' particles, accepted cells) cover disjoint sets of the system's particles
-__global__ void k_bound_caps(const uint32_t *ngroups, uint32_t gmax, const uint32_t *gsys,
-                             const int64_t *sys_off, uint32_t *cap) {
+// cap[g] = sys_cap[system of g]: per-system segment sizes (a system's particle count bounds
+// |EPJ| + |SPJ| of its groups, since a list's entries -- opened leaves' particles, accepted
+// cells -- cover disjoint sets of the system's particles)
+__global__ void k_sys_caps(const uint32_t *ngroups, uint32_t gmax, const uint32_t *gsys,
+                           const uint32_t *sys_cap, uint32_t *cap) {
     const uint32_t G = min(*ngroups, gmax);
-    for (size_t gi = gtid(); gi < G; gi += gstride()) {
-        const uint32_t s = gsys[gi];
-        cap[gi] = (uint32_t)(sys_off[s + 1] - sys_off[s]);
-    }
+    for (size_t gi = gtid(); gi < G; gi += gstride()) cap[gi] = sys_cap[gsys[gi]];
+}
+
+// lmax[s] = longest list of system s (lmax cleared by the caller)
+__global__ void k_sys_lmax(const uint32_t *ngroups, uint32_t gmax, const uint32_t *gsys,
+                           const uint32_t *cnt_e, const uint32_t *cnt_s, uint32_t *lmax) {
+    const uint32_t G = min(*ngroups, gmax);
+    for (size_t gi = gtid(); gi < G; gi += gstride())
+        atomicMax(&lmax[gsys[gi]], cnt_e[gi] + cnt_s[gi]);
 }
 
 // every group's entries out of its segment into contiguous per-kind arrays (one workgroup per
@@ -451,12 +457,21 @@ hipError_t list_caps(size_t gmax, const uint32_t *cnt_e, const uint32_t *cnt_s, 
     return hipGetLastError();
 }
 
-hipError_t bound_caps(size_t gmax, const uint32_t *gsys, const int64_t *sys_off, uint32_t *cap,
-                      DevStatus *st, hipStream_t s) {
+hipError_t sys_caps(size_t gmax, const uint32_t *gsys, const uint32_t *sys_cap, uint32_t *cap,
+                    DevStatus *st, hipStream_t s) {
     size_t b = (gmax + kThreads - 1) / kThreads;
     b = b < 1 ? 1 : (b > 8192 ? 8192 : b);
-    hipLaunchKernelGGL(k_bound_caps, dim3((unsigned)b), dim3(kThreads), 0, s, &st->n_groups_c,
-                       (uint32_t)gmax, gsys, sys_off, cap);
+    hipLaunchKernelGGL(k_sys_caps, dim3((unsigned)b), dim3(kThreads), 0, s, &st->n_groups_c,
+                       (uint32_t)gmax, gsys, sys_cap, cap);
+    return hipGetLastError();
+}
+
+hipError_t sys_lmax(size_t gmax, const uint32_t *gsys, const uint32_t *cnt_e,
+                    const uint32_t *cnt_s, uint32_t *lmax, DevStatus *st, hipStream_t s) {
+    size_t b = (gmax + kThreads - 1) / kThreads;
+    b = b < 1 ? 1 : (b > 8192 ? 8192 : b);
+    hipLaunchKernelGGL(k_sys_lmax, dim3((unsigned)b), dim3(kThreads), 0, s, &st->n_groups_c,
+                       (uint32_t)gmax, gsys, cnt_e, cnt_s, lmax);
     return hipGetLastError();
 }
 

@@ -31,7 +31,8 @@ EXPORTS = ["fdx_create", "fdx_destroy", "fdx_set_particles", "fdx_build_tree", "
            "fdx_get_exchange_stats", "fdx_calc_density", "fdx_get_density",
            "fdx_calc_force_cutoff", "fdx_dd_factor", "fdx_decompose", "fdx_get_decomposition",
            "fdx_get_dd_samples", "fdx_get_dd_destinations", "fdx_exchange_particles",
-           "fdx_get_dd_stats", "fdx_direct_forces", "fdx_autotune_cached"]
+           "fdx_get_dd_stats", "fdx_direct_forces", "fdx_autotune_cached",
+           "fdx_set_graph_list_margin"]
 
 
 class FdxError(RuntimeError):
@@ -47,7 +48,8 @@ class Stats(C.Structure):
         ("n_leaf", C.c_int32), ("n_group", C.c_int32), ("flags", C.c_int32),
         ("shape", C.c_int32), ("theta", C.c_double)] + [(k, C.c_double) for k in (
             "t_keys", "t_sort", "t_tree", "t_moments", "t_groups", "t_walk", "t_force",
-            "t_unsort", "t_predict", "t_total")] + [("fp64_groups", C.c_int64)]
+            "t_unsort", "t_predict", "t_total")] + [("fp64_groups", C.c_int64),
+                                                    ("graph_recoveries", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -111,6 +113,7 @@ def _declare(L):
     L.fdx_last_error.restype = C.c_char_p
     L.fdx_autotune_shapes.argtypes = []
     L.fdx_set_shape.argtypes = [vp, i32]
+    L.fdx_set_graph_list_margin.argtypes = [vp, i32]
     L.fdx_shape_name.argtypes = [i32]
     L.fdx_shape_name.restype = C.c_char_p
     L.fdx_autotune.argtypes = [vp, f64, i32, f64, i32, vp, i32, i32, vp, vp, vp]
@@ -328,6 +331,12 @@ class Context:
 
     def set_shape(self, shape: int):
         self._check(self.lib.fdx_set_shape(self.h, int(shape)), "set_shape")
+
+    def set_graph_list_margin(self, percent: int):
+        """List segments of graph-captured steps with several systems: percent of each
+        system's longest list (0: count walk every step)."""
+        self._check(self.lib.fdx_set_graph_list_margin(self.h, int(percent)),
+                    "set_graph_list_margin")
 
     # -- exchange lists between domains (the systems of the particle set) ----------------
     def build_exchange_lists(self, theta: float, n_leaf: int = 8):
