@@ -105,14 +105,16 @@ def rms_rel_error(a, a_ref) -> float:
     return float(math.sqrt(np.mean(d / r)))
 
 
-def autotune(ctx, theta, quad, persistent):
-    """n_group in {64, 128, 256, 512} x every force-kernel shape, full evaluations timed by the
-    library's autotuner (the median of 2 after one untimed); its choice stays set in ctx."""
+def autotune(ctx, theta, quad, persistent, graph=False):
+    """n_group in {64, 128, 256, 512} x every force-kernel shape, full evaluations (graph:
+    graph-captured steps of dt = 0) timed by the library's autotuner (the median of 2 after one
+    untimed); its choice stays set in ctx."""
     from paper_1601_03138_amd import fdx
     cand = [64, 128, 256, 512]
-    bg, bv, times = ctx.autotune(theta, 8, 0.0,
-                                 fdx.Context.flags(quad=quad, fp32=True, persistent=persistent),
-                                 cand, reps=2)
+    flags = fdx.Context.flags(quad=quad, fp32=True, persistent=persistent)
+    if graph:
+        flags |= fdx.GRAPH
+    bg, bv, times = ctx.autotune(theta, 8, 0.0, flags, cand, reps=2)
     return {"n_group": bg, "shape": bv, "shape_name": ctx.shape_name(bv), "candidates": cand,
             "ms": [[None if np.isnan(v) else round(float(v), 3) for v in row] for row in times]}
 
@@ -235,7 +237,7 @@ def main():
             sys.exit(2)
         ctx.set_shape(names.index(args.shape))
     elif not args.no_autotune and not args.n_group and args.workload in AUTOTUNED:
-        tuned = autotune(ctx, theta, quad, persistent)
+        tuned = autotune(ctx, theta, quad, persistent, graph=args.graph)
         n_group = tuned["n_group"]
         log(f"[bench] autotune: n_group={n_group} shape={tuned['shape_name']} times={tuned['ms']}")
 
@@ -452,7 +454,7 @@ def main():
         ce.set_particles(eps_)
         etuned = None
         if not args.no_autotune:
-            etuned = autotune(ce, eth, equad, True)
+            etuned = autotune(ce, eth, equad, True, graph=True)
             eg = etuned["n_group"]
             log(f"[bench] ensemble autotune: n_group={eg} shape={etuned['shape_name']}")
         f32 = fdx.Context.flags(quad=equad, fp32=True, persistent=True)

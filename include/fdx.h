@@ -194,7 +194,9 @@ int fdx_get_lists(fdx_ctx *ctx, uint32_t *n_epj, uint32_t *n_spj, uint32_t *epj,
  * them, keeps the fastest shape for later calls of the same precision (FDX_FP32REL set or
  * not in `flags`; the other precision keeps its shape) and returns it with its group size;
  * times_ms[k * shapes + v] receives each time (NaN where the shape cannot hold the group
- * size; null skips).  fdx_set_shape fixes the shape of both precisions (-1 = default).
+ * size; null skips).  With FDX_GRAPH in `flags` it times graph-captured leapfrog steps of
+ * dt = 0 (which leave the particles unchanged) instead of eager evaluations, with the
+ * persistent kernel.  fdx_set_shape fixes the shape of both precisions (-1 = default).
  * FDX_EINVAL: no candidates, reps < 1, or a shape out of range. */
 int fdx_autotune_shapes(void);
 const char *fdx_shape_name(int32_t shape);   /* e.g. "nt512_ipl1_pf"; "" if out of range */
@@ -205,7 +207,7 @@ int fdx_autotune(fdx_ctx *ctx, double theta, int32_t n_leaf, double eps, int32_t
 /* fdx_autotune_cached: the same search, with its result recorded in the text file `path`
  * (one JSON object per line: {"key": "...", "n_group": g, "shape": v}); the key holds the
  * device architecture, floor(log2 n), floor(log2 n_sys), theta, n_leaf, the QUAD / FP32REL /
- * PERSISTENT flags, the candidate list and reps.  A recorded key is applied without timing
+ * PERSISTENT / GRAPH flags, the candidate list and reps.  A recorded key is applied without timing
  * (*from_cache = 1: the shape is kept for later calls and the group size returned); otherwise
  * fdx_autotune runs and one line is appended (*from_cache = 0).  Lines that do not parse, or
  * name a shape that cannot hold their group size, are ignored.  FDX_EINVAL: null path, no

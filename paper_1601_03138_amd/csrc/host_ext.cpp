@@ -265,18 +265,24 @@ int fdx_autotune(fdx_ctx *c, double theta, int32_t n_leaf, double eps, int32_t f
     const bool f32 = (flags & FDX_FP32REL) != 0;
     int &slot = c->ext.variant[f32];
     const int saved = slot;
-    flags &= ~(FDX_TIMING | FDX_PREDICTOR);
+    // FDX_GRAPH: time graph-captured leapfrog steps of dt = 0 (x += 0 v, v += 0 a: the state
+    // does not change), which is what a graph-replayed run executes per step
+    const bool graph = (flags & FDX_GRAPH) != 0;
+    flags &= ~(FDX_TIMING | FDX_PREDICTOR | FDX_GRAPH);
+    if (graph) flags |= FDX_PERSISTENT;
     for (int k = 0; k < n_cand; k++) {
         for (int v = 0; v < nv; v++) {
             double t = NAN;
             if (force_variant_capacity(v) >= n_group_cand[k]) {
                 slot = v;
                 int r = fdx_calc_force(c, theta, n_leaf, n_group_cand[k], eps, flags);
+                if (!r && graph) r = fdx_integrate(c, 0.0, 1, FDX_GRAPH);     // capture
                 if (r) { slot = saved; return r; }
                 std::vector<double> ts;
                 for (int q = 0; q < reps; q++) {
                     auto t0 = std::chrono::steady_clock::now();
-                    r = fdx_calc_force(c, theta, n_leaf, n_group_cand[k], eps, flags);
+                    r = graph ? fdx_integrate(c, 0.0, 1, FDX_GRAPH)
+                              : fdx_calc_force(c, theta, n_leaf, n_group_cand[k], eps, flags);
                     if (r) { slot = saved; return r; }
                     auto t1 = std::chrono::steady_clock::now();
                     ts.push_back(std::chrono::duration<double, std::milli>(t1 - t0).count());
@@ -308,7 +314,7 @@ int fdx_autotune_cached(fdx_ctx *c, const char *path, double theta, int32_t n_le
     hipDeviceProp_t prop;
     HIPCHK(c, hipGetDeviceProperties(&prop, c->device));
     auto lg = [](int64_t v) { int k = 0; while (v > 1) { v >>= 1; k++; } return k; };
-    const int32_t fkey = flags & (FDX_QUAD | FDX_FP32REL | FDX_PERSISTENT);
+    const int32_t fkey = flags & (FDX_QUAD | FDX_FP32REL | FDX_PERSISTENT | FDX_GRAPH);
     char head[256];
     snprintf(head, sizeof(head), "%s|n2^%d|sys2^%d|theta=%.9g|leaf=%d|flags=%d|cand=",
              prop.gcnArchName, lg(c->n), lg(c->nsys), theta, n_leaf, fkey);

@@ -82,6 +82,21 @@ def test_autotuner_picks_a_measured_candidate(ctx, fdx):
     ctx.set_shape(-1)
 
 
+def test_autotuner_times_graph_steps_without_moving_particles(ctx, fdx):
+    ens = I.ensemble(n_sys=8, seed=42, nmin=256, nmax=2048)
+    ctx.set_particles(ens)
+    flags = fdx.Context.flags(quad=True, fp32=True, persistent=True) | fdx.GRAPH
+    cand = [64, 128]
+    bg, bv, times = ctx.autotune(0.6, 8, 0.0, flags, cand, reps=2)
+    _say("[autotune graph] times (ms):\n", np.round(times, 3), "best", bg, bv)
+    assert bg in cand and np.nanmin(times) == times[cand.index(bg), bv]
+    # the timed steps had dt = 0: positions and velocities are the input's, bit for bit
+    x = ctx.particles()
+    for a, b in zip(x, (ens.x, ens.y, ens.z, ens.vx, ens.vy, ens.vz)):
+        assert np.array_equal(a, b)
+    ctx.set_shape(-1)
+
+
 def test_autotuner_records_and_reuses_its_choice(ctx, fdx, tmp_path):
     ps = I.plummer(20000, seed=14, eps=1 / 256)
     ctx.set_particles(ps)
