@@ -101,6 +101,24 @@ __device__ __forceinline__ int system_of(const int64_t *off, int nsys, size_t r)
     return lo;
 }
 
+// the same search by a whole wave (every lane gets the result): a 64-way search, one round of
+// loads per factor of 64 in the system count
+__device__ __forceinline__ int wave_system_of(const int64_t *off, int nsys, size_t r) {
+    const int lane = lane_id();
+    int lo = 0, n = nsys;                 // off[lo] <= r < off[lo + n] (off[nsys] = N > r)
+    while (n > 1) {
+        const int step = (n + kWave - 1) / kWave;
+        const int k = lane * step;
+        const bool ok = k < n && (uint64_t)off[lo + k] <= r;
+        const uint64_t m = __ballot(ok);             // lane 0 always qualifies
+        const int last = 63 - __clzll((long long)m);
+        const int nlo = lo + last * step;
+        n = min(step, lo + n - nlo);
+        lo = nlo;
+    }
+    return lo;
+}
+
 // per position: lo(r) and c(r)
 __global__ void k_cells_prefix(size_t n, int nsys, const int64_t *off, const uint64_t *skey,
                                int n_leaf, uint8_t *lo8, int8_t *c8) {
@@ -412,12 +430,8 @@ k_group_geom(const uint32_t *ngroups, int nsys, const int64_t *off, Cells c,
         deep = wave_max_u32(deep);
 #pragma unroll
         for (int d = kWave / 2; d >= 1; d >>= 1) emin = fmin(emin, __shfl_xor(emin, d, kWave));
+        const int slo = wave_system_of(off, nsys, b);   // last s with off[s] <= b
         if (lane == 0) {
-            int slo = 0, shi = nsys - 1;               // last s with off[s] <= b
-            while (slo < shi) {
-                int mid = (slo + shi + 1) >> 1;
-                if ((uint64_t)off[mid] <= b) slo = mid; else shi = mid - 1;
-            }
             const uint32_t cell = g.cell[gi];
             const uint32_t l = c.level[cell];
             const uint64_t corner = c.prefix[cell] << (3 * (kLevels - l));
