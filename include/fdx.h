@@ -125,8 +125,9 @@ int fdx_integrate(fdx_ctx *ctx, double dt, int32_t n_steps, int32_t flags);
  * captured step can size every group's list segment by its system, min(particles of the
  * system, percent / 100 x the longest list the system had in the evaluation before the
  * capture + 64), and fill the lists in one walk, without a count walk, when all segments fit
- * a 16 GiB budget.  A replay whose list outgrew its segment is redone eagerly (counted in
- * fdx_stats.graph_recoveries) and the percentage doubles for the next capture.  percent = 0
+ * a 16 GiB budget.  A list that outgrows its segment is moved to the buffer's spare quarter
+ * inside the walk (fdx_stats.list_spills); a replay where that space ran out is redone
+ * eagerly (fdx_stats.graph_recoveries) and the percentage doubles for the next capture.  percent = 0
  * sizes the segments by a count walk in every step.  Default 200.  FDX_EINVAL: percent < 0. */
 int fdx_set_graph_list_margin(fdx_ctx *ctx, int32_t percent);
 
@@ -161,6 +162,9 @@ typedef struct {
        1e-4 of itself (see FDX_FP32REL) */
     int64_t fp64_groups;
     int64_t graph_recoveries;   /* graph-replayed steps redone eagerly (a capacity overflowed) */
+    int64_t list_spills;        /* lists that outgrew a predicted or per-system segment and were
+                                   moved to the list buffer's spare space inside the walk
+                                   (cumulative over the context) */
 } fdx_stats;
 
 int fdx_get_stats(fdx_ctx *ctx, fdx_stats *out);

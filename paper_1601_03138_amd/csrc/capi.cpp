@@ -223,7 +223,7 @@ int enqueue_sys_caps(fdx_ctx *c, size_t gmax, const uint32_t *sys_cap) {
 }
 
 // Fill pass into the list buffer (its capacity guards every write), then counters.
-int enqueue_fill(fdx_ctx *c, size_t gmax) {
+int enqueue_fill(fdx_ctx *c, size_t gmax, bool spill) {
     hipStream_t s = c->stream;
     Groups gv = groups_view(c);
     if (c->cutoff > 0)
@@ -233,7 +233,7 @@ int enqueue_fill(fdx_ctx *c, size_t gmax) {
     else
         HIPCHK(c, walk(true, gmax, gv, cells_view(c), c->theta * c->theta, c->seg.p, c->lcap.p,
                        c->list_cap, c->list.p, c->cnt_e.p, c->cnt_s.p, c->ovf_list.p, nullptr,
-                       nullptr, c->st, s));
+                       nullptr, c->st, s, spill));
     return FDX_OK;
 }
 
@@ -345,6 +345,7 @@ void finish_stats(fdx_ctx *c) {
     o.n_leaf = c->n_leaf; o.n_group = c->n_group; o.flags = c->flags; o.theta = c->theta;
     o.shape = ext_force_variant(c);
     o.graph_recoveries = c->ext.graph_recoveries;
+    o.list_spills = c->ext.list_spills;
 }
 
 int sync_timing(fdx_ctx *c) {

@@ -135,7 +135,7 @@ int run_force(fdx_ctx *c);
 int enqueue_keys_sort(fdx_ctx *c);
 int enqueue_tree_groups(fdx_ctx *c);
 int enqueue_count(fdx_ctx *c, size_t gmax);
-int enqueue_fill(fdx_ctx *c, size_t gmax);
+int enqueue_fill(fdx_ctx *c, size_t gmax, bool spill = false);
 // segments sized per system (sys_cap, device array indexed by system), no count walk
 int enqueue_sys_caps(fdx_ctx *c, size_t gmax, const uint32_t *sys_cap);
 int enqueue_force(fdx_ctx *c, size_t gmax);

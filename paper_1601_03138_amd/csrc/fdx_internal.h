@@ -32,6 +32,9 @@ struct DevStatus {
     uint32_t wide_groups;     // FP32 evaluation: groups too wide for group-relative FP32
     uint32_t pad_;
     uint32_t xcd_head[8];     // persistent force kernel: next slot of each XCD's queue
+    uint64_t spill_used;      // fill walk: entries taken after list_total by relocated lists
+    uint32_t spilled;         // fill walk: groups whose list was relocated there
+    uint32_t pad2_;
 };
 
 // any device-reported condition that makes this evaluation's forces incomplete
@@ -161,10 +164,13 @@ struct ShortArgs {
     const double *cube = nullptr;
     double r_fixed = 0.0;
 };
+// spill (fill only): a group whose list outgrew its segment moves to the space after all
+// segments (st->list_total + st->spill_used, up to list_cap; seg / cap rewritten) and is walked
+// again; st->spilled counts such groups.  Without room it is left empty and queued in ovf_list.
 hipError_t walk(bool fill, size_t gmax, const Groups g, const Cells c, double theta2,
-                const uint64_t *seg, const uint32_t *cap, uint64_t list_cap, uint32_t *list,
+                uint64_t *seg, uint32_t *cap, uint64_t list_cap, uint32_t *list,
                 uint32_t *cnt_e, uint32_t *cnt_s, uint32_t *ovf_list, const uint32_t *sel,
-                const uint32_t *nsel, DevStatus *st, hipStream_t s);
+                const uint32_t *nsel, DevStatus *st, hipStream_t s, bool spill = false);
 // short-range walk (kind 1: group radius, 2: cell radius, 3: the larger; no superparticles)
 // or the TreePM cutoff walk (kind 4: cells beyond sa.r_fixed dropped, opening angle theta
 // for the rest)

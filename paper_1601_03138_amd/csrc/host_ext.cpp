@@ -28,8 +28,8 @@ int ext_force_variant(fdx_ctx *c) {
 // Graph-captured leapfrog step: kick + drift, the whole force evaluation (walk into a
 // fixed-capacity list buffer, persistent force kernel over per-XCD queues), kick.  With
 // several systems every group's segment is sized by its system: min(particles of the system,
-// percent / 100 x the longest list the system had in the evaluation before the capture + 64),
-// and one
+// percent / 100 x the longest list the system had in the evaluation before the capture + 64;
+// a list that outgrows it moves to the buffer's spare quarter inside the walk), and one
 // fill walk builds the lists, if the segments fit the list budget; otherwise a count walk
 // sizes them first.  Capacities are fixed at capture time with a margin; a step whose tree,
 // groups or lists do not fit is reported by the device status: its final kick is skipped, the
@@ -66,7 +66,7 @@ static int capture_step(fdx_ctx *c, GraphState *g, double dt) {
         if (!q) q = enqueue_tree_groups(c);
         if (!q) q = g->sized ? enqueue_sys_caps(c, c->group_cap, g->sys_cap.p)
                              : enqueue_count(c, c->group_cap);
-        if (!q) q = enqueue_fill(c, c->group_cap);
+        if (!q) q = enqueue_fill(c, c->group_cap, g->sized);
         if (!q) q = enqueue_force(c, c->group_cap);
         if (q) return q;
         HIPCHK(c, kick(n, c->vx, c->vy, c->vz, c->ax.p, c->ay.p, c->az.p, dt, c->st, g->gs));
@@ -181,6 +181,7 @@ int ext_integrate_graph(fdx_ctx *c, double dt, int n_steps) {
         r = read_status(c);
         if (r) break;
         const DevStatus h = c->hst->st;
+        c->ext.list_spills += h.spilled;
         if (h.bad_input) { r = fail(c, FDX_EINVAL, "non-finite particle data"); break; }
         c->have_lists = true;                // the replay's lists (or the eager redo's)
         if (status_incomplete(h)) {

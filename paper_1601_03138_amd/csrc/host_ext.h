@@ -19,6 +19,7 @@ struct HostExt {
     void *dd = nullptr;               // domain decomposition state
     int64_t graph_recoveries = 0;     // replays whose capacities overflowed and were redone
     uint32_t graph_margin_pct = 200;  // graph list segments: percent of each system's longest
+    int64_t list_spills = 0;          // lists moved to the spill space by a fill walk
 };
 
 int ext_force_variant(fdx_ctx *c);

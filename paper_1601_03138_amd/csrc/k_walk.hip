@@ -12,7 +12,11 @@
 //
 // Lists live in one array: group g owns [seg[g], seg[g] + cap[g]); EPJ entries are written
 // from the front and SPJ entries from the back, so the same kernel fills exact-size segments
-// (count pass first) and predicted-capacity segments (single pass, overflow detected).
+// (count pass first) and predicted-capacity segments (single pass, overflow detected).  With
+// spill on, a wave whose list outgrew its segment knows the exact length at the end of its
+// walk: it reserves that much of the space after all segments (st->list_total onwards, up to
+// list_cap), points the group's segment there and walks the group again; only when that
+// space is exhausted is the group left empty and queued for the host.
 #include "dev_util.h"
 #include "fdx_internal.h"
 
@@ -65,9 +69,9 @@ template <bool FILL, int KIND>
 __global__ void __launch_bounds__(kThreads)
 k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, uint32_t ccap,
        double theta2,
-       const uint64_t *seg, const uint32_t *cap, uint64_t list_cap, uint32_t *list,
+       uint64_t *seg, uint32_t *cap, uint64_t list_cap, uint32_t *list,
        uint32_t *cnt_e, uint32_t *cnt_s, uint32_t *ovf_list, const uint32_t *sel,
-       const uint32_t *nsel, DevStatus *st, ShortArgs sa) {
+       const uint32_t *nsel, DevStatus *st, ShortArgs sa, int spill) {
     __shared__ uint32_t stack_all[kWaves][kWalkStack];
     const int w = threadIdx.x / kWave, lane = lane_id();
     const uint64_t lt = lanemask_lt();
@@ -78,9 +82,9 @@ k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, 
         const uint32_t *bx = g.box + 6 * gi;
         const int bminx = 2 * (int)bx[0], bminy = 2 * (int)bx[1], bminz = 2 * (int)bx[2];
         const int bmaxx = 2 * (int)bx[3] + 2, bmaxy = 2 * (int)bx[4] + 2, bmaxz = 2 * (int)bx[5] + 2;
-        const uint64_t base = FILL ? seg[gi] : 0;
-        const bool seg_ok = !FILL || base + cap[gi] <= list_cap;
-        const uint32_t capg = FILL && seg_ok ? cap[gi] : 0;
+        uint64_t base = FILL ? seg[gi] : 0;
+        bool seg_ok = !FILL || base + cap[gi] <= list_cap;
+        uint32_t capg = FILL && seg_ok ? cap[gi] : 0;
         uint32_t ne = 0, ns = 0, sp = 1;
         bool err = false;
         double scale = 0.0, rg = 0.0, Rg2 = 0.0;
@@ -90,6 +94,8 @@ k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, 
             const double R = __dmul_rn(rg, scale);
             Rg2 = __dmul_rn(R, R);
         }
+        for (int pass = 0;; pass++) {
+        ne = 0; ns = 0; sp = 1; err = false;
         if (lane == 0) stk[0] = g.sys[gi];          // roots are cells 0..nsys-1
         wave_barrier();
         while (sp > 0) {
@@ -184,6 +190,28 @@ k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, 
             wave_barrier();
         }
         wave_barrier();
+        if (FILL && spill && pass == 0 && !err && ((uint64_t)ne + ns > capg || !seg_ok)) {
+            const uint32_t need = ne + ns;
+            unsigned long long off = 0;
+            if (lane == 0)
+                off = atomicAdd((unsigned long long *)&st->spill_used, (unsigned long long)need);
+            const uint32_t olo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)off);
+            const uint32_t ohi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(off >> 32));
+            const uint64_t nb = st->list_total + (((uint64_t)ohi << 32) | olo);
+            if (nb + need <= list_cap) {
+                base = nb;
+                capg = need;
+                seg_ok = true;
+                if (lane == 0) {
+                    seg[gi] = nb;
+                    cap[gi] = need;
+                    atomicAdd(&st->spilled, 1u);
+                }
+                continue;                               // walk the group again into its new space
+            }
+        }
+        break;
+        }
         if (lane == 0) {
             if (err) atomicOr(&st->walk_error, 1u);
             if (FILL && ((uint64_t)ne + ns > capg || !seg_ok)) {
@@ -408,33 +436,36 @@ hipError_t exchange_caps(size_t G, const uint32_t *sel, const uint32_t *nsel, co
 
 template <int KIND>
 static void launch_walk(bool fill, size_t gmax, const Groups &g, const Cells &c, double theta2,
-                        const uint64_t *seg, const uint32_t *cap, uint64_t list_cap,
+                        uint64_t *seg, uint32_t *cap, uint64_t list_cap,
                         uint32_t *list, uint32_t *cnt_e, uint32_t *cnt_s, uint32_t *ovf_list,
                         const uint32_t *sel, const uint32_t *nsel, DevStatus *st,
-                        const ShortArgs &sa, hipStream_t s) {
+                        const ShortArgs &sa, hipStream_t s, bool spill = false) {
     if (fill)
         hipLaunchKernelGGL((k_walk<true, KIND>), dim3(grid_waves(gmax)), dim3(kThreads), 0, s,
                            &st->n_groups, g, c.node, c.link, c.cap, theta2, seg, cap, list_cap,
-                           list, cnt_e, cnt_s, ovf_list, sel, nsel, st, sa);
+                           list, cnt_e, cnt_s, ovf_list, sel, nsel, st, sa, spill ? 1 : 0);
     else
         hipLaunchKernelGGL((k_walk<false, KIND>), dim3(grid_waves(gmax)), dim3(kThreads), 0, s,
                            &st->n_groups, g, c.node, c.link, c.cap, theta2, seg, cap, list_cap,
-                           list, cnt_e, cnt_s, ovf_list, sel, nsel, st, sa);
+                           list, cnt_e, cnt_s, ovf_list, sel, nsel, st, sa, 0);
 }
 
 hipError_t walk(bool fill, size_t gmax, const Groups g, const Cells c, double theta2,
-                const uint64_t *seg, const uint32_t *cap, uint64_t list_cap, uint32_t *list,
+                uint64_t *seg, uint32_t *cap, uint64_t list_cap, uint32_t *list,
                 uint32_t *cnt_e, uint32_t *cnt_s, uint32_t *ovf_list, const uint32_t *sel,
-                const uint32_t *nsel, DevStatus *st, hipStream_t s) {
+                const uint32_t *nsel, DevStatus *st, hipStream_t s, bool spill) {
     launch_walk<0>(fill, gmax, g, c, theta2, seg, cap, list_cap, list, cnt_e, cnt_s, ovf_list,
-                   sel, nsel, st, ShortArgs{}, s);
+                   sel, nsel, st, ShortArgs{}, s, spill);
     return hipGetLastError();
 }
 
 hipError_t walk_short(bool fill, int kind, size_t gmax, const Groups g, const Cells c,
-                      const ShortArgs sa, double theta2, const uint64_t *seg, const uint32_t *cap,
-                      uint64_t list_cap, uint32_t *list, uint32_t *cnt_e, uint32_t *cnt_s,
-                      uint32_t *ovf_list, DevStatus *st, hipStream_t s) {
+                      const ShortArgs sa, double theta2, const uint64_t *seg_c,
+                      const uint32_t *cap_c, uint64_t list_cap, uint32_t *list, uint32_t *cnt_e,
+                      uint32_t *cnt_s, uint32_t *ovf_list, DevStatus *st, hipStream_t s) {
+    // short walks never relocate a list, so the segment arrays are only read
+    uint64_t *seg = const_cast<uint64_t *>(seg_c);
+    uint32_t *cap = const_cast<uint32_t *>(cap_c);
     switch (kind) {
         case 1: launch_walk<1>(fill, gmax, g, c, 0.0, seg, cap, list_cap, list, cnt_e, cnt_s,
                                ovf_list, nullptr, nullptr, st, sa, s); break;

@@ -88,22 +88,29 @@ int ext_predicted_walk(fdx_ctx *c, uint32_t G) {
     const uint64_t total = c->hst->st.list_total;
     r = ensure_list_capacity(c, total + total / 8);
     if (r) return r;
-    // single walk into the predicted segments
+    // single walk into the predicted segments; a list that outgrows its segment moves to the
+    // space after all segments (the buffer holds total + total / 8) and is walked again there
     HIPCHK(c, walk(true, G, gv, cv, th2, c->seg.p, c->lcap.p, c->list_cap, c->list.p, c->cnt_e.p,
-                   c->cnt_s.p, c->ovf_list.p, nullptr, nullptr, c->st, s));
+                   c->cnt_s.p, c->ovf_list.p, nullptr, nullptr, c->st, s, true));
     r = read_status(c);
     if (r) return r;
     if (c->hst->st.walk_error) return fail(c, FDX_EHIP, "walk stack exhausted");
     const uint32_t K = c->hst->st.list_overflow;
+    const uint32_t spilled = c->hst->st.spilled;
+    const uint64_t used = total + c->hst->st.spill_used;   // entries in use (some reserved
+                                                            // space may go unused)
+    c->ext.list_spills += spilled;
     uint64_t extra = 0;
     if (K) {
-        // exact re-walk of the overflowed groups into segments appended after `total`
+        // exact re-walk of the groups that found no room, into segments appended after the
+        // relocated lists
         HIPCHK(c, p->nsel.ensure(1));
         HIPCHK(c, p->ocap.ensure(K));
         HIPCHK(c, p->ooff.ensure((size_t)K + 1));
         HIPCHK(c, p->base_total.ensure(2));
         HIPCHK(c, hipMemcpyAsync(p->nsel.p, &c->st->list_overflow, 4, hipMemcpyDeviceToDevice, s));
-        HIPCHK(c, hipMemcpyAsync(p->base_total.p, &c->st->list_total, 8, hipMemcpyDeviceToDevice, s));
+        const uint64_t base_host = std::min<uint64_t>(used, c->list_cap);
+        HIPCHK(c, hipMemcpyAsync(p->base_total.p, &base_host, 8, hipMemcpyHostToDevice, s));
         HIPCHK(c, walk(false, K, gv, cv, th2, nullptr, nullptr, 0, nullptr, c->cnt_e.p, c->cnt_s.p,
                        nullptr, c->ovf_list.p, p->nsel.p, c->st, s));
         HIPCHK(c, ovf_caps(K, p->nsel.p, c->ovf_list.p, c->cnt_e.p, c->cnt_s.p, p->ocap.p, s));
@@ -115,13 +122,14 @@ int ext_predicted_walk(fdx_ctx *c, uint32_t G) {
         HIPCHK(c, hipMemcpyAsync(&ex, p->base_total.p + 1, 8, hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));
         extra = ex;
-        r = grow_list_keep(c, total + extra, total);
+        const uint64_t keep = std::min<uint64_t>(used, c->list_cap);
+        r = grow_list_keep(c, keep + extra, keep);
         if (r) return r;
         HIPCHK(c, walk(true, K, gv, cv, th2, c->seg.p, c->lcap.p, c->list_cap, c->list.p, c->cnt_e.p,
                        c->cnt_s.p, nullptr, c->ovf_list.p, p->nsel.p, c->st, s));
     }
-    c->stats.overflow_groups = K;
-    c->stats.list_capacity = (int64_t)(total + extra);
+    c->stats.overflow_groups = K + spilled;
+    c->stats.list_capacity = (int64_t)(std::min<uint64_t>(used, c->list_cap) + extra);
     return FDX_OK;
 }
 

@@ -49,7 +49,8 @@ class Stats(C.Structure):
         ("shape", C.c_int32), ("theta", C.c_double)] + [(k, C.c_double) for k in (
             "t_keys", "t_sort", "t_tree", "t_moments", "t_groups", "t_walk", "t_force",
             "t_unsort", "t_predict", "t_total")] + [("fp64_groups", C.c_int64),
-                                                    ("graph_recoveries", C.c_int64)]
+                                                    ("graph_recoveries", C.c_int64),
+                                                    ("list_spills", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
