@@ -291,53 +291,63 @@ __global__ void k_cells_finish(int nsys, const int64_t *off, const uint64_t *ske
 
 // moments of one cell: a leaf from its particles, an internal cell from its children (in
 // child order) by the parallel-axis shift
+// One pass over the cell's particles (leaf) or children (internal cell), about a reference
+// point inside the cell -- the first particle, or the first child's centre of mass -- so the
+// offsets are bounded by the cell's size:
+//   M = sum m,  s = sum m r,  T = sum m r r^T (+ the children's own Q),  r = x - ref;
+//   X = ref + s / M,  A = T - M d d^T with d = s / M,  Q = 3 A - tr(A) I (traceless, about X).
+// A massless cell gets X = 0 and Q = 0.
 __device__ void cell_moments(const Cells &c, const double4 *jp, uint32_t cid) {
-    double M = 0, X = 0, Y = 0, Z = 0;
+    double M = 0, sx = 0, sy = 0, sz = 0;
+    double txx = 0, tyy = 0, tzz = 0, txy = 0, txz = 0, tyz = 0;
     double q[6] = {0, 0, 0, 0, 0, 0};
+    double rx = 0, ry = 0, rz = 0;
     const uint32_t nch = c.nchild[cid];
+    auto add = [&](double m, double x, double y, double z) {
+        const double dx = x - rx, dy = y - ry, dz = z - rz;
+        const double mx = m * dx, my = m * dy, mz = m * dz;
+        M += m; sx += mx; sy += my; sz += mz;
+        txx += mx * dx; tyy += my * dy; tzz += mz * dz;
+        txy += mx * dy; txz += mx * dz; tyz += my * dz;
+    };
     if (nch == 0) {
         const uint32_t b = c.begin[cid], e = b + c.count[cid];
-        double sx = 0, sy = 0, sz = 0;
-        for (uint32_t i = b; i < e; i++) {
-            double4 p = jp[i];
-            M += p.w; sx += p.w * p.x; sy += p.w * p.y; sz += p.w * p.z;
+        if (e > b) {
+            const double4 p0 = jp[b];
+            rx = p0.x; ry = p0.y; rz = p0.z;
         }
-        if (M > 0) { X = sx / M; Y = sy / M; Z = sz / M; }
         for (uint32_t i = b; i < e; i++) {
-            double4 p = jp[i];
-            double dx = p.x - X, dy = p.y - Y, dz = p.z - Z;
-            double d2 = dx * dx + dy * dy + dz * dz;
-            q[0] += p.w * (3.0 * dx * dx - d2);
-            q[1] += p.w * (3.0 * dy * dy - d2);
-            q[2] += p.w * (3.0 * dz * dz - d2);
-            q[3] += p.w * (3.0 * dx * dy);
-            q[4] += p.w * (3.0 * dx * dz);
-            q[5] += p.w * (3.0 * dy * dz);
+            const double4 p = jp[i];
+            add(p.w, p.x, p.y, p.z);
         }
     } else {
         const uint32_t f = c.first[cid];
-        double sx = 0, sy = 0, sz = 0;
+        const double2 *m0 = reinterpret_cast<const double2 *>(c.mom + 10 * (size_t)f);
+        const double2 x01 = m0[0], x23 = m0[1];
+        rx = x01.y; ry = x23.x; rz = x23.y;
         for (uint32_t j = f; j < f + nch; j++) {
-            const double *o = c.mom + 10 * (size_t)j;
-            M += o[0]; sx += o[0] * o[1]; sy += o[0] * o[2]; sz += o[0] * o[3];
-        }
-        if (M > 0) { X = sx / M; Y = sy / M; Z = sz / M; }
-        for (uint32_t j = f; j < f + nch; j++) {
-            const double *o = c.mom + 10 * (size_t)j;
-            double dx = o[1] - X, dy = o[2] - Y, dz = o[3] - Z;
-            double d2 = dx * dx + dy * dy + dz * dz;
-            q[0] += o[4] + o[0] * (3.0 * dx * dx - d2);
-            q[1] += o[5] + o[0] * (3.0 * dy * dy - d2);
-            q[2] += o[6] + o[0] * (3.0 * dz * dz - d2);
-            q[3] += o[7] + o[0] * (3.0 * dx * dy);
-            q[4] += o[8] + o[0] * (3.0 * dx * dz);
-            q[5] += o[9] + o[0] * (3.0 * dy * dz);
+            const double2 *o = reinterpret_cast<const double2 *>(c.mom + 10 * (size_t)j);
+            const double2 a = o[0], b = o[1], cq = o[2], dq = o[3], eq = o[4];
+            add(a.x, a.y, b.x, b.y);
+            q[0] += cq.x; q[1] += cq.y; q[2] += dq.x; q[3] += dq.y; q[4] += eq.x; q[5] += eq.y;
         }
     }
-    double *o = c.mom + 10 * (size_t)cid;
-    o[0] = M; o[1] = X; o[2] = Y; o[3] = Z;
-#pragma unroll
-    for (int a = 0; a < 6; a++) o[4 + a] = q[a];
+    double X = 0, Y = 0, Z = 0;
+    if (M > 0) {
+        const double dx = sx / M, dy = sy / M, dz = sz / M;
+        X = rx + dx; Y = ry + dy; Z = rz + dz;
+        const double axx = txx - sx * dx, ayy = tyy - sy * dy, azz = tzz - sz * dz;
+        const double axy = txy - sx * dy, axz = txz - sx * dz, ayz = tyz - sy * dz;
+        const double tr = axx + ayy + azz;
+        q[0] += 3.0 * axx - tr; q[1] += 3.0 * ayy - tr; q[2] += 3.0 * azz - tr;
+        q[3] += 3.0 * axy; q[4] += 3.0 * axz; q[5] += 3.0 * ayz;
+    }
+    double2 *o = reinterpret_cast<double2 *>(c.mom + 10 * (size_t)cid);
+    o[0] = make_double2(M, X);
+    o[1] = make_double2(Y, Z);
+    o[2] = make_double2(q[0], q[1]);
+    o[3] = make_double2(q[2], q[3]);
+    o[4] = make_double2(q[4], q[5]);
 }
 
 // moments of the cells of one level (children already done)
