@@ -316,20 +316,41 @@ __device__ void cell_moments(const Cells &c, const double4 *jp, uint32_t cid) {
             const double4 p0 = jp[b];
             rx = p0.x; ry = p0.y; rz = p0.z;
         }
-        for (uint32_t i = b; i < e; i++) {
-            const double4 p = jp[i];
-            add(p.w, p.x, p.y, p.z);
+        // chunks of 8 with every load of a chunk issued before its sums (leaves hold at most
+        // n_leaf particles, except at the deepest level)
+        for (uint32_t i0 = b; i0 < e; i0 += 8) {
+            double4 p[8];
+#pragma unroll
+            for (int k = 0; k < 8; k++) p[k] = jp[i0 + k < e ? i0 + k : b];   // in range
+#pragma unroll
+            for (int k = 0; k < 8; k++)
+                if (i0 + k < e) add(p[k].w, p[k].x, p[k].y, p[k].z);
         }
     } else {
         const uint32_t f = c.first[cid];
         const double2 *m0 = reinterpret_cast<const double2 *>(c.mom + 10 * (size_t)f);
         const double2 x01 = m0[0], x23 = m0[1];
         rx = x01.y; ry = x23.x; rz = x23.y;
-        for (uint32_t j = f; j < f + nch; j++) {
+        // at most 8 children: their records are loaded together, then summed in order
+        double2 a[8], bb[8];
+#pragma unroll
+        for (uint32_t k = 0; k < 8; k++) {
+            const uint32_t j = k < nch ? f + k : f;                          // in range
             const double2 *o = reinterpret_cast<const double2 *>(c.mom + 10 * (size_t)j);
-            const double2 a = o[0], b = o[1], cq = o[2], dq = o[3], eq = o[4];
-            add(a.x, a.y, b.x, b.y);
-            q[0] += cq.x; q[1] += cq.y; q[2] += dq.x; q[3] += dq.y; q[4] += eq.x; q[5] += eq.y;
+            a[k] = o[0];
+            bb[k] = o[1];
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < 8; k++)
+            if (k < nch) add(a[k].x, a[k].y, bb[k].x, bb[k].y);
+#pragma unroll
+        for (uint32_t k = 0; k < 8; k++) {
+            if (k < nch) {
+                const double2 *o = reinterpret_cast<const double2 *>(c.mom + 10 * (size_t)(f + k));
+                const double2 cq = o[2], dq = o[3], eq = o[4];
+                q[0] += cq.x; q[1] += cq.y; q[2] += dq.x; q[3] += dq.y; q[4] += eq.x;
+                q[5] += eq.y;
+            }
         }
     }
     double X = 0, Y = 0, Z = 0;
