@@ -173,7 +173,7 @@ def main():
                     help="replay each leapfrog step as a captured HIP graph (persistent force)")
     ap.add_argument("--direct", action="store_true",
                     help="one workgroup per group in group order (XCD-aware) instead of the "
-                         "default persistent force kernel over the cost-ordered group queue")
+                         "default persistent force kernel over per-XCD queues of groups")
     ap.add_argument("--walk", default="auto", choices=["auto", "exact", "predicted"],
                     help="exact: count pass + fill pass; predicted: the learned list-length "
                          "predictor sizes the lists for a single fill pass (groups that do not "

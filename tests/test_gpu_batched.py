@@ -1,4 +1,4 @@
-"""GPU: kernel shapes, persistent cost-ordered queue, autotuner, and batched ensembles with
+"""GPU: kernel shapes, persistent per-XCD queues, autotuner, and batched ensembles with
 HIP-graph-captured leapfrog steps, against the oracle and the eager path."""
 import sys
 
