@@ -127,8 +127,9 @@ int fdx_integrate(fdx_ctx *ctx, double dt, int32_t n_steps, int32_t flags);
  * capture + 64), and fill the lists in one walk, without a count walk, when all segments fit
  * a 16 GiB budget.  A list that outgrows its segment is moved to the buffer's spare quarter
  * inside the walk (fdx_stats.list_spills); a replay where that space ran out is redone
- * eagerly (fdx_stats.graph_recoveries) and the percentage doubles for the next capture.  percent = 0
- * sizes the segments by a count walk in every step.  Default 200.  FDX_EINVAL: percent < 0. */
+ * eagerly (fdx_stats.graph_recoveries) and the percentage doubles for the next capture.
+ * percent = 0 sizes the segments by a count walk in every step.  Default 200.  FDX_EINVAL:
+ * percent < 0. */
 int fdx_set_graph_list_margin(fdx_ctx *ctx, int32_t percent);
 
 /* Copy positions and velocities (caller's order) into x..vz (length n each, memory of
@@ -148,7 +149,9 @@ typedef struct {
     int64_t n_epj, n_spj;              /* list entries summed over groups */
     int64_t n_interactions_pp;         /* sum over groups of n_i * |EPJ| (self pairs included) */
     int64_t n_interactions_pc;         /* sum over groups of n_i * |SPJ| */
-    int64_t overflow_groups;           /* predictor path: groups re-walked exactly */
+    int64_t overflow_groups;           /* predictor path: groups whose list outgrew its
+                                          predicted capacity (walked again in spare space, or
+                                          re-walked exactly by a second pass) */
     int64_t list_capacity;             /* list entries allocated in the last walk */
     int32_t n_leaf, n_group, flags;
     int32_t shape;                     /* force-kernel shape used (see fdx_autotune_shapes) */
