@@ -289,9 +289,8 @@ __global__ void k_cells_finish(int nsys, const int64_t *off, const uint64_t *ske
     }
 }
 
-// moments of one cell: a leaf from its particles, an internal cell from its children (in
-// child order) by the parallel-axis shift
-// One pass over the cell's particles (leaf) or children (internal cell), about a reference
+// Moments of one cell: a leaf from its particles, an internal cell from its children (in
+// child order).  One pass over the cell's particles (leaf) or children (internal cell), about a reference
 // point inside the cell -- the first particle, or the first child's centre of mass -- so the
 // offsets are bounded by the cell's size:
 //   M = sum m,  s = sum m r,  T = sum m r r^T (+ the children's own Q),  r = x - ref;
