@@ -95,14 +95,19 @@ def test_clustered16m_predictor_path_is_exact(ctx, fdx):
     a = ctx.forces()
     counts = ctx.list_counts()
     ctx.predictor_load(WEIGHTS)
+    spills0 = ctx.stats()["list_spills"]
     ctx.calc_force(0.5, 8, 256, 0.0, quad=True, fp32=True, predictor=True)
     st = ctx.stats()
-    _say(f"[fullsize] predictor: overflow {st['overflow_groups']} of {st['n_groups']}, capacity "
-         f"{st['list_capacity']} vs exact {int(counts[0].sum() + counts[1].sum())}")
+    spilled = st["list_spills"] - spills0
+    _say(f"[fullsize] predictor: overflow {st['overflow_groups']} of {st['n_groups']} "
+         f"({spilled} walked again in spare space), capacity {st['list_capacity']} vs exact "
+         f"{int(counts[0].sum() + counts[1].sum())}")
     assert np.array_equal(ctx.forces(), a)
     for x, y in zip(ctx.list_counts(), counts):
         assert np.array_equal(x, y)
     assert st["overflow_groups"] <= 0.02 * st["n_groups"]
+    # the buffer's spare eighth holds every list that outgrew its prediction
+    assert spilled == st["overflow_groups"]
 
 
 def test_plummer1m_fp64_fp32_and_ten_steps(ctx, fdx):

@@ -102,6 +102,7 @@ def test_predicted_walk_is_exact(ctx, trained, margin):
     trained_margin = ctx.predictor_margin()
     if margin is not None:
         ctx.predictor_margin(margin)
+    spills0 = ctx.stats()["list_spills"]
     try:
         ctx.calc_force(0.5, 8, 128, 0.0, quad=True, fp32=True, predictor=True)
         st = ctx.stats()
@@ -109,20 +110,54 @@ def test_predicted_walk_is_exact(ctx, trained, margin):
         lists_pred = ctx.lists()
     finally:
         ctx.predictor_margin(trained_margin)
+    spilled = st["list_spills"] - spills0
     _say(f"[predicted walk] margin={margin} overflow groups {st['overflow_groups']} of "
-         f"{st['n_groups']}, capacity {st['list_capacity']} vs exact "
-         f"{int(lists_exact[0].sum() + lists_exact[1].sum())}")
+         f"{st['n_groups']} ({spilled} walked again in spare space), capacity "
+         f"{st['list_capacity']} vs exact {int(lists_exact[0].sum() + lists_exact[1].sum())}")
     assert np.array_equal(a_pred, a_exact)
     for a, b in zip(lists_pred, lists_exact):
         assert np.array_equal(a, b)
     if margin == math.log(0.01):
         assert st["overflow_groups"] > 0.9 * st["n_groups"]
     if margin == math.log(100.0):
-        assert st["overflow_groups"] == 0
+        assert st["overflow_groups"] == 0 and spilled == 0
     if margin is None:
-        # a small training set and an input of another size and seed: most groups still fit
+        # a small training set and an input of another size and seed: most groups still fit,
+        # and the spare eighth of the buffer takes the lists that outgrew their prediction
         assert st["overflow_groups"] <= 0.25 * st["n_groups"]
+        if st["overflow_groups"]:
+            assert spilled > 0
         assert st["list_capacity"] < 3 * int(lists_exact[0].sum() + lists_exact[1].sum())
+
+
+def test_outgrown_lists_beyond_the_spare_space_are_rewalked(ctx, fdx, trained, tmp_path):
+    """A fresh context whose first evaluation is a predicted walk with capacities 100x too
+    small: its list buffer has only the spare eighth of that tiny total, so most outgrown
+    lists find no room inside the walk and take the host's exact re-walk; lists and forces
+    still equal the exact walk's."""
+    ps = I.clustered(n_background=40000, n_clusters=8, n_per_cluster=3000, seed=3)
+    ctx.set_particles(ps)
+    ctx.calc_force(0.5, 8, 128, 0.0, quad=True, fp32=True)
+    a_exact, lists_exact = ctx.forces(), ctx.lists()
+    path = str(tmp_path / "w.bin")
+    ctx.predictor_save(path)
+    c = fdx.Context(0)
+    try:
+        c.predictor_load(path)
+        c.predictor_margin(math.log(0.01))
+        c.set_particles(ps)
+        c.calc_force(0.5, 8, 128, 0.0, quad=True, fp32=True, predictor=True)
+        st = c.stats()
+        a_pred, lists_pred = c.forces(), c.lists()
+    finally:
+        c.close()
+    _say(f"[re-walk] overflow groups {st['overflow_groups']} of {st['n_groups']}, "
+         f"{st['list_spills']} walked again in spare space")
+    assert np.array_equal(a_pred, a_exact)
+    for a, b in zip(lists_pred, lists_exact):
+        assert np.array_equal(a, b)
+    assert st["overflow_groups"] > 0.9 * st["n_groups"]
+    assert st["list_spills"] < st["overflow_groups"]        # the host re-walk ran
 
 
 def test_save_load_round_trip(ctx, fdx, trained):
