@@ -238,9 +238,11 @@ hipError_t compact_lists(size_t G, const uint64_t *seg, const uint32_t *cap,
 // cap[g] = sys_cap[system of g]
 hipError_t sys_caps(size_t gmax, const uint32_t *gsys, const uint32_t *sys_cap, uint32_t *cap,
                     DevStatus *st, hipStream_t s);
-// lmax[s] = max over the groups of system s of |EPJ| + |SPJ| (lmax zeroed by the caller)
+// lmax[s] = max over the groups of system s of |EPJ| + |SPJ|, gcount[s] = groups of system
+// s (both zeroed by the caller); gmax must not exceed the group arrays' current size
 hipError_t sys_lmax(size_t gmax, const uint32_t *gsys, const uint32_t *cnt_e,
-                    const uint32_t *cnt_s, uint32_t *lmax, DevStatus *st, hipStream_t s);
+                    const uint32_t *cnt_s, uint32_t *lmax, uint32_t *gcount, DevStatus *st,
+                    hipStream_t s);
 hipError_t list_stats(size_t gmax, const Groups g, const uint32_t *cnt_e,
                       const uint32_t *cnt_s, DevStatus *st, hipStream_t s);
 

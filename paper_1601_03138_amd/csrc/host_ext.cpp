@@ -114,41 +114,46 @@ void ext_invalidate(fdx_ctx *c) {
 // list entries (4 B each) the per-system segments may take: 16 GiB
 constexpr uint64_t kSizedBudget = 1ull << 32;
 
-// capacities with headroom for the drift of one step; chooses the segment sizing
+// capacities with headroom for the drift of one step; chooses the segment sizing.  The
+// per-system statistics are read from the current groups and lists before any buffer is
+// grown: growing reallocates the group arrays and drops their contents.
 static int graph_headroom(fdx_ctx *c, GraphState *g) {
-    const DevStatus h = c->hst->st;         // the last eager evaluation's tree and lists
+    const DevStatus h = c->hst->st;         // the last evaluation's tree and lists
     const uint32_t ncell = c->hst->lvl[kLevels + 1];
+    const int S = c->nsys;
+    const uint64_t pct = c->ext.graph_margin_pct;
+    const bool try_sized = S > 1 && c->have_lists && pct > 0;
+    std::vector<uint32_t> st2;              // [longest list per system, groups per system]
+    if (try_sized) {
+        HIPCHK(c, g->lmax.ensure(2 * (size_t)S));
+        HIPCHK(c, fill_u32(g->lmax.p, 0u, 2 * (size_t)S, c->stream));
+        HIPCHK(c, sys_lmax(c->group_cap, c->g_sys.p, c->cnt_e.p, c->cnt_s.p, g->lmax.p,
+                           g->lmax.p + S, c->st, c->stream));
+        st2.resize(2 * (size_t)S);
+        HIPCHK(c, hipMemcpyAsync(st2.data(), g->lmax.p, 8 * (size_t)S, hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    c->have_lists = false;                  // buffers may be reallocated below
     uint32_t ccap = std::max<uint32_t>(c->cell_cap, ncell + ncell / 4 + 1024);
     uint32_t gcap = std::max<uint32_t>(c->group_cap, h.n_groups + h.n_groups / 4 + 1024);
     int r = ensure_tree_buffers(c, ccap, gcap);
     if (r) return r;
     uint64_t need = h.list_total;
     g->sized = false;
-    const int S = c->nsys;
-    const uint64_t pct = c->ext.graph_margin_pct;
-    if (S > 1 && c->have_lists && pct > 0) {
-        // per-system segment sizes from the current lists' longest entry per system
-        HIPCHK(c, g->lmax.ensure(S));
-        HIPCHK(c, g->sys_cap.ensure(S));
-        HIPCHK(c, fill_u32(g->lmax.p, 0u, S, c->stream));
-        HIPCHK(c, sys_lmax(gcap, c->g_sys.p, c->cnt_e.p, c->cnt_s.p, g->lmax.p, c->st, c->stream));
-        std::vector<uint32_t> lm(S), cap(S);
-        HIPCHK(c, hipMemcpyAsync(lm.data(), g->lmax.p, 4 * (size_t)S, hipMemcpyDeviceToHost,
-                                 c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (try_sized) {
+        std::vector<uint32_t> cap(S);
+        uint64_t total = 0;
         for (int s = 0; s < S; s++) {
             const uint64_t ns = (uint64_t)(c->sys_off_h[s + 1] - c->sys_off_h[s]);
-            cap[s] = (uint32_t)std::min<uint64_t>(ns, pct * lm[s] / 100 + 64);
+            cap[s] = (uint32_t)std::min<uint64_t>(ns, pct * st2[s] / 100 + 64);
+            total += (uint64_t)st2[S + s] * cap[s];
         }
-        HIPCHK(c, hipMemcpyAsync(g->sys_cap.p, cap.data(), 4 * (size_t)S, hipMemcpyHostToDevice,
-                                 c->stream));
-        // the segments of the current groups (re-sized by the next count or fill pass anyway)
-        r = enqueue_sys_caps(c, gcap, g->sys_cap.p);
-        c->have_lists = false;              // seg / cap no longer describe the stored lists
-        if (!r) r = read_status(c);
-        if (r) return r;
-        const uint64_t total = c->hst->st.list_total;
         if (total + total / 4 + 4096 <= kSizedBudget) {
+            HIPCHK(c, g->sys_cap.ensure(S));
+            HIPCHK(c, hipMemcpyAsync(g->sys_cap.p, cap.data(), 4 * (size_t)S,
+                                     hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));     // cap is a host vector
             g->sized = true;
             need = total;
         }

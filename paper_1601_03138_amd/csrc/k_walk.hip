@@ -244,12 +244,16 @@ __global__ void k_sys_caps(const uint32_t *ngroups, uint32_t gmax, const uint32_
     for (size_t gi = gtid(); gi < G; gi += gstride()) cap[gi] = sys_cap[gsys[gi]];
 }
 
-// lmax[s] = longest list of system s (lmax cleared by the caller)
+// lmax[s] = longest list of system s, gcount[s] = its groups (both cleared by the caller)
 __global__ void k_sys_lmax(const uint32_t *ngroups, uint32_t gmax, const uint32_t *gsys,
-                           const uint32_t *cnt_e, const uint32_t *cnt_s, uint32_t *lmax) {
+                           const uint32_t *cnt_e, const uint32_t *cnt_s, uint32_t *lmax,
+                           uint32_t *gcount) {
     const uint32_t G = min(*ngroups, gmax);
-    for (size_t gi = gtid(); gi < G; gi += gstride())
-        atomicMax(&lmax[gsys[gi]], cnt_e[gi] + cnt_s[gi]);
+    for (size_t gi = gtid(); gi < G; gi += gstride()) {
+        const uint32_t s = gsys[gi];
+        atomicMax(&lmax[s], cnt_e[gi] + cnt_s[gi]);
+        atomicAdd(&gcount[s], 1u);
+    }
 }
 
 // every group's entries out of its segment into contiguous per-kind arrays (one workgroup per
@@ -498,11 +502,12 @@ hipError_t sys_caps(size_t gmax, const uint32_t *gsys, const uint32_t *sys_cap, 
 }
 
 hipError_t sys_lmax(size_t gmax, const uint32_t *gsys, const uint32_t *cnt_e,
-                    const uint32_t *cnt_s, uint32_t *lmax, DevStatus *st, hipStream_t s) {
+                    const uint32_t *cnt_s, uint32_t *lmax, uint32_t *gcount, DevStatus *st,
+                    hipStream_t s) {
     size_t b = (gmax + kThreads - 1) / kThreads;
     b = b < 1 ? 1 : (b > 8192 ? 8192 : b);
     hipLaunchKernelGGL(k_sys_lmax, dim3((unsigned)b), dim3(kThreads), 0, s, &st->n_groups_c,
-                       (uint32_t)gmax, gsys, cnt_e, cnt_s, lmax);
+                       (uint32_t)gmax, gsys, cnt_e, cnt_s, lmax, gcount);
     return hipGetLastError();
 }
 
