@@ -1,0 +1,90 @@
+"""Seeded random call sequences on one long-lived context: new particle sets of growing and
+shrinking sizes and system counts, force evaluations with random parameters and flags,
+eager and graph-captured leapfrog steps with random list sizing, list read-backs.  After
+every evaluation the context's forces must equal, bit for bit, those of a fresh context
+given the same particles and parameters, so no state left by an earlier call (buffers grown
+or reused, captured graphs, shapes, margins) changes a result."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1601_03138_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fdx():
+    from paper_1601_03138_amd import fdx as F
+    return F
+
+
+def _set(rng, seed):
+    sets = []
+    for s in range(int(rng.integers(1, 9))):
+        n = int(rng.integers(100, 6001))
+        sets.append(I.plummer(n, seed=seed * 17 + s, eps=float(rng.uniform(0.005, 0.05))))
+    return sets[0] if len(sets) == 1 else I.concat(sets)
+
+
+def _check_against_fresh(fdx, ctx, ps_now, par):
+    theta, n_group, quad, fp32, persistent = par
+    a = ctx.forces()
+    x, y, z, vx, vy, vz = ctx.particles()
+    q = I._pack(np.stack([x, y, z], axis=1), np.stack([vx, vy, vz], axis=1), ps_now.m,
+                ps_now.eps, ps_now.sys_off)
+    with fdx.Context(0) as f:
+        f.set_particles(q)
+        f.calc_force(theta, 8, n_group, 0.0, quad=quad, fp32=fp32, persistent=persistent)
+        b = f.forces()
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_call_sequence(fdx, seed):
+    rng = np.random.default_rng(8000 + seed)
+    ctx = fdx.Context(0)
+    try:
+        ps = _set(rng, seed * 100)
+        ctx.set_particles(ps)
+        par = None
+        for k in range(14):
+            op = str(rng.choice(["set", "force", "force", "step", "step", "lists", "margin"]))
+            if op == "set":
+                ps = _set(rng, seed * 100 + k + 1)
+                ctx.set_particles(ps)
+                par = None
+                _say(f"[session {seed}.{k}] set n={ps.n} systems={ps.n_sys}")
+            elif op == "force" or par is None:
+                par = (float(rng.uniform(0.3, 0.9)), int(rng.choice([8, 32, 64, 128, 256])),
+                       bool(rng.integers(0, 2)), bool(rng.integers(0, 2)),
+                       bool(rng.integers(0, 2)))
+                theta, n_group, quad, fp32, persistent = par
+                ctx.calc_force(theta, 8, n_group, 0.0, quad=quad, fp32=fp32,
+                               persistent=persistent)
+                _say(f"[session {seed}.{k}] force {par}")
+                _check_against_fresh(fdx, ctx, ps, par)
+            elif op == "step":
+                graph = bool(rng.random() < 0.5)
+                steps = int(rng.integers(1, 4))
+                ctx.integrate(1.0 / 512.0, steps, graph=graph)
+                # graph steps run the persistent kernel, eager steps the flags of the force call
+                used = par if not graph else par[:4] + (True,)
+                _say(f"[session {seed}.{k}] {steps} step(s) graph={graph}")
+                _check_against_fresh(fdx, ctx, ps, used)
+            elif op == "lists":
+                ne, ns, epj, spj = ctx.lists()
+                st = ctx.stats()
+                assert int(ne.sum()) == st["n_epj"] and int(ns.sum()) == st["n_spj"]
+                _say(f"[session {seed}.{k}] lists {st['n_epj']} + {st['n_spj']} entries")
+            else:
+                ctx.set_graph_list_margin(int(rng.choice([0, 25, 200])))
+                _say(f"[session {seed}.{k}] margin")
+    finally:
+        ctx.close()
