@@ -1,9 +1,10 @@
 """Seeded random call sequences on one long-lived context: new particle sets of growing and
 shrinking sizes and system counts, force evaluations with random parameters and flags,
-eager and graph-captured leapfrog steps with random list sizing, list read-backs.  After
-every evaluation the context's forces must equal, bit for bit, those of a fresh context
-given the same particles and parameters, so no state left by an earlier call (buffers grown
-or reused, captured graphs, shapes, margins) changes a result."""
+cutoff (TreePM tree part) forces, SPH densities, eager and graph-captured leapfrog steps with
+random list sizing, list read-backs.  After every evaluation the context's results must
+equal, bit for bit, those of a fresh context given the same particles and parameters, so no
+state left by an earlier call (buffers grown or reused, captured graphs, shapes, margins,
+another kind of walk) changes a result."""
 import sys
 
 import numpy as np
@@ -46,6 +47,15 @@ def _check_against_fresh(fdx, ctx, ps_now, par):
     assert np.array_equal(a, b)
 
 
+def _fresh(fdx, ctx, ps_now):
+    x, y, z, vx, vy, vz = ctx.particles()
+    q = I._pack(np.stack([x, y, z], axis=1), np.stack([vx, vy, vz], axis=1), ps_now.m,
+                ps_now.eps, ps_now.sys_off)
+    f = fdx.Context(0)
+    f.set_particles(q)
+    return f
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_random_call_sequence(fdx, seed):
     rng = np.random.default_rng(8000 + seed)
@@ -55,12 +65,40 @@ def test_random_call_sequence(fdx, seed):
         ctx.set_particles(ps)
         par = None
         for k in range(14):
-            op = str(rng.choice(["set", "force", "force", "step", "step", "lists", "margin"]))
+            op = str(rng.choice(["set", "force", "force", "step", "step", "lists", "margin",
+                                 "cutoff", "density"]))
             if op == "set":
                 ps = _set(rng, seed * 100 + k + 1)
                 ctx.set_particles(ps)
                 par = None
                 _say(f"[session {seed}.{k}] set n={ps.n} systems={ps.n_sys}")
+            elif op == "cutoff":
+                cp = (float(rng.uniform(0.3, 0.9)), int(rng.choice([16, 64, 256])),
+                      float(rng.uniform(0.05, 1.0)), bool(rng.integers(0, 2)),
+                      bool(rng.integers(0, 2)))
+                theta, n_group, r_cut, fp32, persistent = cp
+                ctx.calc_force_cutoff(theta, 8, n_group, 0.0, r_cut, fp32=fp32,
+                                      persistent=persistent)
+                _say(f"[session {seed}.{k}] cutoff {cp}")
+                a = ctx.forces()
+                with _fresh(fdx, ctx, ps) as f:
+                    f.calc_force_cutoff(theta, 8, n_group, 0.0, r_cut, fp32=fp32,
+                                        persistent=persistent)
+                    assert np.array_equal(a, f.forces())
+                par = None
+            elif op == "density":
+                mode = int(rng.integers(0, 4))
+                r_cut = float(rng.uniform(0.03, 0.4))
+                h = np.exp(rng.uniform(np.log(0.02), np.log(0.6), ps.n))
+                n_group = int(rng.choice([16, 64]))
+                ctx.calc_density(mode, r_cut, h, n_group=n_group)
+                _say(f"[session {seed}.{k}] density mode={mode} group={n_group}")
+                rho, nn = ctx.density()
+                with _fresh(fdx, ctx, ps) as f:
+                    f.calc_density(mode, r_cut, h, n_group=n_group)
+                    rho_f, nn_f = f.density()
+                assert np.array_equal(rho, rho_f) and np.array_equal(nn, nn_f)
+                par = None
             elif op == "force" or par is None:
                 par = (float(rng.uniform(0.3, 0.9)), int(rng.choice([8, 32, 64, 128, 256])),
                        bool(rng.integers(0, 2)), bool(rng.integers(0, 2)),
