@@ -185,6 +185,32 @@ def test_empty_input_and_empty_system(ctx, fdx):
     check_lists(ctx.lists(), lists)
 
 
+def test_steps_on_empty_input_and_an_empty_system(ctx, fdx):
+    _say("[empty steps] n = 0, eager and graph steps")
+    empty = I._pack(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0), np.zeros(0))
+    ctx.set_particles(empty)
+    ctx.calc_force(0.5, 8, 64, 0.0, quad=True, fp32=True, persistent=True)
+    ctx.integrate(1.0 / 256.0, 2)
+    ctx.integrate(1.0 / 256.0, 2, graph=True)
+    assert ctx.forces().shape == (0, 4)
+    assert all(a.shape == (0,) for a in ctx.particles())
+    _say("[empty steps] empty middle system, eager against graph steps")
+    a = I.plummer(500, seed=3, eps=0.02)
+    b = I.plummer(300, seed=4, eps=0.02)
+    both = I.concat([a, b])
+    both.sys_off = np.array([0, 500, 500, 800], dtype=np.int64)
+    runs = []
+    for graph in (False, True):
+        ctx.set_particles(both)
+        ctx.calc_force(0.5, 8, 64, 0.0, quad=True, fp32=True, persistent=True)
+        ctx.integrate(1.0 / 256.0, 3, graph=graph)
+        runs.append((ctx.particles(), ctx.forces()))
+    for u, v in zip(runs[0][0], runs[1][0]):
+        assert np.array_equal(u, v)
+    assert np.array_equal(runs[0][1], runs[1][1])
+    assert np.all(np.isfinite(runs[1][1]))
+
+
 def test_invalid_arguments_return_codes(ctx, fdx):
     ps = I.plummer(100, seed=1, eps=0.01)
     ctx.set_particles(ps)
