@@ -350,3 +350,22 @@ def test_fp32_path_hands_wide_groups_to_fp64(ctx):
     e = rel_err(a32[ok], ref[ok])
     _say(f"[wide] fp64 groups {int(wide.sum())} of {g.n}; fp32-path rms vs tree {np.sqrt(np.mean(e ** 2)):.2e}")
     assert np.sqrt(np.mean(e ** 2)) <= F32_RMS_REL_VS_TREE
+
+
+def test_wide_groups_in_graph_steps(ctx):
+    """The same input through eager and graph-captured leapfrog steps with the persistent FP32
+    launch: the group too wide for FP32 goes to the FP64 kernel inside the captured step too."""
+    a = I.plummer(200, seed=81, eps=0.01)
+    a.x[100:] += 1.0e4
+    ps = I.concat([a, I.plummer(3000, seed=82, eps=0.01)])
+    runs = []
+    for graph in (False, True):
+        ctx.set_particles(ps)
+        ctx.calc_force(0.76, 1, 200, 0.0, quad=True, fp32=True, persistent=True)
+        assert ctx.stats()["fp64_groups"] >= 1
+        ctx.integrate(1.0 / 1024.0, 3, graph=graph)
+        runs.append((ctx.particles(), ctx.forces(), ctx.stats()["fp64_groups"]))
+    _say(f"[wide graph] fp64 groups after the steps: eager {runs[0][2]}, graph {runs[1][2]}")
+    for u, v in zip(runs[0][0], runs[1][0]):
+        assert np.array_equal(u, v)
+    assert np.array_equal(runs[0][1], runs[1][1])
