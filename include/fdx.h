@@ -14,7 +14,8 @@
  *
  * Conventions for every call:
  *   - returns FDX_OK (0) on success or a negative FDX_E* code; no C++ exception crosses
- *     this boundary; fdx_last_error() then holds a message for that context;
+ *     this boundary (a host allocation failure inside a call returns FDX_ENOMEM, any other
+ *     exception FDX_EINVAL); fdx_last_error() then holds a message for that context;
  *   - all GPU work is issued on the stream bound at fdx_create, in order, asynchronously;
  *     calls that return data to host memory synchronise that stream first;
  *   - the library owns its tree, list and scratch buffers (device memory it allocates);
@@ -39,7 +40,7 @@ typedef struct fdx_ctx fdx_ctx;
 /* status codes */
 #define FDX_OK 0
 #define FDX_EINVAL -1   /* an argument is out of range, null or non-finite */
-#define FDX_ENOMEM -2   /* a device allocation failed */
+#define FDX_ENOMEM -2   /* a device or host allocation failed */
 #define FDX_EHIP -3     /* a HIP runtime call failed, or a kernel reported an error */
 #define FDX_ESTATE -4   /* calls made in the wrong order (e.g. force before particles) */
 
@@ -113,11 +114,12 @@ int fdx_calc_force(fdx_ctx *ctx, double theta, int32_t n_leaf, int32_t n_group, 
                    int32_t flags);
 
 /* Advance n_steps leapfrog steps of size dt (predict: v += dt/2 a, x += dt v; force;
- * correct: v += dt/2 a), with the tree parameters and flags of the last fdx_calc_force,
- * which must have been called first (the sample program evaluates the force once before
- * its loop).  flags may add FDX_GRAPH: the step is captured once as a HIP graph and
- * replayed.  FDX_ESTATE: no prior force evaluation; FDX_EINVAL: dt not finite or
- * n_steps < 0. */
+ * correct: v += dt/2 a), with the theta, n_leaf, n_group, eps and flags of the last
+ * fdx_calc_force (or fdx_calc_force_cutoff), which must have been called first (the sample
+ * program evaluates the force once before its loop); fdx_build_tree, fdx_calc_density,
+ * fdx_build_exchange_lists and fdx_autotune in between do not change them.  flags may add
+ * FDX_GRAPH: the step is captured once as a HIP graph and replayed.  FDX_ESTATE: no prior
+ * force evaluation; FDX_EINVAL: dt not finite or n_steps < 0. */
 int fdx_integrate(fdx_ctx *ctx, double dt, int32_t n_steps, int32_t flags);
 
 /* List sizing of FDX_GRAPH steps with several systems.  A group's list has at most as many
@@ -157,7 +159,8 @@ typedef struct {
     int32_t shape;                     /* force-kernel shape used (see fdx_autotune_shapes) */
     double theta;
     /* phase times in milliseconds (FDX_TIMING): keys, sort, tree, moments, groups, walk,
-       force, unsort, predict (feature + MLP), total */
+       force, unsort, predict, total; with FDX_PREDICTOR, predict = features, network and
+       capacities and walk = the walk after them (predict = 0 otherwise) */
     double t_keys, t_sort, t_tree, t_moments, t_groups, t_walk, t_force, t_unsort, t_predict,
         t_total;
     /* FP32 evaluations: groups evaluated by the FP64 kernel instead, because FP32 rounding of
@@ -203,7 +206,12 @@ int fdx_get_lists(fdx_ctx *ctx, uint32_t *n_epj, uint32_t *n_spj, uint32_t *epj,
  * times_ms[k * shapes + v] receives each time (NaN where the shape cannot hold the group
  * size; null skips).  With FDX_GRAPH in `flags` it times graph-captured leapfrog steps of
  * dt = 0 (which leave the particles unchanged) instead of eager evaluations, with the
- * persistent kernel.  fdx_set_shape fixes the shape of both precisions (-1 = default).
+ * persistent kernel.  Shapes whose kernel spills registers to scratch memory are not timed
+ * (NaN) when a shape that does not spill can hold the group size.  When the context had a
+ * force evaluation before the call, it is evaluated again at the end with its own
+ * parameters (and the chosen shape), so forces, lists and the parameters of fdx_integrate
+ * are the caller's; otherwise the context is left without a force.
+ * fdx_set_shape fixes the shape of both precisions (-1 = default).
  * FDX_EINVAL: no candidates, reps < 1, or a shape out of range. */
 int fdx_autotune_shapes(void);
 const char *fdx_shape_name(int32_t shape);   /* e.g. "nt512_ipl1_pf"; "" if out of range */

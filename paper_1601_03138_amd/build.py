@@ -52,16 +52,6 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, LIB)
-    # instruction-throughput microbenchmark behind the force kernel's roofline
-    ub = os.path.join(HERE, "ubench", "valu_ceiling.hip")
-    if os.path.exists(ub):
-        exe = os.path.join(HERE, "ubench", "valu_ceiling")
-        cmd = [HIPCC, "-O3", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
-               "-packed-fp32-ops", "-Wno-unused-command-line-argument", ub, "-o", exe + ".tmp"]
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            raise RuntimeError(f"hipcc failed on valu_ceiling.hip:\n{r.stderr}")
-        os.replace(exe + ".tmp", exe)
     return LIB
 
 

@@ -23,12 +23,11 @@ using namespace fdx;
 namespace fdx {
 
 int fail(fdx_ctx *c, int code, const char *fmt, ...) {
-    char buf[512];
+    if (!c) return code;
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(c->err, sizeof c->err, fmt, ap);
     va_end(ap);
-    if (c) c->err = buf;
     return code;
 }
 
@@ -288,6 +287,7 @@ int ensure_list_capacity(fdx_ctx *c, uint64_t total) {
 int run_force(fdx_ctx *c) {
     const uint32_t G = c->hst->st.n_groups;
     int r;
+    c->predict_marked = false;
     if (c->flags & FDX_PREDICTOR) {
         r = ext_predicted_walk(c, G);
         if (r) return r;
@@ -332,6 +332,18 @@ int setup_eval(fdx_ctx *c, double theta, int n_leaf, int n_group, double eps, in
     return ensure_tree_buffers(c, ccap, gcap);
 }
 
+void save_force_params(fdx_ctx *c) {
+    fdx_ctx::ForceParams &p = c->last_force;
+    p.theta = c->theta; p.eps_all = c->eps_all; p.cutoff = c->cutoff;
+    p.n_leaf = c->n_leaf; p.n_group = c->n_group; p.flags = c->flags;
+}
+
+void restore_force_params(fdx_ctx *c) {
+    const fdx_ctx::ForceParams &p = c->last_force;
+    c->theta = p.theta; c->eps_all = p.eps_all; c->cutoff = p.cutoff;
+    c->n_leaf = p.n_leaf; c->n_group = p.n_group; c->flags = p.flags;
+}
+
 void finish_stats(fdx_ctx *c) {
     fdx_stats &o = c->stats;
     const DevStatus &h = c->hst->st;
@@ -356,6 +368,15 @@ int sync_timing(fdx_ctx *c) {
     fdx_stats &o = c->stats;
     o.t_keys = t[0]; o.t_sort = t[1]; o.t_tree = t[2]; o.t_moments = t[3]; o.t_groups = t[4];
     o.t_walk = t[5]; o.t_force = t[6]; o.t_unsort = t[7];
+    o.t_predict = 0.0;
+    if (c->predict_marked) {
+        // predicted walk: features + network + capacities (event 5 -> 9), then the walk
+        float tp = 0.0f, tw = 0.0f;
+        hipEventElapsedTime(&tp, c->ev[5], c->ev[9]);
+        hipEventElapsedTime(&tw, c->ev[9], c->ev[6]);
+        o.t_predict = tp;
+        o.t_walk = tw;
+    }
     float tot = 0;
     hipEventElapsedTime(&tot, c->ev[0], c->ev[8]);
     o.t_total = tot;
@@ -379,6 +400,7 @@ int read_counters(fdx_ctx *c) {
 extern "C" {
 
 int fdx_create(fdx_ctx **out, int device, void *hip_stream) {
+    FDX_ABI_TRY
     if (!out) return FDX_EINVAL;
     *out = nullptr;
     int ndev = 0;
@@ -404,9 +426,11 @@ int fdx_create(fdx_ctx **out, int device, void *hip_stream) {
     if (c->partial.ensure(kScanBlocks + 1) != hipSuccess) { fdx_destroy(c); return FDX_ENOMEM; }
     *out = c;
     return FDX_OK;
+    FDX_ABI_CATCH(nullptr)
 }
 
 int fdx_destroy(fdx_ctx *c) {
+    FDX_ABI_TRY
     if (!c) return FDX_OK;
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
@@ -437,11 +461,13 @@ int fdx_destroy(fdx_ctx *c) {
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 int fdx_set_particles(fdx_ctx *c, int64_t n, const double *x, const double *y, const double *z,
                       const double *vx, const double *vy, const double *vz, const double *m,
                       const double *eps, const int64_t *sys_off, int32_t n_sys, int32_t mem_kind) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, FDX_EHIP, "hipSetDevice failed");
     if (n < 0 || n >= (1ll << 31)) return fail(c, FDX_EINVAL, "n must be in [0, 2^31)");
@@ -528,9 +554,11 @@ int fdx_set_particles(fdx_ctx *c, int64_t n, const double *x, const double *y, c
     c->have_particles = true;
     c->stats = fdx_stats{};
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 int fdx_build_tree(fdx_ctx *c, int32_t n_leaf, int32_t n_group) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, FDX_EHIP, "hipSetDevice failed");
     double eps = c->eps_given ? 0.0 : (c->eps_all > 0 ? c->eps_all : 1.0);
@@ -540,10 +568,12 @@ int fdx_build_tree(fdx_ctx *c, int32_t n_leaf, int32_t n_group) {
     if (r) return r;
     finish_stats(c);
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 int fdx_calc_force(fdx_ctx *c, double theta, int32_t n_leaf, int32_t n_group, double eps,
                    int32_t flags) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, FDX_EHIP, "hipSetDevice failed");
     c->cutoff = 0.0;
@@ -553,14 +583,17 @@ int fdx_calc_force(fdx_ctx *c, double theta, int32_t n_leaf, int32_t n_group, do
     if (r) return r;
     r = run_force(c);
     if (r) return r;
+    save_force_params(c);
     finish_stats(c);
     r = sync_timing(c);
     if (r) return r;
     return read_counters(c);
+    FDX_ABI_CATCH(c)
 }
 
 int fdx_calc_force_cutoff(fdx_ctx *c, double theta, int32_t n_leaf, int32_t n_group, double eps,
                           double r_cut, int32_t flags) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, FDX_EHIP, "hipSetDevice failed");
     if (!(std::isfinite(r_cut) && r_cut > 0.0)) return fail(c, FDX_EINVAL, "r_cut must be finite and > 0");
@@ -573,17 +606,21 @@ int fdx_calc_force_cutoff(fdx_ctx *c, double theta, int32_t n_leaf, int32_t n_gr
     if (r) return r;
     r = run_force(c);
     if (r) return r;
+    save_force_params(c);
     finish_stats(c);
     r = sync_timing(c);
     if (r) return r;
     return read_counters(c);
+    FDX_ABI_CATCH(c)
 }
 
 int fdx_integrate(fdx_ctx *c, double dt, int32_t n_steps, int32_t flags) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, FDX_EHIP, "hipSetDevice failed");
     if (!c->have_force) return fail(c, FDX_ESTATE, "evaluate the force once before integrating");
     if (!std::isfinite(dt) || n_steps < 0) return fail(c, FDX_EINVAL, "bad dt or n_steps");
+    restore_force_params(c);
     if ((flags & FDX_GRAPH) && c->cutoff > 0)
         return fail(c, FDX_EINVAL, "graph capture is not available with the cutoff kernel");
     if (flags & FDX_GRAPH) return ext_integrate_graph(c, dt, n_steps);
@@ -603,10 +640,12 @@ int fdx_integrate(fdx_ctx *c, double dt, int32_t n_steps, int32_t flags) {
         if (r) return r;
     }
     return read_counters(c);
+    FDX_ABI_CATCH(c)
 }
 
 int fdx_get_particles(fdx_ctx *c, double *x, double *y, double *z, double *vx, double *vy,
                       double *vz, int32_t mem_kind) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     if (!c->have_particles) return fail(c, FDX_ESTATE, "no particles");
     hipMemcpyKind k = mem_kind == FDX_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
@@ -617,9 +656,11 @@ int fdx_get_particles(fdx_ctx *c, double *x, double *y, double *z, double *vx, d
         if (dst[i] && bytes) HIPCHK(c, hipMemcpyAsync(dst[i], src[i], bytes, k, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 int fdx_get_forces(fdx_ctx *c, double *ax, double *ay, double *az, double *pot, int32_t mem_kind) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     if (!c->have_force) return fail(c, FDX_ESTATE, "no force evaluated");
     hipMemcpyKind k = mem_kind == FDX_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
@@ -630,17 +671,21 @@ int fdx_get_forces(fdx_ctx *c, double *ax, double *ay, double *az, double *pot, 
         if (dst[i] && bytes) HIPCHK(c, hipMemcpyAsync(dst[i], src[i], bytes, k, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 int fdx_get_stats(fdx_ctx *c, fdx_stats *out) {
+    FDX_ABI_TRY
     if (!c || !out) return FDX_EINVAL;
     *out = c->stats;
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 int fdx_get_tree(fdx_ctx *c, double *cube, uint64_t *key, uint32_t *perm, int32_t *level,
                  uint64_t *prefix, uint32_t *begin, uint32_t *count, uint32_t *first_child,
                  uint32_t *nchild, uint32_t *parent, double *mom) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     if (!c->skey) return fail(c, FDX_ESTATE, "no tree built");
     hipStream_t s = c->stream;
@@ -662,10 +707,12 @@ int fdx_get_tree(fdx_ctx *c, double *cube, uint64_t *key, uint32_t *perm, int32_
     HIPCHK(c, cp(mom, c->c_mom.p, 80 * nc));
     HIPCHK(c, hipStreamSynchronize(s));
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 int fdx_get_groups(fdx_ctx *c, uint32_t *cell, uint32_t *begin, uint32_t *count, uint32_t *qmin,
                    uint32_t *qmax, double *centre) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     if (!c->skey) return fail(c, FDX_ESTATE, "no tree built");
     hipStream_t s = c->stream;
@@ -687,9 +734,11 @@ int fdx_get_groups(fdx_ctx *c, uint32_t *cell, uint32_t *begin, uint32_t *count,
             if (qmax) qmax[3 * g + a] = box[6 * g + 3 + a];
         }
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 int fdx_get_lists(fdx_ctx *c, uint32_t *n_epj, uint32_t *n_spj, uint32_t *epj, uint32_t *spj) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     if (!c->have_lists) return fail(c, FDX_ESTATE, "no walk done on the current groups");
     hipStream_t s = c->stream;
@@ -735,11 +784,12 @@ int fdx_get_lists(fdx_ctx *c, uint32_t *n_epj, uint32_t *n_spj, uint32_t *epj, u
         if (e != hipSuccess) return fail(c, FDX_EHIP, "get_lists: %s", hipGetErrorString(e));
     }
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 const char *fdx_last_error(const fdx_ctx *c) {
     if (!c) return "null context";
-    return c->err.c_str();
+    return c->err;
 }
 
 }  // extern "C"

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/fdx.h"
+#include "abi_guard.h"
 #include "fdx_internal.h"
 #include "host_ext.h"
 
@@ -46,7 +47,8 @@ struct fdx_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    std::string err;
+    char err[512] = {};           // message of the last failed call (fixed size: writing it
+                                  // never allocates)
 
     // particles (caller's order)
     int64_t n = 0;
@@ -105,8 +107,16 @@ struct fdx_ctx {
     double theta = 0.5, eps_all = 0.0;
     int n_leaf = 8, n_group = 64, flags = 0, variant = -1;
     double cutoff = 0.0;           // > 0: the last evaluation was the TreePM cutoff kernel
+    // parameters of the last fdx_calc_force / fdx_calc_force_cutoff: fdx_integrate steps with
+    // these (the tree-only, density, exchange-list and autotuner calls set the fields above
+    // for their own passes)
+    struct ForceParams {
+        double theta = 0.5, eps_all = 0.0, cutoff = 0.0;
+        int n_leaf = 8, n_group = 64, flags = 0;
+    } last_force;
     fdx_stats stats{};
     hipEvent_t ev[12] = {};
+    bool predict_marked = false;   // event 9 holds the end of the predictor's network
 
     fdx::HostExt ext;   // predictor, autotuner, graph state
     // bumped by every fdx_set_particles and every reallocation of a buffer a captured graph
@@ -117,6 +127,11 @@ struct fdx_ctx {
 namespace fdx {
 
 int fail(fdx_ctx *c, int code, const char *fmt, ...);
+
+// FDX_ABI_CATCH handler: status code of the exception in flight, message into c->err
+inline int abi_exception(fdx_ctx *c) noexcept {
+    return classify_exception(c ? c->err : nullptr, c ? sizeof c->err : 0);
+}
 
 #define HIPCHK(ctx, expr)                                                                     \
     do {                                                                                      \
@@ -141,6 +156,8 @@ int enqueue_sys_caps(fdx_ctx *c, size_t gmax, const uint32_t *sys_cap);
 int enqueue_force(fdx_ctx *c, size_t gmax);
 int ensure_list_capacity(fdx_ctx *c, uint64_t total);
 int setup_eval(fdx_ctx *c, double theta, int n_leaf, int n_group, double eps, int flags);
+void save_force_params(fdx_ctx *c);
+void restore_force_params(fdx_ctx *c);
 void finish_stats(fdx_ctx *c);
 int sync_timing(fdx_ctx *c);
 int read_counters(fdx_ctx *c);

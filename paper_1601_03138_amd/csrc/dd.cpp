@@ -113,6 +113,7 @@ using namespace fdx;
 extern "C" {
 
 int fdx_dd_factor(int32_t n, int32_t *nx, int32_t *ny, int32_t *nz) {
+    FDX_ABI_TRY
     if (n < 1 || !nx || !ny || !nz) return FDX_EINVAL;
     int32_t ba = n, bb = 1, bc = 1;            // n x 1 x 1 always exists
     for (int32_t c = 1; (int64_t)c * c * c <= n; c++) {
@@ -128,10 +129,12 @@ int fdx_dd_factor(int32_t n, int32_t *nx, int32_t *ny, int32_t *nz) {
     }
     *nx = ba; *ny = bb; *nz = bc;
     return FDX_OK;
+    FDX_ABI_CATCH(nullptr)
 }
 
 int fdx_decompose(fdx_ctx *c, int32_t nx, int32_t ny, int32_t nz, int64_t n_sample,
                   const double *cost, uint64_t seed, int32_t flags) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, FDX_EHIP, "hipSetDevice failed");
     if (!c->have_particles) return fail(c, FDX_ESTATE, "no particles: call fdx_set_particles first");
@@ -265,10 +268,12 @@ int fdx_decompose(fdx_ctx *c, int32_t nx, int32_t ny, int32_t nz, int64_t n_samp
     d->built = true;
     d->gen = c->gen;
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 int fdx_get_decomposition(fdx_ctx *c, double *bx, double *by, double *bz, int64_t *send_counts,
                           int64_t *dom_off) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     int r = check_built(c);
     if (r) return r;
@@ -285,10 +290,12 @@ int fdx_get_decomposition(fdx_ctx *c, double *bx, double *by, double *bz, int64_
     if (send_counts) std::copy(d->counts.begin(), d->counts.end(), send_counts);
     if (dom_off) std::copy(d->dom_off.begin(), d->dom_off.end(), dom_off);
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 int fdx_get_dd_samples(fdx_ctx *c, int64_t *k_per_domain, uint32_t *sample_idx,
                        uint32_t *sample_domain) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     int r = check_built(c);
     if (r) return r;
@@ -301,9 +308,11 @@ int fdx_get_dd_samples(fdx_ctx *c, int64_t *k_per_domain, uint32_t *sample_idx,
                                  c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 int fdx_get_dd_destinations(fdx_ctx *c, uint32_t *dest, uint32_t *order, int32_t mem_kind) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     if (mem_kind != FDX_MEM_HOST && mem_kind != FDX_MEM_DEVICE)
         return fail(c, FDX_EINVAL, "mem_kind must be FDX_MEM_HOST or FDX_MEM_DEVICE");
@@ -317,9 +326,11 @@ int fdx_get_dd_destinations(fdx_ctx *c, uint32_t *dest, uint32_t *order, int32_t
     if (order && N) HIPCHK(c, hipMemcpyAsync(order, d->order, 4 * N, k, c->stream));
     if (mem_kind == FDX_MEM_HOST) HIPCHK(c, hipStreamSynchronize(c->stream));
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 int fdx_exchange_particles(fdx_ctx *c) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, FDX_EHIP, "hipSetDevice failed");
     int r = check_built(c);
@@ -371,9 +382,11 @@ int fdx_exchange_particles(fdx_ctx *c) {
     d->gen = c->gen;
     d->applied = true;
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 int fdx_get_dd_stats(fdx_ctx *c, fdx_dd_stats *out) {
+    FDX_ABI_TRY
     if (!c || !out) return FDX_EINVAL;
     int r = check_built(c);
     if (r) return r;
@@ -401,6 +414,7 @@ int fdx_get_dd_stats(fdx_ctx *c, fdx_dd_stats *out) {
         out->ms_exchange = te;
     }
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 }  // extern "C"

@@ -11,6 +11,7 @@ extern "C" {
 
 int fdx_direct_forces(fdx_ctx *c, const int64_t *targets, int64_t n_targets, double eps,
                       double *out) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, FDX_EHIP, "hipSetDevice failed");
     if (!c->have_particles) return fail(c, FDX_ESTATE, "no particles: call fdx_set_particles first");
@@ -46,6 +47,7 @@ int fdx_direct_forces(fdx_ctx *c, const int64_t *targets, int64_t n_targets, dou
         return fail(c, e == hipErrorOutOfMemory ? FDX_ENOMEM : FDX_EHIP, "direct forces: %s",
                     hipGetErrorString(e));
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 }  // extern "C"

@@ -68,6 +68,7 @@ using namespace fdx;
 extern "C" {
 
 int fdx_build_exchange_lists(fdx_ctx *c, double theta, int32_t n_leaf) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, FDX_EHIP, "hipSetDevice failed");
     if (!c->have_particles) return fail(c, FDX_ESTATE, "no particles: call fdx_set_particles first");
@@ -163,9 +164,11 @@ int fdx_build_exchange_lists(fdx_ctx *c, double theta, int32_t n_leaf) {
     x->gen = c->gen;
     x->built = true;
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 int fdx_get_exchange_counts(fdx_ctx *c, uint32_t *n_epj, uint32_t *n_spj) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     int r = check_built(c);
     if (r) return r;
@@ -189,9 +192,11 @@ int fdx_get_exchange_counts(fdx_ctx *c, uint32_t *n_epj, uint32_t *n_spj) {
             if (n_spj) n_spj[s * S + q] = sp;
         }
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 int fdx_get_exchange_lists(fdx_ctx *c, uint32_t *epj, uint32_t *spj) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     int r = check_built(c);
     if (r) return r;
@@ -226,9 +231,11 @@ int fdx_get_exchange_lists(fdx_ctx *c, uint32_t *epj, uint32_t *spj) {
     if (spj)
         for (size_t i = 0; i < os; i++) spj[i] = sp[i];
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 int fdx_get_exchange_stats(fdx_ctx *c, fdx_exchange_stats *out) {
+    FDX_ABI_TRY
     if (!c || !out) return FDX_EINVAL;
     int r = check_built(c);
     if (r) return r;
@@ -241,6 +248,7 @@ int fdx_get_exchange_stats(fdx_ctx *c, fdx_exchange_stats *out) {
     out->ms_tree = x->ms_tree;
     out->ms_lists = x->ms_lists;
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 }  // extern "C"

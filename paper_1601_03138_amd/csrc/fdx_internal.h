@@ -269,5 +269,8 @@ hipError_t force(size_t G, const ForceArgs &a, hipStream_t s);
 int force_variants();
 const char *force_variant_name(int v);
 int force_variant_capacity(int v);   // largest group one workgroup of variant v takes
+// scratch (private) bytes per lane of variant v's kernel for this precision, moment order and
+// launch: > 0 when its registers spill to memory (-1 if the runtime cannot tell)
+int force_variant_scratch(bool fp32, bool quad, bool persistent, int v);
 
 }  // namespace fdx

@@ -245,23 +245,28 @@ const char *fdx_shape_name(int32_t shape) {
 }
 
 int fdx_set_graph_list_margin(fdx_ctx *c, int32_t percent) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     if (percent < 0) return fail(c, FDX_EINVAL, "percent must be >= 0");
     c->ext.graph_margin_pct = (uint32_t)percent;
     ext_invalidate(c);
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 int fdx_set_shape(fdx_ctx *c, int32_t shape) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     if (shape < -1 || shape >= force_variants()) return fail(c, FDX_EINVAL, "shape out of range");
     c->ext.variant[0] = c->ext.variant[1] = shape;
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 int fdx_autotune(fdx_ctx *c, double theta, int32_t n_leaf, double eps, int32_t flags,
                  const int32_t *n_group_cand, int32_t n_cand, int32_t reps, double *times_ms,
                  int32_t *best_n_group, int32_t *best_shape) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     if (!n_group_cand || n_cand < 1 || reps < 1) return fail(c, FDX_EINVAL, "no candidates");
     const int nv = force_variants();
@@ -276,10 +281,24 @@ int fdx_autotune(fdx_ctx *c, double theta, int32_t n_leaf, double eps, int32_t f
     const bool graph = (flags & FDX_GRAPH) != 0;
     flags &= ~(FDX_TIMING | FDX_PREDICTOR | FDX_GRAPH);
     if (graph) flags |= FDX_PERSISTENT;
+    // the caller's last force evaluation, re-done at the end so that forces, lists and the
+    // parameters fdx_integrate uses are the caller's again, not the last candidate's
+    const bool had_force = c->have_force;
+    const fdx_ctx::ForceParams caller = c->last_force;
+    // shapes whose registers spill are not timed when a shape that does not spill can take
+    // the group size: they move their spills through memory on every tile, and a tie decided
+    // by timing noise would pick them
+    std::vector<int> spills(nv);
+    for (int v = 0; v < nv; v++)
+        spills[v] = force_variant_scratch(f32, (flags & FDX_QUAD) != 0,
+                                          (flags & FDX_PERSISTENT) != 0, v) > 0;
     for (int k = 0; k < n_cand; k++) {
+        bool clean = false;
+        for (int v = 0; v < nv; v++)
+            clean |= force_variant_capacity(v) >= n_group_cand[k] && !spills[v];
         for (int v = 0; v < nv; v++) {
             double t = NAN;
-            if (force_variant_capacity(v) >= n_group_cand[k]) {
+            if (force_variant_capacity(v) >= n_group_cand[k] && !(clean && spills[v])) {
                 slot = v;
                 int r = fdx_calc_force(c, theta, n_leaf, n_group_cand[k], eps, flags);
                 if (!r && graph) r = fdx_integrate(c, 0.0, 1, FDX_GRAPH);     // capture
@@ -301,9 +320,20 @@ int fdx_autotune(fdx_ctx *c, double theta, int32_t n_leaf, double eps, int32_t f
         }
     }
     slot = bv;
+    if (had_force) {
+        const int r = caller.cutoff > 0
+            ? fdx_calc_force_cutoff(c, caller.theta, caller.n_leaf, caller.n_group,
+                                    caller.eps_all, caller.cutoff, caller.flags)
+            : fdx_calc_force(c, caller.theta, caller.n_leaf, caller.n_group, caller.eps_all,
+                             caller.flags);
+        if (r) return r;
+    } else {
+        c->have_force = false;      // the candidates' evaluations were not the caller's
+    }
     if (best_n_group) *best_n_group = bg;
     if (best_shape) *best_shape = bv;
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 // Autotuner results recorded in a text file, one JSON object per line:
@@ -313,6 +343,7 @@ int fdx_autotune(fdx_ctx *c, double theta, int32_t n_leaf, double eps, int32_t f
 int fdx_autotune_cached(fdx_ctx *c, const char *path, double theta, int32_t n_leaf, double eps,
                         int32_t flags, const int32_t *n_group_cand, int32_t n_cand, int32_t reps,
                         int32_t *best_n_group, int32_t *best_shape, int32_t *from_cache) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     if (!path || !n_group_cand || n_cand < 1 || reps < 1)
         return fail(c, FDX_EINVAL, "null path or no candidates");
@@ -364,6 +395,7 @@ int fdx_autotune_cached(fdx_ctx *c, const char *path, double theta, int32_t n_le
     if (best_n_group) *best_n_group = bg;
     if (best_shape) *best_shape = bv;
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 }  // extern "C"

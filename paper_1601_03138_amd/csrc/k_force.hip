@@ -456,7 +456,40 @@ hipError_t launch_v(const KArgs &k, bool persistent, int v, hipStream_t s) {
     }
 }
 
+// private (scratch) bytes per lane of one kernel instance: > 0 means registers spill
+template <class T, bool QUAD, int NT, int IPL, bool PF, int OCC = 1>
+int scratch_of(bool persistent) {
+    hipFuncAttributes at{};
+    const void *f = persistent
+        ? reinterpret_cast<const void *>(k_force_persistent<T, QUAD, NT, IPL, PF, OCC, false>)
+        : reinterpret_cast<const void *>(k_force_direct<T, QUAD, NT, IPL, PF, OCC, false>);
+    if (hipFuncGetAttributes(&at, f) != hipSuccess) return -1;
+    return (int)at.localSizeBytes;
+}
+
+template <class T, bool QUAD>
+int scratch_v(bool persistent, int v) {
+    switch (v) {
+        case 0: return scratch_of<T, QUAD, 256, 1, true>(persistent);
+        case 1: return scratch_of<T, QUAD, 256, 2, true>(persistent);
+        case 2: return scratch_of<T, QUAD, 512, 1, true>(persistent);
+        case 3: return scratch_of<T, QUAD, 512, 2, true>(persistent);
+        case 4: return scratch_of<T, QUAD, 256, 1, false>(persistent);
+        case 5: return scratch_of<T, QUAD, 256, 2, false>(persistent);
+        case 6: return scratch_of<T, QUAD, 512, 1, false>(persistent);
+        case 7: return scratch_of<T, QUAD, 512, 2, false>(persistent);
+        case 8: return scratch_of<T, QUAD, 512, 1, true, sizeof(T) == 4 ? 8 : 1>(persistent);
+        default: return scratch_of<T, QUAD, 512, 1, false, sizeof(T) == 4 ? 8 : 1>(persistent);
+    }
+}
+
 }  // namespace
+
+int force_variant_scratch(bool fp32, bool quad, bool persistent, int v) {
+    if (v < 0 || v >= kNumVariants) return -1;
+    if (fp32) return quad ? scratch_v<float, true>(persistent, v) : scratch_v<float, false>(persistent, v);
+    return quad ? scratch_v<double, true>(persistent, v) : scratch_v<double, false>(persistent, v);
+}
 
 int force_variants() { return kNumVariants; }
 const char *force_variant_name(int v) {

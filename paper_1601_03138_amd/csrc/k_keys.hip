@@ -5,8 +5,11 @@
 // This library builds it from space-filling-curve keys: the root cube of a system is the
 // smallest power-of-two cube anchored at the exact per-axis minimum that covers the exact
 // extent; each coordinate is quantised to 21 bits and the bits are interleaved (x on bit
-// 3b+2, y on 3b+1, z on 3b).  Only exact operations enter a key: min/max, a subtraction and
-// a multiplication by a power of two, so keys are bit-reproducible.
+// 3b+2, y on 3b+1, z on 3b).  A key comes from exact min/max, one correctly rounded FP64
+// subtraction (x - o), an exact scaling by the power of two 2^21 / Lr and a floor.  The
+// oracle performs the same subtraction and scaling operation for operation, with
+// contraction off on both sides, so keys agree bit for bit; fusing the two into an FMA,
+// reassociating them or precomputing a scaled origin would break that parity.
 #include "dev_util.h"
 #include "fdx_internal.h"
 

@@ -81,6 +81,8 @@ int ext_predicted_walk(fdx_ctx *c, uint32_t G) {
     for (int k = 0; k < c->nsys; k++)
         cap_max = std::max<uint32_t>(cap_max, (uint32_t)(c->sys_off_h[k + 1] - c->sys_off_h[k]));
     HIPCHK(c, pred_caps(G, p->y.p, p->margin, std::max<uint32_t>(cap_max, 1), c->lcap.p, c->st, s));
+    mark(c, 9);
+    c->predict_marked = (c->flags & FDX_TIMING) != 0;
     HIPCHK(c, scan_u32_to_u64(c->lcap.p, c->seg.p, 0, nullptr, &c->st->n_groups_c, c->partial.p,
                               &c->st->list_total, s));
     int r = read_status(c);
@@ -175,6 +177,7 @@ int fdx_mlp_params(void) { return kMlpParams; }
 
 // Raw (unstandardised) features of every group of the last tree: X[8 g + k].
 int fdx_predictor_features(fdx_ctx *c, float *X) {
+    FDX_ABI_TRY
     if (!c || !X) return FDX_EINVAL;
     if (!c->skey) return fail(c, FDX_ESTATE, "no tree built");
     Pred *p = pred_of(c);
@@ -191,10 +194,12 @@ int fdx_predictor_features(fdx_ctx *c, float *X) {
                                     c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 // y = MLP_P(X) for n standardised feature rows (host arrays).
 int fdx_mlp_forward(fdx_ctx *c, const float *P, const float *X, int64_t n, float *y) {
+    FDX_ABI_TRY
     if (!c || !P || !X || !y || n < 0) return FDX_EINVAL;
     Pred *p = pred_of(c);
     DBuf<float> dP, dX, dy;
@@ -214,11 +219,13 @@ int fdx_mlp_forward(fdx_ctx *c, const float *P, const float *X, int64_t n, float
     (void)p;
     dP.release(); dX.release(); dy.release();
     return r;
+    FDX_ABI_CATCH(c)
 }
 
 // Full-batch gradient of mean((MLP_P(X) - t)^2) with respect to the 4801 parameters.
 int fdx_mlp_grad(fdx_ctx *c, const float *P, const float *X, const float *t, int64_t n,
                  float *grad, float *loss) {
+    FDX_ABI_TRY
     if (!c || !P || !X || !t || !grad || n < 1) return FDX_EINVAL;
     DBuf<float> dP, dX, dT, gp, lp, dg, dl;
     DBuf<uint32_t> di;
@@ -246,6 +253,7 @@ int fdx_mlp_grad(fdx_ctx *c, const float *P, const float *X, const float *t, int
     for (auto *b : {&dP, &dX, &dT, &gp, &lp, &dg, &dl}) b->release();
     di.release();
     return r;
+    FDX_ABI_CATCH(c)
 }
 
 // Train the predictor on n (raw features, ln list length) samples: standardise with the
@@ -254,6 +262,7 @@ int fdx_mlp_grad(fdx_ctx *c, const float *P, const float *X, const float *t, int
 // the held-out 10 %.  losses[e] = mean training loss of epoch e (optional).
 int fdx_predictor_train(fdx_ctx *c, const float *X, const float *t, int64_t n, int32_t epochs,
                         int32_t batch, double lr, int64_t seed, float *losses) {
+    FDX_ABI_TRY
     if (!c || !X || !t || n < 16 || epochs < 1 || batch < 1) return FDX_EINVAL;
     Pred *p = pred_of(c);
     hipStream_t s = c->stream;
@@ -335,22 +344,26 @@ int fdx_predictor_train(fdx_ctx *c, const float *X, const float *t, int64_t n, i
     HIPCHK(c, hipStreamSynchronize(s));
     p->loaded = true;
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 // margin: ln of the factor applied to predicted lengths (the trained value when the
 // argument is NaN); returns the margin in effect through *out (optional).
 int fdx_predictor_margin(fdx_ctx *c, double margin, double *out) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     Pred *p = pred_of(c);
     if (!p->loaded) return fail(c, FDX_ESTATE, "no predictor trained or loaded");
     if (!std::isnan(margin)) p->margin = (float)margin;
     if (out) *out = p->margin;
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 static const char kMagic[8] = {'F', 'D', 'X', 'M', 'L', 'P', '1', 0};
 
 int fdx_predictor_save(fdx_ctx *c, const char *path) {
+    FDX_ABI_TRY
     if (!c || !path) return FDX_EINVAL;
     Pred *p = pred_of(c);
     if (!p->loaded) return fail(c, FDX_ESTATE, "no predictor trained or loaded");
@@ -363,9 +376,11 @@ int fdx_predictor_save(fdx_ctx *c, const char *path) {
               std::fwrite(P.data(), 4, kMlpParams, f) == (size_t)kMlpParams;
     ok = (std::fclose(f) == 0) && ok;
     return ok ? FDX_OK : fail(c, FDX_EINVAL, "write failed: %s", path);
+    FDX_ABI_CATCH(c)
 }
 
 int fdx_predictor_load(fdx_ctx *c, const char *path) {
+    FDX_ABI_TRY
     if (!c || !path) return FDX_EINVAL;
     Pred *p = pred_of(c);
     FILE *f = std::fopen(path, "rb");
@@ -389,6 +404,7 @@ int fdx_predictor_load(fdx_ctx *c, const char *path) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     p->loaded = true;
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 }  // extern "C"

@@ -46,6 +46,7 @@ extern "C" {
 
 int fdx_calc_density(fdx_ctx *c, int32_t mode, double r_cut, const double *h, int32_t mem_kind,
                      int32_t n_leaf, int32_t n_group, int32_t flags) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, FDX_EHIP, "hipSetDevice failed");
     if (!c->have_particles) return fail(c, FDX_ESTATE, "no particles: call fdx_set_particles first");
@@ -131,9 +132,11 @@ int fdx_calc_density(fdx_ctx *c, int32_t mode, double r_cut, const double *h, in
     x->gen = c->gen;
     x->built = true;
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 int fdx_get_density(fdx_ctx *c, double *rho, uint32_t *n_ngb, int32_t mem_kind) {
+    FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
     SphState *x = static_cast<SphState *>(c->ext.sph);
     if (!x || !x->built || x->gen != c->gen)
@@ -144,6 +147,7 @@ int fdx_get_density(fdx_ctx *c, double *rho, uint32_t *n_ngb, int32_t mem_kind) 
     if (n_ngb && n) HIPCHK(c, hipMemcpyAsync(n_ngb, x->nngb.p, n * sizeof(uint32_t), k, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return FDX_OK;
+    FDX_ABI_CATCH(c)
 }
 
 }  // extern "C"
