@@ -243,6 +243,9 @@ int fdx_autotune_cached(fdx_ctx *ctx, const char *path, double theta, int32_t n_
  *   mass / system mass), ln(parent side / root side), depth, ln(parent density), log2 N_sys.
  * fdx_mlp_forward / fdx_mlp_grad: the network's forward pass and the full-batch gradient of
  *   the mean squared error on given weights P[4801] and standardised inputs (for checks).
+ * fdx_mlp_adam: n_steps steps of the training's Adam kernel (Kingma & Ba, beta1 0.9, beta2
+ *   0.999, eps 1e-8, learning rate lr) on P, m, v (4801 each, updated in place) with the
+ *   gradient grads[4801 k ...] at step number step0 + k + 1 (for checks).
  * fdx_predictor_train: trains on n samples (raw features, ln length) with the library's own
  *   forward/backward/Adam kernels: seeded 90/10 split, standardisation from the training
  *   part, `epochs` passes of minibatches of `batch`, learning rate lr; the capacity margin is
@@ -255,6 +258,8 @@ int fdx_predictor_features(fdx_ctx *ctx, float *X);
 int fdx_mlp_forward(fdx_ctx *ctx, const float *P, const float *X, int64_t n, float *y);
 int fdx_mlp_grad(fdx_ctx *ctx, const float *P, const float *X, const float *t, int64_t n,
                  float *grad, float *loss);
+int fdx_mlp_adam(fdx_ctx *ctx, float *P, float *m, float *v, const float *grads, int32_t n_steps,
+                 int32_t step0, double lr);
 int fdx_predictor_train(fdx_ctx *ctx, const float *X, const float *t, int64_t n, int32_t epochs,
                         int32_t batch, double lr, int64_t seed, float *losses);
 int fdx_predictor_margin(fdx_ctx *ctx, double margin, double *out);

@@ -234,6 +234,43 @@ def make_groups(tree: Tree, n_group: int) -> Groups:
     return Groups(tree, n_group)
 
 
+def group_features(tree: Tree, grp: Groups) -> np.ndarray:
+    """The eight per-group inputs of the list-length network, [G, 8] in FP64.  The paper models
+    only the mean list length (equation nlist_long, from the group size, the opening angle and
+    the particle count); these are cheap per-group stand-ins for its terms.  With the group's
+    integer box [qmin, qmax] (grid units, 2^21 per root side), its cell c at level l_c and
+    p = the parent of c (c itself for a root) at level l_p:
+      0 ln n_i                               1 ln(1 + max_a (qmax_a - qmin_a))
+      2 ln(1 + |box centre - root centre|),  box centre (qmin + qmax + 1) / 2, root centre 2^20
+      3 ln(M_p / M_system)                   4 ln(side_p / side_root) = -l_p ln 2
+      5 l_c                                  6 ln(count_p / (side_p / side_root)^3)
+      7 log2 N_system"""
+    if tree.mom is None:
+        tree.compute_moments()
+    G = grp.n
+    X = np.zeros((G, 8))
+    off = tree.off
+    for g in range(G):
+        c = int(grp.cell[g])
+        p = int(tree.parent[c])
+        if p == 0xFFFFFFFF:
+            p = c
+        s = int(tree.csys[c])
+        lo = grp.qmin[g].astype(np.float64)
+        hi = grp.qmax[g].astype(np.float64)
+        centre = 0.5 * (lo + hi + 1.0) - 2.0 ** 20
+        lp = int(tree.level[p])
+        X[g, 0] = math.log(int(grp.count[g]))
+        X[g, 1] = math.log(1.0 + float(np.max(hi - lo)))
+        X[g, 2] = math.log(1.0 + math.sqrt(float(centre @ centre)))
+        X[g, 3] = math.log(tree.mom[p, 0] / tree.mom[s, 0])
+        X[g, 4] = -lp * math.log(2.0)
+        X[g, 5] = float(tree.level[c])
+        X[g, 6] = math.log(int(tree.count[p])) + 3.0 * lp * math.log(2.0)
+        X[g, 7] = math.log2(int(off[s + 1] - off[s]))
+    return X
+
+
 class Lists:
     """Interaction lists of selected groups, CSR: EPJ (sorted particle positions) and SPJ
     (cell ids), each in depth-first walk order."""
@@ -377,7 +414,9 @@ def list_force(x, y, z, eps, jx, jy, jz, jm, mom, quad: bool = True, self_mask=N
     """{ax, ay, az, phi} on the targets (x, y, z, eps) from particles (jx, jy, jz, jm) and
     superparticles (rows of `mom`: M, X, Y, Z, Qxx, Qyy, Qzz, Qxy, Qxz, Qyz), FP64, with the
     particle term of equation ParticleParticleNbody and the quadrupole superparticle term
-    (reading R6); pairs at zero separation contribute nothing (the self term)."""
+    (the Taylor expansion of 1/r about the centre of mass to second order, softened like
+    equation ParticleSuperparticleNbody); pairs at zero separation contribute nothing (the
+    self term)."""
     out = np.zeros((x.shape[0], 4))
     e2 = (eps * eps)[:, None]
     if jx.shape[0]:

@@ -1,8 +1,9 @@
 """FP64 reference of the list-length network (test infrastructure only).
 
-MLP 8 -> 64 -> 64 -> 1 with SiLU activations, loss = mean((y - t)^2); the flat parameter
-layout is W1[8][64], b1[64], W2[64][64], b2[64], W3[64], b3 (4801 values).  Forward and
-backward are written out layer by layer (chain rule), with no framework autodiff.
+MLP 8 -> 64 -> 64 -> 1 with SiLU activations (silu(z) = z * sigmoid(z), Elfwing, Uchibe & Doya
+2018), loss = mean((y - t)^2); the flat parameter layout is W1[8][64], b1[64], W2[64][64],
+b2[64], W3[64], b3 (4801 values).  Forward and backward are written out layer by layer (chain
+rule), with no framework autodiff.  The optimiser is Adam (Kingma & Ba 2015, Algorithm 1).
 """
 from __future__ import annotations
 
@@ -67,3 +68,15 @@ def loss_and_grad(P, X, t):
     gb1 = dz1.sum(axis=0)
     g = np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3, [gb3]])
     return loss, g
+
+
+def adam(P, m, v, g, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step (Kingma & Ba 2015, Algorithm 1) at step number t >= 1: first and second
+    moment estimates, their bias corrections, and the parameter update; returns the new
+    (P, m, v) in FP64."""
+    P, m, v, g = (np.asarray(a, dtype=np.float64) for a in (P, m, v, g))
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * (g * g)
+    m_hat = m / (1.0 - b1 ** t)
+    v_hat = v / (1.0 - b2 ** t)
+    return P - lr * m_hat / (np.sqrt(v_hat) + eps), m, v

@@ -256,6 +256,41 @@ int fdx_mlp_grad(fdx_ctx *c, const float *P, const float *X, const float *t, int
     FDX_ABI_CATCH(c)
 }
 
+// n_steps Adam steps of the training kernel on host arrays P, m, v (updated in place) with
+// the gradients grads[k * 4801 ...], step numbers step0 + 1 ... step0 + n_steps.
+int fdx_mlp_adam(fdx_ctx *c, float *P, float *m, float *v, const float *grads, int32_t n_steps,
+                 int32_t step0, double lr) {
+    FDX_ABI_TRY
+    if (!c || !P || !m || !v || !grads || n_steps < 0 || step0 < 0) return FDX_EINVAL;
+    if (!(std::isfinite(lr) && lr > 0)) return fail(c, FDX_EINVAL, "lr must be finite and > 0");
+    DBuf<float> dP, dm, dv, dg;
+    auto run = [&]() -> int {
+        const size_t bytes = (size_t)kMlpParams * 4;
+        HIPCHK(c, dP.ensure(kMlpParams));
+        HIPCHK(c, dm.ensure(kMlpParams));
+        HIPCHK(c, dv.ensure(kMlpParams));
+        HIPCHK(c, dg.ensure((size_t)std::max(n_steps, 1) * kMlpParams));
+        HIPCHK(c, hipMemcpyAsync(dP.p, P, bytes, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(dm.p, m, bytes, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(dv.p, v, bytes, hipMemcpyHostToDevice, c->stream));
+        if (n_steps)
+            HIPCHK(c, hipMemcpyAsync(dg.p, grads, (size_t)n_steps * bytes, hipMemcpyHostToDevice,
+                                     c->stream));
+        for (int k = 0; k < n_steps; k++)
+            HIPCHK(c, mlp_adam(dP.p, dg.p + (size_t)k * kMlpParams, dm.p, dv.p, step0 + k + 1,
+                               (float)lr, c->stream));
+        HIPCHK(c, hipMemcpyAsync(P, dP.p, bytes, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(m, dm.p, bytes, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(v, dv.p, bytes, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return FDX_OK;
+    };
+    const int r = run();
+    for (auto *b : {&dP, &dm, &dv, &dg}) b->release();
+    return r;
+    FDX_ABI_CATCH(c)
+}
+
 // Train the predictor on n (raw features, ln list length) samples: standardise with the
 // statistics of a seeded 90 % training split, Adam on minibatches of `batch` for `epochs`
 // passes, then pick the capacity margin as the 99th percentile of the residual ln t - y on

@@ -25,7 +25,8 @@ EXPORTS = ["fdx_create", "fdx_destroy", "fdx_set_particles", "fdx_build_tree", "
            "fdx_integrate", "fdx_get_particles", "fdx_get_forces", "fdx_get_stats",
            "fdx_get_tree", "fdx_get_groups", "fdx_get_lists", "fdx_last_error",
            "fdx_autotune_shapes", "fdx_shape_name", "fdx_set_shape", "fdx_autotune", "fdx_mlp_params",
-           "fdx_predictor_features", "fdx_mlp_forward", "fdx_mlp_grad", "fdx_predictor_train",
+           "fdx_predictor_features", "fdx_mlp_forward", "fdx_mlp_grad", "fdx_mlp_adam",
+           "fdx_predictor_train",
            "fdx_predictor_margin", "fdx_predictor_save", "fdx_predictor_load",
            "fdx_build_exchange_lists", "fdx_get_exchange_counts", "fdx_get_exchange_lists",
            "fdx_get_exchange_stats", "fdx_calc_density", "fdx_get_density",
@@ -122,6 +123,7 @@ def _declare(L):
     L.fdx_predictor_features.argtypes = [vp, vp]
     L.fdx_mlp_forward.argtypes = [vp, vp, vp, i64, vp]
     L.fdx_mlp_grad.argtypes = [vp, vp, vp, vp, i64, vp, vp]
+    L.fdx_mlp_adam.argtypes = [vp, vp, vp, vp, vp, i32, i32, f64]
     L.fdx_predictor_train.argtypes = [vp, vp, vp, i64, i32, i32, f64, i64, vp]
     L.fdx_predictor_margin.argtypes = [vp, f64, vp]
     L.fdx_predictor_save.argtypes = [vp, C.c_char_p]
@@ -489,6 +491,15 @@ class Context:
         self._check(self.lib.fdx_mlp_grad(self.h, _ptr(P), _ptr(X), _ptr(t), X.shape[0], _ptr(g),
                                           _ptr(loss)), "mlp_grad")
         return g, float(loss[0])
+
+    def mlp_adam(self, P, m, v, grads, step0=0, lr=1e-3):
+        """Adam steps of the training kernel: returns the new (P, m, v) after one step per row
+        of grads."""
+        P, m, v = (np.array(a, np.float32) for a in (P, m, v))
+        g = np.ascontiguousarray(grads, np.float32).reshape(-1, P.shape[0])
+        self._check(self.lib.fdx_mlp_adam(self.h, _ptr(P), _ptr(m), _ptr(v), _ptr(g), g.shape[0],
+                                          int(step0), float(lr)), "mlp_adam")
+        return P, m, v
 
     def predictor_train(self, X, t, epochs=20, batch=4096, lr=1e-3, seed=1):
         X = np.ascontiguousarray(X, np.float32)

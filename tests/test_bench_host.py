@@ -1,6 +1,6 @@
 """Host-side logic of bench.py (no GPU): the one-GPU rule, the traffic lookup that ties a
 committed counter summary to the kernel source, shape and launch it was taken for, the flop
-accounting of the roofline and the error metric of reading R14."""
+accounting of the roofline and the rms relative error of the accelerations."""
 import os
 import subprocess
 import sys

@@ -46,6 +46,48 @@ def test_forward_matches_oracle(ctx):
     assert np.max(np.abs(y - ref)) <= 1e-4 * max(1.0, np.max(np.abs(ref)))
 
 
+def test_adam_kernel_matches_oracle_over_several_steps(ctx):
+    # seven steps of the training's Adam kernel from m = v = 0 (step numbers 1..7, then 8..10
+    # continuing from the returned moments) against the FP64 Adam of the oracle
+    rng = np.random.default_rng(11)
+    P0 = _params(12)
+    grads = (rng.normal(size=(10, M.N_PARAMS)) * 10.0 ** rng.uniform(-3, 1, (10, M.N_PARAMS))
+             ).astype(np.float32)
+    lr = 1e-3
+    P, m, v = ctx.mlp_adam(P0, np.zeros_like(P0), np.zeros_like(P0), grads[:7], step0=0, lr=lr)
+    P, m, v = ctx.mlp_adam(P, m, v, grads[7:], step0=7, lr=lr)
+    Pr, mr, vr = P0.astype(np.float64), np.zeros(M.N_PARAMS), np.zeros(M.N_PARAMS)
+    for t in range(10):
+        Pr, mr, vr = M.adam(Pr, mr, vr, grads[t].astype(np.float64), t + 1, lr)
+    # every step moves a weight by at most lr (1 + small), so P differs by FP32 rounding of
+    # the steps and of P itself
+    assert np.max(np.abs(P - Pr)) <= 1e-6 + 1e-6 * np.max(np.abs(Pr))
+    assert np.allclose(m, mr, rtol=1e-5, atol=1e-12 * np.abs(mr).max())
+    assert np.allclose(v, vr, rtol=1e-5, atol=1e-12 * np.abs(vr).max())
+    # the displacement itself, relative to the learning rate
+    d_gpu, d_ref = P - P0, Pr - P0
+    assert np.max(np.abs(d_gpu - d_ref)) <= 2e-3 * lr * 10
+
+
+def test_features_match_oracle(ctx, oracle_mod):
+    O = oracle_mod
+    for k, ps in enumerate([I.plummer(20000, seed=41, eps=1e-3),
+                            I.ensemble(n_sys=6, seed=42, nmin=500, nmax=9000),
+                            I.clustered(n_background=30000, n_clusters=8, n_per_cluster=4000,
+                                        seed=43)]):
+        for n_group in (16, 128):
+            ctx.set_particles(ps)
+            ctx.build_tree(8, n_group)
+            X = ctx.predictor_features()
+            tr = O.build_tree(ps, 8)
+            g = O.make_groups(tr, n_group)
+            ref = O.group_features(tr, g)
+            _say(f"[features] case {k} n_group {n_group}: {g.n} groups, max |d| "
+                 f"{np.max(np.abs(X - ref)):.2e}")
+            assert X.shape == ref.shape
+            assert np.allclose(X, ref, rtol=2e-6, atol=2e-5), np.max(np.abs(X - ref), axis=0)
+
+
 def test_gradients_match_oracle_per_tensor(ctx):
     rng = np.random.default_rng(5)
     P = _params(6)

@@ -233,6 +233,26 @@ def _spj_force_error(quad, size, rng):
     return np.linalg.norm(acc[0, :3] - exact[:3]) / np.linalg.norm(exact[:3])
 
 
+def _spj_potential_error(quad, size, rng):
+    """Relative error of the potential of the same far superparticle at the origin (the
+    particle's own list entry is itself, whose term is excluded), against the exact
+    -sum_k m_k / |x_k| of the cluster's particles written out here."""
+    n = 40
+    cl = 0.7 + rng.uniform(-size, size, (n, 3))
+    ms = rng.uniform(0.5, 1.5, n) / n
+    pos = np.vstack([[[0.0, 0.0, 0.0]], cl])
+    m = np.concatenate([[1e-30], ms])
+    ps = _pos_set(pos, m, eps=0.0)
+    exact = -float(np.sum(ms / np.linalg.norm(cl, axis=1)))
+    tr = O.build_tree(ps, n_leaf=1)
+    g = O.make_groups(tr, 1)
+    sel = [k for k in range(g.n) if tr.perm[g.begin[k]] == 0]
+    lists = O.walk(tr, g, theta=0.5, sel=sel)
+    epj, spj = lists.group_lists(0)
+    assert epj.tolist() == [0] and len(spj) == 1 and tr.count[spj[0]] == n
+    return abs(lists.force(quad)[0, 3] - exact) / abs(exact)
+
+
 def test_multipole_convergence_order():
     # with eps = 0 the monopole error of a far cell falls like (s/d)^2 and the quadrupole
     # error like (s/d)^3 (the dipole vanishes about the centre of mass)
@@ -244,6 +264,20 @@ def test_multipole_convergence_order():
     assert sm == pytest.approx(2.0, abs=0.2)
     assert sq == pytest.approx(3.0, abs=0.2)
     assert all(q < m for q, m in zip(eq, em))
+
+
+def test_multipole_potential_convergence_order():
+    # the potential of a far cell: the monopole leaves the quadrupole term, an error falling
+    # like (s/d)^2; with the quadrupole term the error is the octupole's, (s/d)^3.  A wrong
+    # sign or factor of the quadrupole potential term leaves an (s/d)^2 error.
+    sizes = np.array([0.16, 0.08, 0.04, 0.02])
+    em = [_spj_potential_error(False, s, np.random.default_rng(2)) for s in sizes]
+    eq = [_spj_potential_error(True, s, np.random.default_rng(2)) for s in sizes]
+    sm = np.polyfit(np.log(sizes), np.log(em), 1)[0]
+    sq = np.polyfit(np.log(sizes), np.log(eq), 1)[0]
+    assert sm == pytest.approx(2.0, abs=0.2)
+    assert sq == pytest.approx(3.0, abs=0.25)
+    assert all(q < 0.2 * m for q, m in zip(eq, em))
 
 
 # ---------------------------------------------------------------------------------------
@@ -387,3 +421,70 @@ def test_mean_list_length_near_paper_model():
         mean = np.sum((lists.n_epj + lists.n_spj) * g.count) / ps.n
         model = O.nlist_model(ng, 0.5, ps.n)
         assert 0.5 < mean / model < 2.0
+
+
+def _cell_by_halving(p, o, Lr, level):
+    """Lower corner and side of the level-`level` cube holding point p, by halving the root
+    cube geometrically (no keys, no bit arithmetic)."""
+    lo = np.array(o, float)
+    size = Lr
+    for _ in range(level):
+        size /= 2
+        lo = lo + size * (p >= lo + size)
+    return lo, size
+
+
+def test_group_centre_is_its_cell_centre_by_geometric_halving():
+    ps = I.concat([I.plummer(3000, seed=8, eps=0.01), I.uniform_cube(900, 9, 0.01, side=0.3)])
+    tr = O.build_tree(ps, n_leaf=8, moments=False)
+    g = O.make_groups(tr, 32)
+    for k in range(0, g.n, 7):
+        c = int(g.cell[k])
+        s = int(tr.csys[c])
+        o, Lr = tr.cube[s, :3], tr.cube[s, 3]
+        b = int(g.begin[k])
+        p = np.array([tr.sx[b], tr.sy[b], tr.sz[b]])
+        lo, side = _cell_by_halving(p, o, Lr, int(tr.level[c]))
+        assert np.allclose(g.centre[k], lo + side / 2, rtol=0, atol=4e-16 * (abs(o).max() + Lr))
+        # every member lies in the cube of half-width side / 2 about the centre
+        mem = slice(b, b + int(g.count[k]))
+        for a, arr in enumerate((tr.sx, tr.sy, tr.sz)):
+            assert np.all(np.abs(arr[mem] - g.centre[k, a]) <= side / 2 * (1 + 1e-12))
+
+
+def test_group_features_from_geometry():
+    # the network's eight inputs, recomputed from positions alone: cubes by geometric halving
+    # of the root cube, counts and masses by membership, the integer box by quantising the
+    # members' coordinates to the 2^21 grid of the root side
+    ps = I.concat([I.plummer(2500, seed=10, eps=0.01), I.plummer(700, seed=11, eps=0.01)])
+    tr = O.build_tree(ps, n_leaf=8)
+    g = O.make_groups(tr, 40)
+    X = O.group_features(tr, g)
+    off = ps.offsets()
+    pos = np.stack([ps.x, ps.y, ps.z], axis=1)
+    checked = 0
+    for k in range(0, g.n, 11):
+        c = int(g.cell[k])
+        s = int(tr.csys[c])
+        o, Lr = tr.cube[s, :3], tr.cube[s, 3]
+        sl = slice(int(off[s]), int(off[s + 1]))
+        b = int(g.begin[k])
+        p0 = np.array([tr.sx[b], tr.sy[b], tr.sz[b]])
+        lc = int(tr.level[c])
+        lp = max(lc - 1, 0)
+        lo_p, side_p = _cell_by_halving(p0, o, Lr, lp)
+        inside = np.all((pos[sl] >= lo_p) & (pos[sl] < lo_p + side_p), axis=1)
+        mem = slice(b, b + int(g.count[k]))
+        q = np.floor((np.stack([tr.sx[mem], tr.sy[mem], tr.sz[mem]], 1) - o) * (2.0 ** 21 / Lr))
+        q = np.minimum(q, 2.0 ** 21 - 1)
+        ctr = 0.5 * (q.min(0) + q.max(0) + 1.0) - 2.0 ** 20
+        want = [math.log(int(g.count[k])),
+                math.log(1.0 + float(np.max(q.max(0) - q.min(0)))),
+                math.log(1.0 + float(np.linalg.norm(ctr))),
+                math.log(ps.m[sl][inside].sum() / ps.m[sl].sum()),
+                math.log(side_p / Lr), float(lc),
+                math.log(int(inside.sum()) / (side_p / Lr) ** 3),
+                math.log2(int(off[s + 1] - off[s]))]
+        assert np.allclose(X[k], want, rtol=1e-12, atol=1e-12), (k, X[k], want)
+        checked += 1
+    assert checked > 20
