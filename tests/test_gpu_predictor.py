@@ -62,8 +62,12 @@ def test_adam_kernel_matches_oracle_over_several_steps(ctx):
     # every step moves a weight by at most lr (1 + small), so P differs by FP32 rounding of
     # the steps and of P itself
     assert np.max(np.abs(P - Pr)) <= 1e-6 + 1e-6 * np.max(np.abs(Pr))
-    assert np.allclose(m, mr, rtol=1e-5, atol=1e-12 * np.abs(mr).max())
-    assert np.allclose(v, vr, rtol=1e-5, atol=1e-12 * np.abs(vr).max())
+    # the moments are running sums of up to ten terms with two FP32 roundings per step: per
+    # weight they err by at most 2 * 10 * 2^-24 of the largest term, whatever cancellation
+    # leaves of the sum
+    gmax = np.max(np.abs(grads.astype(np.float64)), axis=0)
+    assert np.all(np.abs(m - mr) <= 2e-6 * gmax + 1e-6 * np.abs(mr))
+    assert np.all(np.abs(v - vr) <= 2e-6 * gmax ** 2 + 1e-6 * np.abs(vr))
     # the displacement itself, relative to the learning rate
     d_gpu, d_ref = P - P0, Pr - P0
     assert np.max(np.abs(d_gpu - d_ref)) <= 2e-3 * lr * 10
