@@ -433,6 +433,33 @@ int fdx_get_dd_stats(fdx_ctx *ctx, fdx_dd_stats *out);
 int fdx_direct_forces(fdx_ctx *ctx, const int64_t *targets, int64_t n_targets, double eps,
                       double *out);
 
+/* ---- One force evaluation that allocates nothing ---------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid the allocator).  The same evaluation as fdx_calc_force on one
+ * system, without a context: every buffer the library would own (keys, sort scratch, sorted
+ * particles, cells, moments, groups, interaction lists, device status) is carved from one
+ * 128 MiB array in device memory that the library declares statically; each device holds its
+ * own copy from the first call on it until the process ends.  The call issues no device or
+ * host allocation.
+ * device: HIP device; hip_stream: the hipStream_t to work on (NULL: the null stream); the call
+ *   returns after the evaluation finished on it.
+ * x, y, z, m, eps (or null), ax, ay, az, pot: device arrays of length n (the caller owns them;
+ *   eps null uses eps_all); results in the caller's order, as fdx_get_forces.
+ * theta, n_leaf, n_group: as fdx_calc_force; flags: FDX_QUAD, FDX_FP32REL, FDX_PERSISTENT.
+ * err (optional, err_len bytes): the message of a failure ("" on success).
+ * Limits: n <= 131072 (2^17); the interaction lists get what the array has left after the
+ * other buffers (about 80 MiB at n = 2^17, 2e7 entries).
+ * Every call on a device shares its array and leaves its contents there: calls that overlap on
+ * one device (two host threads, or two streams) race and must not be issued.
+ * FDX_EINVAL: n outside [0, 2^17], other flags, a null array, a bad parameter (as
+ * fdx_calc_force), or non-finite particle data; FDX_ENOMEM: the lists or cells do not fit the
+ * array (nothing is allocated instead); FDX_EHIP: a HIP call failed. */
+int fdx_calc_force_noalloc(int device, void *hip_stream, int64_t n, const double *x,
+                           const double *y, const double *z, const double *m, const double *eps,
+                           double eps_all, double theta, int32_t n_leaf, int32_t n_group,
+                           int32_t flags, double *ax, double *ay, double *az, double *pot,
+                           char *err, int32_t err_len);
+
 /* Message of the last failed call on ctx (never null; "" when none). */
 const char *fdx_last_error(const fdx_ctx *ctx);
 

@@ -20,9 +20,11 @@ template <class T>
 struct DBuf {
     T *p = nullptr;
     size_t cap = 0;
+    bool fixed = false;      // memory the buffer does not own: never grown or freed
     hipError_t ensure(size_t n) {
         if (n == 0) n = 1;
         if (n <= cap) return hipSuccess;
+        if (fixed) return hipErrorOutOfMemory;
         release();
         hipError_t e = hipMalloc((void **)&p, n * sizeof(T));
         if (e != hipSuccess) { p = nullptr; cap = 0; return e; }
@@ -30,7 +32,7 @@ struct DBuf {
         return hipSuccess;
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && !fixed) (void)hipFree(p);
         p = nullptr;
         cap = 0;
     }

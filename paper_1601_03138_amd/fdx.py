@@ -33,7 +33,7 @@ EXPORTS = ["fdx_create", "fdx_destroy", "fdx_set_particles", "fdx_build_tree", "
            "fdx_calc_force_cutoff", "fdx_dd_factor", "fdx_decompose", "fdx_get_decomposition",
            "fdx_get_dd_samples", "fdx_get_dd_destinations", "fdx_exchange_particles",
            "fdx_get_dd_stats", "fdx_direct_forces", "fdx_autotune_cached",
-           "fdx_set_graph_list_margin"]
+           "fdx_set_graph_list_margin", "fdx_calc_force_noalloc"]
 
 
 class FdxError(RuntimeError):
@@ -145,6 +145,8 @@ def _declare(L):
     L.fdx_direct_forces.argtypes = [vp, vp, i64, f64, vp]
     L.fdx_autotune_cached.argtypes = [vp, C.c_char_p, f64, i32, f64, i32, vp, i32, i32, vp, vp,
                                       vp]
+    L.fdx_calc_force_noalloc.argtypes = [C.c_int, vp, i64] + [vp] * 5 + [f64, f64, i32, i32, i32] \
+        + [vp] * 4 + [C.c_char_p, i32]
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -521,6 +523,22 @@ class Context:
 
     def predictor_load(self, path: str):
         self._check(self.lib.fdx_predictor_load(self.h, path.encode()), "predictor_load")
+
+
+def calc_force_noalloc(device: int, stream, x, y, z, m, eps, eps_all: float, theta: float,
+                       n_leaf: int, n_group: int, flags: int, ax, ay, az, pot):
+    """fdx_calc_force_noalloc on device tensors (torch FP64, contiguous, one length); eps may
+    be None.  stream: a torch stream or None (the null stream).  Raises FdxError on failure."""
+    L = load()
+    n = int(x.numel())
+    s = None if stream is None else C.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+    err = C.create_string_buffer(256)
+    rc = L.fdx_calc_force_noalloc(int(device), s, n, _dptr(x), _dptr(y), _dptr(z), _dptr(m),
+                                  _dptr(eps), float(eps_all), float(theta), int(n_leaf),
+                                  int(n_group), int(flags), _dptr(ax), _dptr(ay), _dptr(az),
+                                  _dptr(pot), err, 256)
+    if rc != OK:
+        raise FdxError(rc, f"calc_force_noalloc: {err.value.decode()}")
 
 
 def dd_factor(n: int):

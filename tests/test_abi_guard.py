@@ -40,7 +40,7 @@ UNGUARDED = {"fdx_autotune_shapes", "fdx_mlp_params", "fdx_shape_name", "fdx_las
 
 def _definitions():
     for fn in sorted(os.listdir(CSRC)):
-        if not fn.endswith(".cpp"):
+        if not fn.endswith((".cpp", ".hip")):
             continue
         lines = open(os.path.join(CSRC, fn)).read().split("\n")
         i = 0
