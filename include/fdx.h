@@ -63,6 +63,17 @@ typedef struct fdx_ctx fdx_ctx;
                              XCD's queue, then takes slots from the others' */
 #define FDX_GRAPH 16      /* fdx_integrate: capture one step as a HIP graph and replay it */
 #define FDX_TIMING 32     /* record per-phase times (fdx_get_stats) */
+#define FDX_FUSED 64      /* walk and force in one persistent launch (the paper's multiwalk,
+                             section "Design concept of FDPS"): each wave pops a group, walks
+                             the tree for it and evaluates the entries in tiles of 64 as the
+                             walk emits them, so no interaction list is stored (lists and the
+                             opening test are those of the separate walk; forces agree within
+                             rounding).  The groups, in tree order, are cut into one queue per
+                             XCD at equal cumulative cost: members x the learned predictor's
+                             list length with FDX_PREDICTOR (nothing precedes the kernel that
+                             knows the lengths), else members.  n_group <= 256; FDX_PERSISTENT
+                             is implied.  fdx_get_lists returns the counts only unless
+                             fdx_set_list_capture is on. */
 
 /* Create a context on HIP device `device`, issuing work on `hip_stream` (a hipStream_t;
  * NULL = the library creates its own stream).  Corresponds to FDPS's Initialize.
@@ -134,6 +145,12 @@ int fdx_integrate(fdx_ctx *ctx, double dt, int32_t n_steps, int32_t flags);
  * percent < 0. */
 int fdx_set_graph_list_margin(fdx_ctx *ctx, int32_t percent);
 
+/* List capture for FDX_FUSED evaluations (for checks): when on, an eager FDX_FUSED evaluation
+ * first sizes every group's list by a counting walk and the fused kernel also writes the
+ * entries it evaluates into them, so fdx_get_lists returns them (graph-captured steps never
+ * capture).  Default off. */
+int fdx_set_list_capture(fdx_ctx *ctx, int32_t on);
+
 /* Copy positions and velocities (caller's order) into x..vz (length n each, memory of
  * kind mem_kind).  Any pointer may be null to skip that array. */
 int fdx_get_particles(fdx_ctx *ctx, double *x, double *y, double *z, double *vx, double *vy,
@@ -160,7 +177,9 @@ typedef struct {
     double theta;
     /* phase times in milliseconds (FDX_TIMING): keys, sort, tree, moments, groups, walk,
        force, unsort, predict, total; with FDX_PREDICTOR, predict = features, network and
-       capacities and walk = the walk after them (predict = 0 otherwise) */
+       capacities and walk = the walk after them (predict = 0 otherwise); with FDX_FUSED,
+       predict = features, network and queue boundaries, walk = 0 and force = the one
+       walk + force launch */
     double t_keys, t_sort, t_tree, t_moments, t_groups, t_walk, t_force, t_unsort, t_predict,
         t_total;
     /* FP32 evaluations: groups evaluated by the FP64 kernel instead, because FP32 rounding of

@@ -15,7 +15,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfdx.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["k_misc.hip", "k_keys.hip", "k_sort.hip", "k_tree.hip", "k_walk.hip", "k_force.hip",
+SOURCES = ["k_misc.hip", "k_keys.hip", "k_sort.hip", "k_tree.hip", "k_walk.hip", "k_force.hip", "k_fused.hip",
            "k_mlp.hip", "capi.cpp", "host_ext.cpp", "predictor.cpp", "exchange.cpp",
            "k_sph.hip", "sph.cpp", "k_dd.hip", "dd.cpp",
            "k_direct.hip", "direct.cpp", "noalloc.hip"]

@@ -58,6 +58,7 @@ int ensure_tree_buffers(fdx_ctx *c, uint32_t cell_cap, uint32_t group_cap) {
         c->cell_cap = cell_cap;
     }
     HIPCHK(c, c->c_lvl.ensure(kLevels + 2));
+    HIPCHK(c, c->f_bounds.ensure(9));
     HIPCHK(c, c->tmp_n.ensure(n + S + 1));                 // >= 3 n bytes
     HIPCHK(c, c->tmp_off.ensure(std::max(n + S + 2, tree_scratch_u32(n))));
     if (group_cap > c->group_cap || !c->g_cell.p) {
@@ -76,6 +77,8 @@ int ensure_tree_buffers(fdx_ctx *c, uint32_t cell_cap, uint32_t group_cap) {
         HIPCHK(c, c->seg.ensure((size_t)group_cap + 1));
         HIPCHK(c, c->ovf_list.ensure(group_cap));
         HIPCHK(c, c->rs_scratch.ensure(radix_scratch_u32(std::max<size_t>(n, group_cap))));
+        HIPCHK(c, c->f_cost.ensure(group_cap));
+        HIPCHK(c, c->f_pre.ensure((size_t)group_cap + 1));
         c->group_cap = group_cap;
     }
     return FDX_OK;
@@ -158,6 +161,7 @@ int enqueue_tree_groups(fdx_ctx *c) {
 // when the device reports an overflow.  Leaves the status (group count, levels) in c->hst.
 int run_tree(fdx_ctx *c, bool sync) {
     c->have_lists = false;
+    c->have_counts = false;
     int r = enqueue_keys_sort(c);
     if (r) return r;
     for (int attempt = 0;; attempt++) {
@@ -273,6 +277,51 @@ int enqueue_force(fdx_ctx *c, size_t gmax) {
     return FDX_OK;
 }
 
+int enqueue_fused(fdx_ctx *c, size_t gmax, bool capture) {
+    hipStream_t s = c->stream;
+    const size_t n = (size_t)c->n;
+    Groups gv = groups_view(c);
+    Cells cv = cells_view(c);
+    // queue runs at equal cumulative cost (members x predicted list length, or members)
+    const float *y = nullptr;
+    if (c->flags & FDX_PREDICTOR) {
+        const int r = ext_predicted_lengths(c, gmax, &y);
+        if (r) return r;
+    }
+    HIPCHK(c, fused_bounds(gmax, gv.count, y, c->f_cost.p, c->f_pre.p, c->f_bounds.p,
+                           c->partial.p, c->st, s));
+    mark(c, 6);
+    FusedArgs fa{};
+    fa.g = gv;
+    fa.node = cv.node; fa.link = cv.link; fa.ccap = cv.cap;
+    fa.jp = c->jp.p; fa.seps = c->seps.p; fa.mom = c->c_mom.p;
+    fa.theta2 = c->theta * c->theta;
+    fa.bounds = c->f_bounds.p; fa.order = nullptr; fa.count = nullptr;
+    fa.cnt_e = c->cnt_e.p; fa.cnt_s = c->cnt_s.p;
+    fa.seg = capture ? c->seg.p : nullptr;
+    fa.cap = capture ? c->lcap.p : nullptr;
+    fa.list = capture ? c->list.p : nullptr;
+    fa.fs = c->fs.p; fa.st = c->st;
+    const bool fp32 = (c->flags & FDX_FP32REL) != 0, quad = (c->flags & FDX_QUAD) != 0;
+    fa.skip_wide = fp32 ? 1 : 0;
+    HIPCHK(c, fused(gmax, fa, fp32, quad, c->n_group, s));
+    if (fp32) {
+        // groups too wide for group-relative FP32: a second pass of the FP64 kernel over the
+        // device-side list of them (empty when no group is wide)
+        HIPCHK(c, wide_group_list(gmax, gv, c->wide_list.p, c->st, s));
+        FusedArgs fw = fa;
+        fw.order = c->wide_list.p;
+        fw.count = &c->st->wide_groups;
+        fw.skip_wide = 0;
+        HIPCHK(c, fused(gmax, fw, false, quad, c->n_group, s));
+    }
+    HIPCHK(c, list_stats(gmax, gv, c->cnt_e.p, c->cnt_s.p, c->st, s));
+    mark(c, 7);
+    HIPCHK(c, unsort_forces(n, c->fs.p, c->inv.p, c->ax.p, c->ay.p, c->az.p, c->pot.p, s));
+    mark(c, 8);
+    return FDX_OK;
+}
+
 int ensure_list_capacity(fdx_ctx *c, uint64_t total) {
     if (total > c->list_cap || !c->list.p) {
         c->gen++;
@@ -288,6 +337,28 @@ int run_force(fdx_ctx *c) {
     const uint32_t G = c->hst->st.n_groups;
     int r;
     c->predict_marked = false;
+    if (c->flags & FDX_FUSED) {
+        const bool capture = c->capture_lists;
+        if (capture) {
+            // exact list sizes for the entries the fused kernel will store as it evaluates them
+            r = enqueue_count(c, G);
+            if (!r) r = read_status(c);
+            if (r) return r;
+            if (c->hst->st.walk_error) return fail(c, FDX_EHIP, "walk stack exhausted");
+            r = ensure_list_capacity(c, c->hst->st.list_total);
+            if (r) return r;
+            c->stats.list_capacity = (int64_t)c->hst->st.list_total;
+        } else {
+            c->stats.list_capacity = 0;
+        }
+        c->stats.overflow_groups = 0;
+        r = enqueue_fused(c, G, capture);
+        if (r) return r;
+        c->have_counts = true;
+        c->have_lists = capture;
+        c->have_force = true;
+        return FDX_OK;
+    }
     if (c->flags & FDX_PREDICTOR) {
         r = ext_predicted_walk(c, G);
         if (r) return r;
@@ -306,6 +377,7 @@ int run_force(fdx_ctx *c) {
         c->stats.overflow_groups = 0;
     }
     c->have_lists = true;
+    c->have_counts = true;
     r = enqueue_force(c, G);
     if (r) return r;
     c->have_force = true;
@@ -324,6 +396,9 @@ int setup_eval(fdx_ctx *c, double theta, int n_leaf, int n_group, double eps, in
     if (n_group < 1 || n_group > kMaxGroup) return fail(c, FDX_EINVAL, "n_group must be in [1, %d]", kMaxGroup);
     if (!c->eps_given && !(std::isfinite(eps) && eps > 0.0))
         return fail(c, FDX_EINVAL, "eps must be finite and > 0");
+    if ((flags & FDX_FUSED) && n_group > kFusedMaxGroup)
+        return fail(c, FDX_EINVAL, "FDX_FUSED takes n_group <= %d", kFusedMaxGroup);
+    if (flags & FDX_FUSED) flags |= FDX_PERSISTENT;
     c->theta = theta; c->n_leaf = n_leaf; c->n_group = n_group; c->eps_all = eps;
     c->flags = flags;
     const size_t n = (size_t)c->n, S = (size_t)c->nsys;
@@ -369,7 +444,11 @@ int sync_timing(fdx_ctx *c) {
     o.t_keys = t[0]; o.t_sort = t[1]; o.t_tree = t[2]; o.t_moments = t[3]; o.t_groups = t[4];
     o.t_walk = t[5]; o.t_force = t[6]; o.t_unsort = t[7];
     o.t_predict = 0.0;
-    if (c->predict_marked) {
+    if (c->flags & FDX_FUSED) {
+        // queue boundaries (and the predictor's network) before the one walk + force launch
+        o.t_predict = o.t_walk;
+        o.t_walk = 0.0;
+    } else if (c->predict_marked) {
         // predicted walk: features + network + capacities (event 5 -> 9), then the walk
         float tp = 0.0f, tw = 0.0f;
         hipEventElapsedTime(&tp, c->ev[5], c->ev[9]);
@@ -387,6 +466,9 @@ int read_counters(fdx_ctx *c) {
     HIPCHK(c, hipMemcpyAsync(&c->hst->st, c->st, sizeof(DevStatus), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const DevStatus &h = c->hst->st;
+    if (h.walk_error) return fail(c, FDX_EHIP, "walk stack exhausted");
+    if ((c->flags & FDX_FUSED) && h.list_overflow)
+        return fail(c, FDX_EHIP, "a captured list outgrew its counted size");
     c->stats.n_epj = (int64_t)h.n_epj;
     c->stats.n_spj = (int64_t)h.n_spj;
     c->stats.n_interactions_pp = (int64_t)h.inter_pp;
@@ -499,6 +581,7 @@ int fdx_set_particles(fdx_ctx *c, int64_t n, const double *x, const double *y, c
     c->have_particles = false;
     c->have_force = false;
     c->have_lists = false;
+    c->have_counts = false;
     c->gen++;
     ext_invalidate(c);
     c->n = n;
@@ -597,8 +680,9 @@ int fdx_calc_force_cutoff(fdx_ctx *c, double theta, int32_t n_leaf, int32_t n_gr
     if (!c) return FDX_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, FDX_EHIP, "hipSetDevice failed");
     if (!(std::isfinite(r_cut) && r_cut > 0.0)) return fail(c, FDX_EINVAL, "r_cut must be finite and > 0");
-    if (flags & (FDX_QUAD | FDX_PREDICTOR | FDX_GRAPH))
-        return fail(c, FDX_EINVAL, "the cutoff kernel is monopole only, without predictor or graph");
+    if (flags & (FDX_QUAD | FDX_PREDICTOR | FDX_GRAPH | FDX_FUSED))
+        return fail(c, FDX_EINVAL, "the cutoff kernel is monopole only, without predictor, graph "
+                                   "or fused launch");
     int r = setup_eval(c, theta, n_leaf, n_group, eps, flags);
     if (r) return r;
     c->cutoff = r_cut;
@@ -740,15 +824,15 @@ int fdx_get_groups(fdx_ctx *c, uint32_t *cell, uint32_t *begin, uint32_t *count,
 int fdx_get_lists(fdx_ctx *c, uint32_t *n_epj, uint32_t *n_spj, uint32_t *epj, uint32_t *spj) {
     FDX_ABI_TRY
     if (!c) return FDX_EINVAL;
-    if (!c->have_lists) return fail(c, FDX_ESTATE, "no walk done on the current groups");
+    if (!c->have_counts) return fail(c, FDX_ESTATE, "no walk done on the current groups");
+    if ((epj || spj) && !c->have_lists)
+        return fail(c, FDX_ESTATE, "the last evaluation (FDX_FUSED) stored no lists: call "
+                                   "fdx_set_list_capture(ctx, 1) before it");
     hipStream_t s = c->stream;
     const size_t G = (size_t)c->stats.n_groups;
-    std::vector<uint32_t> ce(G), cs(G), cap(G);
-    std::vector<uint64_t> seg(G);
+    std::vector<uint32_t> ce(G), cs(G);
     HIPCHK(c, hipMemcpyAsync(ce.data(), c->cnt_e.p, 4 * G, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(cs.data(), c->cnt_s.p, 4 * G, hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(cap.data(), c->lcap.p, 4 * G, hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipMemcpyAsync(seg.data(), c->seg.p, 8 * G, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     // entries compacted on the device (segments may be far longer than their lists)
     std::vector<uint64_t> oe(G + 1, 0), os(G + 1, 0);
@@ -783,6 +867,14 @@ int fdx_get_lists(fdx_ctx *c, uint32_t *n_epj, uint32_t *n_spj, uint32_t *epj, u
         doe.release(); dos.release(); de.release(); ds.release();
         if (e != hipSuccess) return fail(c, FDX_EHIP, "get_lists: %s", hipGetErrorString(e));
     }
+    return FDX_OK;
+    FDX_ABI_CATCH(c)
+}
+
+int fdx_set_list_capture(fdx_ctx *c, int32_t on) {
+    FDX_ABI_TRY
+    if (!c) return FDX_EINVAL;
+    c->capture_lists = on != 0;
     return FDX_OK;
     FDX_ABI_CATCH(c)
 }

@@ -95,6 +95,12 @@ struct fdx_ctx {
     fdx::DBuf<uint64_t> seg;
     uint64_t list_cap = 0;
 
+    // one-launch walk + force: cost per group, its prefix sums, the eight queue runs
+    fdx::DBuf<uint32_t> f_cost, f_bounds;
+    fdx::DBuf<uint64_t> f_pre;
+    bool capture_lists = false;    // FDX_FUSED: also store the lists (fdx_set_list_capture)
+    bool have_counts = false;      // cnt_e / cnt_s belong to the current groups
+
     // forces
     fdx::DBuf<double4> fs;
     fdx::DBuf<double> ax, ay, az, pot;
@@ -156,6 +162,8 @@ int enqueue_fill(fdx_ctx *c, size_t gmax, bool spill = false);
 // segments sized per system (sys_cap, device array indexed by system), no count walk
 int enqueue_sys_caps(fdx_ctx *c, size_t gmax, const uint32_t *sys_cap);
 int enqueue_force(fdx_ctx *c, size_t gmax);
+// walk + force in one launch, then the return of forces (capture: lists into c->list)
+int enqueue_fused(fdx_ctx *c, size_t gmax, bool capture);
 int ensure_list_capacity(fdx_ctx *c, uint64_t total);
 int setup_eval(fdx_ctx *c, double theta, int n_leaf, int n_group, double eps, int flags);
 void save_force_params(fdx_ctx *c);

@@ -376,6 +376,7 @@ int fdx_exchange_particles(fdx_ctx *c) {
     c->sys_off_h = d->dom_off;
     c->have_force = false;
     c->have_lists = false;
+    c->have_counts = false;
     c->gen++;
     ext_invalidate(c);
     c->stats = fdx_stats{};

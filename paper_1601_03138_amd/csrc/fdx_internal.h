@@ -228,6 +228,40 @@ hipError_t direct_forces(uint32_t nt, const uint32_t *targets, const double *x, 
                          const uint32_t *sysid, const int64_t *sys_off, double *out,
                          hipStream_t s);
 
+// walk + force in one persistent launch (k_fused.hip): each wave pops a group, walks it and
+// evaluates the entries in tiles of 64 as the walk emits them; no list is stored unless `list`
+// is given (then every group's entries are also written to its segment [seg, seg + cap):
+// particles from the front, superparticles from the back).  Groups come from eight per-XCD runs
+// [bounds[x], bounds[x+1]) in tree order, or, with order, from order[k] for k < *count.
+struct FusedArgs {
+    Groups g;
+    const uint4 *node;
+    const uint2 *link;
+    uint32_t ccap;
+    const double4 *jp;
+    const double *seps;
+    const double *mom;
+    double theta2;
+    const uint32_t *bounds;
+    const uint32_t *order;
+    const uint32_t *count;
+    uint32_t *cnt_e, *cnt_s;
+    const uint64_t *seg;
+    const uint32_t *cap;
+    uint32_t *list;
+    double4 *fs;
+    DevStatus *st;
+    int skip_wide;           // FP32 pass: groups flagged wide are left to an FP64 pass
+};
+constexpr int kFusedMaxGroup = 256;      // largest n_group the fused kernel takes
+// bounds[0..8] of the per-XCD runs at equal cumulative cost (members x exp(y) with predicted
+// ln lengths y, or members when y is null); cost: G words, pre: G + 1 words of scratch
+hipError_t fused_bounds(size_t gmax, const uint32_t *gcount, const float *y, uint32_t *cost,
+                        uint64_t *pre, uint32_t *bounds, uint64_t *partial, DevStatus *st,
+                        hipStream_t s);
+hipError_t fused(size_t gmax, const FusedArgs &a, bool fp32, bool quad, int n_group,
+                 hipStream_t s);
+
 hipError_t list_caps(size_t gmax, const uint32_t *cnt_e, const uint32_t *cnt_s, uint32_t *cap,
                      DevStatus *st, hipStream_t s);
 // lists out of their segments: epj[oe[g] ...] and spj[os[g] ...] (offsets exclusive sums)

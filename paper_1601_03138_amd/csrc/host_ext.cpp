@@ -64,10 +64,14 @@ static int capture_step(fdx_ctx *c, GraphState *g, double dt) {
                              dt, g->gs));
         int q = enqueue_keys_sort(c);
         if (!q) q = enqueue_tree_groups(c);
-        if (!q) q = g->sized ? enqueue_sys_caps(c, c->group_cap, g->sys_cap.p)
-                             : enqueue_count(c, c->group_cap);
-        if (!q) q = enqueue_fill(c, c->group_cap, g->sized);
-        if (!q) q = enqueue_force(c, c->group_cap);
+        if (c->flags & FDX_FUSED) {
+            if (!q) q = enqueue_fused(c, c->group_cap, false);
+        } else {
+            if (!q) q = g->sized ? enqueue_sys_caps(c, c->group_cap, g->sys_cap.p)
+                                 : enqueue_count(c, c->group_cap);
+            if (!q) q = enqueue_fill(c, c->group_cap, g->sized);
+            if (!q) q = enqueue_force(c, c->group_cap);
+        }
         if (q) return q;
         HIPCHK(c, kick(n, c->vx, c->vy, c->vz, c->ax.p, c->ay.p, c->az.p, dt, c->st, g->gs));
         return FDX_OK;
@@ -122,7 +126,7 @@ static int graph_headroom(fdx_ctx *c, GraphState *g) {
     const uint32_t ncell = c->hst->lvl[kLevels + 1];
     const int S = c->nsys;
     const uint64_t pct = c->ext.graph_margin_pct;
-    const bool try_sized = S > 1 && c->have_lists && pct > 0;
+    const bool try_sized = S > 1 && c->have_lists && pct > 0 && !(c->flags & FDX_FUSED);
     std::vector<uint32_t> st2;              // [longest list per system, groups per system]
     if (try_sized) {
         HIPCHK(c, g->lmax.ensure(2 * (size_t)S));
@@ -135,10 +139,17 @@ static int graph_headroom(fdx_ctx *c, GraphState *g) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     c->have_lists = false;                  // buffers may be reallocated below
+    c->have_counts = false;
     uint32_t ccap = std::max<uint32_t>(c->cell_cap, ncell + ncell / 4 + 1024);
     uint32_t gcap = std::max<uint32_t>(c->group_cap, h.n_groups + h.n_groups / 4 + 1024);
     int r = ensure_tree_buffers(c, ccap, gcap);
     if (r) return r;
+    if (c->flags & FDX_FUSED) {
+        // one walk + force launch: no list buffer; the predictor's buffers (if used) are sized
+        // now, outside the capture
+        g->sized = false;
+        return (c->flags & FDX_PREDICTOR) ? ext_predictor_reserve(c) : FDX_OK;
+    }
     uint64_t need = h.list_total;
     g->sized = false;
     if (try_sized) {
@@ -172,7 +183,10 @@ int ext_integrate_graph(fdx_ctx *c, double dt, int n_steps) {
     const int user_flags = c->flags;
     HIPCHK(c, hipStreamSynchronize(user));
     c->stream = g->gs;
-    c->flags = (user_flags | FDX_PERSISTENT) & ~(FDX_TIMING | FDX_PREDICTOR);
+    // the predicted walk reads its totals back on the host, so it is not captured; the fused
+    // launch uses the predictor on the device only and keeps it
+    c->flags = (user_flags | FDX_PERSISTENT) &
+               ~(FDX_TIMING | ((user_flags & FDX_FUSED) ? 0 : FDX_PREDICTOR));
     const size_t n = (size_t)c->n;
     int r = FDX_OK;
     for (int k = 0; k < n_steps && !r; k++) {
@@ -188,7 +202,9 @@ int ext_integrate_graph(fdx_ctx *c, double dt, int n_steps) {
         const DevStatus h = c->hst->st;
         c->ext.list_spills += h.spilled;
         if (h.bad_input) { r = fail(c, FDX_EINVAL, "non-finite particle data"); break; }
-        c->have_lists = true;                // the replay's lists (or the eager redo's)
+        // the replay's lists (or the eager redo's); the fused launch stores counts only
+        c->have_lists = !(c->flags & FDX_FUSED);
+        c->have_counts = true;
         if (status_incomplete(h)) {
             // positions and velocities hold kick + drift; redo force and kick eagerly
             r = run_tree(c, true);
@@ -296,9 +312,14 @@ int fdx_autotune(fdx_ctx *c, double theta, int32_t n_leaf, double eps, int32_t f
         bool clean = false;
         for (int v = 0; v < nv; v++)
             clean |= force_variant_capacity(v) >= n_group_cand[k] && !spills[v];
+        // the fused launch has no separate force-kernel shape: one timing per group size
+        const bool fused = (flags & FDX_FUSED) != 0;
         for (int v = 0; v < nv; v++) {
             double t = NAN;
-            if (force_variant_capacity(v) >= n_group_cand[k] && !(clean && spills[v])) {
+            const bool fits = fused ? (v == 0 && n_group_cand[k] <= kFusedMaxGroup)
+                                    : force_variant_capacity(v) >= n_group_cand[k] &&
+                                          !(clean && spills[v]);
+            if (fits) {
                 slot = v;
                 int r = fdx_calc_force(c, theta, n_leaf, n_group_cand[k], eps, flags);
                 if (!r && graph) r = fdx_integrate(c, 0.0, 1, FDX_GRAPH);     // capture

@@ -27,6 +27,10 @@ int ext_integrate_graph(fdx_ctx *c, double dt, int n_steps);
 void ext_release(fdx_ctx *c);
 void ext_invalidate(fdx_ctx *c);   // drop any captured graph (particles or buffers changed)
 int ext_predicted_walk(fdx_ctx *c, uint32_t G);
+// predicted ln list length of every group (features + network on the device, no host wait)
+int ext_predicted_lengths(fdx_ctx *c, size_t gmax, const float **y);
+// device buffers of ext_predicted_lengths for the current group capacity (before a capture)
+int ext_predictor_reserve(fdx_ctx *c);
 void exchange_release(fdx_ctx *c);
 void sph_release(fdx_ctx *c);
 void dd_release(fdx_ctx *c);

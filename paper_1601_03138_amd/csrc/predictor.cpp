@@ -135,6 +135,25 @@ int ext_predicted_walk(fdx_ctx *c, uint32_t G) {
     return FDX_OK;
 }
 
+int ext_predictor_reserve(fdx_ctx *c) {
+    Pred *p = pred_of(c);
+    if (!p->loaded) return fail(c, FDX_ESTATE, "FDX_PREDICTOR: no predictor trained or loaded");
+    HIPCHK(c, p->X.ensure((size_t)c->group_cap * kMlpIn));
+    HIPCHK(c, p->y.ensure(c->group_cap));
+    return FDX_OK;
+}
+
+int ext_predicted_lengths(fdx_ctx *c, size_t gmax, const float **y) {
+    const int r = ext_predictor_reserve(c);
+    if (r) return r;
+    Pred *p = pred_of(c);
+    HIPCHK(c, mlp_features(gmax, groups_view(c), cells_view(c), c->sys_off.p, p->mu.p, p->sd.p,
+                           p->X.p, c->st, c->stream));
+    HIPCHK(c, mlp_infer(gmax, &c->st->n_groups_c, p->X.p, p->P.p, p->y.p, c->stream));
+    *y = p->y.p;
+    return FDX_OK;
+}
+
 void predictor_release(fdx_ctx *c) {
     Pred *p = static_cast<Pred *>(c->ext.pred);
     if (!p) return;

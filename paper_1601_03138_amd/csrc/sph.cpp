@@ -113,6 +113,7 @@ int fdx_calc_density(fdx_ctx *c, int32_t mode, double r_cut, const double *h, in
     HIPCHK(c, walk_short(true, kind, G, gv, cv, sa, 0.0, c->seg.p, c->lcap.p, c->list_cap, c->list.p,
                          c->cnt_e.p, c->cnt_s.p, nullptr, c->st, s));
     c->have_lists = true;
+    c->have_counts = true;
     c->stats.list_capacity = (int64_t)hs.list_total;
     c->stats.overflow_groups = 0;
     HIPCHK(c, list_stats(G, gv, c->cnt_e.p, c->cnt_s.p, c->st, s));

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libfdx.so")
 
 OK, EINVAL, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4
 MEM_HOST, MEM_DEVICE = 0, 1
-QUAD, FP32REL, PREDICTOR, PERSISTENT, GRAPH, TIMING = 1, 2, 4, 8, 16, 32
+QUAD, FP32REL, PREDICTOR, PERSISTENT, GRAPH, TIMING, FUSED = 1, 2, 4, 8, 16, 32, 64
 CUT_FIXED, CUT_SCATTER, CUT_GATHER, CUT_SYMMETRIC = 0, 1, 2, 3
 DD_COST_LISTS = 1
 
@@ -33,7 +33,7 @@ EXPORTS = ["fdx_create", "fdx_destroy", "fdx_set_particles", "fdx_build_tree", "
            "fdx_calc_force_cutoff", "fdx_dd_factor", "fdx_decompose", "fdx_get_decomposition",
            "fdx_get_dd_samples", "fdx_get_dd_destinations", "fdx_exchange_particles",
            "fdx_get_dd_stats", "fdx_direct_forces", "fdx_autotune_cached",
-           "fdx_set_graph_list_margin", "fdx_calc_force_noalloc"]
+           "fdx_set_graph_list_margin", "fdx_calc_force_noalloc", "fdx_set_list_capture"]
 
 
 class FdxError(RuntimeError):
@@ -116,6 +116,7 @@ def _declare(L):
     L.fdx_autotune_shapes.argtypes = []
     L.fdx_set_shape.argtypes = [vp, i32]
     L.fdx_set_graph_list_margin.argtypes = [vp, i32]
+    L.fdx_set_list_capture.argtypes = [vp, i32]
     L.fdx_shape_name.argtypes = [i32]
     L.fdx_shape_name.restype = C.c_char_p
     L.fdx_autotune.argtypes = [vp, f64, i32, f64, i32, vp, i32, i32, vp, vp, vp]
@@ -231,9 +232,15 @@ class Context:
 
     # -- evaluation ------------------------------------------------------------------
     @staticmethod
-    def flags(quad=True, fp32=False, predictor=False, persistent=False, timing=False) -> int:
+    def flags(quad=True, fp32=False, predictor=False, persistent=False, timing=False,
+              fused=False) -> int:
         return ((QUAD if quad else 0) | (FP32REL if fp32 else 0) | (PREDICTOR if predictor else 0)
-                | (PERSISTENT if persistent else 0) | (TIMING if timing else 0))
+                | (PERSISTENT if persistent else 0) | (TIMING if timing else 0)
+                | (FUSED if fused else 0))
+
+    def set_list_capture(self, on: bool):
+        """FDX_FUSED evaluations also store the lists they evaluate (for checks)."""
+        self._check(self.lib.fdx_set_list_capture(self.h, 1 if on else 0), "set_list_capture")
 
     def build_tree(self, n_leaf: int = 8, n_group: int = 64):
         self._check(self.lib.fdx_build_tree(self.h, n_leaf, n_group), "build_tree")

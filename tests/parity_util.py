@@ -2,6 +2,7 @@
 import numpy as np
 
 import oracle as O
+from paper_1601_03138_amd import inputs as I
 
 # FP64 kernel vs the oracle tree (same lists, different summation order): recursive summation
 # of L terms errs by at most ~L u sum|t_j| with u = 2^-53.  With L <= 2e4 entries and the
@@ -106,3 +107,41 @@ def fp32_error_bound(t, g, lists, ref_sorted):
         with np.errstate(divide="ignore", invalid="ignore"):
             out[b:b + n] = np.where(amag > 0, term.sum(axis=1) / amag, np.inf)
     return out
+
+
+def _random_set(rng, kind, n, seed):
+    if kind == "plummer" or (kind == "clustered" and n < 400):
+        return I.plummer(n, seed=seed, eps=float(rng.uniform(1e-3, 0.05)))
+    if kind == "cube":
+        return I.uniform_cube(n, seed, float(rng.uniform(1e-3, 0.05)))
+    if kind == "clustered":
+        k = max(1, n // 400)
+        return I.clustered(n_background=n - k * 200, n_clusters=k, n_per_cluster=200, seed=seed,
+                           eps=float(rng.uniform(1e-3, 0.02)))
+    if kind == "lattice":                  # many coincident particles
+        q = rng.integers(-3, 4, size=(n, 3)).astype(np.float64) * 0.25
+        v = np.zeros((n, 3))
+        return I._pack(q, v, np.full(n, 1.0 / n), np.full(n, 0.05))
+    # two clumps 10^4 apart: a deep tree with a huge dynamic range
+    p = I.plummer(n, seed=seed, eps=0.01)
+    p.x[n // 2:] += 1.0e4
+    return p
+
+
+def random_case(seed):
+    """Seeded random configuration: one to three systems of ragged sizes drawn from Plummer,
+    uniform cube, clustered, coarse lattice (coincident particles) and two far-apart clumps,
+    with random n_leaf, n_group, theta and moment order."""
+    rng = np.random.default_rng(1000 + seed)
+    kinds = ["plummer", "cube", "clustered", "lattice", "clumps"]
+    n_sys = int(rng.integers(1, 4))
+    sets = []
+    for s in range(n_sys):
+        n = int(rng.choice([1, 2, int(rng.integers(3, 300)), int(rng.integers(300, 4000))]))
+        sets.append(_random_set(rng, kinds[int(rng.integers(0, len(kinds)))], n, seed * 10 + s))
+    ps = sets[0] if n_sys == 1 else I.concat(sets)
+    n_leaf = int(rng.choice([1, 2, 4, 8, 16, 32]))
+    n_group = int(rng.choice([1, 7, 64, 200, 512]))
+    theta = float(rng.uniform(0.2, 1.0))
+    quad = bool(rng.integers(0, 2))
+    return ps, n_leaf, n_group, theta, quad

@@ -16,8 +16,8 @@ import oracle as O
 from paper_1601_03138_amd import inputs as I
 
 from parity_util import (F32_RMS_REL_VS_TREE, F64_MAX_REL, F64_RMS_REL, check_groups,
-                         check_lists, check_moments, check_tree, fp32_error_bound, rel_err,
-                         tree_ref)
+                         check_lists, check_moments, check_tree, fp32_error_bound, random_case,
+                         rel_err, tree_ref)
 
 pytestmark = pytest.mark.gpu
 
@@ -35,44 +35,9 @@ def ctx():
     c.close()
 
 
-def _one(rng, kind, n, seed):
-    if kind == "plummer" or (kind == "clustered" and n < 400):
-        return I.plummer(n, seed=seed, eps=float(rng.uniform(1e-3, 0.05)))
-    if kind == "cube":
-        return I.uniform_cube(n, seed, float(rng.uniform(1e-3, 0.05)))
-    if kind == "clustered":
-        k = max(1, n // 400)
-        return I.clustered(n_background=n - k * 200, n_clusters=k, n_per_cluster=200, seed=seed,
-                           eps=float(rng.uniform(1e-3, 0.02)))
-    if kind == "lattice":                  # many coincident particles
-        q = rng.integers(-3, 4, size=(n, 3)).astype(np.float64) * 0.25
-        v = np.zeros((n, 3))
-        return I._pack(q, v, np.full(n, 1.0 / n), np.full(n, 0.05))
-    # two clumps 10^4 apart: a deep tree with a huge dynamic range
-    p = I.plummer(n, seed=seed, eps=0.01)
-    p.x[n // 2:] += 1.0e4
-    return p
-
-
-def _case(seed):
-    rng = np.random.default_rng(1000 + seed)
-    kinds = ["plummer", "cube", "clustered", "lattice", "clumps"]
-    n_sys = int(rng.integers(1, 4))
-    sets = []
-    for s in range(n_sys):
-        n = int(rng.choice([1, 2, int(rng.integers(3, 300)), int(rng.integers(300, 4000))]))
-        sets.append(_one(rng, kinds[int(rng.integers(0, len(kinds)))], n, seed * 10 + s))
-    ps = sets[0] if n_sys == 1 else I.concat(sets)
-    n_leaf = int(rng.choice([1, 2, 4, 8, 16, 32]))
-    n_group = int(rng.choice([1, 7, 64, 200, 512]))
-    theta = float(rng.uniform(0.2, 1.0))
-    quad = bool(rng.integers(0, 2))
-    return ps, n_leaf, n_group, theta, quad
-
-
 @pytest.mark.parametrize("seed", range(24))
 def test_random_configuration(ctx, seed):
-    ps, n_leaf, n_group, theta, quad = _case(seed)
+    ps, n_leaf, n_group, theta, quad = random_case(seed)
     _say(f"[random {seed}] n={ps.n} sys={ps.n_sys} leaf={n_leaf} group={n_group} "
          f"theta={theta:.3f} quad={quad}")
     t, g, lists = tree_ref(ps, n_leaf, n_group, theta)
