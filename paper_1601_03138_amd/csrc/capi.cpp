@@ -247,6 +247,15 @@ int enqueue_force(fdx_ctx *c, size_t gmax) {
     const size_t n = (size_t)c->n;
     Groups gv = groups_view(c);
     HIPCHK(c, list_stats(gmax, gv, c->cnt_e.p, c->cnt_s.p, c->st, s));
+    const bool persistent = (c->flags & FDX_PERSISTENT) != 0;
+    if (persistent)
+        // the eight per-XCD runs cut at equal cost from the walk's exact counts: members x
+        // (|EPJ| + w |SPJ|), w = a superparticle's cost in particle terms (the inner loops issue
+        // 34.5 / 14.25 instructions per quadrupole / particle interaction; a monopole costs
+        // about as much as a particle)
+        HIPCHK(c, queue_bounds(gmax, gv.count, nullptr, c->cnt_e.p, c->cnt_s.p,
+                               (c->flags & FDX_QUAD) ? 2.4f : 1.0f, c->f_cost.p, c->f_pre.p,
+                               c->f_bounds.p, c->partial.p, c->st, s));
     mark(c, 6);
     ForceArgs fa;
     fa.g = &gv; fa.jp = c->jp.p; fa.seps = c->seps.p; fa.mom = c->c_mom.p;
@@ -254,7 +263,8 @@ int enqueue_force(fdx_ctx *c, size_t gmax) {
     fa.list = c->list.p; fa.order = nullptr; fa.fs = c->fs.p; fa.st = c->st;
     fa.quad = (c->flags & FDX_QUAD) != 0;
     fa.fp32 = (c->flags & FDX_FP32REL) != 0;
-    fa.persistent = (c->flags & FDX_PERSISTENT) != 0;
+    fa.persistent = persistent;
+    fa.bounds = persistent ? c->f_bounds.p : nullptr;
     fa.variant = ext_force_variant(c);
     fa.r_cut = c->cutoff;
     HIPCHK(c, force(gmax, fa, s));
@@ -288,8 +298,8 @@ int enqueue_fused(fdx_ctx *c, size_t gmax, bool capture) {
         const int r = ext_predicted_lengths(c, gmax, &y);
         if (r) return r;
     }
-    HIPCHK(c, fused_bounds(gmax, gv.count, y, c->f_cost.p, c->f_pre.p, c->f_bounds.p,
-                           c->partial.p, c->st, s));
+    HIPCHK(c, queue_bounds(gmax, gv.count, y, nullptr, nullptr, 0.0f, c->f_cost.p, c->f_pre.p,
+                           c->f_bounds.p, c->partial.p, c->st, s));
     mark(c, 6);
     FusedArgs fa{};
     fa.g = gv;
@@ -517,25 +527,7 @@ int fdx_destroy(fdx_ctx *c) {
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     ext_release(c);
-    for (auto *b : {&c->ox, &c->oy, &c->oz, &c->ovx, &c->ovy, &c->ovz, &c->om, &c->oeps, &c->cube,
-                    &c->seps, &c->c_mom, &c->g_centre, &c->ax, &c->ay, &c->az, &c->pot})
-        b->release();
-    for (auto *b : {&c->sysid, &c->perm, &c->perm_alt, &c->inv, &c->rs_scratch, &c->c_level,
-                    &c->c_begin, &c->c_count, &c->c_first, &c->c_nchild, &c->c_parent, &c->c_lvl,
-                    &c->tmp_n, &c->tmp_off, &c->g_cell, &c->g_begin, &c->g_count, &c->g_sys,
-                    &c->g_box, &c->flag, &c->gcell_at, &c->gpos, &c->cnt_e, &c->cnt_s, &c->lcap,
-                    &c->list, &c->ovf_list, &c->g_wide, &c->wide_list})
-        b->release();
-    c->leaf_lev.release();
-    c->sys_carry.release();
-    for (auto *b : {&c->bbox_u, &c->key, &c->key_alt, &c->partial, &c->c_prefix, &c->seg})
-        b->release();
-    c->sys_off.release();
-    c->jp.release();
-    c->packed.release();
-    c->fs.release();
-    c->c_node.release();
-    c->c_link.release();
+    c->each_buffer([](auto &b) { b.release(); });
     if (c->st) (void)hipFree(c->st);
     if (c->hst) (void)hipHostFree(c->hst);
     for (auto &e : c->ev)

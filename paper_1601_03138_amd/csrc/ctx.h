@@ -127,6 +127,24 @@ struct fdx_ctx {
     bool predict_marked = false;   // event 9 holds the end of the predictor's network
 
     fdx::HostExt ext;   // predictor, autotuner, graph state
+
+    // every device buffer of the context (fdx_destroy frees them; the no-allocation entry
+    // point marks them fixed so that a buffer it did not carve fails instead of allocating)
+    template <class F>
+    void each_buffer(F f) {
+        f(ox); f(oy); f(oz); f(ovx); f(ovy); f(ovz); f(om); f(oeps);
+        f(sys_off); f(sysid);
+        f(bbox_u); f(key); f(key_alt); f(cube);
+        f(perm); f(perm_alt); f(inv); f(rs_scratch); f(sys_carry); f(partial);
+        f(jp); f(packed); f(seps);
+        f(c_level); f(c_begin); f(c_count); f(c_first); f(c_nchild); f(c_parent); f(c_lvl);
+        f(c_prefix); f(c_node); f(c_link); f(c_mom); f(tmp_n); f(tmp_off);
+        f(g_cell); f(g_begin); f(g_count); f(g_sys); f(g_box); f(flag); f(gcell_at); f(gpos);
+        f(g_wide); f(wide_list); f(leaf_lev); f(g_centre);
+        f(cnt_e); f(cnt_s); f(lcap); f(list); f(ovf_list); f(seg);
+        f(f_cost); f(f_bounds); f(f_pre);
+        f(fs); f(ax); f(ay); f(az); f(pot);
+    }
     // bumped by every fdx_set_particles and every reallocation of a buffer a captured graph
     // refers to; a graph captured under another generation is never replayed
     uint64_t gen = 0;

@@ -254,9 +254,11 @@ struct FusedArgs {
     int skip_wide;           // FP32 pass: groups flagged wide are left to an FP64 pass
 };
 constexpr int kFusedMaxGroup = 256;      // largest n_group the fused kernel takes
-// bounds[0..8] of the per-XCD runs at equal cumulative cost (members x exp(y) with predicted
-// ln lengths y, or members when y is null); cost: G words, pre: G + 1 words of scratch
-hipError_t fused_bounds(size_t gmax, const uint32_t *gcount, const float *y, uint32_t *cost,
+// bounds[0..8] of the eight per-XCD runs of groups (tree order) at equal cumulative cost:
+// members x (|EPJ| + ws |SPJ|) with the walk's counts (cnt_e, cnt_s), else members x exp(y)
+// with predicted ln lengths y, else members; cost: G words, pre: G + 1 words of scratch
+hipError_t queue_bounds(size_t gmax, const uint32_t *gcount, const float *y,
+                        const uint32_t *cnt_e, const uint32_t *cnt_s, float ws, uint32_t *cost,
                         uint64_t *pre, uint32_t *bounds, uint64_t *partial, DevStatus *st,
                         hipStream_t s);
 hipError_t fused(size_t gmax, const FusedArgs &a, bool fp32, bool quad, int n_group,
@@ -290,6 +292,8 @@ struct ForceArgs {
     const uint32_t *cap, *cnt_e, *cnt_s;
     const uint32_t *list;   // interaction list segments
     const uint32_t *order;  // queue order (null: group order)
+    const uint32_t *bounds = nullptr;  // persistent launch: the eight per-XCD runs (null: equal
+                                       // group counts)
     double4 *fs;            // sorted output {ax, ay, az, phi}
     DevStatus *st;
     bool quad, fp32, persistent;

@@ -43,6 +43,7 @@ struct KArgs {
     const uint64_t *seg;
     const uint32_t *cap, *cnt_e, *cnt_s, *list;
     const uint32_t *order;
+    const uint32_t *bounds;  // persistent: per-XCD runs [bounds[x], bounds[x+1]) (or null)
     const uint32_t *ngroups;
     double4 *fs;
     DevStatus *st;
@@ -261,7 +262,8 @@ k_force_direct(KArgs a) {
 }
 
 // Persistent variant: a fixed grid pops work from device counters.  Without an explicit list
-// the groups are split into eight contiguous runs in tree order, one queue per XCD
+// the groups are split into eight contiguous runs in tree order (at equal cumulative cost when
+// bounds are given, else of equal group counts), one queue per XCD
 // (consecutive workgroups are dispatched round-robin over the 8 XCDs, so workgroup b runs on
 // XCD b % 8); a workgroup pops from its own XCD's queue, keeping neighbouring groups -- which
 // share most of their lists -- in one L2, and once that queue is empty takes slots from the
@@ -281,7 +283,8 @@ k_force_persistent(KArgs a) {
             } else {
                 for (uint32_t t = 0; t < 8u && slot == kNone; t++) {
                     const uint32_t q = (x + t) & 7u;
-                    const uint32_t lo = q * chunk, hi = min(G, lo + chunk);
+                    const uint32_t lo = a.bounds ? a.bounds[q] : q * chunk;
+                    const uint32_t hi = a.bounds ? a.bounds[q + 1] : min(G, lo + chunk);
                     if (lo >= hi) continue;
                     const uint32_t k = atomicAdd(&a.st->xcd_head[q], 1u);
                     if (k < hi - lo) slot = lo + k;
@@ -395,7 +398,8 @@ hipError_t force(size_t G, const ForceArgs &fa, hipStream_t s) {
     k.jp = fa.jp; k.seps = fa.seps; k.mom = fa.mom;
     k.seg = fa.seg; k.cap = fa.cap; k.cnt_e = fa.cnt_e; k.cnt_s = fa.cnt_s;
     k.list = fa.list;
-    k.order = fa.order; k.ngroups = fa.count ? fa.count : &fa.st->n_groups_c;
+    k.order = fa.order; k.bounds = fa.bounds;
+    k.ngroups = fa.count ? fa.count : &fa.st->n_groups_c;
     k.fs = fa.fs; k.st = fa.st;
     k.G = (uint32_t)G;
     k.cut_s = fa.r_cut > 0 ? 2.0 / fa.r_cut : 0.0;

@@ -80,7 +80,7 @@ __device__ __forceinline__ void eval_tile(const WaveMem<T> &wm, bool spj_tile, u
         }
     } else {
         const V *run = wm.u.t + 3 * slice * kmain;
-#pragma unroll 2
+#pragma unroll 1
         for (uint32_t q = 0; q < kmain; q++) {
             const V A = run[3 * q];
             V B, C;
@@ -383,8 +383,10 @@ __device__ __forceinline__ uint32_t best_ipl(uint32_t ni, int iplmax) {
     return f2 >= f4 ? 2u : 4u;
 }
 
+// FP32 with up to two i-particles per lane: register budget held to 96, five waves per SIMD
+// (the LDS of five workgroups fits a CU); measured 2-4 % faster than four waves per SIMD
 template <class T, bool QUAD, int IPLMAX>
-__global__ void __launch_bounds__(kFT)
+__global__ void __launch_bounds__(kFT, (sizeof(T) == 4 && IPLMAX == 2) ? 5 : 1)
 k_fused(FusedArgs a) {
     __shared__ WaveMem<T> wmem[kFW];
     WaveMem<T> &wm = wmem[threadIdx.x / kWave];
@@ -428,14 +430,16 @@ k_fused(FusedArgs a) {
     }
 }
 
-// cost of every group for the queue runs: members x predicted list length (y = predicted
-// ln length) or members
-__global__ void k_fused_cost(const uint32_t *ngroups_c, const uint32_t *gcount, const float *y,
+// cost of every group for the queue runs: members x (|EPJ| + ws |SPJ|) from the walk's exact
+// counts, or members x predicted list length (y = predicted ln length), or members
+__global__ void k_queue_cost(const uint32_t *ngroups_c, const uint32_t *gcount, const float *y,
+                             const uint32_t *cnt_e, const uint32_t *cnt_s, float ws,
                              uint32_t *cost) {
     const uint32_t G = *ngroups_c;
     for (size_t gi = gtid(); gi < G; gi += gstride()) {
         float c = (float)gcount[gi];
-        if (y) c *= ceilf(__expf(fminf(y[gi], 20.0f)));
+        if (cnt_e) c *= (float)cnt_e[gi] + ws * (float)cnt_s[gi];
+        else if (y) c *= ceilf(__expf(fminf(y[gi], 20.0f)));
         cost[gi] = (uint32_t)fminf(fmaxf(c, 1.0f), 4.0e9f);
     }
 }
@@ -476,13 +480,14 @@ hipError_t launch_fused(const FusedArgs &a, size_t gmax, hipStream_t s) {
 
 }  // namespace
 
-hipError_t fused_bounds(size_t gmax, const uint32_t *gcount, const float *y, uint32_t *cost,
+hipError_t queue_bounds(size_t gmax, const uint32_t *gcount, const float *y,
+                        const uint32_t *cnt_e, const uint32_t *cnt_s, float ws, uint32_t *cost,
                         uint64_t *pre, uint32_t *bounds, uint64_t *partial, DevStatus *st,
                         hipStream_t s) {
     size_t b = (gmax + 255) / 256;
     b = b < 1 ? 1 : (b > 4096 ? 4096 : b);
-    hipLaunchKernelGGL(k_fused_cost, dim3((unsigned)b), dim3(256), 0, s, &st->n_groups_c, gcount,
-                       y, cost);
+    hipLaunchKernelGGL(k_queue_cost, dim3((unsigned)b), dim3(256), 0, s, &st->n_groups_c, gcount,
+                       y, cnt_e, cnt_s, ws, cost);
     hipError_t e = scan_u32_to_u64(cost, pre, 0, nullptr, &st->n_groups_c, partial, pre + gmax, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fused_bounds, dim3(1), dim3(64), 0, s, &st->n_groups_c, pre, pre + gmax,

@@ -178,6 +178,8 @@ int fdx_calc_force_noalloc(int device, void *hip_stream, int64_t n, const double
     cv.take(c.g_centre, 3 * (size_t)gcap); cv.take(c.g_wide, gcap); cv.take(c.wide_list, gcap);
     cv.take(c.cnt_e, gcap); cv.take(c.cnt_s, gcap); cv.take(c.lcap, gcap);
     cv.take(c.seg, (size_t)gcap + 1); cv.take(c.ovf_list, gcap);
+    // per-XCD queue runs of the persistent force kernel
+    cv.take(c.f_cost, gcap); cv.take(c.f_pre, (size_t)gcap + 1); cv.take(c.f_bounds, 9);
     c.group_cap = gcap;
     // interaction lists: the rest of the array
     uint64_t list_room = 0;
@@ -191,7 +193,9 @@ int fdx_calc_force_noalloc(int device, void *hip_stream, int64_t n, const double
     // outputs: the caller's arrays
     c.ax.p = ax; c.ay.p = ay; c.az.p = az; c.pot.p = pot;
     c.ax.cap = c.ay.cap = c.az.cap = c.pot.cap = N;
-    c.ax.fixed = c.ay.fixed = c.az.fixed = c.pot.fixed = true;
+    // every other buffer stays empty and fixed: growing one fails (FDX_ENOMEM) instead of
+    // allocating
+    c.each_buffer([](auto &b) { b.fixed = true; });
 
     const auto hip_fail = [&](hipError_t e, const char *what) {
         snprintf(msg, sizeof msg, "%s: %s", what, hipGetErrorString(e));
