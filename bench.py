@@ -105,42 +105,72 @@ def rms_rel_error(a, a_ref) -> float:
     return float(math.sqrt(np.mean(d / r)))
 
 
-def autotune(ctx, theta, quad, persistent, graph=False):
-    """n_group in {64, 128, 256, 512} x every force-kernel shape, full evaluations (graph:
-    graph-captured steps of dt = 0) timed by the library's autotuner (the median of 2 after one
-    untimed); its choice stays set in ctx."""
+def autotune(ctx, theta, quad, persistent, graph=False, fused=False):
+    """n_group in {64, 128, 256, 512} x every force-kernel shape (the fused launch: n_group up to
+    256, one timing each), full evaluations (graph: graph-captured steps of dt = 0) timed by the
+    library's autotuner (the median of 3 after one untimed; shapes that spill registers are not
+    timed); its choice stays set in ctx."""
     from paper_1601_03138_amd import fdx
-    cand = [64, 128, 256, 512]
-    flags = fdx.Context.flags(quad=quad, fp32=True, persistent=persistent)
+    cand = [64, 128, 256] if fused else [64, 128, 256, 512]
+    flags = fdx.Context.flags(quad=quad, fp32=True, persistent=persistent, fused=fused)
     if graph:
         flags |= fdx.GRAPH
-    bg, bv, times = ctx.autotune(theta, 8, 0.0, flags, cand, reps=2)
+    bg, bv, times = ctx.autotune(theta, 8, 0.0, flags, cand, reps=3)
     return {"n_group": bg, "shape": bv, "shape_name": ctx.shape_name(bv), "candidates": cand,
             "ms": [[None if np.isnan(v) else round(float(v), 3) for v in row] for row in times]}
 
 
-def cpu_baseline(ps, n_group, theta, quad, n_sample_groups, seed=7):
+def cpu_model() -> str:
+    """The host CPU's model name (as lscpu prints it), from /proc/cpuinfo."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(ps, n_group, theta, quad, n_sample_groups, n_sample_groups_1t=64, seed=7):
     """The oracle as it stands (FP64 serial tree, OpenMP over groups): the full tree build of
     the workload plus the walk and force of a random sample of groups, scaled to one whole
-    force evaluation."""
+    force evaluation -- on all the threads OpenMP is given, and once more single-threaded (a
+    smaller sample of groups)."""
     import oracle as O
-    t0 = time.perf_counter()
-    tr = O.build_tree(ps, 8)
-    g = O.make_groups(tr, n_group)
-    t1 = time.perf_counter()
-    rng = np.random.default_rng(seed)
-    k = min(n_sample_groups, g.n)
-    sel = np.sort(rng.choice(g.n, k, replace=False))
-    lists = O.walk(tr, g, theta, sel)
-    lists.force(quad)
-    t2 = time.perf_counter()
-    t_eval = (t1 - t0) + (t2 - t1) * g.n / k
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+    def one(k_groups):
+        t0 = time.perf_counter()
+        tr = O.build_tree(ps, 8)
+        g = O.make_groups(tr, n_group)
+        t1 = time.perf_counter()
+        rng = np.random.default_rng(seed)
+        k = min(k_groups, g.n)
+        sel = np.sort(rng.choice(g.n, k, replace=False))
+        lists = O.walk(tr, g, theta, sel)
+        lists.force(quad)
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1, k, g.n
+
+    threads = O.set_threads(0)
+    tb, tw, k, G = one(n_sample_groups)
+    t_eval = tb + tw * G / k
+    O.set_threads(1)
+    try:
+        tb1, tw1, k1, _ = one(n_sample_groups_1t)
+    finally:
+        O.set_threads(threads)
+    t_eval1 = tb1 + tw1 * G / k1
     return {"value": ps.n / t_eval, "unit": "particles/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 oracle tree: full build of all {ps.n} particles "
-                      f"({t1 - t0:.1f} s) + walk and force of {k} random groups of {g.n} "
-                      f"({t2 - t1:.2f} s), scaled to all groups; est. {t_eval:.0f} s per "
-                      f"force evaluation"}
+            "cpu_model": cpu_model(),
+            "sample": f"FP64 oracle tree on {threads} threads: full build of all {ps.n} "
+                      f"particles ({tb:.1f} s) + walk and force of {k} random groups of {G} "
+                      f"({tw:.2f} s), scaled to all groups; est. {t_eval:.0f} s per force "
+                      f"evaluation",
+            "single_thread": {"value": ps.n / t_eval1, "unit": "particles/s", "cores": 1,
+                              "sample": f"full build ({tb1:.1f} s) + walk and force of {k1} "
+                                        f"random groups ({tw1:.2f} s), scaled to all "
+                                        f"groups; est. {t_eval1:.0f} s per force "
+                                        f"evaluation"}}
 
 
 def system_energies(ps, ctx):
@@ -199,9 +229,10 @@ def main():
     ap.add_argument("--treepm-log2n", type=int, default=24,
                     help="also time the tree part of TreePM (uniform cube of 2^k particles, cutoff "
                          "of three mesh widths; 0: skip)")
-    ap.add_argument("--ensemble-steps", type=int, default=10,
-                    help="also time the batched ensemble (512 Plummer systems, persistent force, "
-                         "graph-captured steps) for this many steps (0: skip)")
+    ap.add_argument("--ensemble-steps", type=int, default=100,
+                    help="also time the batched ensemble (512 Plummer systems, graph-captured "
+                         "steps; one walk + force launch, and walk then force) for this many "
+                         "steps (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -444,53 +475,77 @@ def main():
         del sps
         log(f"[bench] sph: {sph}")
 
-    # batched ensemble: 512 independent Plummer systems in one persistent force launch, steps
-    # captured as a HIP graph; FP32 group-relative and FP64 against direct summation
+    # batched ensemble: 512 independent Plummer systems, steps captured as a HIP graph; the walk
+    # and force of all systems in one persistent launch (FDX_FUSED), and beside it the walk
+    # launch followed by the persistent force launch; FP32 group-relative and FP64 against
+    # direct summation; per-system energy drift over the graph-replayed steps
     ens = None
     if args.ensemble_steps > 0 and args.workload != "ensemble512":
-        eg, eth, equad, edt = WORKLOADS["ensemble512"]
+        eg0, eth, equad, edt = WORKLOADS["ensemble512"]
         eps_ = inputs.workload("ensemble512")
         ce = fdx.Context(0)
         ce.set_particles(eps_)
-        etuned = None
-        if not args.no_autotune:
-            etuned = autotune(ce, eth, equad, True, graph=True)
-            eg = etuned["n_group"]
-            log(f"[bench] ensemble autotune: n_group={eg} shape={etuned['shape_name']}")
-        f32 = fdx.Context.flags(quad=equad, fp32=True, persistent=True)
-        ce.calc_force_flags(eth, 8, eg, 0.0, f32)
-        for _ in range(2):
-            ce.integrate(edt, 1, graph=True)
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        for _ in range(args.ensemble_steps):
-            ce.integrate(edt, 1, graph=True)
-        torch.cuda.synchronize()
-        ms_graph = (time.perf_counter() - ta) * 1e3 / args.ensemble_steps
-        recoveries = int(ce.stats()["graph_recoveries"])
         sub = inputs.subset(eps_.n, min(args.accuracy_subset, eps_.n), seed=103)
         d = ce.direct_forces(sub)
-        ce.calc_force_flags(eth, 8, eg, 0.0, f32 | fdx.TIMING)
-        e32 = rms_rel_error(ce.forces()[sub], d)
-        t32 = ce.stats()["t_total"]
-        f64 = fdx.Context.flags(quad=equad, fp32=False, persistent=True, timing=True)
-        ce.calc_force_flags(eth, 8, eg, 0.0, f64)
-        ce.calc_force_flags(eth, 8, eg, 0.0, f64)
-        t64 = ce.stats()["t_total"]
-        e64 = rms_rel_error(ce.forces()[sub], d)
-        ens = {"n": eps_.n, "systems": eps_.n_sys, "theta": eth, "n_group": eg,
-               "steps_graph": args.ensemble_steps, "ms_per_step_graph": round(ms_graph, 3),
-               "particles_per_s_graph": float(round(eps_.n / (ms_graph / 1e3), -5)),
-               "ms_per_eval_fp32": round(float(t32), 3), "ms_per_eval_fp64": round(float(t64), 3),
-               "particles_per_s_fp64": float(round(eps_.n / (t64 / 1e3), -5)),
-               "rms_da_over_a_fp32": e32, "rms_da_over_a_fp64": e64,
+        ens = {"n": eps_.n, "systems": eps_.n_sys, "theta": eth, "steps_graph": args.ensemble_steps,
                "accuracy_subset": f"{len(sub)} particles, seed 103, FP64 direct sum within each "
-                                  "system",
-               "graph_recoveries": recoveries,
-               "autotune": etuned and {k: etuned[k] for k in ("n_group", "shape_name")}}
+                                  "system"}
+        for mode in ("fused", "separate"):
+            fused = mode == "fused"
+            eg, etuned = eg0, None
+            if not args.no_autotune:
+                etuned = autotune(ce, eth, equad, True, graph=True, fused=fused)
+                eg = etuned["n_group"]
+                log(f"[bench] ensemble ({mode}) autotune: n_group={eg} shape={etuned['shape_name']}")
+            f32 = fdx.Context.flags(quad=equad, fp32=True, persistent=True, fused=fused)
+            ce.set_particles(eps_)
+            ce.calc_force_flags(eth, 8, eg, 0.0, f32)
+            for _ in range(2):
+                ce.integrate(edt, 1, graph=True)
+            e_start = system_energies(eps_, ce)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            ce.integrate(edt, args.ensemble_steps, graph=True)
+            torch.cuda.synchronize()
+            ms_graph = (time.perf_counter() - ta) * 1e3 / args.ensemble_steps
+            e_end = system_energies(eps_, ce)
+            drift = np.abs((e_end - e_start) / e_start)
+            recoveries = int(ce.stats()["graph_recoveries"])
+            # kernel timing, accuracy and the FP64 path on the initial particles
+            ce.set_particles(eps_)
+            tf, fl32 = [], []
+            for _ in range(3):
+                ce.calc_force_flags(eth, 8, eg, 0.0, f32 | fdx.TIMING)
+                st_ = ce.stats()
+                tf.append(st_["t_force"] + st_["t_walk"])
+                fl32.append(force_flops(st_, equad))
+            t32 = ce.stats()["t_total"]
+            e32 = rms_rel_error(ce.forces()[sub], d)
+            f64 = fdx.Context.flags(quad=equad, fp32=False, persistent=True, timing=True,
+                                    fused=fused)
+            ce.calc_force_flags(eth, 8, eg, 0.0, f64)
+            ce.calc_force_flags(eth, 8, eg, 0.0, f64)
+            t64 = ce.stats()["t_total"]
+            e64 = rms_rel_error(ce.forces()[sub], d)
+            kms = float(np.median(tf))
+            ens[mode] = {
+                "launch": ("one walk + force launch (FDX_FUSED)" if fused else
+                           "walk launch, then persistent force launch"),
+                "n_group": eg, "ms_per_step_graph": round(ms_graph, 3),
+                "particles_per_s_graph": float(round(eps_.n / (ms_graph / 1e3), -5)),
+                "walk_plus_force_ms": round(kms, 3),
+                "walk_plus_force_tflops": round(float(np.mean(fl32)) / (kms / 1e3) / 1e12, 2),
+                "ms_per_eval_fp32": round(float(t32), 3), "ms_per_eval_fp64": round(float(t64), 3),
+                "particles_per_s_fp64": float(round(eps_.n / (t64 / 1e3), -5)),
+                "rms_da_over_a_fp32": e32, "rms_da_over_a_fp64": e64,
+                "energy_drift_per_system": {"max": float(drift.max()),
+                                            "median": float(np.median(drift)),
+                                            "steps": args.ensemble_steps},
+                "graph_recoveries": recoveries,
+                "autotune": etuned and {k: etuned[k] for k in ("n_group", "shape_name")}}
+            log(f"[bench] ensemble ({mode}): {ens[mode]}")
         ce.close()
         del eps_
-        log(f"[bench] ensemble: {ens}")
 
     # tree part of TreePM: monopole tree with the S2 cutoff, FP32 group-relative
     treepm = None

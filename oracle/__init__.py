@@ -46,6 +46,8 @@ def _p(a):
 def _declare(L):
     vp, i64, i32, f64 = C.c_void_p, C.c_int64, C.c_int32, C.c_double
     L.or_direct.argtypes = [i64, i64, vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp]
+    L.or_set_threads.argtypes = [C.c_int]
+    L.or_set_threads.restype = C.c_int
     L.or_keys.argtypes = [i64, vp, vp, vp, vp, vp, vp]
     L.or_interleave.argtypes = [C.c_uint32] * 3
     L.or_interleave.restype = C.c_uint64
@@ -100,6 +102,11 @@ def _c(a, dt):
 
 # ----------------------------------------------------------------------------------------
 # O-D
+def set_threads(n: int) -> int:
+    """Threads of the oracle's OpenMP loops from now on; returns the previous maximum."""
+    return int(lib().or_set_threads(int(n)))
+
+
 def direct(ps, targets=None) -> np.ndarray:
     """Direct-sum {ax, ay, az, phi} on the target particles (user indices), each against the
     particles of its own system only.  Returns an array [len(targets), 4]."""

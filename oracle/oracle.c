@@ -27,9 +27,18 @@
  * product and sum below is rounded exactly as written).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Threads of the OpenMP loops (for timing the oracle single-threaded); returns the previous
+ * maximum. */
+int or_set_threads(int n) {
+    const int prev = omp_get_max_threads();
+    if (n > 0) omp_set_num_threads(n);
+    return prev;
+}
 
 #define OR_LEVELS 21            /* bits per axis of a key; deepest cell level */
 #define OR_NONE 0xFFFFFFFFu

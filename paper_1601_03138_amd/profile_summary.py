@@ -8,6 +8,11 @@
       same counters read for a plain streaming kernel of known size
   python -m paper_1601_03138_amd.profile_summary sq DIR --kernel REGEX
       SQ counters per dispatch of the matching kernel
+  python -m paper_1601_03138_amd.profile_summary phases TRACE_DIR FETCH_DIR WRITE_DIR
+      --n N --cells C --groups G --entries E --calib REGEX --calib-read B --calib-write B
+      per kernel of the force evaluation: dispatches per step, median duration (kernel trace),
+      HBM bytes per dispatch from FETCH_SIZE and WRITE_SIZE (scaled as for pmc), the bytes the
+      kernel's algorithm must move (ALGO_BYTES below) and both as GB/s
 """
 from __future__ import annotations
 
@@ -92,6 +97,87 @@ def sq(path, kernel):
     return "\n".join(out)
 
 
+# Bytes each kernel of the path must move once per dispatch (N particles, C cells, G groups,
+# E interaction-list entries): the arrays it reads and writes, each counted once.
+ALGO_BYTES = [
+    # (kernel regex, what, bytes per dispatch)
+    (r"^k_bbox\b", "read x, y, z", lambda N, C, G, E: 24 * N),
+    (r"^k_keys\b", "read x, y, z; write key, index", lambda N, C, G, E: 36 * N),
+    (r"^k_pack\b", "read x, y, z, m; write (x, y, z, m)", lambda N, C, G, E: 64 * N),
+    (r"^void k_rs_hist", "read key (one 8-bit pass)", lambda N, C, G, E: 8 * N),
+    (r"^void k_rs_scatter", "read and write key + index (one pass)", lambda N, C, G, E: 24 * N),
+    (r"^k_gather_sorted\b", "read index, record, eps; write record, eps, inverse",
+     lambda N, C, G, E: 88 * N),
+    (r"^k_cells_prefix\b", "read keys; write two bytes per position", lambda N, C, G, E: 10 * N),
+    (r"^void k_cells_count|^k_cells_count\b", "read two bytes, write one per position",
+     lambda N, C, G, E: 3 * N),
+    (r"^k_cells_emit\b", "read keys + three bytes per position; write 20 B per cell",
+     lambda N, C, G, E: 11 * N + 20 * C),
+    (r"^k_cells_finish\b", "read 20 B, write 36 B per cell", lambda N, C, G, E: 56 * C),
+    (r"^k_moments\b", "all levels: write 80 B per cell, read 80 B per child and 32 B per "
+     "particle", lambda N, C, G, E: 160 * C + 32 * N),
+    (r"^k_group_flags\b", "read counts, write flags per cell", lambda N, C, G, E: 12 * C),
+    (r"^k_leaf_level\b", "write a byte per particle", lambda N, C, G, E: 1 * N),
+    (r"^void k_group_geom|^k_group_geom\b", "read member keys; write box and centre per group",
+     lambda N, C, G, E: 8 * N + 48 * G),
+    (r"^void k_walk<true, 0>", "write 4 B per list entry", lambda N, C, G, E: 4 * E),
+    (r"^k_unsort\b", "read inverse, result; write four arrays", lambda N, C, G, E: 68 * N),
+    (r"^k_kick_drift\b", "read x, v, a; write x, v", lambda N, C, G, E: 120 * N),
+    (r"^k_kick\b", "read v, a; write v", lambda N, C, G, E: 72 * N),
+]
+
+
+def _durations(path):
+    """Per-dispatch durations (ms) by kernel name from a kernel trace in CSV form
+    (rocprofv3 --kernel-trace --output-format csv: *kernel_trace.csv)."""
+    files = glob.glob(os.path.join(path, "**", "*kernel_trace.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no kernel_trace.csv under {path}")
+    out = collections.defaultdict(list)
+    for r in csv.DictReader(open(files[0])):
+        out[r["Kernel_Name"]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
+    return out
+
+
+def stats_csv(path, top=25):
+    """stats from a CSV kernel trace: calls, total and average per kernel."""
+    durs = _durations(path)
+    tot_all = sum(sum(v) for v in durs.values())
+    rows = sorted(durs.items(), key=lambda kv: -sum(kv[1]))
+    out = ["| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
+    for name, v in rows[:top]:
+        out.append(f"| `{_short(name)}` | {len(v)} | {sum(v):.3f} | {1e3 * sum(v) / len(v):.1f} | "
+                   f"{100 * sum(v) / tot_all:.2f} |")
+    return "\n".join(out)
+
+
+def _short(name):
+    n = re.sub(r"fdx::\(anonymous namespace\)::", "", name)
+    return re.sub(r"\(.*", "", n)
+
+
+def phases(trace_dir, fetch_dir, write_dir, N, C, G, E, calib, calib_read, calib_write):
+    f, w = _pmc(fetch_dir), _pmc(write_dir)
+    sf = calib_read / (statistics.median(v for v, _ in _pick(f, calib, "FETCH_SIZE")) * 1024)
+    sw = calib_write / (statistics.median(v for v, _ in _pick(w, calib, "WRITE_SIZE")) * 1024)
+    durs = _durations(trace_dir)
+    out = ["| kernel | what it must move | median ms (trace) | algorithmic B | HBM B (counters) "
+           "| algorithmic GB/s | HBM GB/s |", "|---|---|---|---|---|---|---|"]
+    for rx, what, fn in ALGO_BYTES:
+        names = [k for k in durs if re.search(rx, _short(k))]
+        if not names:
+            continue
+        d = statistics.median(x for k in names for x in durs[k])
+        fe = [v for (k, c), vs in f.items() if c == "FETCH_SIZE" and k in names for v, _ in vs]
+        wr = [v for (k, c), vs in w.items() if c == "WRITE_SIZE" and k in names for v, _ in vs]
+        hbm = (statistics.median(fe) * sf + statistics.median(wr) * sw) * 1024 if fe and wr else None
+        alg = fn(N, C, G, E)
+        out.append(f"| `{_short(names[0])}` | {what} | {d:.3f} | {alg:.3e} | "
+                   f"{'n/a' if hbm is None else f'{hbm:.3e}'} | {alg / (d / 1e3) / 1e9:.0f} | "
+                   f"{'n/a' if hbm is None else f'{hbm / (d / 1e3) / 1e9:.0f}'} |")
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -107,9 +193,23 @@ def main():
     c = sub.add_parser("sq")
     c.add_argument("dir")
     c.add_argument("--kernel", required=True)
+    d = sub.add_parser("phases")
+    d.add_argument("trace_dir")
+    d.add_argument("fetch_dir")
+    d.add_argument("write_dir")
+    for k in ("n", "cells", "groups", "entries"):
+        d.add_argument("--" + k, type=float, required=True)
+    d.add_argument("--calib", required=True)
+    d.add_argument("--calib-read", type=float, required=True)
+    d.add_argument("--calib-write", type=float, required=True)
     args = ap.parse_args()
+    if args.cmd == "phases":
+        print(phases(args.trace_dir, args.fetch_dir, args.write_dir, args.n, args.cells,
+                     args.groups, args.entries, args.calib, args.calib_read, args.calib_write))
+        return
     if args.cmd == "stats":
-        print(stats(args.dir))
+        has_db = glob.glob(os.path.join(args.dir, "**", "*_results.db"), recursive=True)
+        print(stats(args.dir) if has_db else stats_csv(args.dir))
     elif args.cmd == "pmc":
         print(pmc(args.fetch_dir, args.write_dir, args.kernel, args.calib, args.calib_read,
                   args.calib_write))

@@ -53,3 +53,28 @@ def test_missing_kernel_is_an_error(tmp_path):
     _write(str(tmp_path / "w"), [("copy", "WRITE_SIZE", 1, 0, 1)])
     with pytest.raises(SystemExit):
         P.pmc(str(tmp_path / "f"), str(tmp_path / "w"), "k_force", "copy", 1, 1)
+
+
+def test_phases_table_scales_counters_and_counts_algorithmic_bytes(tmp_path):
+    # one plain copy kernel of 1 MiB each way for the calibration (FETCH_SIZE reads half the
+    # bytes, WRITE_SIZE all of them), and k_unsort at N = 1000 particles: 68 N algorithmic bytes
+    trace = tmp_path / "trace"
+    os.makedirs(trace)
+    with open(trace / "run_kernel_trace.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        for t in (2000, 1000, 3000):             # ns: median 2 us
+            w.writerow({"Kernel_Name": "k_unsort(unsigned long, ...)", "Start_Timestamp": 0,
+                        "End_Timestamp": t})
+    _write(str(tmp_path / "f"), [("copy", "FETCH_SIZE", 512.0, 0, 1),
+                                 ("k_unsort(unsigned long, ...)", "FETCH_SIZE", 40.0, 0, 1)])
+    _write(str(tmp_path / "w"), [("copy", "WRITE_SIZE", 1024.0, 0, 1),
+                                 ("k_unsort(unsigned long, ...)", "WRITE_SIZE", 30.0, 0, 1)])
+    out = P.phases(str(trace), str(tmp_path / "f"), str(tmp_path / "w"), 1000, 0, 0, 0, "copy",
+                   1048576, 1048576)
+    row = [r for r in out.splitlines() if "k_unsort" in r][0].split("|")
+    assert float(row[3]) == pytest.approx(0.002)                 # ms
+    assert float(row[4]) == pytest.approx(68000)                 # algorithmic bytes
+    assert float(row[5]) == pytest.approx((40 * 2 + 30) * 1024, rel=1e-3)   # scaled counters
+    assert float(row[6]) == pytest.approx(68000 / 2e-6 / 1e9, abs=1)
+    assert P.stats_csv(str(trace)).splitlines()[2].startswith("| `k_unsort` | 3 | 0.006 |")
