@@ -509,7 +509,7 @@ def main():
             torch.cuda.synchronize()
             ms_graph = (time.perf_counter() - ta) * 1e3 / args.ensemble_steps
             e_end = system_energies(eps_, ce)
-            drift = np.abs((e_end - e_start) / e_start)
+            sys_drift = np.abs((e_end - e_start) / e_start)
             recoveries = int(ce.stats()["graph_recoveries"])
             # kernel timing, accuracy and the FP64 path on the initial particles
             ce.set_particles(eps_)
@@ -538,8 +538,8 @@ def main():
                 "ms_per_eval_fp32": round(float(t32), 3), "ms_per_eval_fp64": round(float(t64), 3),
                 "particles_per_s_fp64": float(round(eps_.n / (t64 / 1e3), -5)),
                 "rms_da_over_a_fp32": e32, "rms_da_over_a_fp64": e64,
-                "energy_drift_per_system": {"max": float(drift.max()),
-                                            "median": float(np.median(drift)),
+                "energy_drift_per_system": {"max": float(sys_drift.max()),
+                                            "median": float(np.median(sys_drift)),
                                             "steps": args.ensemble_steps},
                 "graph_recoveries": recoveries,
                 "autotune": etuned and {k: etuned[k] for k in ("n_group", "shape_name")}}

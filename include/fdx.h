@@ -218,7 +218,10 @@ int fdx_get_lists(fdx_ctx *ctx, uint32_t *n_epj, uint32_t *n_spj, uint32_t *epj,
  * The paper finds an optimal group size from the trade-off between list construction and
  * force cost (section "Tree traverse and interaction calculation"); the autotuner measures
  * it instead.  fdx_autotune_shapes() = number of force-kernel shapes (threads per workgroup x
- * i-particles per thread).  fdx_autotune times fdx_calc_force (median of `reps` calls after
+ * i-particles per thread x j-entries per LDS tile, with or without the next tile's loads issued
+ * early; the name gives each: nt512_ipl1_w8_jt128 = 512 threads, one i-particle per thread,
+ * 8 waves per SIMD, tiles of 128 entries; without _jt the tile is the workgroup size).
+ * fdx_autotune times fdx_calc_force (median of `reps` calls after
  * one warm-up) for each of the n_cand candidate group sizes and every shape that can hold
  * them, keeps the fastest shape for later calls of the same precision (FDX_FP32REL set or
  * not in `flags`; the other precision keeps its shape) and returns it with its group size;

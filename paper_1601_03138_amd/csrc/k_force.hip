@@ -3,9 +3,9 @@
 // The paper asks for an interaction routine that takes many i-particles and many
 // j-particles at once so each j is reused from fast memory (section "Design concept of
 // FDPS"), with particles (EPJ) and superparticles (SPJ) as two sums (equation geqL).  Here
-// one workgroup evaluates one group: j entries are gathered tile by tile into LDS (the next
-// tile's global loads are issued before the current tile is computed), and thread t owns
-// IPL i-particles and one slice of every tile.  The group's n_i particles map onto
+// one workgroup evaluates one group: j entries are gathered tile by tile into LDS, JT entries
+// per tile (JT <= NT; with PF the next tile's global loads are issued before the current tile
+// is computed), and thread t owns IPL i-particles and one slice of every tile.  The group's n_i particles map onto
 // tps = ceil(n_i / IPL) threads per slice and floor(NT / tps) slices, so nearly all lanes
 // carry a real i-particle whatever n_i is.  Slices are combined at the end in slice order,
 // so the result is deterministic.
@@ -68,19 +68,20 @@ template <> struct Acc<float> {
     __device__ __forceinline__ double val() const { return (double)s - (double)c; }
 };
 
-template <class T, int NT, int IPL>
+template <class T, int NT, int IPL, int JT>
 struct Smem {
     using V = typename V4<T>::t;
     union {
-        V e[NT];                        // particle tile
-        V s[3 * NT];                    // superparticle tile (A, B, C per entry)
+        V e[JT];                        // particle tile
+        V s[3 * JT];                    // superparticle tile (A, B, C per entry)
         double red[NT * IPL * 4];       // per-thread slice partials
     };
     uint32_t slot;
 };
 
-template <class T, bool QUAD, int NT, int IPL, bool PF, bool CUT = false>
-__device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T, NT, IPL> &sm) {
+template <class T, bool QUAD, int NT, int IPL, bool PF, bool CUT, int JT>
+__device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T, NT, IPL, JT> &sm) {
+    static_assert(JT <= NT && NT % JT == 0, "a tile holds at most one entry per thread");
     using V = typename V4<T>::t;
     const int tid = threadIdx.x;
     const uint32_t gb = a.gbegin[gi], ni = a.gcount[gi];
@@ -114,9 +115,9 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
     // registers while the current one is computed)
     {
         double4 nxt = make_double4(0, 0, 0, 0);
-        if (PF && (uint32_t)tid < ne) nxt = a.jp[epj[tid]];
-        for (uint32_t t0 = 0; t0 < ne; t0 += NT) {
-            const uint32_t nt = min((uint32_t)NT, ne - t0);
+        if (PF && (uint32_t)tid < min((uint32_t)JT, ne)) nxt = a.jp[epj[tid]];
+        for (uint32_t t0 = 0; t0 < ne; t0 += JT) {
+            const uint32_t nt = min((uint32_t)JT, ne - t0);
             __syncthreads();
             if ((uint32_t)tid < nt) {
                 if (!PF) nxt = a.jp[epj[t0 + tid]];
@@ -125,7 +126,7 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
                 sm.e[tid] = v;
             }
             __syncthreads();
-            if (PF && t0 + NT + tid < ne) nxt = a.jp[epj[t0 + NT + tid]];
+            if (PF && tid < JT && t0 + JT + tid < ne) nxt = a.jp[epj[t0 + JT + tid]];
             if (active) {
                 T tx[IPL], ty[IPL], tz[IPL], tp[IPL];
 #pragma unroll
@@ -165,9 +166,9 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
             m0 = o[0]; m1 = o[1]; m2 = o[2]; m3 = o[3];
             if (QUAD) { q0 = o[4]; q1 = o[5]; q2 = o[6]; q3 = o[7]; q4 = o[8]; q5 = o[9]; }
         };
-        if (PF && (uint32_t)tid < ns) fetch(tid);
-        for (uint32_t t0 = 0; t0 < ns; t0 += NT) {
-            const uint32_t nt = min((uint32_t)NT, ns - t0);
+        if (PF && (uint32_t)tid < min((uint32_t)JT, ns)) fetch(tid);
+        for (uint32_t t0 = 0; t0 < ns; t0 += JT) {
+            const uint32_t nt = min((uint32_t)JT, ns - t0);
             __syncthreads();
             if ((uint32_t)tid < nt) {
                 if (!PF) fetch(t0 + tid);
@@ -183,7 +184,7 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
                 }
             }
             __syncthreads();
-            if (PF && t0 + NT + tid < ns) fetch(t0 + NT + tid);
+            if (PF && tid < JT && t0 + JT + tid < ns) fetch(t0 + JT + tid);
             if (active) {
                 T tx[IPL], ty[IPL], tz[IPL], tp[IPL];
 #pragma unroll
@@ -248,17 +249,17 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
 }
 
 // OCC: minimum waves per SIMD the register allocation must allow (1 = no constraint).
-template <class T, bool QUAD, int NT, int IPL, bool PF, int OCC, bool CUT>
+template <class T, bool QUAD, int NT, int IPL, bool PF, int OCC, bool CUT, int JT>
 __global__ void __launch_bounds__(NT, OCC)
 k_force_direct(KArgs a) {
-    __shared__ Smem<T, NT, IPL> sm;
+    __shared__ Smem<T, NT, IPL, JT> sm;
     // XCD-aware order: consecutive blocks go round-robin over the 8 XCDs, so hand each XCD a
     // contiguous run of groups (neighbouring groups share most of their lists -> L2 reuse).
     const uint32_t G = a.G;
     const uint32_t chunk = (G + 7) / 8;
     const uint32_t q = (blockIdx.x % 8) * chunk + blockIdx.x / 8;
     if (q >= G) return;
-    force_group<T, QUAD, NT, IPL, PF, CUT>(a, a.order ? a.order[q] : q, sm);
+    force_group<T, QUAD, NT, IPL, PF, CUT, JT>(a, a.order ? a.order[q] : q, sm);
 }
 
 // Persistent variant: a fixed grid pops work from device counters.  Without an explicit list
@@ -269,10 +270,10 @@ k_force_direct(KArgs a) {
 // share most of their lists -- in one L2, and once that queue is empty takes slots from the
 // other XCDs' queues, which balances the load.  With an explicit list (order + device count)
 // it pops one shared queue.
-template <class T, bool QUAD, int NT, int IPL, bool PF, int OCC, bool CUT>
+template <class T, bool QUAD, int NT, int IPL, bool PF, int OCC, bool CUT, int JT>
 __global__ void __launch_bounds__(NT, OCC)
 k_force_persistent(KArgs a) {
-    __shared__ Smem<T, NT, IPL> sm;
+    __shared__ Smem<T, NT, IPL, JT> sm;
     const uint32_t G = *a.ngroups;
     const uint32_t x = blockIdx.x % 8u, chunk = (G + 7u) / 8u;
     for (;;) {
@@ -296,11 +297,11 @@ k_force_persistent(KArgs a) {
         const uint32_t slot = sm.slot;
         __syncthreads();
         if (slot >= G) break;
-        force_group<T, QUAD, NT, IPL, PF, CUT>(a, a.order ? a.order[slot] : slot, sm);
+        force_group<T, QUAD, NT, IPL, PF, CUT, JT>(a, a.order ? a.order[slot] : slot, sm);
     }
 }
 
-template <class T, bool QUAD, int NT, int IPL, bool PF, int OCC = 1, bool CUT = false>
+template <class T, bool QUAD, int NT, int IPL, bool PF, int OCC = 1, bool CUT = false, int JT = NT>
 hipError_t launch(const KArgs &k, bool persistent, hipStream_t s) {
     if (persistent) {
         int dev = 0, ncu = 256;
@@ -308,28 +309,34 @@ hipError_t launch(const KArgs &k, bool persistent, hipStream_t s) {
         (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
         int per_cu = 0;
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(k_force_persistent<T, QUAD, NT, IPL, PF, OCC, CUT>), NT, 0);
+            &per_cu, reinterpret_cast<const void *>(k_force_persistent<T, QUAD, NT, IPL, PF, OCC, CUT, JT>), NT, 0);
         if (per_cu < 1) per_cu = 1;
         size_t grid = (size_t)ncu * per_cu;
         if (k.G && grid > k.G) grid = k.G;
-        hipLaunchKernelGGL((k_force_persistent<T, QUAD, NT, IPL, PF, OCC, CUT>), dim3((unsigned)grid), dim3(NT),
+        hipLaunchKernelGGL((k_force_persistent<T, QUAD, NT, IPL, PF, OCC, CUT, JT>), dim3((unsigned)grid), dim3(NT),
                            0, s, k);
     } else {
         if (k.G == 0) return hipSuccess;
         const uint32_t chunk = (k.G + 7) / 8;
-        hipLaunchKernelGGL((k_force_direct<T, QUAD, NT, IPL, PF, OCC, CUT>), dim3(8 * chunk), dim3(NT), 0, s, k);
+        hipLaunchKernelGGL((k_force_direct<T, QUAD, NT, IPL, PF, OCC, CUT, JT>), dim3(8 * chunk), dim3(NT), 0, s, k);
     }
     return hipGetLastError();
 }
 
 struct Variant { int nt, ipl; bool pf; const char *name; };
+// the j-tile equals the workgroup size unless the name says otherwise (_jtN: N entries per tile)
 constexpr Variant kVariants[] = {
     {256, 1, true, "nt256_ipl1_pf"}, {256, 2, true, "nt256_ipl2_pf"},
     {512, 1, true, "nt512_ipl1_pf"}, {512, 2, true, "nt512_ipl2_pf"},
     {256, 1, false, "nt256_ipl1"},   {256, 2, false, "nt256_ipl2"},
     {512, 1, false, "nt512_ipl1"},   {512, 2, false, "nt512_ipl2"},
-    {512, 1, true, "nt512_ipl1_pf_w8"}, {512, 1, false, "nt512_ipl1_w8"}};
-constexpr int kNumVariants = 10;
+    {512, 1, true, "nt512_ipl1_pf_w8"}, {512, 1, false, "nt512_ipl1_w8"},
+    {256, 1, false, "nt256_ipl1_jt64"}, {256, 1, false, "nt256_ipl1_jt128"},
+    {512, 1, false, "nt512_ipl1_w8_jt128"}, {512, 1, false, "nt512_ipl1_w8_jt256"}};
+constexpr int kNumVariants = 14;
+
+// FP32: register allocation held to 64 VGPRs, 8 waves per SIMD (4 workgroups per CU)
+template <class T> constexpr int kW8 = sizeof(T) == 4 ? 8 : 1;
 
 template <class T, bool QUAD>
 hipError_t launch_v(const KArgs &k, bool persistent, int v, hipStream_t s) {
@@ -342,19 +349,22 @@ hipError_t launch_v(const KArgs &k, bool persistent, int v, hipStream_t s) {
         case 5: return launch<T, QUAD, 256, 2, false>(k, persistent, s);
         case 6: return launch<T, QUAD, 512, 1, false>(k, persistent, s);
         case 7: return launch<T, QUAD, 512, 2, false>(k, persistent, s);
-        // FP32: register allocation held to 64 VGPRs, 8 waves per SIMD (4 workgroups per CU)
-        case 8: return launch<T, QUAD, 512, 1, true, sizeof(T) == 4 ? 8 : 1>(k, persistent, s);
-        default: return launch<T, QUAD, 512, 1, false, sizeof(T) == 4 ? 8 : 1>(k, persistent, s);
+        case 8: return launch<T, QUAD, 512, 1, true, kW8<T>>(k, persistent, s);
+        case 9: return launch<T, QUAD, 512, 1, false, kW8<T>>(k, persistent, s);
+        case 10: return launch<T, QUAD, 256, 1, false, 1, false, 64>(k, persistent, s);
+        case 11: return launch<T, QUAD, 256, 1, false, 1, false, 128>(k, persistent, s);
+        case 12: return launch<T, QUAD, 512, 1, false, kW8<T>, false, 128>(k, persistent, s);
+        default: return launch<T, QUAD, 512, 1, false, kW8<T>, false, 256>(k, persistent, s);
     }
 }
 
 // private (scratch) bytes per lane of one kernel instance: > 0 means registers spill
-template <class T, bool QUAD, int NT, int IPL, bool PF, int OCC = 1>
+template <class T, bool QUAD, int NT, int IPL, bool PF, int OCC = 1, int JT = NT>
 int scratch_of(bool persistent) {
     hipFuncAttributes at{};
     const void *f = persistent
-        ? reinterpret_cast<const void *>(k_force_persistent<T, QUAD, NT, IPL, PF, OCC, false>)
-        : reinterpret_cast<const void *>(k_force_direct<T, QUAD, NT, IPL, PF, OCC, false>);
+        ? reinterpret_cast<const void *>(k_force_persistent<T, QUAD, NT, IPL, PF, OCC, false, JT>)
+        : reinterpret_cast<const void *>(k_force_direct<T, QUAD, NT, IPL, PF, OCC, false, JT>);
     if (hipFuncGetAttributes(&at, f) != hipSuccess) return -1;
     return (int)at.localSizeBytes;
 }
@@ -370,8 +380,12 @@ int scratch_v(bool persistent, int v) {
         case 5: return scratch_of<T, QUAD, 256, 2, false>(persistent);
         case 6: return scratch_of<T, QUAD, 512, 1, false>(persistent);
         case 7: return scratch_of<T, QUAD, 512, 2, false>(persistent);
-        case 8: return scratch_of<T, QUAD, 512, 1, true, sizeof(T) == 4 ? 8 : 1>(persistent);
-        default: return scratch_of<T, QUAD, 512, 1, false, sizeof(T) == 4 ? 8 : 1>(persistent);
+        case 8: return scratch_of<T, QUAD, 512, 1, true, kW8<T>>(persistent);
+        case 9: return scratch_of<T, QUAD, 512, 1, false, kW8<T>>(persistent);
+        case 10: return scratch_of<T, QUAD, 256, 1, false, 1, 64>(persistent);
+        case 11: return scratch_of<T, QUAD, 256, 1, false, 1, 128>(persistent);
+        case 12: return scratch_of<T, QUAD, 512, 1, false, kW8<T>, 128>(persistent);
+        default: return scratch_of<T, QUAD, 512, 1, false, kW8<T>, 256>(persistent);
     }
 }
 

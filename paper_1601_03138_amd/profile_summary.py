@@ -10,9 +10,10 @@
       SQ counters per dispatch of the matching kernel
   python -m paper_1601_03138_amd.profile_summary phases TRACE_DIR FETCH_DIR WRITE_DIR
       --n N --cells C --groups G --entries E --calib REGEX --calib-read B --calib-write B
-      per kernel of the force evaluation: dispatches per step, median duration (kernel trace),
-      HBM bytes per dispatch from FETCH_SIZE and WRITE_SIZE (scaled as for pmc), the bytes the
-      kernel's algorithm must move (ALGO_BYTES below) and both as GB/s
+      per kernel of the force evaluation: median duration per dispatch (kernel trace), HBM bytes
+      per dispatch from FETCH_SIZE and WRITE_SIZE (scaled as for pmc), the bytes the kernel's
+      algorithm must move (ALGO_BYTES below) and both as GB/s; kernels launched once per tree
+      level are summed over one evaluation
 """
 from __future__ import annotations
 
@@ -97,8 +98,10 @@ def sq(path, kernel):
     return "\n".join(out)
 
 
-# Bytes each kernel of the path must move once per dispatch (N particles, C cells, G groups,
-# E interaction-list entries): the arrays it reads and writes, each counted once.
+# Bytes each kernel of the path must move per dispatch (N particles, C cells, G groups,
+# E interaction-list entries): the arrays it reads and writes, each counted once.  Rows in
+# PER_EVALUATION are dispatched several times in one force evaluation with different sizes
+# (one launch per tree level) and are given per evaluation instead.
 ALGO_BYTES = [
     # (kernel regex, what, bytes per dispatch)
     (r"^k_bbox\b", "read x, y, z", lambda N, C, G, E: 24 * N),
@@ -114,8 +117,8 @@ ALGO_BYTES = [
     (r"^k_cells_emit\b", "read keys + three bytes per position; write 20 B per cell",
      lambda N, C, G, E: 11 * N + 20 * C),
     (r"^k_cells_finish\b", "read 20 B, write 36 B per cell", lambda N, C, G, E: 56 * C),
-    (r"^k_moments\b", "all levels: write 80 B per cell, read 80 B per child and 32 B per "
-     "particle", lambda N, C, G, E: 160 * C + 32 * N),
+    (r"^k_moments\b", "all levels of one evaluation (one dispatch per level): write 80 B per "
+     "cell, read 80 B per child and 32 B per particle", lambda N, C, G, E: 160 * C + 32 * N),
     (r"^k_group_flags\b", "read counts, write flags per cell", lambda N, C, G, E: 12 * C),
     (r"^k_leaf_level\b", "write a byte per particle", lambda N, C, G, E: 1 * N),
     (r"^void k_group_geom|^k_group_geom\b", "read member keys; write box and centre per group",
@@ -125,6 +128,11 @@ ALGO_BYTES = [
     (r"^k_kick_drift\b", "read x, v, a; write x, v", lambda N, C, G, E: 120 * N),
     (r"^k_kick\b", "read v, a; write v", lambda N, C, G, E: 72 * N),
 ]
+
+
+PER_EVALUATION = {r"^k_moments\b"}
+# a kernel dispatched exactly once per force evaluation: counts the evaluations in a trace
+EVALUATION_MARKER = r"^k_bbox_init\b"
 
 
 def _durations(path):
@@ -161,16 +169,31 @@ def phases(trace_dir, fetch_dir, write_dir, N, C, G, E, calib, calib_read, calib
     sf = calib_read / (statistics.median(v for v, _ in _pick(f, calib, "FETCH_SIZE")) * 1024)
     sw = calib_write / (statistics.median(v for v, _ in _pick(w, calib, "WRITE_SIZE")) * 1024)
     durs = _durations(trace_dir)
-    out = ["| kernel | what it must move | median ms (trace) | algorithmic B | HBM B (counters) "
+
+    def evaluations(per_kernel):
+        return sum(len(v) if isinstance(v, list) else 1 for k, v in per_kernel
+                   if re.search(EVALUATION_MARKER, _short(k)))
+
+    n_eval = evaluations(durs.items())
+    f_eval = evaluations([(k, v) for (k, c), v in f.items() if c == "FETCH_SIZE"])
+    w_eval = evaluations([(k, v) for (k, c), v in w.items() if c == "WRITE_SIZE"])
+    out = ["| kernel | what it must move | ms (trace) | algorithmic B | HBM B (counters) "
            "| algorithmic GB/s | HBM GB/s |", "|---|---|---|---|---|---|---|"]
     for rx, what, fn in ALGO_BYTES:
         names = [k for k in durs if re.search(rx, _short(k))]
         if not names:
             continue
-        d = statistics.median(x for k in names for x in durs[k])
         fe = [v for (k, c), vs in f.items() if c == "FETCH_SIZE" and k in names for v, _ in vs]
         wr = [v for (k, c), vs in w.items() if c == "WRITE_SIZE" and k in names for v, _ in vs]
-        hbm = (statistics.median(fe) * sf + statistics.median(wr) * sw) * 1024 if fe and wr else None
+        if rx in PER_EVALUATION:
+            # sums over one evaluation's dispatches, averaged over the evaluations
+            if not (n_eval and f_eval and w_eval):
+                raise SystemExit(f"no dispatch of /{EVALUATION_MARKER}/ to count evaluations")
+            d = sum(x for k in names for x in durs[k]) / n_eval
+            hbm = ((sum(fe) / f_eval) * sf + (sum(wr) / w_eval) * sw) * 1024 if fe and wr else None
+        else:
+            d = statistics.median(x for k in names for x in durs[k])
+            hbm = (statistics.median(fe) * sf + statistics.median(wr) * sw) * 1024 if fe and wr else None
         alg = fn(N, C, G, E)
         out.append(f"| `{_short(names[0])}` | {what} | {d:.3f} | {alg:.3e} | "
                    f"{'n/a' if hbm is None else f'{hbm:.3e}'} | {alg / (d / 1e3) / 1e9:.0f} | "

@@ -3,7 +3,8 @@ times: keys, order, every cell and every group bit-exact against the oracle's fu
 build; lists and forces on sampled groups; accuracy against FP64 direct summation on seeded
 subsets; the ensemble with graph-captured steps; the predictor path at full size; the
 exchange lists of the benchmark input cut into 64 and 512 domains; its multisection domain
-decomposition; the whole path at 4x the benchmark size."""
+decomposition; the whole path at 4x the benchmark size; the ensemble in the one-launch walk +
+force kernel."""
 import os
 import sys
 
@@ -72,42 +73,60 @@ def _sampled_force_check(ctx, t, g, sel, lists, quad):
     return float(np.sqrt(np.mean(e ** 2)))
 
 
+def _check_sampled_entry_sets(gpu_lists, lists, sel):
+    """The GPU's entry sets of the sampled groups equal the oracle's (as sets: the order of
+    entries within a list is not part of the result)."""
+    ne, ns, epj, spj = gpu_lists
+    oe = np.concatenate([[0], np.cumsum(ne.astype(np.int64))])
+    os_ = np.concatenate([[0], np.cumsum(ns.astype(np.int64))])
+    for q, k in enumerate(sel):
+        e_ref, s_ref = lists.group_lists(q)
+        assert np.array_equal(np.sort(epj[oe[k]:oe[k + 1]]), np.sort(e_ref)), k
+        assert np.array_equal(np.sort(spj[os_[k]:os_[k + 1]]), np.sort(s_ref)), k
+
+
 def test_clustered16m_bench_configuration(ctx, fdx):
+    """The benchmark input: tree, groups and the entry sets of 256 sampled groups against the
+    oracle for the exact walk; then the timed configuration (persistent force kernel over
+    per-XCD queues, predicted walk) in the two FP32 shapes the benchmark chooses between, each
+    bit-identical to the direct launch of the same shape after the exact walk, with the same
+    entry sets, within the FP32 tolerance of the oracle tree on the sampled groups."""
     ps = I.workload("clustered16m")
     _say(f"[fullsize] clustered16m n={ps.n}")
     ctx.set_particles(ps)
     ctx.calc_force(0.5, 8, 256, 0.0, quad=True, fp32=True)
-    t, g, sel, lists = _compare_full(ctx, ps, 8, 256, 0.5, True, 48, seed=5)
+    t, g, sel, lists = _compare_full(ctx, ps, 8, 256, 0.5, True, 256, seed=5)
+    gl = ctx.lists()
+    _check_sampled_entry_sets(gl, lists, sel)
+    del gl
     e_tree = _sampled_force_check(ctx, t, g, sel, lists, True)
     sub = I.subset(ps.n, 256, seed=102)
     e_direct = O.rms_rel_error(ctx.forces()[sub], O.direct(ps, sub))
-    _say(f"  cells {t.n_cells} groups {g.n}; fp32 vs tree (sampled) {e_tree:.2e}; "
+    _say(f"  cells {t.n_cells} groups {g.n}; fp32 vs tree (256 sampled groups) {e_tree:.2e}; "
          f"vs direct {e_direct:.2e}")
     assert e_tree <= F32_RMS_REL_VS_TREE
     assert e_direct <= BAR_RMS_VS_DIRECT
-
-
-@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained predictor weights not present")
-def test_clustered16m_predictor_path_is_exact(ctx, fdx):
-    ps = I.workload("clustered16m")
-    ctx.set_particles(ps)
-    ctx.calc_force(0.5, 8, 256, 0.0, quad=True, fp32=True)
-    a = ctx.forces()
-    counts = ctx.list_counts()
+    if not os.path.exists(WEIGHTS):
+        pytest.skip("trained predictor weights not present")
     ctx.predictor_load(WEIGHTS)
-    spills0 = ctx.stats()["list_spills"]
-    ctx.calc_force(0.5, 8, 256, 0.0, quad=True, fp32=True, predictor=True)
-    st = ctx.stats()
-    spilled = st["list_spills"] - spills0
-    _say(f"[fullsize] predictor: overflow {st['overflow_groups']} of {st['n_groups']} "
-         f"({spilled} walked again in spare space), capacity {st['list_capacity']} vs exact "
-         f"{int(counts[0].sum() + counts[1].sum())}")
-    assert np.array_equal(ctx.forces(), a)
-    for x, y in zip(ctx.list_counts(), counts):
-        assert np.array_equal(x, y)
-    assert st["overflow_groups"] <= 0.02 * st["n_groups"]
-    # the buffer's spare eighth holds every list that outgrew its prediction
-    assert spilled == st["overflow_groups"]
+    names = [ctx.shape_name(v) for v in range(ctx.lib.fdx_autotune_shapes())]
+    for name in ("nt512_ipl1_pf_w8", "nt512_ipl1_w8"):
+        ctx.set_shape(names.index(name))
+        ctx.calc_force(0.5, 8, 256, 0.0, quad=True, fp32=True)
+        a_direct = ctx.forces()
+        ctx.calc_force(0.5, 8, 256, 0.0, quad=True, fp32=True, persistent=True, predictor=True)
+        st = ctx.stats()
+        assert st["shape"] == names.index(name)
+        a = ctx.forces()
+        assert np.array_equal(a, a_direct), name
+        gl = ctx.lists()
+        _check_sampled_entry_sets(gl, lists, sel)
+        del gl
+        e = _sampled_force_check(ctx, t, g, sel, lists, True)
+        _say(f"  {name}: persistent + predicted walk == direct + exact walk; overflow groups "
+             f"{st['overflow_groups']}; fp32 vs tree {e:.2e}")
+        assert e <= F32_RMS_REL_VS_TREE
+    ctx.set_shape(-1)
 
 
 def test_plummer1m_fp64_fp32_and_ten_steps(ctx, fdx):
@@ -162,6 +181,39 @@ def test_ensemble512_graph_configuration(ctx, fdx):
     g_state = (ctx.particles(), ctx.forces())
     ctx.set_particles(ens)
     ctx.calc_force(0.6, 8, 128, 0.0, quad=True, fp32=True, persistent=True)
+    assert all(np.array_equal(a, b) for a, b in zip(ctx.particles(), x0))
+    ctx.integrate(1.0 / 256.0, 3)
+    for a, b in zip(ctx.particles(), g_state[0]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(ctx.forces(), g_state[1])
+
+
+def test_ensemble512_fused_walk_and_force(ctx, fdx):
+    """The ensemble in the one-launch walk + force kernel, as the benchmark's ensemble line
+    runs it: entry sets of 256 sampled groups against the oracle (lists captured), the
+    separate walk's counts for every group, FP32 forces within the tolerance of the oracle
+    tree, and graph-captured steps equal to eager steps."""
+    ens = I.workload("ensemble512")
+    _say(f"[fullsize] ensemble512 fused n={ens.n}")
+    ctx.set_particles(ens)
+    ctx.calc_force(0.6, 8, 128, 0.0, quad=True, fp32=True, persistent=True)
+    counts = ctx.list_counts()
+    flags = fdx.Context.flags(quad=True, fp32=True, persistent=True, fused=True)
+    ctx.set_list_capture(True)
+    ctx.calc_force_flags(0.6, 8, 128, 0.0, flags)
+    ctx.set_list_capture(False)
+    t, g, sel, lists = _compare_full(ctx, ens, 8, 128, 0.6, True, 256, seed=17)
+    _check_sampled_entry_sets(ctx.lists(), lists, sel)
+    for x, y in zip(ctx.list_counts(), counts):
+        assert np.array_equal(x, y)
+    e = _sampled_force_check(ctx, t, g, sel, lists, True)
+    _say(f"  fused fp32 vs tree (256 sampled groups) {e:.2e}")
+    assert e <= F32_RMS_REL_VS_TREE
+    x0 = ctx.particles()
+    ctx.integrate(1.0 / 256.0, 3, graph=True)
+    g_state = (ctx.particles(), ctx.forces())
+    ctx.set_particles(ens)
+    ctx.calc_force_flags(0.6, 8, 128, 0.0, flags)
     assert all(np.array_equal(a, b) for a, b in zip(ctx.particles(), x0))
     ctx.integrate(1.0 / 256.0, 3)
     for a, b in zip(ctx.particles(), g_state[0]):

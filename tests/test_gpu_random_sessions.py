@@ -126,3 +126,47 @@ def test_random_call_sequence(fdx, seed):
                 _say(f"[session {seed}.{k}] margin")
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("between", ["density", "build_tree", "exchange", "autotune", "cutoff"])
+@pytest.mark.parametrize("graph", [False, True])
+def test_steps_after_other_calls_use_the_last_force_parameters(fdx, between, graph):
+    # density, tree builds, exchange lists, the autotuner and cutoff forces each set up their
+    # own tree parameters; leapfrog steps taken right after them still use those of the last
+    # fdx_calc_force (the cutoff force is itself such a call: steps after it use the cutoff)
+    ps = I.concat([I.plummer(3000, seed=31, eps=0.02), I.plummer(1700, seed=32, eps=0.01)])
+    theta, n_group, dt = 0.7, 32, 1.0 / 512.0
+    kw = dict(quad=True, fp32=True, persistent=False)
+    _say(f"[after {between}] graph={graph}")
+    with fdx.Context(0) as c:
+        c.set_particles(ps)
+        c.calc_force(theta, 8, n_group, 0.0, **kw)
+        if between == "density":
+            c.calc_density(0, 0.1, np.full(ps.n, 0.05), n_group=64)
+        elif between == "build_tree":
+            c.build_tree(4, 128)
+        elif between == "exchange":
+            c.build_exchange_lists(0.5, 8)
+        elif between == "autotune":
+            c.autotune(0.5, 8, 0.0, fdx.Context.flags(quad=False, fp32=False), [64, 256], reps=1)
+            c.set_shape(-1)
+        else:
+            c.calc_force_cutoff(0.4, 8, 64, 0.0, 0.3, fp32=False, persistent=False)
+            if graph:
+                # graph capture is not offered for the cutoff kernel, whatever came before
+                with pytest.raises(fdx.FdxError) as e:
+                    c.integrate(dt, 2, graph=True)
+                assert e.value.code == fdx.EINVAL
+                return
+        c.integrate(dt, 2, graph=graph)
+        got = (np.array(c.particles()), c.forces())
+    with fdx.Context(0) as f:
+        f.set_particles(ps)
+        if between == "cutoff":
+            f.calc_force_cutoff(0.4, 8, 64, 0.0, 0.3, fp32=False, persistent=False)
+        else:
+            f.calc_force(theta, 8, n_group, 0.0, **kw)
+        f.integrate(dt, 2, graph=graph)
+        want = (np.array(f.particles()), f.forces())
+    assert np.array_equal(got[0], want[0])
+    assert np.array_equal(got[1], want[1])
