@@ -71,24 +71,34 @@ def force_flops(st, quad):
         FLOPS_PC_QUAD if quad else FLOPS_PC_MONO)
 
 
+def force_source_sha():
+    """sha256 over the force kernel's sources (k_force.hip, then interact.h, byte for byte):
+    a traffic summary counts only for the code it was measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("k_force.hip", "interact.h"):
+        try:
+            h.update(open(os.path.join(ROOT, "paper_1601_03138_amd", "csrc", f), "rb").read())
+        except OSError:
+            return None
+    return h.hexdigest()
+
+
 def read_traffic(kernel_tag: str, shape: str, launch: str):
     """HBM bytes per launch of the force kernel measured by rocprofv3 counters, if a summary
     for the current kernel source, this shape and this launch is committed under profiles/
     (files <kernel_tag>_<shape>_traffic.txt; else None)."""
     import glob
-    import hashlib
-    try:
-        src = open(os.path.join(ROOT, "paper_1601_03138_amd", "csrc", "k_force.hip"), "rb").read()
-    except OSError:
+    sha = force_source_sha()
+    if sha is None:
         return None
-    sha = hashlib.sha256(src).hexdigest()
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"{kernel_tag}_*traffic.txt"))):
         vals = {}
         for line in open(path):
             if ":" in line:
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-        if (vals.get("k_force.hip sha256") != sha or vals.get("shape") != shape
+        if (vals.get("force kernel sources sha256") != sha or vals.get("shape") != shape
                 or vals.get("launch") != launch):
             continue
         try:
@@ -204,6 +214,8 @@ def main():
     ap.add_argument("--direct", action="store_true",
                     help="one workgroup per group in group order (XCD-aware) instead of the "
                          "default persistent force kernel over per-XCD queues of groups")
+    ap.add_argument("--fused", action="store_true",
+                    help="walk and force in one persistent launch (FDX_FUSED; n_group <= 256)")
     ap.add_argument("--walk", default="auto", choices=["auto", "exact", "predicted"],
                     help="exact: count pass + fill pass; predicted: the learned list-length "
                          "predictor sizes the lists for a single fill pass (groups that do not "
@@ -258,8 +270,9 @@ def main():
     ps = inputs.workload(args.workload)
     ctx = fdx.Context(0)
     ctx.set_particles(ps)
-    persistent = not args.direct or args.graph
-    flags = fdx.Context.flags(quad=quad, fp32=True, timing=True, persistent=persistent)
+    persistent = not args.direct or args.graph or args.fused
+    flags = fdx.Context.flags(quad=quad, fp32=True, timing=True, persistent=persistent,
+                              fused=args.fused)
     tuned = None
     if args.shape:
         names = [ctx.shape_name(v) for v in range(ctx.lib.fdx_autotune_shapes())]
@@ -268,7 +281,7 @@ def main():
             sys.exit(2)
         ctx.set_shape(names.index(args.shape))
     elif not args.no_autotune and not args.n_group and args.workload in AUTOTUNED:
-        tuned = autotune(ctx, theta, quad, persistent, graph=args.graph)
+        tuned = autotune(ctx, theta, quad, persistent, graph=args.graph, fused=args.fused)
         n_group = tuned["n_group"]
         log(f"[bench] autotune: n_group={n_group} shape={tuned['shape_name']} times={tuned['ms']}")
 
@@ -341,9 +354,9 @@ def main():
                  "groups": gbs(18 * ps.n, phase_ms["groups"]),
                  "walk_list_write": gbs(4 * (int(st["n_epj"]) + int(st["n_spj"])),
                                         phase_ms["walk"])}
-    traffic = read_traffic(f"force_fp32_quad_{args.workload}" if quad else
-                           f"force_fp32_mono_{args.workload}", shape,
-                           "persistent" if persistent else "direct")
+    traffic = None if args.fused else read_traffic(
+        f"force_fp32_quad_{args.workload}" if quad else f"force_fp32_mono_{args.workload}",
+        shape, "persistent" if persistent else "direct")
 
     # the same evaluation with the exact and the predicted walk
     pred = None
@@ -606,13 +619,15 @@ def main():
         "config": {"workload": args.workload, "n": ps.n, "systems": ps.n_sys, "theta": theta,
                    "n_group": n_group, "n_leaf": 8, "quadrupole": quad,
                    "eps": float(ps.eps[0]) if ps.n_sys == 1 else "4/N_s^(1/3)", "dt": dt,
-                   "graph": args.graph, "persistent": persistent,
+                   "graph": args.graph, "persistent": persistent, "fused": args.fused,
                    "walk": ("predicted single pass, exact re-walk of groups that overflow"
                             if walk == "predicted" else "exact count + fill passes"),
                    "step": "leapfrog kick-drift, full force evaluation, kick"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                     "traffic": traffic, "kernel": (f"k_force_persistent<float, quad> {shape}" if persistent
+                     "traffic": traffic,
+                     "kernel": ("k_fused<float, quad> (walk + force, one launch)" if args.fused
+                                else f"k_force_persistent<float, quad> {shape}" if persistent
                                 else f"k_force_direct<float, quad> {shape}"),
                      "kernel_ms": round(mean_force_ms, 3),
                      "interactions_per_launch": int(st["n_interactions_pp"] + st["n_interactions_pc"]),
