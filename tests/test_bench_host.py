@@ -24,7 +24,7 @@ def _summary(shape, launch, hbm, sha):
     return (f"HBM traffic of a force kernel\n"
             f"fetch bytes per launch (scaled): 1.0e+09\n"
             f"hbm bytes per launch: {hbm:.6e}\n"
-            f"shape: {shape}\nlaunch: {launch}\nk_force.hip sha256: {sha}\n")
+            f"shape: {shape}\nlaunch: {launch}\nforce kernel sources sha256: {sha}\n")
 
 
 def test_traffic_lookup_matches_source_shape_and_launch(tmp_path, monkeypatch):
@@ -35,7 +35,9 @@ def test_traffic_lookup_matches_source_shape_and_launch(tmp_path, monkeypatch):
     (root / "profiles").mkdir()
     src = root / "paper_1601_03138_amd" / "csrc" / "k_force.hip"
     src.write_text("// kernel source as profiled\n")
-    sha = hashlib.sha256(src.read_bytes()).hexdigest()
+    inc = root / "paper_1601_03138_amd" / "csrc" / "interact.h"
+    inc.write_text("// interaction functions as profiled\n")
+    sha = hashlib.sha256(src.read_bytes() + inc.read_bytes()).hexdigest()
     (root / "profiles" / f"{tag}_nt512_ipl1_w8_traffic.txt").write_text(
         _summary("nt512_ipl1_w8", "persistent", 8.3e9, sha))
     (root / "profiles" / f"{tag}_nt512_ipl1_pf_w8_traffic.txt").write_text(
@@ -49,7 +51,11 @@ def test_traffic_lookup_matches_source_shape_and_launch(tmp_path, monkeypatch):
     assert bench.read_traffic(tag, "nt256_ipl1", "direct") is None          # stale source
     assert bench.read_traffic(tag, "no_such_shape", "persistent") is None
     assert bench.read_traffic("force_fp32_quad_other", "nt512_ipl1_w8", "persistent") is None
-    # the kernel source changes after the counters were taken: no traffic is reported
+    # a kernel source changes after the counters were taken: no traffic is reported
+    inc.write_text("// interaction functions as profiled\n// changed\n")
+    assert bench.read_traffic(tag, "nt512_ipl1_w8", "persistent") is None
+    inc.write_text("// interaction functions as profiled\n")
+    assert bench.read_traffic(tag, "nt512_ipl1_w8", "persistent") == 8.3e9
     src.write_text("// kernel source as profiled\n// changed\n")
     assert bench.read_traffic(tag, "nt512_ipl1_w8", "persistent") is None
 
