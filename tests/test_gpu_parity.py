@@ -252,6 +252,39 @@ def test_device_borrowed_input_and_device_check(ctx, fdx):
     assert ei.value.code == fdx.EINVAL
 
 
+def test_uniform_eps_array_takes_the_global_softening_path(ctx, fdx):
+    # an eps array whose values are all equal is gathered as one value: forces equal those of
+    # the global eps, from host and from device input; one differing value switches the
+    # per-particle gather back on (its forces then match the oracle tree)
+    import torch
+    ps = I.plummer(5000, seed=26, eps=0.01)
+    ctx.set_particles(ps, per_particle_eps=False)
+    ctx.calc_force(0.5, 8, 64, 0.01, quad=True, fp32=True)
+    a_global = ctx.forces()
+    ctx.set_particles(ps)
+    ctx.calc_force(0.5, 8, 64, 0.0, quad=True, fp32=True)
+    assert np.array_equal(ctx.forces(), a_global)
+    dev = {k: torch.tensor(getattr(ps, k), dtype=torch.float64, device="cuda")
+           for k in ("x", "y", "z", "vx", "vy", "vz", "m", "eps")}
+    ctx.set_particles_device(dev)
+    ctx.calc_force(0.5, 8, 64, 0.0, quad=True, fp32=True)
+    assert np.array_equal(ctx.forces(), a_global)
+    q = I._pack(np.stack([ps.x, ps.y, ps.z], 1), np.stack([ps.vx, ps.vy, ps.vz], 1), ps.m,
+                ps.eps.copy())
+    q.eps[1234] = 0.02
+    ref = O.tree_force(q, 0.5, 8, 64, quad=True)
+    for host in (True, False):
+        if host:
+            ctx.set_particles(q)
+        else:
+            dev["eps"][1234] = 0.02
+            ctx.set_particles_device(dev)
+        ctx.calc_force(0.5, 8, 64, 0.0, quad=True, fp32=False)
+        a = ctx.forces()
+        assert not np.array_equal(a, a_global)
+        assert np.allclose(a, ref, rtol=1e-9, atol=1e-12)
+
+
 def test_leapfrog_step_matches_oracle(ctx):
     # one force evaluation plus one KDK step of the sample program, dt = 1/128, N = 4096
     ps = I.workload("plummer4k")
