@@ -97,9 +97,14 @@ k_scan_reduce(const uint32_t *in, size_t n_host, const uint32_t *lo, const uint3
     const size_t n = scan_count(n_host, lo, hi);
     const size_t chunk = (n + kScanBlocks - 1) / kScanBlocks;
     const size_t b0 = blockIdx.x * chunk, b1 = min(n, b0 + chunk);
-    uint64_t s = 0;
-    for (size_t i = b0 + threadIdx.x; i < b1; i += kThreads) s += in[i];
-    s = wave_sum_u64(s);
+    // four independent sums: four loads in flight per thread
+    uint64_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    size_t i = b0 + threadIdx.x;
+    for (; i + 3 * kThreads < b1; i += 4 * kThreads) {
+        s0 += in[i]; s1 += in[i + kThreads]; s2 += in[i + 2 * kThreads]; s3 += in[i + 3 * kThreads];
+    }
+    for (; i < b1; i += kThreads) s0 += in[i];
+    uint64_t s = wave_sum_u64(s0 + s1 + s2 + s3);
     if (lane_id() == 0) lds[threadIdx.x / kWave] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -141,14 +146,66 @@ k_scan_down(const uint32_t *in, T *out, size_t n_host, const uint32_t *lo, const
     }
 }
 
+// The down-sweep for 32-bit outputs (the prefix fits 32 bits, so every partial sum does):
+// 4 x 256 elements per iteration, each 256-element sub-tile scanned per wave with DPP, the 16
+// wave totals combined through LDS -- one barrier pair per 1024 elements.  The same sums as
+// k_scan_down<uint32_t> (unsigned arithmetic modulo 2^32), in far fewer barriers.
+constexpr int kSub = 4;
+__global__ void __launch_bounds__(kThreads)
+k_scan_down32(const uint32_t *in, uint32_t *out, size_t n_host, const uint32_t *lo,
+              const uint32_t *hi, const uint64_t *partial) {
+    __shared__ uint32_t lds[kSub][kThreads / kWave];
+    const size_t n = scan_count(n_host, lo, hi);
+    const size_t chunk = (n + kScanBlocks - 1) / kScanBlocks;
+    const size_t b0 = blockIdx.x * chunk, b1 = min(n, b0 + chunk);
+    const int w = threadIdx.x / kWave, l = lane_id();
+    uint32_t base = (uint32_t)partial[blockIdx.x];
+    for (size_t t0 = b0; t0 < b1; t0 += kSub * kThreads) {
+        uint32_t v[kSub], inc[kSub];
+#pragma unroll
+        for (int k = 0; k < kSub; k++) {
+            const size_t i = t0 + (size_t)k * kThreads + threadIdx.x;
+            v[k] = i < b1 ? in[i] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kSub; k++) {
+            inc[k] = wave_incl_scan_dpp(v[k]);
+            if (l == kWave - 1) lds[k][w] = inc[k];
+        }
+        __syncthreads();
+        // offset of (sub-tile k, wave w): every wave of the earlier sub-tiles, then the
+        // earlier waves of sub-tile k
+        uint32_t run = 0, off[kSub];
+#pragma unroll
+        for (int k = 0; k < kSub; k++) {
+#pragma unroll
+            for (int q = 0; q < kThreads / kWave; q++) {
+                if (q == w) off[k] = run;
+                run += lds[k][q];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kSub; k++) {
+            const size_t i = t0 + (size_t)k * kThreads + threadIdx.x;
+            if (i < b1) out[i] = base + off[k] + inc[k] - v[k];
+        }
+        base += run;
+        __syncthreads();
+    }
+}
+
 template <class T>
 hipError_t scan_impl(const uint32_t *in, T *out, size_t n_host, const uint32_t *lo,
                      const uint32_t *hi, uint64_t *partial, T *total, hipStream_t s) {
     hipLaunchKernelGGL(k_scan_reduce, dim3(kScanBlocks), dim3(kThreads), 0, s, in, n_host, lo,
                        hi, partial);
     hipLaunchKernelGGL(k_scan_top<T>, dim3(1), dim3(kScanBlocks), 0, s, partial, total);
-    hipLaunchKernelGGL(k_scan_down<T>, dim3(kScanBlocks), dim3(kThreads), 0, s, in, out, n_host,
-                       lo, hi, (const uint64_t *)partial);
+    if constexpr (sizeof(T) == 4)
+        hipLaunchKernelGGL(k_scan_down32, dim3(kScanBlocks), dim3(kThreads), 0, s, in,
+                           (uint32_t *)out, n_host, lo, hi, (const uint64_t *)partial);
+    else
+        hipLaunchKernelGGL(k_scan_down<T>, dim3(kScanBlocks), dim3(kThreads), 0, s, in, out,
+                           n_host, lo, hi, (const uint64_t *)partial);
     return hipGetLastError();
 }
 
