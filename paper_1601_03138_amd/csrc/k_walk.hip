@@ -151,25 +151,33 @@ k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, 
             }
             // the stores of a lane run in unrolled chunks of 8 with immediate offsets (the
             // capacity bound hoisted out of the chunk), so a wave spends a few instructions
-            // per slot instead of a masked loop iteration
+            // per slot instead of a masked loop iteration; no store is predicated (a slot past
+            // the lane's count rewrites its last slot with the same value), which keeps the
+            // exec mask and the scalar unit out of the chunk
             if (FILL && leaf) {
                 const uint32_t e0 = ne + lex;
                 const uint32_t nw = e0 < capg ? min(lc, capg - e0) : 0u;
                 uint32_t *dst = list + base + e0;
+                // unconditional stores: slots past nw rewrite slot nw - 1 with its own value
                 for (uint32_t k0 = 0; k0 < nw; k0 += 8) {
 #pragma unroll
-                    for (uint32_t k = 0; k < 8; k++)
-                        if (k0 + k < nw) dst[k0 + k] = lk.x + k0 + k;
+                    for (uint32_t k = 0; k < 8; k++) {
+                        const uint32_t j = min(k0 + k, nw - 1);
+                        dst[j] = lk.x + j;
+                    }
                 }
             }
             ne += ltot;
             // children of opened internal cells onto the stack (at most 8 per cell)
             if (sp + ctot > (uint32_t)kWalkStack) { err = true; break; }
             if (inner) {
+                // unconditional stores, as for the list entries
                 uint32_t *d = stk + sp + cex;
 #pragma unroll
-                for (uint32_t k = 0; k < 8; k++)
-                    if (k < cc) d[k] = lk.x + k;
+                for (uint32_t k = 0; k < 8; k++) {
+                    const uint32_t j = min(k, cc - 1);
+                    d[j] = lk.x + j;
+                }
             }
             sp += ctot;
             wave_barrier();
