@@ -179,8 +179,7 @@ typedef struct {
        force, unsort, predict, total; with FDX_PREDICTOR, predict = features, network and
        capacities and walk = the walk after them (predict = 0 otherwise); with FDX_FUSED,
        predict = features, network and queue boundaries, walk = 0 and force = the one
-       walk + force launch; unsort is 0 and kept for the layout: the force kernels write each
-       particle's result at its place in the caller's order themselves */
+       walk + force launch */
     double t_keys, t_sort, t_tree, t_moments, t_groups, t_walk, t_force, t_unsort, t_predict,
         t_total;
     /* FP32 evaluations: groups evaluated by the FP64 kernel instead, because FP32 rounding of

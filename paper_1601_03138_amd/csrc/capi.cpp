@@ -246,6 +246,7 @@ int enqueue_fill(fdx_ctx *c, size_t gmax, bool spill) {
 // persistent kernels (device count).
 int enqueue_force(fdx_ctx *c, size_t gmax) {
     hipStream_t s = c->stream;
+    const size_t n = (size_t)c->n;
     Groups gv = groups_view(c);
     HIPCHK(c, list_stats(gmax, gv, c->cnt_e.p, c->cnt_s.p, c->st, s));
     const bool persistent = (c->flags & FDX_PERSISTENT) != 0;
@@ -261,8 +262,7 @@ int enqueue_force(fdx_ctx *c, size_t gmax) {
     ForceArgs fa;
     fa.g = &gv; fa.jp = c->jp.p; fa.seps = c->seps.p; fa.mom = c->c_mom.p;
     fa.seg = c->seg.p; fa.cap = c->lcap.p; fa.cnt_e = c->cnt_e.p; fa.cnt_s = c->cnt_s.p;
-    fa.list = c->list.p; fa.order = nullptr; fa.st = c->st;
-    fa.out = ForceOut{c->sperm, c->ax.p, c->ay.p, c->az.p, c->pot.p};
+    fa.list = c->list.p; fa.order = nullptr; fa.fs = c->fs.p; fa.st = c->st;
     fa.quad = (c->flags & FDX_QUAD) != 0;
     fa.fp32 = (c->flags & FDX_FP32REL) != 0;
     fa.persistent = persistent;
@@ -284,12 +284,14 @@ int enqueue_force(fdx_ctx *c, size_t gmax) {
         HIPCHK(c, force(gmax, fw, s));
     }
     mark(c, 7);
-    mark(c, 8);        // no return pass: the force kernels write the caller's order
+    HIPCHK(c, unsort_forces(n, c->fs.p, c->inv.p, c->ax.p, c->ay.p, c->az.p, c->pot.p, s));
+    mark(c, 8);
     return FDX_OK;
 }
 
 int enqueue_fused(fdx_ctx *c, size_t gmax, bool capture) {
     hipStream_t s = c->stream;
+    const size_t n = (size_t)c->n;
     Groups gv = groups_view(c);
     Cells cv = cells_view(c);
     // queue runs at equal cumulative cost (members x predicted list length, or members)
@@ -311,8 +313,7 @@ int enqueue_fused(fdx_ctx *c, size_t gmax, bool capture) {
     fa.seg = capture ? c->seg.p : nullptr;
     fa.cap = capture ? c->lcap.p : nullptr;
     fa.list = capture ? c->list.p : nullptr;
-    fa.out = ForceOut{c->sperm, c->ax.p, c->ay.p, c->az.p, c->pot.p};
-    fa.st = c->st;
+    fa.fs = c->fs.p; fa.st = c->st;
     const bool fp32 = (c->flags & FDX_FP32REL) != 0, quad = (c->flags & FDX_QUAD) != 0;
     fa.skip_wide = fp32 ? 1 : 0;
     HIPCHK(c, fused(gmax, fa, fp32, quad, c->n_group, s));
@@ -328,6 +329,7 @@ int enqueue_fused(fdx_ctx *c, size_t gmax, bool capture) {
     }
     HIPCHK(c, list_stats(gmax, gv, c->cnt_e.p, c->cnt_s.p, c->st, s));
     mark(c, 7);
+    HIPCHK(c, unsort_forces(n, c->fs.p, c->inv.p, c->ax.p, c->ay.p, c->az.p, c->pot.p, s));
     mark(c, 8);
     return FDX_OK;
 }
@@ -626,6 +628,7 @@ int fdx_set_particles(fdx_ctx *c, int64_t n, const double *x, const double *y, c
     HIPCHK(c, c->gcell_at.ensure(N));
     HIPCHK(c, c->gpos.ensure(N));
     HIPCHK(c, c->leaf_lev.ensure(N));
+    HIPCHK(c, c->fs.ensure(N));
     HIPCHK(c, c->ax.ensure(N));
     HIPCHK(c, c->ay.ensure(N));
     HIPCHK(c, c->az.ensure(N));

@@ -107,6 +107,7 @@ struct fdx_ctx {
     bool have_counts = false;      // cnt_e / cnt_s belong to the current groups
 
     // forces
+    fdx::DBuf<double4> fs;
     fdx::DBuf<double> ax, ay, az, pot;
     bool have_force = false;
     bool have_lists = false;       // the lists belong to the current groups (last walk)
@@ -147,7 +148,7 @@ struct fdx_ctx {
         f(g_wide); f(wide_list); f(leaf_lev); f(g_centre);
         f(cnt_e); f(cnt_s); f(lcap); f(list); f(ovf_list); f(seg);
         f(f_cost); f(f_bounds); f(f_pre);
-        f(ax); f(ay); f(az); f(pot);
+        f(fs); f(ax); f(ay); f(az); f(pot);
     }
     // bumped by every fdx_set_particles and every reallocation of a buffer a captured graph
     // refers to; a graph captured under another generation is never replayed

@@ -78,6 +78,9 @@ hipError_t kick_drift(size_t n, double *x, double *y, double *z, double *vx, dou
 hipError_t kick(size_t n, double *vx, double *vy, double *vz, const double *ax,
                 const double *ay, const double *az, double dt, const DevStatus *st,
                 hipStream_t s);
+hipError_t unsort_forces(size_t n, const double4 *fs, const uint32_t *inv, double *ax,
+                         double *ay, double *az, double *pot, hipStream_t s);
+
 // scan: exclusive prefix sums of u32 counts.  The element count is n_host, or, if lo/hi are
 // given, (*hi - *lo) read on the device.  partial must hold kScanBlocks + 1 entries.
 constexpr int kScanBlocks = 512;
@@ -232,14 +235,6 @@ hipError_t direct_forces(uint32_t nt, const uint32_t *targets, const double *x, 
 // is given (then every group's entries are also written to its segment [seg, seg + cap):
 // particles from the front, superparticles from the back).  Groups come from eight per-XCD runs
 // [bounds[x], bounds[x+1]) in tree order, or, with order, from order[k] for k < *count.
-// Where a force kernel writes its results: the particle at sorted rank r is the caller's
-// particle perm[r], and its {ax, ay, az, phi} go to ax[perm[r]], ... directly (the caller's
-// order, so no separate return pass follows the force kernel).
-struct ForceOut {
-    const uint32_t *perm;
-    double *ax, *ay, *az, *pot;
-};
-
 struct FusedArgs {
     Groups g;
     const uint4 *node;
@@ -256,7 +251,7 @@ struct FusedArgs {
     const uint64_t *seg;
     const uint32_t *cap;
     uint32_t *list;
-    ForceOut out;
+    double4 *fs;
     DevStatus *st;
     int skip_wide;           // FP32 pass: groups flagged wide are left to an FP64 pass
 };
@@ -301,7 +296,7 @@ struct ForceArgs {
     const uint32_t *order;  // queue order (null: group order)
     const uint32_t *bounds = nullptr;  // persistent launch: the eight per-XCD runs (null: equal
                                        // group counts)
-    ForceOut out;           // results, written in the caller's order
+    double4 *fs;            // sorted output {ax, ay, az, phi}
     DevStatus *st;
     bool quad, fp32, persistent;
     int variant;            // kernel shape chosen by the autotuner

@@ -45,7 +45,7 @@ struct KArgs {
     const uint32_t *order;
     const uint32_t *bounds;  // persistent: per-XCD runs [bounds[x], bounds[x+1]) (or null)
     const uint32_t *ngroups;
-    ForceOut out;
+    double4 *fs;
     DevStatus *st;
     uint32_t G;              // groups (direct launch); persistent kernels read *ngroups
     double cut_s;            // cutoff kernel: 2 / r_cut
@@ -242,9 +242,7 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
             const uint32_t r = gb + i;
             const T mi = (T)a.jp[r].w;
             const T self = CUT ? (T)0 : mi * rsqrt_t(e2[k]);
-            const uint32_t u = a.out.perm[r];
-            a.out.ax[u] = s[0]; a.out.ay[u] = s[1]; a.out.az[u] = s[2];
-            a.out.pot[u] = CUT ? 0.0 : s[3] + (double)self;
+            a.fs[r] = make_double4(s[0], s[1], s[2], CUT ? 0.0 : s[3] + (double)self);
         }
     }
     __syncthreads();
@@ -416,7 +414,7 @@ hipError_t force(size_t G, const ForceArgs &fa, hipStream_t s) {
     k.list = fa.list;
     k.order = fa.order; k.bounds = fa.bounds;
     k.ngroups = fa.count ? fa.count : &fa.st->n_groups_c;
-    k.out = fa.out; k.st = fa.st;
+    k.fs = fa.fs; k.st = fa.st;
     k.G = (uint32_t)G;
     k.cut_s = fa.r_cut > 0 ? 2.0 / fa.r_cut : 0.0;
     if (fa.r_cut > 0) {                // tree part of TreePM: monopole with the S2 cutoff

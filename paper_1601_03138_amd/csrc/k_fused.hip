@@ -353,9 +353,7 @@ __device__ __forceinline__ void fused_group(const FusedArgs &a, uint32_t gi, uin
             const uint32_t r = gb + i;
             const T mi = (T)a.jp[r].w;
             const T self = mi * rsqrt_t(e2[k]);
-            const uint32_t u = a.out.perm[r];
-            a.out.ax[u] = s0; a.out.ay[u] = s1; a.out.az[u] = s2;
-            a.out.pot[u] = s3 + (double)self;
+            a.fs[r] = make_double4(s0, s1, s2, s3 + (double)self);
         }
     }
     wave_barrier();

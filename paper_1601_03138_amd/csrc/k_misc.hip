@@ -81,6 +81,16 @@ __global__ void k_kick(size_t n, double *vx, double *vy, double *vz, const doubl
     }
 }
 
+// Forces from sorted rank back to the caller's order: a[u] = fs[inv[u]] (coalesced writes,
+// one 32-byte gather per particle).
+__global__ void k_unsort(size_t n, const double4 *fs, const uint32_t *inv, double *ax,
+                         double *ay, double *az, double *pot) {
+    for (size_t u = gtid(); u < n; u += gstride()) {
+        double4 f = fs[inv[u]];
+        ax[u] = f.x; ay[u] = f.y; az[u] = f.z; pot[u] = f.w;
+    }
+}
+
 // ---------------------------------------------------------------------------------------
 // Reduce-then-scan over a fixed grid of kScanBlocks blocks; the element count may live in
 // device memory (so the whole tree build runs without host round trips).
@@ -257,6 +267,13 @@ hipError_t kick(size_t n, double *vx, double *vy, double *vz, const double *ax,
     if (!n) return hipSuccess;
     hipLaunchKernelGGL(k_kick, dim3(grid_for(n)), dim3(kThreads), 0, s, n, vx, vy, vz, ax, ay,
                        az, dt, st);
+    return hipGetLastError();
+}
+hipError_t unsort_forces(size_t n, const double4 *fs, const uint32_t *inv, double *ax,
+                         double *ay, double *az, double *pot, hipStream_t s) {
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(k_unsort, dim3(grid_for(n)), dim3(kThreads), 0, s, n, fs, inv, ax, ay,
+                       az, pot);
     return hipGetLastError();
 }
 hipError_t scan_u32_to_u32(const uint32_t *in, uint32_t *out, size_t n_host,

@@ -162,6 +162,7 @@ int fdx_calc_force_noalloc(int device, void *hip_stream, int64_t n, const double
     cv.take(c.gcell_at, N);
     cv.take(c.gpos, N);
     cv.take(c.leaf_lev, N);
+    cv.take(c.fs, N);
     // cells
     cv.take(c.c_level, ccap); cv.take(c.c_begin, ccap); cv.take(c.c_count, ccap);
     cv.take(c.c_first, ccap); cv.take(c.c_nchild, ccap); cv.take(c.c_parent, ccap);
