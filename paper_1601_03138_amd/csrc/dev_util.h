@@ -131,6 +131,17 @@ __device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t *lds, u
     return base + x - v;
 }
 
+// a value that every lane of the wave holds, moved to a scalar register
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+    return (uint64_t)uniform_u32((uint32_t)v) | ((uint64_t)uniform_u32((uint32_t)(v >> 32)) << 32);
+}
+__device__ __forceinline__ double uniform_f64(double v) {
+    return __longlong_as_double((long long)uniform_u64((uint64_t)__double_as_longlong(v)));
+}
+
 __device__ __forceinline__ void wave_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();

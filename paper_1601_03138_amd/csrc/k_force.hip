@@ -84,13 +84,17 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
     static_assert(JT <= NT && NT % JT == 0, "a tile holds at most one entry per thread");
     using V = typename V4<T>::t;
     const int tid = threadIdx.x;
-    const uint32_t gb = a.gbegin[gi], ni = a.gcount[gi];
-    const uint32_t ne = a.cnt_e[gi], ns = a.cnt_s[gi], capg = a.cap[gi];
-    const uint32_t *epj = a.list + a.seg[gi];
+    // the group's values are the same in every lane: held in scalar registers
+    gi = uniform_u32(gi);
+    const uint32_t gb = uniform_u32(a.gbegin[gi]), ni = uniform_u32(a.gcount[gi]);
+    const uint32_t ne = uniform_u32(a.cnt_e[gi]), ns = uniform_u32(a.cnt_s[gi]);
+    const uint32_t capg = uniform_u32(a.cap[gi]);
+    const uint32_t *epj = a.list + uniform_u64(a.seg[gi]);
     const uint32_t *spj = epj + capg - ns;
     const bool fp32 = sizeof(T) == 4;
-    const double cx = fp32 ? a.gcentre[3 * gi] : 0.0, cy = fp32 ? a.gcentre[3 * gi + 1] : 0.0,
-                 cz = fp32 ? a.gcentre[3 * gi + 2] : 0.0;
+    const double cx = fp32 ? uniform_f64(a.gcentre[3 * gi]) : 0.0;
+    const double cy = fp32 ? uniform_f64(a.gcentre[3 * gi + 1]) : 0.0;
+    const double cz = fp32 ? uniform_f64(a.gcentre[3 * gi + 2]) : 0.0;
     const T cut_s = (T)a.cut_s;
 
     uint32_t tps = (ni + IPL - 1) / IPL;
@@ -225,25 +229,30 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
 #pragma unroll
         for (int k = 0; k < IPL; k++) {
             double *o = sm.red + 4 * ((size_t)k * NT + tid);
-            o[0] = ax[k].val(); o[1] = ay[k].val(); o[2] = az[k].val(); o[3] = ph[k].val();
+            // slice 0 carries the potential's self term (added first, in FP64); only slots
+            // that hold a particle of the group read its mass (a slot past n_i does not)
+            const uint32_t i = li + k * tps;
+            double self = 0.0;
+            if (!CUT && slice == 0 && i < ni) self = (double)((T)a.jp[gb + i].w * rsqrt_t(e2[k]));
+            o[0] = ax[k].val(); o[1] = ay[k].val(); o[2] = az[k].val(); o[3] = self + ph[k].val();
         }
     }
     __syncthreads();
-    if (slice == 0) {
-#pragma unroll
-        for (int k = 0; k < IPL; k++) {
-            const uint32_t i = li + k * tps;
-            if (i >= ni) continue;
-            double s[4] = {0, 0, 0, 0};
-            for (uint32_t q = 0; q < nslice; q++) {
-                const double *o = sm.red + 4 * ((size_t)k * NT + q * tps + li);
-                s[0] += o[0]; s[1] += o[1]; s[2] += o[2]; s[3] += o[3];
-            }
-            const uint32_t r = gb + i;
-            const T mi = (T)a.jp[r].w;
-            const T self = CUT ? (T)0 : mi * rsqrt_t(e2[k]);
-            a.fs[r] = make_double4(s[0], s[1], s[2], CUT ? 0.0 : s[3] + (double)self);
-        }
+    // one thread per (component, i-particle slot) sums that component over the slices in
+    // slice order -- the same order for every launch shape that shares tps -- so a small
+    // group's many slices are combined by 4 x tps threads instead of tps
+#pragma unroll 1
+    for (uint32_t t = (uint32_t)tid; t < 4u * IPL * tps; t += NT) {
+        const uint32_t c = t & 3u, slot = t >> 2;
+        const uint32_t k = IPL == 1 ? 0u : slot / tps, lk = slot - k * tps;
+        const uint32_t i = lk + k * tps;
+        if (i >= ni) continue;
+        double v = 0;
+        const double *o = sm.red + 4 * ((size_t)k * NT + lk) + c;
+#pragma unroll 1
+        for (uint32_t q = 0; q < nslice; q++) v += o[4 * (size_t)q * tps];
+        const uint32_t r = gb + i;
+        reinterpret_cast<double *>(a.fs + r)[c] = (CUT && c == 3) ? 0.0 : v;
     }
     __syncthreads();
 }

@@ -61,6 +61,36 @@ def test_every_shape_and_the_persistent_queue(ctx, fdx):
     ctx.set_shape(-1)
 
 
+def test_every_shape_with_a_page_exact_particle_array(fdx):
+    # 2^16 particles: the sorted particle records (32 B each) fill exactly 2 MiB, so nothing
+    # lies behind the last one; the last group holds 3 particles, so a shape with two
+    # i-particles per lane has slots past the group's end in it.  Every shape, direct and
+    # persistent, FP32 and FP64, agrees with the oracle tree; a kernel that read a slot past
+    # the group would read past the array here.
+    ps = I.clustered(n_background=(1 << 16) - 8 * 2000, n_clusters=8, n_per_cluster=2000,
+                     seed=44, eps=0.01)
+    t = O.build_tree(ps, 8)
+    g = O.make_groups(t, 200)
+    assert ps.n == 1 << 16 and int(g.count[-1]) % 2 == 1
+    ref = _ref_forces(ps, 8, 200, 0.5, True)
+    with fdx.Context(0) as c:                   # a fresh context: buffers sized exactly
+        c.set_particles(ps)
+        for shape in range(c.lib.fdx_autotune_shapes()):
+            c.set_shape(shape)
+            _say(f"[page-exact] shape {c.shape_name(shape)}")
+            for fp32 in (False, True):
+                c.calc_force(0.5, 8, 200, 0.0, quad=True, fp32=fp32)
+                a = c.forces()
+                c.calc_force(0.5, 8, 200, 0.0, quad=True, fp32=fp32, persistent=True)
+                assert np.array_equal(a, c.forces())
+                e = rel_err(a, ref)
+                if fp32:
+                    assert np.sqrt(np.mean(e ** 2)) <= F32_RMS_REL_VS_TREE
+                else:
+                    assert e.max() <= F64_MAX_REL
+                assert np.allclose(a[:, 3], ref[:, 3], rtol=1e-4 if fp32 else 1e-9, atol=0)
+
+
 def test_autotuner_picks_a_measured_candidate(ctx, fdx):
     ps = I.plummer(60000, seed=13, eps=1 / 256)
     ctx.set_particles(ps)
