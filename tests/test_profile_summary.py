@@ -78,3 +78,38 @@ def test_phases_table_scales_counters_and_counts_algorithmic_bytes(tmp_path):
     assert float(row[5]) == pytest.approx((40 * 2 + 30) * 1024, rel=1e-3)   # scaled counters
     assert float(row[6]) == pytest.approx(68000 / 2e-6 / 1e9, abs=1)
     assert P.stats_csv(str(trace)).splitlines()[2].startswith("| `k_unsort` | 3 | 0.006 |")
+
+
+def test_phases_table_sums_per_level_kernels_over_an_evaluation(tmp_path):
+    # two evaluations (two k_bbox_init dispatches), each with three k_moments launches of 1, 2
+    # and 3 us and counter readings 10, 20, 30 KiB: the row is per evaluation (6 us, 60 KiB
+    # scaled), not a median over the launches
+    trace = tmp_path / "trace"
+    os.makedirs(trace)
+    names = []
+    with open(trace / "run_kernel_trace.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        for _ in range(2):
+            w.writerow({"Kernel_Name": "k_bbox_init(int, ...)", "Start_Timestamp": 0,
+                        "End_Timestamp": 500})
+            for t in (1000, 2000, 3000):
+                w.writerow({"Kernel_Name": "k_moments(int, ...)", "Start_Timestamp": 0,
+                            "End_Timestamp": t})
+    f_rows = [("copy", "FETCH_SIZE", 512.0, 0, 1)]
+    w_rows = [("copy", "WRITE_SIZE", 1024.0, 0, 1)]
+    for _ in range(2):
+        f_rows.append(("k_bbox_init(int, ...)", "FETCH_SIZE", 1.0, 0, 1))
+        w_rows.append(("k_bbox_init(int, ...)", "WRITE_SIZE", 1.0, 0, 1))
+        for v in (10.0, 20.0, 30.0):
+            f_rows.append(("k_moments(int, ...)", "FETCH_SIZE", v, 0, 1))
+            w_rows.append(("k_moments(int, ...)", "WRITE_SIZE", v, 0, 1))
+    _write(str(tmp_path / "f"), f_rows)
+    _write(str(tmp_path / "w"), w_rows)
+    N, C = 1000, 100
+    out = P.phases(str(trace), str(tmp_path / "f"), str(tmp_path / "w"), N, C, 0, 0, "copy",
+                   1048576, 1048576)
+    row = [r for r in out.splitlines() if "k_moments" in r][0].split("|")
+    assert float(row[3]) == pytest.approx(0.006)                         # ms per evaluation
+    assert float(row[4]) == pytest.approx(160 * C + 32 * N)              # algorithmic bytes
+    assert float(row[5]) == pytest.approx((60 * 2 + 60) * 1024, rel=1e-3)  # scaled counters
