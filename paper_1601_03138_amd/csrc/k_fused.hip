@@ -135,9 +135,10 @@ __device__ __forceinline__ void fused_group(const FusedArgs &a, uint32_t gi, uin
     const Groups &g = a.g;
     const uint32_t gb = (uint32_t)__builtin_amdgcn_readfirstlane((int)g.begin[gi]);
     const bool fp32 = sizeof(T) == 4;
-    const double cx = fp32 ? g.centre[3 * (size_t)gi] : 0.0;
-    const double cy = fp32 ? g.centre[3 * (size_t)gi + 1] : 0.0;
-    const double cz = fp32 ? g.centre[3 * (size_t)gi + 2] : 0.0;
+    // the group's values are the same in every lane: held in scalar registers
+    const double cx = fp32 ? uniform_f64(g.centre[3 * (size_t)gi]) : 0.0;
+    const double cy = fp32 ? uniform_f64(g.centre[3 * (size_t)gi + 1]) : 0.0;
+    const double cz = fp32 ? uniform_f64(g.centre[3 * (size_t)gi + 2]) : 0.0;
 
     uint32_t tps = (ni + ipl - 1) / ipl;
     tps = tps < 1 ? 1 : (tps > (uint32_t)kWave ? (uint32_t)kWave : tps);
@@ -168,8 +169,10 @@ __device__ __forceinline__ void fused_group(const FusedArgs &a, uint32_t gi, uin
     }
 
     const uint32_t *bx = g.box + 6 * (size_t)gi;
-    const int bminx = 2 * (int)bx[0], bminy = 2 * (int)bx[1], bminz = 2 * (int)bx[2];
-    const int bmaxx = 2 * (int)bx[3] + 2, bmaxy = 2 * (int)bx[4] + 2, bmaxz = 2 * (int)bx[5] + 2;
+    const int bminx = 2 * (int)uniform_u32(bx[0]), bminy = 2 * (int)uniform_u32(bx[1]);
+    const int bminz = 2 * (int)uniform_u32(bx[2]);
+    const int bmaxx = 2 * (int)uniform_u32(bx[3]) + 2, bmaxy = 2 * (int)uniform_u32(bx[4]) + 2;
+    const int bmaxz = 2 * (int)uniform_u32(bx[5]) + 2;
 
     // wave-uniform bookkeeping
     uint32_t ns_p = 0, ne_p = 0, nr = 0;         // pending superparticles, particles, ranges
