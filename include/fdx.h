@@ -95,9 +95,9 @@ int fdx_destroy(fdx_ctx *ctx);
  *   unchanged by others until fdx_destroy or the next fdx_set_particles.  sys_off is always
  *   a host pointer.
  * Masses must be finite and >= 0, eps finite and > 0 (checked on the host for host memory
- * and on the device, reported by the next fdx_calc_force, for device memory).  When every
- * eps is the same value (checked once here), evaluations use that value directly instead of
- * reading the array per particle; the results are the same.
+ * and on the device, reported by the next fdx_calc_force, for device memory).  When all eps
+ * of each system are one value (checked once here), evaluations take it from the system's
+ * first particle instead of reading the array per particle; the results are the same.
  * FDX_EINVAL: n < 0, n >= 2^31, a null array, n_sys < 1, offsets not ascending from 0 to n,
  * or an invalid value. */
 int fdx_set_particles(fdx_ctx *ctx, int64_t n, const double *x, const double *y,

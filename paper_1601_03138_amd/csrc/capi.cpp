@@ -134,10 +134,9 @@ int enqueue_keys_sort(fdx_ctx *c) {
                                                                            : nullptr));
     c->skey = alt ? c->key_alt.p : c->key.p;
     c->sperm = alt ? c->perm_alt.p : c->perm.p;
-    const bool eps_each = c->eps_given && !c->eps_uniform;
-    HIPCHK(c, gather_sorted(n, c->sperm, c->packed.p, eps_each ? c->eps : nullptr,
-                            c->eps_given ? c->eps_uniform_val : c->eps_all, c->jp.p, c->seps.p,
-                            c->inv.p, s));
+    HIPCHK(c, gather_sorted(n, c->sperm, c->packed.p, c->eps_given ? c->eps : nullptr,
+                            c->eps_all, c->eps_given && c->eps_per_system, c->sys_off.p, S,
+                            c->jp.p, c->seps.p, c->inv.p, s));
     mark(c, 2);
     return FDX_OK;
 }
@@ -572,11 +571,13 @@ int fdx_set_particles(fdx_ctx *c, int64_t n, const double *x, const double *y, c
                 if (!(eps[i] > 0.0) || !std::isfinite(eps[i]))
                     return fail(c, FDX_EINVAL, "eps must be finite and > 0");
     }
-    c->eps_uniform = false;
-    c->eps_uniform_val = 0.0;
+    c->eps_per_system = false;
     if (mem_kind == FDX_MEM_HOST && eps && n > 0) {
-        c->eps_uniform = std::all_of(eps, eps + n, [&](double e) { return e == eps[0]; });
-        c->eps_uniform_val = eps[0];
+        bool same = true;
+        for (int s = 0; s < n_sys && same; s++)
+            same = std::all_of(eps + off[s], eps + off[s + 1],
+                               [&](double e) { return e == eps[off[s]]; });
+        c->eps_per_system = same;
     }
     c->have_particles = false;
     c->have_force = false;
@@ -636,16 +637,12 @@ int fdx_set_particles(fdx_ctx *c, int64_t n, const double *x, const double *y, c
     const bool dev_eps = c->borrowed && eps && n > 0;
     if (dev_eps) {
         HIPCHK(c, fill_u32(&c->st->eps_varies, 0u, 1, s));
-        HIPCHK(c, eps_varies(N, c->eps, &c->st->eps_varies, s));
+        HIPCHK(c, eps_varies(N, c->eps, c->sysid.p, c->sys_off.p, &c->st->eps_varies, s));
         HIPCHK(c, hipMemcpyAsync(&c->hst->st.eps_varies, &c->st->eps_varies, sizeof(uint32_t),
                                  hipMemcpyDeviceToHost, s));
-        HIPCHK(c, hipMemcpyAsync(&c->hst->eps0, c->eps, sizeof(double), hipMemcpyDeviceToHost, s));
     }
     HIPCHK(c, hipStreamSynchronize(s));   // host arrays may be freed by the caller afterwards
-    if (dev_eps) {
-        c->eps_uniform = c->hst->st.eps_varies == 0;
-        c->eps_uniform_val = c->hst->eps0;
-    }
+    if (dev_eps) c->eps_per_system = c->hst->st.eps_varies == 0;
     c->have_particles = true;
     c->stats = fdx_stats{};
     return FDX_OK;

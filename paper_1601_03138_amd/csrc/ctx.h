@@ -41,7 +41,6 @@ struct DBuf {
 struct HostStatus {
     DevStatus st;
     uint32_t lvl[kLevels + 2];
-    double eps0;              // the first particle's eps (device-resident input)
 };
 
 }  // namespace fdx
@@ -57,10 +56,10 @@ struct fdx_ctx {
     int64_t n = 0;
     int nsys = 0;
     bool have_particles = false, borrowed = false, eps_given = false;
-    // every particle has the same eps (eps_uniform_val): the sorted gather writes that value
-    // instead of reading eps through the permutation (the same result, one random read less)
-    bool eps_uniform = false;
-    double eps_uniform_val = 0.0;
+    // every system's particles share one eps: the sorted gather takes it from the system's first
+    // particle instead of reading eps through the permutation (the same result, one random
+    // read per particle less)
+    bool eps_per_system = false;
     std::vector<int64_t> sys_off_h;
     fdx::DBuf<double> ox, oy, oz, ovx, ovy, ovz, om, oeps;       // owned copies
     double *x = nullptr, *y = nullptr, *z = nullptr, *vx = nullptr, *vy = nullptr,

@@ -30,7 +30,8 @@ struct DevStatus {
     uint32_t group_overflow;  // more groups than the group arrays hold
     uint32_t top_level;       // deepest tree level whose cells fit the cell capacity
     uint32_t wide_groups;     // FP32 evaluation: groups too wide for group-relative FP32
-    uint32_t eps_varies;      // fdx_set_particles, device eps: some eps differs from eps[0]
+    uint32_t eps_varies;      // fdx_set_particles, device eps: some eps differs from the eps of
+                              // its system's first particle
     uint32_t xcd_head[8];     // persistent force kernel: next slot of each XCD's queue
     uint64_t spill_used;      // fill walk: entries taken after list_total by relocated lists
     uint32_t spilled;         // fill walk: groups whose list was relocated there
@@ -113,11 +114,13 @@ hipError_t radix_sort(size_t n, uint64_t *key, uint64_t *key_alt, uint32_t *val,
 // sorted particle data
 hipError_t pack_particles(size_t n, const double *x, const double *y, const double *z,
                           const double *m, double4 *packed, hipStream_t s);
-// flag |= 1 if some eps[i] differs from eps[0] (n >= 1)
-hipError_t eps_varies(size_t n, const double *eps, uint32_t *flag, hipStream_t s);
+// flag |= 1 if some eps[i] differs from the eps of its system's first particle
+hipError_t eps_varies(size_t n, const double *eps, const uint32_t *sysid, const int64_t *off,
+                      uint32_t *flag, hipStream_t s);
+// per_system: every system's particles share one eps (taken from its first particle)
 hipError_t gather_sorted(size_t n, const uint32_t *perm, const double4 *packed,
-                         const double *eps, double eps_all, double4 *jp, double *seps,
-                         uint32_t *inv, hipStream_t s);
+                         const double *eps, double eps_all, bool per_system, const int64_t *off,
+                         int nsys, double4 *jp, double *seps, uint32_t *inv, hipStream_t s);
 
 // tree
 // scratch words tree_build needs besides 3 n bytes

@@ -38,11 +38,12 @@ __global__ void k_check_input(size_t n, const double *x, const double *y, const 
     if (bad) atomicOr(&st->bad_input, 1u);
 }
 
-// flag |= 1 if some eps[i] differs from eps[0] (a NaN differs from everything)
-__global__ void k_eps_varies(size_t n, const double *eps, uint32_t *flag) {
-    const double e0 = eps[0];
+// flag |= 1 if some eps[i] differs from the eps of the first particle of its system (a NaN
+// differs from everything)
+__global__ void k_eps_varies(size_t n, const double *eps, const uint32_t *sysid,
+                             const int64_t *off, uint32_t *flag) {
     bool v = false;
-    for (size_t i = gtid(); i < n; i += gstride()) v |= !(eps[i] == e0);
+    for (size_t i = gtid(); i < n; i += gstride()) v |= !(eps[i] == eps[off[sysid[i]]]);
     if (v) atomicOr(flag, 1u);
 }
 
@@ -243,9 +244,11 @@ hipError_t check_input(size_t n, const double *x, const double *y, const double 
                        z, m, eps, st);
     return hipGetLastError();
 }
-hipError_t eps_varies(size_t n, const double *eps, uint32_t *flag, hipStream_t s) {
+hipError_t eps_varies(size_t n, const double *eps, const uint32_t *sysid, const int64_t *off,
+                      uint32_t *flag, hipStream_t s) {
     if (!n) return hipSuccess;
-    hipLaunchKernelGGL(k_eps_varies, dim3(grid_for(n, 4096)), dim3(kThreads), 0, s, n, eps, flag);
+    hipLaunchKernelGGL(k_eps_varies, dim3(grid_for(n, 4096)), dim3(kThreads), 0, s, n, eps, sysid,
+                       off, flag);
     return hipGetLastError();
 }
 hipError_t sysid_fill(const int64_t *off, int nsys, uint32_t *sysid, size_t n, hipStream_t s) {

@@ -36,13 +36,28 @@ __global__ void k_pack(size_t n, const double *x, const double *y, const double 
     for (size_t i = gtid(); i < n; i += gstride()) packed[i] = make_double4(x[i], y[i], z[i], m[i]);
 }
 
+// system holding sorted position r: the last s with off[s] <= r (skips empty systems)
+__device__ __forceinline__ int system_of(const int64_t *off, int nsys, size_t r) {
+    int lo = 0, hi = nsys - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((uint64_t)off[mid] <= r) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Sorted records, softenings and the inverse permutation.  The sort keeps every system's
+// particles in the same range [off[s], off[s + 1]) as the caller's layout, so when every
+// system's particles share one softening (per_system) rank r takes it from the first particle
+// of its system -- a cached read per system instead of a random read per particle.
 __global__ void k_gather_sorted(size_t n, const uint32_t *perm, const double4 *packed,
-                                const double *eps, double eps_all, double4 *jp, double *seps,
+                                const double *eps, double eps_all, int per_system,
+                                const int64_t *off, int nsys, double4 *jp, double *seps,
                                 uint32_t *inv) {
     for (size_t r = gtid(); r < n; r += gstride()) {
         const uint32_t i = perm[r];
         jp[r] = packed[i];
-        seps[r] = eps ? eps[i] : eps_all;
+        seps[r] = per_system ? eps[off[system_of(off, nsys, r)]] : (eps ? eps[i] : eps_all);
         inv[i] = (uint32_t)r;
     }
 }
@@ -89,16 +104,6 @@ constexpr int kTileW = kTileRounds * kWave;        // 1024 positions per wave ti
 __device__ __forceinline__ int shared_levels(uint64_t a, uint64_t b) {
     const uint64_t x = a ^ b;                       // keys use the low 63 bits
     return x ? (__clzll((long long)x) - 1) / 3 : kLevels;
-}
-
-// system holding sorted position r: the last s with off[s] <= r (skips empty systems)
-__device__ __forceinline__ int system_of(const int64_t *off, int nsys, size_t r) {
-    int lo = 0, hi = nsys - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if ((uint64_t)off[mid] <= r) lo = mid; else hi = mid - 1;
-    }
-    return lo;
 }
 
 // the same search by a whole wave (every lane gets the result): a 64-way search, one round of
@@ -495,11 +500,11 @@ hipError_t pack_particles(size_t n, const double *x, const double *y, const doub
 }
 
 hipError_t gather_sorted(size_t n, const uint32_t *perm, const double4 *packed,
-                         const double *eps, double eps_all, double4 *jp, double *seps,
-                         uint32_t *inv, hipStream_t s) {
+                         const double *eps, double eps_all, bool per_system, const int64_t *off,
+                         int nsys, double4 *jp, double *seps, uint32_t *inv, hipStream_t s) {
     if (!n) return hipSuccess;
     hipLaunchKernelGGL(k_gather_sorted, dim3(grid_for(n)), dim3(kThreads), 0, s, n, perm, packed,
-                       eps, eps_all, jp, seps, inv);
+                       eps, eps_all, (per_system && eps) ? 1 : 0, off, nsys, jp, seps, inv);
     return hipGetLastError();
 }
 

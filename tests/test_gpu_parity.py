@@ -285,6 +285,34 @@ def test_uniform_eps_array_takes_the_global_softening_path(ctx, fdx):
         assert np.allclose(a, ref, rtol=1e-9, atol=1e-12)
 
 
+def test_eps_shared_within_each_system(ctx, fdx):
+    # systems of one softening each (different between systems, empty systems first, in the
+    # middle and last): the sorted gather takes each system's value from its first particle;
+    # one differing value inside a system switches the per-particle gather back on.  Forces
+    # match the oracle tree either way, from host and from device input.
+    import torch
+    sets = [I.plummer(700, seed=27, eps=0.01), I.plummer(1300, seed=28, eps=0.03),
+            I.uniform_cube(900, seed=29, eps=0.005)]
+    both = I.concat(sets)
+    both.sys_off = np.array([0, 0, 700, 700, 2000, 2900, 2900], dtype=np.int64)
+    _say(f"[eps per system] n={both.n} systems={len(both.sys_off) - 1}")
+    for k in (None, 1500):                      # None: one eps per system; else one differs
+        q = I._pack(np.stack([both.x, both.y, both.z], 1), np.zeros((both.n, 3)), both.m,
+                    both.eps.copy(), both.sys_off)
+        if k is not None:
+            q.eps[k] *= 2.0
+        ref = O.tree_force(q, 0.5, 8, 64, quad=True)
+        dev = {name: torch.tensor(getattr(q, name), dtype=torch.float64, device="cuda")
+               for name in ("x", "y", "z", "vx", "vy", "vz", "m", "eps")}
+        for host in (True, False):
+            if host:
+                ctx.set_particles(q)
+            else:
+                ctx.set_particles_device(dev, q.sys_off)
+            ctx.calc_force(0.5, 8, 64, 0.0, quad=True, fp32=False)
+            assert np.allclose(ctx.forces(), ref, rtol=1e-9, atol=1e-12), (k, host)
+
+
 def test_leapfrog_step_matches_oracle(ctx):
     # one force evaluation plus one KDK step of the sample program, dt = 1/128, N = 4096
     ps = I.workload("plummer4k")
