@@ -210,8 +210,9 @@ int enqueue_count(fdx_ctx *c, size_t gmax) {
                              nullptr, nullptr, 0, nullptr, c->cnt_e.p, c->cnt_s.p, c->ovf_list.p,
                              c->st, s));
     else
-        HIPCHK(c, walk(false, gmax, gv, cells_view(c), c->theta * c->theta, nullptr, nullptr, 0,
-                       nullptr, c->cnt_e.p, c->cnt_s.p, c->ovf_list.p, nullptr, nullptr, c->st, s));
+        HIPCHK(c, walk_runs(false, gmax, gv, cells_view(c), c->theta * c->theta, nullptr,
+                            nullptr, 0, nullptr, c->cnt_e.p, c->cnt_s.p, c->ovf_list.p, nullptr,
+                            nullptr, c->st, s));
     HIPCHK(c, list_caps(gmax, c->cnt_e.p, c->cnt_s.p, c->lcap.p, c->st, s));
     HIPCHK(c, scan_u32_to_u64(c->lcap.p, c->seg.p, 0, nullptr, &c->st->n_groups_c, c->partial.p,
                               &c->st->list_total, s));
@@ -235,9 +236,9 @@ int enqueue_fill(fdx_ctx *c, size_t gmax, bool spill) {
                              c->seg.p, c->lcap.p, c->list_cap, c->list.p, c->cnt_e.p, c->cnt_s.p,
                              c->ovf_list.p, c->st, s));
     else
-        HIPCHK(c, walk(true, gmax, gv, cells_view(c), c->theta * c->theta, c->seg.p, c->lcap.p,
-                       c->list_cap, c->list.p, c->cnt_e.p, c->cnt_s.p, c->ovf_list.p, nullptr,
-                       nullptr, c->st, s, spill));
+        HIPCHK(c, walk_runs(true, gmax, gv, cells_view(c), c->theta * c->theta, c->seg.p,
+                            c->lcap.p, c->list_cap, c->list.p, c->cnt_e.p, c->cnt_s.p,
+                            c->ovf_list.p, nullptr, nullptr, c->st, s, spill));
     return FDX_OK;
 }
 

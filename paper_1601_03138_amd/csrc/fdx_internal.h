@@ -176,6 +176,12 @@ hipError_t walk(bool fill, size_t gmax, const Groups g, const Cells c, double th
                 uint64_t *seg, uint32_t *cap, uint64_t list_cap, uint32_t *list,
                 uint32_t *cnt_e, uint32_t *cnt_s, uint32_t *ovf_list, const uint32_t *sel,
                 const uint32_t *nsel, DevStatus *st, hipStream_t s, bool spill = false);
+// the same lists (as sets; the order differs) from walks that share the upper tree between
+// runs of consecutive groups; for the tree's own groups (g.sys holds each group's system)
+hipError_t walk_runs(bool fill, size_t gmax, const Groups g, const Cells c, double theta2,
+                     uint64_t *seg, uint32_t *cap, uint64_t list_cap, uint32_t *list,
+                     uint32_t *cnt_e, uint32_t *cnt_s, uint32_t *ovf_list, const uint32_t *sel,
+                     const uint32_t *nsel, DevStatus *st, hipStream_t s, bool spill = false);
 // short-range walk (kind 1: group radius, 2: cell radius, 3: the larger; no superparticles)
 // or the TreePM cutoff walk (kind 4: cells beyond sa.r_fixed dropped, opening angle theta
 // for the rest)

@@ -221,6 +221,287 @@ k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, 
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// Gravity walk by runs of kRun consecutive groups (tree order, so neighbours in space) that
+// share the upper tree.  The run's box B contains every member's box, so for a cell c:
+//   * if c passes the opening test against B, it passes against every member's box (the
+//     distance to a member's box is at least the distance to B, and the rounded product is
+//     monotone in it);
+//   * if c fails the test even at B's far corners (per axis the larger distance from the
+//     cell centre to B's faces bounds the distance to any member's box), every member opens c;
+//   * otherwise c is a frontier cell: each member tests it in its own walk.
+// A first walk of B descends only through cells every member opens and emits the entries
+// every member's list holds (accepted cells, particles of opened leaves) into each member's
+// segment; each member then walks on from the frontier.  Every member's list is the same set
+// as the one its own walk from the root gives (all of an emitted cell's ancestors are opened
+// by every member); only the order of the entries differs.  Runs that straddle two systems,
+// or whose frontier outgrows kFront, are walked group by group from the root.  With a
+// selection (groups re-walked after an overflow) a selected group repeats its run's first
+// walk, so its entries come in the same order as in a walk of all groups.
+constexpr int kRun = 4;                 // groups per run
+constexpr int kFront = 224;             // frontier cells kept per wave
+
+// the opening test at the box's far corners: false means every box inside [bmin, bmax] opens
+// the cell (per axis max(c - bmin, bmax - c) bounds the distance to any box inside; the
+// squares are exact integers and the product is rounded once, as in cell_accepted)
+__device__ __forceinline__ bool far_accepted(const uint4 nd, int bminx, int bminy, int bminz,
+                                             int bmaxx, int bmaxy, int bmaxz, double theta2) {
+    const int lv = (int)(nd.w & 0xFFu);
+    const int cx = (int)nd.x, cy = (int)nd.y, cz = (int)nd.z;
+    const int ex = max(cx - bminx, bmaxx - cx);
+    const int ey = max(cy - bminy, bmaxy - cy);
+    const int ez = max(cz - bminz, bmaxz - cz);
+    const double E2 = (double)ex * (double)ex + (double)ey * (double)ey +
+                      (double)ez * (double)ez;
+    const double S2 = __longlong_as_double((long long)(1023 + 2 * (22 - lv)) << 52);
+    return S2 < __dmul_rn(theta2, E2);
+}
+
+// The stack loop of one walk (the loop of k_walk, gravity only).  SUPER: the run's first walk
+// (frontier cells to `front`, entries to the first nt of kRun targets); else a member's own
+// walk (one target).  Returns 0, 1 when the stack is exhausted, 2 when the frontier is full.
+template <bool FILL, bool SUPER>
+__device__ __forceinline__ int run_stack(uint32_t *stk, uint32_t sp, uint32_t *front,
+                                         uint32_t &nf, const uint4 *node, const uint2 *link,
+                                         uint32_t ccap, double theta2, const int (&b)[6],
+                                         uint32_t *list, const uint64_t (&base)[kRun],
+                                         const uint32_t (&capg)[kRun], int nt, uint32_t &ne,
+                                         uint32_t &ns) {
+    constexpr int NT = SUPER ? kRun : 1;
+    const int lane = lane_id();
+    const uint64_t lt = lanemask_lt();
+    while (sp > 0) {
+        const int room = kWalkStack - kSlack - (int)sp;
+        uint32_t p = min(64u, sp);
+        if (room < 7 * (int)p) p = room >= 7 ? (uint32_t)(room / 7) : 1u;
+        const bool act = (uint32_t)lane < p;
+        uint32_t cid = 0;
+        if (act) cid = stk[sp - p + lane];
+        if (__ballot(act && cid >= ccap)) return 1;                  // never: stack intact
+        wave_barrier();
+        sp -= p;
+        const uint4 nd = node[cid];
+        const uint2 lk = link[cid];
+        const uint32_t nch = nd.w >> 8;
+        const bool accept = act && cell_accepted(nd, b[0], b[1], b[2], b[3], b[4], b[5], theta2);
+        bool open = act && !accept;
+        if (SUPER) {
+            const bool all = open && !far_accepted(nd, b[0], b[1], b[2], b[3], b[4], b[5], theta2);
+            const bool fr = open && !all;
+            open = all;
+            const uint64_t bf = __ballot(fr);
+            const uint32_t ftot = (uint32_t)__popcll(bf);
+            if (nf + ftot > (uint32_t)kFront) return 2;
+            if (fr) front[nf + (uint32_t)__popcll(bf & lt)] = cid;
+            nf += ftot;
+        }
+        const bool leaf = open && nch == 0 && lk.y > 0;
+        const bool inner = open && nch != 0;
+        // superparticles, from the back of each target's segment
+        const uint64_t bs = __ballot(accept);
+        if (FILL && accept) {
+            const uint32_t j = ns + (uint32_t)__popcll(bs & lt);
+#pragma unroll
+            for (int k = 0; k < NT; k++)
+                if (k < nt && j < capg[k]) list[base[k] + capg[k] - 1 - j] = cid;
+        }
+        ns += (uint32_t)__popcll(bs);
+        // leaf particles and children: one prefix sum of both counts packed in a word unless
+        // a leaf holds 2^16 particles or more (as in k_walk)
+        const uint32_t lc = leaf ? lk.y : 0u;
+        const uint32_t cc = inner ? nch : 0u;
+        uint32_t lex, ltot, cex, ctot;
+        if (__ballot(lc >= (1u << 16)) == 0) {
+            const uint32_t pk = lc | (cc << 22);
+            const uint32_t inc = wave_incl_scan_dpp(pk);
+            const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
+            const uint32_t ex = inc - pk;
+            lex = ex & 0x3FFFFFu; cex = ex >> 22;
+            ltot = tot & 0x3FFFFFu; ctot = tot >> 22;
+        } else {
+            const uint32_t li = wave_incl_scan_dpp(lc), ci = wave_incl_scan_dpp(cc);
+            ltot = (uint32_t)__builtin_amdgcn_readlane((int)li, kWave - 1);
+            ctot = (uint32_t)__builtin_amdgcn_readlane((int)ci, kWave - 1);
+            lex = li - lc; cex = ci - cc;
+        }
+        if (FILL && leaf) {
+            const uint32_t e0 = ne + lex;
+#pragma unroll
+            for (int k = 0; k < NT; k++) {
+                if (k >= nt) continue;
+                const uint32_t nw = e0 < capg[k] ? min(lc, capg[k] - e0) : 0u;
+                uint32_t *dst = list + base[k] + e0;
+                // unconditional stores: slots past nw rewrite slot nw - 1 with its own value
+                for (uint32_t k0 = 0; k0 < nw; k0 += 8) {
+#pragma unroll
+                    for (uint32_t u = 0; u < 8; u++) {
+                        const uint32_t j = min(k0 + u, nw - 1);
+                        dst[j] = lk.x + j;
+                    }
+                }
+            }
+        }
+        ne += ltot;
+        if (sp + ctot > (uint32_t)kWalkStack) return 1;
+        if (inner) {
+            uint32_t *d = stk + sp + cex;
+#pragma unroll
+            for (uint32_t u = 0; u < 8; u++) {
+                const uint32_t j = min(u, cc - 1);
+                d[j] = lk.x + j;
+            }
+        }
+        sp += ctot;
+        wave_barrier();
+    }
+    return 0;
+}
+
+// a group's box in half-grid units
+__device__ __forceinline__ void group_box(const Groups &g, uint32_t gi, int (&b)[6]) {
+    const uint32_t *bx = g.box + 6 * (size_t)gi;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        b[a] = 2 * (int)bx[a];
+        b[3 + a] = 2 * (int)bx[3 + a] + 2;
+    }
+}
+
+// One wave per run (or per selected group).  Arguments as k_walk's (gravity).  Held to 8
+// waves per SIMD (the limit that the LDS of 8 workgroups per CU also sets).
+template <bool FILL>
+__global__ void __launch_bounds__(kThreads, 8)
+k_walk_runs(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link,
+            uint32_t ccap, double theta2, uint64_t *seg, uint32_t *cap, uint64_t list_cap,
+            uint32_t *list, uint32_t *cnt_e, uint32_t *cnt_s, uint32_t *ovf_list,
+            const uint32_t *sel, const uint32_t *nsel, DevStatus *st, int spill) {
+    __shared__ uint32_t stack_all[kWaves][kWalkStack];
+    __shared__ uint32_t front_all[kWaves][kFront];
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    uint32_t *stk = stack_all[w];
+    uint32_t *front = front_all[w];
+    const uint32_t G = min(*ngroups, g.cap);
+    const uint32_t items = sel ? *nsel : (G + kRun - 1) / kRun;
+    for (size_t q = (size_t)blockIdx.x * kWaves + w; q < items; q += (size_t)gridDim.x * kWaves) {
+        // targets [t0, t1) of run [r0, r1)
+        const uint32_t t0 = uniform_u32(sel ? sel[q] : (uint32_t)q * kRun);
+        if (t0 >= G) continue;
+        const uint32_t t1 = sel ? t0 + 1 : min(t0 + kRun, G);
+        const uint32_t r0 = t0 / kRun * kRun, r1 = min(r0 + kRun, G);
+        const int nt = (int)(t1 - t0);
+        const uint32_t root = g.sys[r0];                  // roots are cells 0..nsys-1
+        bool shared = r1 - r0 > 1 && g.sys[r1 - 1] == root;
+        int rb[6];
+        group_box(g, r0, rb);
+        for (uint32_t k = r0 + 1; k < r1; k++) {
+            int b[6];
+            group_box(g, k, b);
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                rb[a] = min(rb[a], b[a]);
+                rb[3 + a] = max(rb[3 + a], b[3 + a]);
+            }
+        }
+        // the members' segments for the run's first walk (constant indices only, so the
+        // arrays stay in registers)
+        uint64_t base[kRun];
+        uint32_t capg[kRun];
+#pragma unroll
+        for (int k = 0; k < kRun; k++) {
+            base[k] = 0; capg[k] = 0;
+            if (FILL && k < nt) {
+                base[k] = seg[t0 + k];
+                capg[k] = base[k] + cap[t0 + k] <= list_cap ? cap[t0 + k] : 0u;
+            }
+        }
+        bool err = false;
+        uint32_t ne0 = 0, ns0 = 0, nf = 0;
+        if (shared) {
+            if (lane == 0) stk[0] = root;
+            wave_barrier();
+            const int r = run_stack<FILL, true>(stk, 1, front, nf, node, link, ccap, theta2, rb,
+                                                list, base, capg, nt, ne0, ns0);
+            if (r == 1) err = true;
+            if (r != 0) shared = false;                // each member walks from the root
+        }
+        if (!shared) { ne0 = 0; ns0 = 0; nf = 0; }
+        for (int k = 0; k < nt; k++) {
+            const uint32_t gi = t0 + (uint32_t)k;
+            int gb[6];
+            group_box(g, gi, gb);
+            uint64_t bk[kRun] = {0, 0, 0, 0};
+            uint32_t ck[kRun] = {0, 0, 0, 0};
+            bool ok = true;
+            if (FILL) {                                // as read for the first walk
+                bk[0] = seg[gi];
+                ok = bk[0] + cap[gi] <= list_cap;
+                ck[0] = ok ? cap[gi] : 0u;
+            }
+            uint32_t ne = 0, ns = 0;
+            bool gerr = false;
+            for (int pass = 0;; pass++) {
+                ne = ne0; ns = ns0;
+                if (pass > 0 && shared) {
+                    // the run's first walk again, into this group's new space only
+                    uint32_t nf2 = 0;
+                    ne = 0; ns = 0;
+                    if (lane == 0) stk[0] = root;
+                    wave_barrier();
+                    if (run_stack<FILL, true>(stk, 1, front, nf2, node, link, ccap, theta2, rb,
+                                              list, bk, ck, 1, ne, ns) != 0)
+                        gerr = true;                   // never: the first walk completed
+                }
+                uint32_t sp;
+                if (shared) {
+                    for (uint32_t i = (uint32_t)lane; i < nf; i += kWave) stk[i] = front[i];
+                    sp = nf;
+                } else {
+                    if (lane == 0) stk[0] = g.sys[gi];
+                    sp = 1;
+                }
+                wave_barrier();
+                uint32_t nf_unused = 0;
+                if (!gerr && run_stack<FILL, false>(stk, sp, nullptr, nf_unused, node, link, ccap,
+                                                    theta2, gb, list, bk, ck, 1, ne, ns) != 0)
+                    gerr = true;
+                wave_barrier();
+                if (FILL && spill && pass == 0 && !gerr && ((uint64_t)ne + ns > ck[0] || !ok)) {
+                    const uint32_t need = ne + ns;
+                    unsigned long long off = 0;
+                    if (lane == 0)
+                        off = atomicAdd((unsigned long long *)&st->spill_used,
+                                        (unsigned long long)need);
+                    const uint64_t nb = st->list_total + uniform_u64((uint64_t)off);
+                    if (nb + need <= list_cap) {
+                        bk[0] = nb;
+                        ck[0] = need;
+                        ok = true;
+                        if (lane == 0) {
+                            seg[gi] = nb;
+                            cap[gi] = need;
+                            atomicAdd(&st->spilled, 1u);
+                        }
+                        continue;                      // walk the group again into its new space
+                    }
+                }
+                break;
+            }
+            if (lane == 0) {
+                if (err || gerr) atomicOr(&st->walk_error, 1u);
+                if (FILL && ((uint64_t)ne + ns > ck[0] || !ok)) {
+                    cnt_e[gi] = 0;
+                    cnt_s[gi] = 0;
+                    uint32_t o = atomicAdd(&st->list_overflow, 1u);
+                    if (ovf_list && o < g.cap) ovf_list[o] = gi;
+                } else {
+                    cnt_e[gi] = ne;
+                    cnt_s[gi] = ns;
+                }
+            }
+        }
+    }
+}
+
 // cap[g] = |EPJ| + |SPJ| (exact segment sizes)
 __global__ void k_list_caps(const uint32_t *ngroups, uint32_t gmax, const uint32_t *cnt_e,
                             const uint32_t *cnt_s, uint32_t *cap) {
@@ -453,6 +734,22 @@ hipError_t walk(bool fill, size_t gmax, const Groups g, const Cells c, double th
                 const uint32_t *nsel, DevStatus *st, hipStream_t s, bool spill) {
     launch_walk<0>(fill, gmax, g, c, theta2, seg, cap, list_cap, list, cnt_e, cnt_s, ovf_list,
                    sel, nsel, st, ShortArgs{}, s, spill);
+    return hipGetLastError();
+}
+
+hipError_t walk_runs(bool fill, size_t gmax, const Groups g, const Cells c, double theta2,
+                     uint64_t *seg, uint32_t *cap, uint64_t list_cap, uint32_t *list,
+                     uint32_t *cnt_e, uint32_t *cnt_s, uint32_t *ovf_list, const uint32_t *sel,
+                     const uint32_t *nsel, DevStatus *st, hipStream_t s, bool spill) {
+    const size_t items = sel ? gmax : (gmax + kRun - 1) / kRun;
+    if (fill)
+        hipLaunchKernelGGL(k_walk_runs<true>, dim3(grid_waves(items)), dim3(kThreads), 0, s,
+                           &st->n_groups, g, c.node, c.link, c.cap, theta2, seg, cap, list_cap,
+                           list, cnt_e, cnt_s, ovf_list, sel, nsel, st, spill ? 1 : 0);
+    else
+        hipLaunchKernelGGL(k_walk_runs<false>, dim3(grid_waves(items)), dim3(kThreads), 0, s,
+                           &st->n_groups, g, c.node, c.link, c.cap, theta2, seg, cap, list_cap,
+                           list, cnt_e, cnt_s, ovf_list, sel, nsel, st, 0);
     return hipGetLastError();
 }
 

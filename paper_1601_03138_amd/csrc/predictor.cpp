@@ -92,8 +92,8 @@ int ext_predicted_walk(fdx_ctx *c, uint32_t G) {
     if (r) return r;
     // single walk into the predicted segments; a list that outgrows its segment moves to the
     // space after all segments (the buffer holds total + total / 8) and is walked again there
-    HIPCHK(c, walk(true, G, gv, cv, th2, c->seg.p, c->lcap.p, c->list_cap, c->list.p, c->cnt_e.p,
-                   c->cnt_s.p, c->ovf_list.p, nullptr, nullptr, c->st, s, true));
+    HIPCHK(c, walk_runs(true, G, gv, cv, th2, c->seg.p, c->lcap.p, c->list_cap, c->list.p,
+                        c->cnt_e.p, c->cnt_s.p, c->ovf_list.p, nullptr, nullptr, c->st, s, true));
     r = read_status(c);
     if (r) return r;
     if (c->hst->st.walk_error) return fail(c, FDX_EHIP, "walk stack exhausted");
@@ -113,8 +113,8 @@ int ext_predicted_walk(fdx_ctx *c, uint32_t G) {
         HIPCHK(c, hipMemcpyAsync(p->nsel.p, &c->st->list_overflow, 4, hipMemcpyDeviceToDevice, s));
         const uint64_t base_host = std::min<uint64_t>(used, c->list_cap);
         HIPCHK(c, hipMemcpyAsync(p->base_total.p, &base_host, 8, hipMemcpyHostToDevice, s));
-        HIPCHK(c, walk(false, K, gv, cv, th2, nullptr, nullptr, 0, nullptr, c->cnt_e.p, c->cnt_s.p,
-                       nullptr, c->ovf_list.p, p->nsel.p, c->st, s));
+        HIPCHK(c, walk_runs(false, K, gv, cv, th2, nullptr, nullptr, 0, nullptr, c->cnt_e.p,
+                            c->cnt_s.p, nullptr, c->ovf_list.p, p->nsel.p, c->st, s));
         HIPCHK(c, ovf_caps(K, p->nsel.p, c->ovf_list.p, c->cnt_e.p, c->cnt_s.p, p->ocap.p, s));
         HIPCHK(c, scan_u32_to_u64(p->ocap.p, p->ooff.p, K, nullptr, nullptr, c->partial.p,
                                   p->base_total.p + 1, s));
@@ -127,8 +127,8 @@ int ext_predicted_walk(fdx_ctx *c, uint32_t G) {
         const uint64_t keep = std::min<uint64_t>(used, c->list_cap);
         r = grow_list_keep(c, keep + extra, keep);
         if (r) return r;
-        HIPCHK(c, walk(true, K, gv, cv, th2, c->seg.p, c->lcap.p, c->list_cap, c->list.p, c->cnt_e.p,
-                       c->cnt_s.p, nullptr, c->ovf_list.p, p->nsel.p, c->st, s));
+        HIPCHK(c, walk_runs(true, K, gv, cv, th2, c->seg.p, c->lcap.p, c->list_cap, c->list.p,
+                            c->cnt_e.p, c->cnt_s.p, nullptr, c->ovf_list.p, p->nsel.p, c->st, s));
     }
     c->stats.overflow_groups = K + spilled;
     c->stats.list_capacity = (int64_t)(std::min<uint64_t>(used, c->list_cap) + extra);
