@@ -123,7 +123,7 @@ ALGO_BYTES = [
     (r"^k_leaf_level\b", "write a byte per particle", lambda N, C, G, E: 1 * N),
     (r"^void k_group_geom|^k_group_geom\b", "read member keys; write box and centre per group",
      lambda N, C, G, E: 8 * N + 48 * G),
-    (r"^void k_walk<true, 0>", "write 4 B per list entry", lambda N, C, G, E: 4 * E),
+    (r"^void k_walk(_runs)?<true(, 0)?>", "write 4 B per list entry", lambda N, C, G, E: 4 * E),
     (r"^k_unsort\b", "read inverse, result; write four arrays", lambda N, C, G, E: 68 * N),
     (r"^k_kick_drift\b", "read x, v, a; write x, v", lambda N, C, G, E: 120 * N),
     (r"^k_kick\b", "read v, a; write v", lambda N, C, G, E: 72 * N),
