@@ -20,6 +20,7 @@
 #include "dev_util.h"
 #include "fdx_internal.h"
 #include "opening.h"
+#include "walk_order.h"
 
 namespace fdx {
 
@@ -239,6 +240,7 @@ k_walk(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link, 
 // selection (groups re-walked after an overflow) a selected group repeats its run's first
 // walk, so its entries come in the same order as in a walk of all groups.
 constexpr int kRun = 4;                 // groups per run
+static_assert(kWaves == (int)kWalkOrderWaves, "walk_order.h assumes the walk's waves per block");
 constexpr int kFront = 224;             // frontier cells kept per wave
 
 // the opening test at the box's far corners: false means every box inside [bmin, bmax] opens
@@ -369,12 +371,16 @@ __device__ __forceinline__ void group_box(const Groups &g, uint32_t gi, int (&b)
 
 // One wave per run (or per selected group).  Arguments as k_walk's (gravity).  Held to 8
 // waves per SIMD (the limit that the LDS of 8 workgroups per CU also sets).
+//
+// Order of the runs without a selection: XCD-aware chunks of `chunk` runs (walk_order.h);
+// with a selection the waves stride over it.
 template <bool FILL>
 __global__ void __launch_bounds__(kThreads, 8)
 k_walk_runs(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *link,
             uint32_t ccap, double theta2, uint64_t *seg, uint32_t *cap, uint64_t list_cap,
             uint32_t *list, uint32_t *cnt_e, uint32_t *cnt_s, uint32_t *ovf_list,
-            const uint32_t *sel, const uint32_t *nsel, DevStatus *st, int spill) {
+            const uint32_t *sel, const uint32_t *nsel, DevStatus *st, int spill,
+            uint32_t chunk) {
     __shared__ uint32_t stack_all[kWaves][kWalkStack];
     __shared__ uint32_t front_all[kWaves][kFront];
     const int w = threadIdx.x / kWave, lane = lane_id();
@@ -382,7 +388,9 @@ k_walk_runs(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *l
     uint32_t *front = front_all[w];
     const uint32_t G = min(*ngroups, g.cap);
     const uint32_t items = sel ? *nsel : (G + kRun - 1) / kRun;
-    for (size_t q = (size_t)blockIdx.x * kWaves + w; q < items; q += (size_t)gridDim.x * kWaves) {
+    // this wave's slot within each W: a permutation of 0..W-1
+    const uint32_t slot = walk_order_slot(blockIdx.x, (uint32_t)w, gridDim.x, sel ? 0u : chunk);
+    for (size_t q = slot; q < items; q += (size_t)gridDim.x * kWaves) {
         // targets [t0, t1) of run [r0, r1)
         const uint32_t t0 = uniform_u32(sel ? sel[q] : (uint32_t)q * kRun);
         if (t0 >= G) continue;
@@ -742,14 +750,17 @@ hipError_t walk_runs(bool fill, size_t gmax, const Groups g, const Cells c, doub
                      uint32_t *cnt_e, uint32_t *cnt_s, uint32_t *ovf_list, const uint32_t *sel,
                      const uint32_t *nsel, DevStatus *st, hipStream_t s, bool spill) {
     const size_t items = sel ? gmax : (gmax + kRun - 1) / kRun;
+    size_t grid = grid_waves(items);
+    uint32_t chunk = 0;
+    if (!sel) walk_order_launch(items, grid, &grid, &chunk);
     if (fill)
-        hipLaunchKernelGGL(k_walk_runs<true>, dim3(grid_waves(items)), dim3(kThreads), 0, s,
+        hipLaunchKernelGGL(k_walk_runs<true>, dim3((unsigned)grid), dim3(kThreads), 0, s,
                            &st->n_groups, g, c.node, c.link, c.cap, theta2, seg, cap, list_cap,
-                           list, cnt_e, cnt_s, ovf_list, sel, nsel, st, spill ? 1 : 0);
+                           list, cnt_e, cnt_s, ovf_list, sel, nsel, st, spill ? 1 : 0, chunk);
     else
-        hipLaunchKernelGGL(k_walk_runs<false>, dim3(grid_waves(items)), dim3(kThreads), 0, s,
+        hipLaunchKernelGGL(k_walk_runs<false>, dim3((unsigned)grid), dim3(kThreads), 0, s,
                            &st->n_groups, g, c.node, c.link, c.cap, theta2, seg, cap, list_cap,
-                           list, cnt_e, cnt_s, ovf_list, sel, nsel, st, 0);
+                           list, cnt_e, cnt_s, ovf_list, sel, nsel, st, 0, chunk);
     return hipGetLastError();
 }
 

@@ -9,6 +9,10 @@ The union must be the member's own list, entry for entry (as a set), for every g
 that straddle two systems or whose frontier exceeds the kernel's 224 cells are walked group
 by group.  This is a model of the rule, in plain Python on the oracle's tree; the GPU kernel
 that follows it is checked against the oracle's lists by the GPU parity tests."""
+import os
+import shutil
+import subprocess
+
 import numpy as np
 import pytest
 
@@ -16,6 +20,7 @@ import oracle as O
 from paper_1601_03138_amd import inputs as I
 
 RUN, FRONT = 4, 224
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _centres(t):
@@ -144,3 +149,16 @@ def test_far_corner_test_separates_opened_from_undecided_cells():
             elif any(_accepted(cen, t.level, c, _box(g, k), theta2) for k in range(r0, r0 + RUN)):
                 lost += 1                               # a frontier cell some member accepts
     assert lost > 0
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_xcd_aware_run_order_is_a_permutation(tmp_path):
+    # the walk kernel's launch rule and wave -> run mapping (walk_order.h), compiled into a
+    # small host program: every run is taken exactly once per grid-wide round
+    exe = tmp_path / "walk_order_check"
+    src = os.path.join(ROOT, "tests", "native", "walk_order_check.cpp")
+    inc = os.path.join(ROOT, "paper_1601_03138_amd", "csrc")
+    subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-I", inc, src, "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert out.returncode == 0 and out.stdout.strip() == "ok", out.stdout
