@@ -208,6 +208,34 @@ def test_graph_list_sizing_and_recovery(ctx, fdx, percent):
         ctx.set_graph_list_margin(-1)
 
 
+def test_graph_steps_with_many_lists_moved_to_spare_space(fdx):
+    """A fresh context runs the 50 % case twice.  In the second run the list buffer, grown by
+    the first run's eager redo, has room for every list that outgrows its segment, so hundreds
+    of groups per step are walked again in the spare space inside graph replays (for runs of
+    groups that share the upper tree, the run's first walk is repeated into the new space).
+    Every step equals the eager one bit for bit."""
+    ens = I.ensemble(n_sys=12, seed=41, nmin=256, nmax=2048)
+    dt, steps = 1.0 / 256.0, 4
+    with fdx.Context(0) as c:
+        for rep in range(2):
+            runs = {}
+            for graph in (False, True):
+                c.set_particles(ens)
+                c.set_graph_list_margin(50 if graph else 200)
+                c.calc_force(0.6, 8, 64, 0.0, quad=True, fp32=True, persistent=True)
+                s0 = c.stats()["list_spills"]
+                c.integrate(dt, steps, graph=graph)
+                st = c.stats()
+                runs[graph] = ([a.copy() for a in c.particles()], c.forces(),
+                               st["list_spills"] - s0)
+            _say(f"[graph spare space] run {rep}: lists walked again in spare space "
+                 f"{runs[True][2]}")
+            for a, b in zip(runs[False][0], runs[True][0]):
+                assert np.array_equal(a, b), rep
+            assert np.array_equal(runs[False][1], runs[True][1]), rep
+        assert runs[True][2] > 100 * steps // 2         # the second run moved many lists
+
+
 def test_ensemble_energy_and_force_error(ctx, fdx):
     ens = I.ensemble(n_sys=16, seed=50, nmin=512, nmax=4096)
     off = ens.offsets()
