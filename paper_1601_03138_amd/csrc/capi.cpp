@@ -124,8 +124,8 @@ int enqueue_keys_sort(fdx_ctx *c) {
     mark(c, 0);
     HIPCHK(c, bbox(n, c->x, c->y, c->z, c->sysid.p, S, c->bbox_u.p, s));
     HIPCHK(c, root_cubes(S, c->bbox_u.p, c->cube.p, s));
-    HIPCHK(c, morton_keys(n, c->x, c->y, c->z, c->sysid.p, c->cube.p, c->key.p, c->perm.p, s));
-    HIPCHK(c, pack_particles(n, c->x, c->y, c->z, c->m, c->packed.p, s));
+    HIPCHK(c, morton_keys(n, c->x, c->y, c->z, c->m, c->sysid.p, S, c->cube.p, c->key.p,
+                          c->perm.p, c->packed.p, s));
     mark(c, 1);
     bool alt = false;
     HIPCHK(c, radix_sort(n, c->key.p, c->key_alt.p, c->perm.p, c->perm_alt.p, c->sysid.p, S, 64,

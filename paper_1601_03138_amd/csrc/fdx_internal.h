@@ -96,9 +96,10 @@ hipError_t scan_u32_to_u64(const uint32_t *in, uint64_t *out, size_t n_host,
 hipError_t bbox(size_t n, const double *x, const double *y, const double *z,
                 const uint32_t *sysid, int nsys, uint64_t *bbox_u, hipStream_t s);
 hipError_t root_cubes(int nsys, const uint64_t *bbox_u, double *cube, hipStream_t s);
+// keys, the identity permutation and each particle's (x, y, z, m) record for the sorted gather
 hipError_t morton_keys(size_t n, const double *x, const double *y, const double *z,
-                       const uint32_t *sysid, const double *cube, uint64_t *key,
-                       uint32_t *perm, hipStream_t s);
+                       const double *m, const uint32_t *sysid, int nsys, const double *cube,
+                       uint64_t *key, uint32_t *perm, double4 *packed, hipStream_t s);
 
 // radix sort of (key, perm) pairs by key, then (stable) by system id of the original index.
 size_t radix_scratch_u32(size_t n);
@@ -112,8 +113,6 @@ hipError_t radix_sort(size_t n, uint64_t *key, uint64_t *key_alt, uint32_t *val,
                       uint16_t *carry = nullptr);
 
 // sorted particle data
-hipError_t pack_particles(size_t n, const double *x, const double *y, const double *z,
-                          const double *m, double4 *packed, hipStream_t s);
 // flag |= 1 if some eps[i] differs from the eps of its system's first particle
 hipError_t eps_varies(size_t n, const double *eps, const uint32_t *sysid, const int64_t *off,
                       uint32_t *flag, hipStream_t s);

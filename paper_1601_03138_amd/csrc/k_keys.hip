@@ -33,7 +33,7 @@ k_bbox(size_t n, const double *x, const double *y, const double *z, const uint32
     const size_t b0 = (size_t)blockIdx.x * kBboxChunk;
     if (b0 >= n) return;
     const size_t b1 = min(n, b0 + kBboxChunk);
-    const uint32_t s0 = sysid[b0];
+    const uint32_t s0 = sysid ? sysid[b0] : 0u;
     const int lane = lane_id();
     uint64_t mn[3] = {~0ull, ~0ull, ~0ull}, mx[3] = {0, 0, 0};
     // wave-uniform trip count: every lane of a wave takes part in the ballots below
@@ -44,7 +44,7 @@ k_bbox(size_t n, const double *x, const double *y, const double *z, const uint32
         uint32_t s = s0;
         if (valid) {
             v[0] = dbl_to_ord(x[i]); v[1] = dbl_to_ord(y[i]); v[2] = dbl_to_ord(z[i]);
-            s = sysid[i];
+            s = sysid ? sysid[i] : s0;
             if (s == s0) {
 #pragma unroll
                 for (int a = 0; a < 3; a++) { mn[a] = min(mn[a], v[a]); mx[a] = max(mx[a], v[a]); }
@@ -143,15 +143,20 @@ __device__ __forceinline__ uint32_t grid_coord(double v, double o, double scale)
     return (uint32_t)f;
 }
 
+// Keys and the identity permutation; the same pass writes each particle's (x, y, z, m) record
+// for the sorted gather (one read of the coordinates for both).  sysid null: one system.
 __global__ void k_keys(size_t n, const double *x, const double *y, const double *z,
-                       const uint32_t *sysid, const double *cube, uint64_t *key, uint32_t *perm) {
+                       const double *m, const uint32_t *sysid, const double *cube, uint64_t *key,
+                       uint32_t *perm, double4 *packed) {
     for (size_t i = gtid(); i < n; i += gstride()) {
-        const double *c = cube + 4 * sysid[i];
+        const double *c = cube + 4 * (size_t)(sysid ? sysid[i] : 0u);
         const double scale = 2097152.0 / c[3];
-        uint64_t qx = grid_coord(x[i], c[0], scale), qy = grid_coord(y[i], c[1], scale),
-                 qz = grid_coord(z[i], c[2], scale);
+        const double xi = x[i], yi = y[i], zi = z[i];
+        uint64_t qx = grid_coord(xi, c[0], scale), qy = grid_coord(yi, c[1], scale),
+                 qz = grid_coord(zi, c[2], scale);
         key[i] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
         perm[i] = (uint32_t)i;
+        packed[i] = make_double4(xi, yi, zi, m[i]);
     }
 }
 
@@ -170,8 +175,8 @@ hipError_t bbox(size_t n, const double *x, const double *y, const double *z,
     hipLaunchKernelGGL(k_bbox_init, dim3((6 * nsys + 255) / 256), dim3(256), 0, s, nsys, bbox_u);
     if (!n) return hipGetLastError();
     size_t blocks = (n + kBboxChunk - 1) / kBboxChunk;
-    hipLaunchKernelGGL(k_bbox, dim3((unsigned)blocks), dim3(kThreads), 0, s, n, x, y, z, sysid,
-                       bbox_u);
+    hipLaunchKernelGGL(k_bbox, dim3((unsigned)blocks), dim3(kThreads), 0, s, n, x, y, z,
+                       nsys > 1 ? sysid : nullptr, bbox_u);
     return hipGetLastError();
 }
 
@@ -181,11 +186,11 @@ hipError_t root_cubes(int nsys, const uint64_t *bbox_u, double *cube, hipStream_
 }
 
 hipError_t morton_keys(size_t n, const double *x, const double *y, const double *z,
-                       const uint32_t *sysid, const double *cube, uint64_t *key,
-                       uint32_t *perm, hipStream_t s) {
+                       const double *m, const uint32_t *sysid, int nsys, const double *cube,
+                       uint64_t *key, uint32_t *perm, double4 *packed, hipStream_t s) {
     if (!n) return hipSuccess;
-    hipLaunchKernelGGL(k_keys, dim3(grid_for(n)), dim3(kThreads), 0, s, n, x, y, z, sysid, cube,
-                       key, perm);
+    hipLaunchKernelGGL(k_keys, dim3(grid_for(n)), dim3(kThreads), 0, s, n, x, y, z, m,
+                       nsys > 1 ? sysid : nullptr, cube, key, perm, packed);
     return hipGetLastError();
 }
 

@@ -31,11 +31,6 @@ inline unsigned grid_for(size_t n, unsigned cap = 16384) {
 
 // (x, y, z, m) of every particle as one 32-byte record in the caller's order (coalesced), so
 // the sorted gather below reads one sector per particle instead of four.
-__global__ void k_pack(size_t n, const double *x, const double *y, const double *z,
-                       const double *m, double4 *packed) {
-    for (size_t i = gtid(); i < n; i += gstride()) packed[i] = make_double4(x[i], y[i], z[i], m[i]);
-}
-
 // system holding sorted position r: the last s with off[s] <= r (skips empty systems)
 __device__ __forceinline__ int system_of(const int64_t *off, int nsys, size_t r) {
     int lo = 0, hi = nsys - 1;
@@ -491,13 +486,6 @@ k_group_geom(const uint32_t *ngroups, int nsys, const int64_t *off, Cells c,
 }
 
 }  // namespace
-
-hipError_t pack_particles(size_t n, const double *x, const double *y, const double *z,
-                          const double *m, double4 *packed, hipStream_t s) {
-    if (!n) return hipSuccess;
-    hipLaunchKernelGGL(k_pack, dim3(grid_for(n)), dim3(kThreads), 0, s, n, x, y, z, m, packed);
-    return hipGetLastError();
-}
 
 hipError_t gather_sorted(size_t n, const uint32_t *perm, const double4 *packed,
                          const double *eps, double eps_all, bool per_system, const int64_t *off,

@@ -105,8 +105,8 @@ def sq(path, kernel):
 ALGO_BYTES = [
     # (kernel regex, what, bytes per dispatch)
     (r"^k_bbox\b", "read x, y, z", lambda N, C, G, E: 24 * N),
-    (r"^k_keys\b", "read x, y, z; write key, index", lambda N, C, G, E: 36 * N),
-    (r"^k_pack\b", "read x, y, z, m; write (x, y, z, m)", lambda N, C, G, E: 64 * N),
+    (r"^k_keys\b", "read x, y, z, m; write key, index, (x, y, z, m)",
+     lambda N, C, G, E: 76 * N),
     (r"^void k_rs_hist", "read key (one 8-bit pass)", lambda N, C, G, E: 8 * N),
     (r"^void k_rs_scatter", "read and write key + index (one pass)", lambda N, C, G, E: 24 * N),
     (r"^k_gather_sorted\b", "read index, record, eps; write record, eps, inverse",
