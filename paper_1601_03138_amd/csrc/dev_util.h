@@ -95,15 +95,51 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
     return v;
 }
 
-__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, d, kWave));
-    return v;
+// Minimum / maximum over the 64 lanes, returned to every lane (all lanes must be active): the
+// lane moves of wave_incl_scan_dpp with min / max in place of the sum (lanes shifted in from
+// outside a row, and the rows a broadcast skips, read the operation's identity), after which
+// lane 63 holds the result.
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+    constexpr int id = -1;                                                          // 0xFFFFFFFF
+    x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)x, 0x111, 0xf, 0xf, false));
+    x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)x, 0x112, 0xf, 0xf, false));
+    x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)x, 0x114, 0xf, 0xf, false));
+    x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)x, 0x118, 0xf, 0xf, false));
+    x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)x, 0x142, 0xa, 0xf, false));
+    x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)x, 0x143, 0xc, 0xf, false));
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, kWave - 1);
 }
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, d, kWave));
-    return v;
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false));
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, kWave - 1);
+}
+// one DPP lane move of a 64-bit value (both halves from the same lane; identity all ones)
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint64_t dpp_move_u64_max_id(uint64_t u) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)(uint32_t)u, CTRL,
+                                                              ROW_MASK, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)(uint32_t)(u >> 32), CTRL,
+                                                              ROW_MASK, 0xf, false);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+// minimum of non-negative doubles (or +inf) over the 64 lanes, as wave_min_u32 on the bit
+// patterns (ordered like the values for non-negative doubles)
+__device__ __forceinline__ double wave_min_nonneg_f64(double v) {
+    uint64_t u = (uint64_t)__double_as_longlong(v), o;
+    o = dpp_move_u64_max_id<0x111, 0xf>(u); u = o < u ? o : u;
+    o = dpp_move_u64_max_id<0x112, 0xf>(u); u = o < u ? o : u;
+    o = dpp_move_u64_max_id<0x114, 0xf>(u); u = o < u ? o : u;
+    o = dpp_move_u64_max_id<0x118, 0xf>(u); u = o < u ? o : u;
+    o = dpp_move_u64_max_id<0x142, 0xa>(u); u = o < u ? o : u;
+    o = dpp_move_u64_max_id<0x143, 0xc>(u); u = o < u ? o : u;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, kWave - 1);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), kWave - 1);
+    return __longlong_as_double((long long)((uint64_t)lo | ((uint64_t)hi << 32)));
 }
 
 // Exclusive prefix sum over a block of NT threads (NT a multiple of 64, <= 1024); returns the

@@ -458,8 +458,7 @@ k_group_geom(const uint32_t *ngroups, int nsys, const int64_t *off, Cells c,
 #pragma unroll
         for (int a = 0; a < 3; a++) { lo[a] = wave_min_u32(lo[a]); hi[a] = wave_max_u32(hi[a]); }
         deep = wave_max_u32(deep);
-#pragma unroll
-        for (int d = kWave / 2; d >= 1; d >>= 1) emin = fmin(emin, __shfl_xor(emin, d, kWave));
+        emin = wave_min_nonneg_f64(emin);
         const int slo = wave_system_of(off, nsys, b);   // last s with off[s] <= b
         if (lane == 0) {
             const uint32_t cell = g.cell[gi];
