@@ -370,7 +370,9 @@ __device__ __forceinline__ void group_box(const Groups &g, uint32_t gi, int (&b)
 }
 
 // One wave per run (or per selected group).  Arguments as k_walk's (gravity).  Held to 8
-// waves per SIMD (the limit that the LDS of 8 workgroups per CU also sets).
+// waves per SIMD (the limit that the LDS of 8 workgroups per CU also sets); the bound makes
+// the compiler keep some scalar values in vector lanes, and without it the kernel ran at 7
+// waves per SIMD and was slower.
 //
 // Order of the runs without a selection: XCD-aware chunks of `chunk` runs (walk_order.h);
 // with a selection the waves stride over it.
