@@ -139,7 +139,10 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
                 // constant LDS stride), then the nt mod nslice leftover entries one per slice
                 const uint32_t kmain = nt / nslice;
                 const V *run = sm.e + slice * kmain;
-#pragma unroll 4
+                // FP32 with two i-particles per lane: those already give two independent
+                // chains; unrolled 4 (and the superparticle loop 2) the kernel held 98 VGPRs,
+                // 2 and 1 hold 72 (6 waves per SIMD instead of 4)
+#pragma unroll (IPL == 2 && sizeof(T) == 4 ? 2 : 4)
                 for (uint32_t q = 0; q < kmain; q++) {
                     const V J = run[q];
 #pragma unroll
@@ -195,7 +198,8 @@ __device__ __forceinline__ void force_group(const KArgs &a, uint32_t gi, Smem<T,
                 for (int k = 0; k < IPL; k++) tx[k] = ty[k] = tz[k] = tp[k] = 0;
                 const uint32_t kmain = nt / nslice;
                 const V *run = sm.s + 3 * slice * kmain;
-#pragma unroll 2
+                // (FP32, two i-particles per lane: not unrolled, as above)
+#pragma unroll (IPL == 2 && sizeof(T) == 4 ? 1 : 2)
                 for (uint32_t q = 0; q < kmain; q++) {
                     const V A = run[3 * q];
                     V B, C;

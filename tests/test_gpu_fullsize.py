@@ -88,7 +88,7 @@ def _check_sampled_entry_sets(gpu_lists, lists, sel):
 def test_clustered16m_bench_configuration(ctx, fdx):
     """The benchmark input: tree, groups and the entry sets of 256 sampled groups against the
     oracle for the exact walk; then the timed configuration (persistent force kernel over
-    per-XCD queues, predicted walk) in the two FP32 shapes the benchmark chooses between, each
+    per-XCD queues, predicted walk) in the FP32 shapes the benchmark chooses between, each
     bit-identical to the direct launch of the same shape after the exact walk, with the same
     entry sets, within the FP32 tolerance of the oracle tree on the sampled groups."""
     ps = I.workload("clustered16m")
@@ -110,7 +110,7 @@ def test_clustered16m_bench_configuration(ctx, fdx):
         pytest.skip("trained predictor weights not present")
     ctx.predictor_load(WEIGHTS)
     names = [ctx.shape_name(v) for v in range(ctx.lib.fdx_autotune_shapes())]
-    for name in ("nt512_ipl1_pf_w8", "nt512_ipl1_w8"):
+    for name in ("nt512_ipl1_pf_w8", "nt512_ipl1_w8", "nt512_ipl2"):
         ctx.set_shape(names.index(name))
         ctx.calc_force(0.5, 8, 256, 0.0, quad=True, fp32=True)
         a_direct = ctx.forces()
