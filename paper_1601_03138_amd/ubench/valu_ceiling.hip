@@ -2,9 +2,13 @@
 // disabled, as in the library): FP32 and FP64 FMA rates, v_rsq_f32 and v_rsq_f64 rates, and
 // the quadrupole particle-cell interaction with its j-record broadcast from LDS (no global
 // memory in the loop), in FP32 and in FP64 (hardware estimate + two Newton steps, as in the
-// library).  Prints one line per measurement; used to derive the force kernels' rooflines.
+// library).  A second FP32 form takes the linear part Q r = Q x_i - Q X from 4x4x1 FP32
+// MFMAs (the alternative that was measured and not adopted); it prints how far its results
+// are from the VALU form's.  Prints one line per measurement; used to derive the force
+// kernels' rooflines.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdio>
 #include <vector>
 
@@ -42,7 +46,7 @@ __global__ void __launch_bounds__(256) k_rsq(float *out, int iters, float a) {
 }
 
 // the library's quadrupole particle-cell interaction, j from a 64-entry LDS table
-__global__ void __launch_bounds__(256) k_pc(float *out, int iters, const float4 *tab) {
+__global__ void __launch_bounds__(256) k_pc(float4 *out4, int iters, const float4 *tab) {
     __shared__ float4 t[3 * 64];
     for (int k = threadIdx.x; k < 3 * 64; k += blockDim.x) t[k] = tab[k];
     __syncthreads();
@@ -53,18 +57,52 @@ __global__ void __launch_bounds__(256) k_pc(float *out, int iters, const float4 
         const float4 A = t[3 * j], B = t[3 * j + 1], C = t[3 * j + 2];
         const float rx = xi - A.x, ry = yi - A.y, rz = zi - A.z;
         const float R2 = fmaf(rz, rz, fmaf(ry, ry, fmaf(rx, rx, e2)));
-        const float Ri = __builtin_amdgcn_rsqf(R2), Ri2 = Ri * Ri, MRi = A.w * Ri, MRi3 = MRi * Ri2;
+        const float Ri = __builtin_amdgcn_rsqf(R2), Ri2 = Ri * Ri, MRi = A.w * Ri;
         const float qx = fmaf(B.w, ry, fmaf(C.x, rz, B.x * rx));
         const float qy = fmaf(B.w, rx, fmaf(C.y, rz, B.y * ry));
         const float qz = fmaf(C.x, rx, fmaf(C.y, ry, B.z * rz));
         const float rqr = fmaf(rx, qx, fmaf(ry, qy, rz * qz));
-        const float Ri5 = Ri * Ri2 * Ri2, tt = rqr * Ri5, u = fmaf(2.5f * tt, Ri2, MRi3);
+        const float Ri5 = Ri * Ri2 * Ri2, tt = rqr * Ri5, u = Ri2 * fmaf(2.5f, tt, MRi);
         ax = fmaf(-u, rx, fmaf(Ri5, qx, ax));
         ay = fmaf(-u, ry, fmaf(Ri5, qy, ay));
         az = fmaf(-u, rz, fmaf(Ri5, qz, az));
         ph -= fmaf(0.5f, tt, MRi);
     }
-    out[blockIdx.x * blockDim.x + threadIdx.x] = ax + ay + az + ph;
+    out4[blockIdx.x * blockDim.x + threadIdx.x] = make_float4(ax, ay, az, ph);
+}
+
+// The same interaction with Q r from three 4x4x1 FP32 MFMAs.  Per j six float4 in LDS: (X, M),
+// (-(Q X), 0), and the rows (Q[r][0..2], 0) for r = 0..3 (row 3 zero).  The four lanes of a
+// 4-lane block share the j-entry (here every lane does); lane l supplies A = Q[l % 4][k] and
+// B = its own coordinate k, so after k = 0, 1, 2 its accumulator holds (Q x_i - Q X)_r,
+// r = 0..3, for its own particle; the accumulator starts at -(Q X).
+__global__ void __launch_bounds__(256) k_pc_mfma(float4 *out4, int iters, const float4 *tab) {
+    __shared__ float4 t[6 * 64];
+    for (int k = threadIdx.x; k < 6 * 64; k += blockDim.x) t[k] = tab[k];
+    __syncthreads();
+    const float xi = threadIdx.x * 1e-3f, yi = 0.5f - xi, zi = 0.25f + xi, e2 = 1e-6f;
+    const int row = threadIdx.x & 3;
+    float ax = 0, ay = 0, az = 0, ph = 0;
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    for (int i = 0; i < iters; i++) {
+        const int j = i & 63;
+        const float4 XM = t[6 * j], nqx = t[6 * j + 1], Ar = t[6 * j + 2 + row];
+        f4 acc = {nqx.x, nqx.y, nqx.z, nqx.w};
+        acc = __builtin_amdgcn_mfma_f32_4x4x1f32(Ar.x, xi, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_4x4x1f32(Ar.y, yi, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_4x4x1f32(Ar.z, zi, acc, 0, 0, 0);
+        const float qx = acc[0], qy = acc[1], qz = acc[2];
+        const float rx = xi - XM.x, ry = yi - XM.y, rz = zi - XM.z;
+        const float R2 = fmaf(rz, rz, fmaf(ry, ry, fmaf(rx, rx, e2)));
+        const float Ri = __builtin_amdgcn_rsqf(R2), Ri2 = Ri * Ri, MRi = XM.w * Ri;
+        const float rqr = fmaf(rx, qx, fmaf(ry, qy, rz * qz));
+        const float Ri5 = Ri * Ri2 * Ri2, tt = rqr * Ri5, u = Ri2 * fmaf(2.5f, tt, MRi);
+        ax = fmaf(-u, rx, fmaf(Ri5, qx, ax));
+        ay = fmaf(-u, ry, fmaf(Ri5, qy, ay));
+        az = fmaf(-u, rz, fmaf(Ri5, qz, az));
+        ph -= fmaf(0.5f, tt, MRi);
+    }
+    out4[blockIdx.x * blockDim.x + threadIdx.x] = make_float4(ax, ay, az, ph);
 }
 
 __global__ void __launch_bounds__(256) k_fma64(double *out, int iters, double a, double b) {
@@ -139,11 +177,32 @@ int main() {
         h64[k] = make_double4(0.1 * (k % 7) + 1, 0.2 * (k % 5) + 1, 0.3 * (k % 3) + 1, 1e-3);
     CK(hipMemcpy(tab64, h64.data(), sizeof(double4) * h64.size(), hipMemcpyHostToDevice));
     CK(hipMalloc(&out, sizeof(float) * blocks * threads));
+    // FP32 superparticle table: 64 entries (X, M, Q), in the VALU layout (A = (X, M),
+    // B = (Qxx, Qyy, Qzz, Qxy), C = (Qxz, Qyz, 0, 0)) and in the MFMA layout
+    float4 *tab_m = nullptr, *out4 = nullptr, *out4_m = nullptr;
+    const size_t nlane = (size_t)blocks * threads;
     CK(hipMalloc(&tab, sizeof(float4) * 3 * 64));
-    std::vector<float4> h(3 * 64);
-    for (int k = 0; k < 3 * 64; k++)
-        h[k] = make_float4(0.1f * (k % 7) + 1, 0.2f * (k % 5) + 1, 0.3f * (k % 3) + 1, 1e-3f);
+    CK(hipMalloc(&tab_m, sizeof(float4) * 6 * 64));
+    CK(hipMalloc(&out4, sizeof(float4) * nlane));
+    CK(hipMalloc(&out4_m, sizeof(float4) * nlane));
+    std::vector<float4> h(3 * 64), hm(6 * 64);
+    for (int j = 0; j < 64; j++) {
+        const float X = 1.0f + 0.1f * (j % 7), Y = 1.0f + 0.2f * (j % 5), Z = 1.0f + 0.3f * (j % 3);
+        const float qxx = 1e-4f * (1 + j % 3), qyy = 2e-4f * (1 + j % 5), qzz = 1.5e-4f,
+                    qxy = 3e-5f * (j % 4), qxz = -2e-5f * (j % 3), qyz = 1e-5f * (j % 5);
+        h[3 * j] = make_float4(X, Y, Z, 1e-3f);
+        h[3 * j + 1] = make_float4(qxx, qyy, qzz, qxy);
+        h[3 * j + 2] = make_float4(qxz, qyz, 0, 0);
+        const float Q[3][3] = {{qxx, qxy, qxz}, {qxy, qyy, qyz}, {qxz, qyz, qzz}};
+        hm[6 * j] = h[3 * j];
+        float qX[3];
+        for (int r = 0; r < 3; r++) qX[r] = Q[r][0] * X + Q[r][1] * Y + Q[r][2] * Z;
+        hm[6 * j + 1] = make_float4(-qX[0], -qX[1], -qX[2], 0);
+        for (int r = 0; r < 3; r++) hm[6 * j + 2 + r] = make_float4(Q[r][0], Q[r][1], Q[r][2], 0);
+        hm[6 * j + 5] = make_float4(0, 0, 0, 0);
+    }
     CK(hipMemcpy(tab, h.data(), sizeof(float4) * h.size(), hipMemcpyHostToDevice));
+    CK(hipMemcpy(tab_m, hm.data(), sizeof(float4) * hm.size(), hipMemcpyHostToDevice));
     hipEvent_t a, b;
     CK(hipEventCreate(&a));
     CK(hipEventCreate(&b));
@@ -164,13 +223,20 @@ int main() {
         const double rs = (double)blocks * threads * iters * 8;
         std::printf("rep %d rsq+add: %.3f ms, %.2f T rsq/s\n", rep, ms, rs / ms / 1e9);
         CK(hipEventRecord(a));
-        hipLaunchKernelGGL(k_pc, dim3(blocks), dim3(threads), 0, 0, out, iters * 4, tab);
+        hipLaunchKernelGGL(k_pc, dim3(blocks), dim3(threads), 0, 0, out4, iters * 4, tab);
         CK(hipEventRecord(b));
         CK(hipEventSynchronize(b));
         CK(hipEventElapsedTime(&ms, a, b));
         const double pcs = (double)blocks * threads * iters * 4;
         std::printf("rep %d quadrupole pc (LDS j): %.3f ms, %.3e interactions/s, %.1f TFLOP/s at 54\n",
                     rep, ms, pcs / (ms * 1e-3), pcs * 54 / (ms * 1e-3) / 1e12);
+        CK(hipEventRecord(a));
+        hipLaunchKernelGGL(k_pc_mfma, dim3(blocks), dim3(threads), 0, 0, out4_m, iters * 4, tab_m);
+        CK(hipEventRecord(b));
+        CK(hipEventSynchronize(b));
+        CK(hipEventElapsedTime(&ms, a, b));
+        std::printf("rep %d quadrupole pc, Q r on 4x4x1 MFMA (LDS j): %.3f ms, %.3e interactions/s\n",
+                    rep, ms, pcs / (ms * 1e-3));
         CK(hipEventRecord(a));
         hipLaunchKernelGGL(k_fma64, dim3(blocks), dim3(threads), 0, 0, out64, iters, 1.0001, 0.5);
         CK(hipEventRecord(b));
@@ -192,6 +258,23 @@ int main() {
         std::printf("rep %d quadrupole pc f64 (LDS j): %.3f ms, %.3e interactions/s, %.1f TFLOP/s at 54\n",
                     rep, ms, pcs64 / (ms * 1e-3), pcs64 * 54 / (ms * 1e-3) / 1e12);
     }
+    {   // the two FP32 forms on the first workgroup's lanes (the other workgroups repeat them)
+        std::vector<float4> r1(threads), r2(threads);
+        CK(hipMemcpy(r1.data(), out4, sizeof(float4) * threads, hipMemcpyDeviceToHost));
+        CK(hipMemcpy(r2.data(), out4_m, sizeof(float4) * threads, hipMemcpyDeviceToHost));
+        double da = 0, dp = 0;
+        for (int t = 0; t < threads; t++) {
+            const double ex = r2[t].x - r1[t].x, ey = r2[t].y - r1[t].y, ez = r2[t].z - r1[t].z;
+            const double n = std::sqrt((double)r1[t].x * r1[t].x + (double)r1[t].y * r1[t].y +
+                                       (double)r1[t].z * r1[t].z);
+            da = std::fmax(da, std::sqrt(ex * ex + ey * ey + ez * ez) / n);
+            dp = std::fmax(dp, std::fabs((double)r2[t].w - r1[t].w) / std::fabs((double)r1[t].w));
+        }
+        std::printf("MFMA form vs VALU form: max rel acceleration diff %.2e, potential %.2e\n", da, dp);
+    }
+    CK(hipFree(tab_m));
+    CK(hipFree(out4));
+    CK(hipFree(out4_m));
     CK(hipFree(out64));
     CK(hipFree(tab64));
     CK(hipFree(out));
