@@ -178,6 +178,19 @@ __device__ __forceinline__ double uniform_f64(double v) {
     return __longlong_as_double((long long)uniform_u64((uint64_t)__double_as_longlong(v)));
 }
 
+// A 64-bit kernel argument copied into a scalar register pair of its own.  Arguments arrive
+// in wide scalar tuples, and when the allocator spills such a tuple into vector lanes it
+// reloads the whole tuple wherever one member is read: an argument read in a hot loop then
+// costs one readlane per tuple register on every pass.  The copy is one s_mov_b64 that the
+// compiler cannot fold back into the tuple (a readfirstlane of a scalar value it does).
+template <class T>
+__device__ __forceinline__ T own_sgpr_pair(T v) {
+    static_assert(sizeof(T) == 8, "a 64-bit value");
+    T r;
+    asm("s_mov_b64 %0, %1" : "=s"(r) : "s"(v));
+    return r;
+}
+
 __device__ __forceinline__ void wave_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();

@@ -392,6 +392,11 @@ k_walk_runs(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *l
     const uint32_t items = sel ? *nsel : (G + kRun - 1) / kRun;
     // this wave's slot within each W: a permutation of 0..W-1
     const uint32_t slot = walk_order_slot(blockIdx.x, (uint32_t)w, gridDim.x, sel ? 0u : chunk);
+    // the two arguments the stack loops read: apart from the argument tuples, so that the
+    // loops reload none of the scalar registers spilled under the occupancy bound (each such
+    // reload was 16 readlanes in the opening test and in the particle-entry stores)
+    const double th2 = own_sgpr_pair(theta2);
+    uint32_t *const lst = own_sgpr_pair(list);
     for (size_t q = slot; q < items; q += (size_t)gridDim.x * kWaves) {
         // targets [t0, t1) of run [r0, r1)
         const uint32_t t0 = uniform_u32(sel ? sel[q] : (uint32_t)q * kRun);
@@ -429,8 +434,8 @@ k_walk_runs(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *l
         if (shared) {
             if (lane == 0) stk[0] = root;
             wave_barrier();
-            const int r = run_stack<FILL, true>(stk, 1, front, nf, node, link, ccap, theta2, rb,
-                                                list, base, capg, nt, ne0, ns0);
+            const int r = run_stack<FILL, true>(stk, 1, front, nf, node, link, ccap, th2, rb,
+                                                lst, base, capg, nt, ne0, ns0);
             if (r == 1) err = true;
             if (r != 0) shared = false;                // each member walks from the root
         }
@@ -457,8 +462,8 @@ k_walk_runs(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *l
                     ne = 0; ns = 0;
                     if (lane == 0) stk[0] = root;
                     wave_barrier();
-                    if (run_stack<FILL, true>(stk, 1, front, nf2, node, link, ccap, theta2, rb,
-                                              list, bk, ck, 1, ne, ns) != 0)
+                    if (run_stack<FILL, true>(stk, 1, front, nf2, node, link, ccap, th2, rb,
+                                              lst, bk, ck, 1, ne, ns) != 0)
                         gerr = true;                   // never: the first walk completed
                 }
                 uint32_t sp;
@@ -472,7 +477,7 @@ k_walk_runs(const uint32_t *ngroups, Groups g, const uint4 *node, const uint2 *l
                 wave_barrier();
                 uint32_t nf_unused = 0;
                 if (!gerr && run_stack<FILL, false>(stk, sp, nullptr, nf_unused, node, link, ccap,
-                                                    theta2, gb, list, bk, ck, 1, ne, ns) != 0)
+                                                    th2, gb, lst, bk, ck, 1, ne, ns) != 0)
                     gerr = true;
                 wave_barrier();
                 if (FILL && spill && pass == 0 && !gerr && ((uint64_t)ne + ns > ck[0] || !ok)) {
