@@ -24,8 +24,8 @@
 // rounded to FP32 when a tile is staged; the inner loop is FP32 (hardware reciprocal square
 // root); each slice sums a tile plainly and adds the tile total into a Kahan-compensated
 // accumulator; outputs are FP64.
-// FP64 variant: the same loop in FP64; 1/sqrt from the hardware estimate refined by two
-// Newton-Raphson steps.
+// FP64 variant: the same loop in FP64; 1/sqrt from the hardware estimate refined by one
+// Newton-Raphson step.
 #include "dev_util.h"
 #include "fdx_internal.h"
 #include "interact.h"

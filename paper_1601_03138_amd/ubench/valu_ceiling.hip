@@ -1,7 +1,7 @@
 // Instruction-throughput ceilings of gfx950 for the force kernels' arithmetic (packed FP32
 // disabled, as in the library): FP32 and FP64 FMA rates, v_rsq_f32 and v_rsq_f64 rates, and
 // the quadrupole particle-cell interaction with its j-record broadcast from LDS (no global
-// memory in the loop), in FP32 and in FP64 (hardware estimate + two Newton steps, as in the
+// memory in the loop), in FP32 and in FP64 (hardware estimate + one Newton step, as in the
 // library).  A second FP32 form takes the linear part Q r = Q x_i - Q X from 4x4x1 FP32
 // MFMAs (the alternative that was measured and not adopted); it prints how far its results
 // are from the VALU form's.  Prints one line per measurement; used to derive the force
@@ -129,13 +129,10 @@ __global__ void __launch_bounds__(256) k_rsq64(double *out, int iters, double a)
     out[blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
-__device__ __forceinline__ double rsqrt_nr2(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    for (int k = 0; k < 2; k++) {
-        const double r = fma(-(x * y), y, 1.0);
-        y = fma(y * r, 0.5, y);
-    }
-    return y;
+__device__ __forceinline__ double rsqrt_nr1(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double r = fma(-(x * y), y, 1.0);
+    return fma(y * r, 0.5, y);
 }
 
 // the library's FP64 quadrupole particle-cell interaction, j from a 64-entry LDS table
@@ -150,7 +147,7 @@ __global__ void __launch_bounds__(256) k_pc64(double *out, int iters, const doub
         const double4 A = t[3 * j], B = t[3 * j + 1], C = t[3 * j + 2];
         const double rx = xi - A.x, ry = yi - A.y, rz = zi - A.z;
         const double R2 = fma(rz, rz, fma(ry, ry, fma(rx, rx, e2)));
-        const double Ri = rsqrt_nr2(R2), Ri2 = Ri * Ri, MRi = A.w * Ri;
+        const double Ri = rsqrt_nr1(R2), Ri2 = Ri * Ri, MRi = A.w * Ri;
         const double qx = fma(B.w, ry, fma(C.x, rz, B.x * rx));
         const double qy = fma(B.w, rx, fma(C.y, rz, B.y * ry));
         const double qz = fma(C.x, rx, fma(C.y, ry, B.z * rz));
