@@ -29,8 +29,6 @@ inline unsigned grid_for(size_t n, unsigned cap = 16384) {
     return (unsigned)b;
 }
 
-// (x, y, z, m) of every particle as one 32-byte record in the caller's order (coalesced), so
-// the sorted gather below reads one sector per particle instead of four.
 // system holding sorted position r: the last s with off[s] <= r (skips empty systems)
 __device__ __forceinline__ int system_of(const int64_t *off, int nsys, size_t r) {
     int lo = 0, hi = nsys - 1;
@@ -41,7 +39,9 @@ __device__ __forceinline__ int system_of(const int64_t *off, int nsys, size_t r)
     return lo;
 }
 
-// Sorted records, softenings and the inverse permutation.  The sort keeps every system's
+// Sorted records, softenings and the inverse permutation.  The records are read from the
+// (x, y, z, m) array the key kernel wrote in the caller's order (one 32-byte sector per
+// particle instead of four scattered reads).  The sort keeps every system's
 // particles in the same range [off[s], off[s + 1]) as the caller's layout, so when every
 // system's particles share one softening (per_system) rank r takes it from the first particle
 // of its system -- a cached read per system instead of a random read per particle.
