@@ -338,7 +338,8 @@ def main():
     phase_ms = {k[2:]: round(float(np.mean([p[k] for p in phases])), 4) for k in phases[0]}
     shape = ctx.shape_name(st["shape"])
     # algorithmic bytes of the HBM-bound phases (per particle unless stated): keys = bbox read
-    # 24 + key read 24 / write 12 + AoS pack read 32 / write 32; sort = 32 per radix pass (8 B
+    # 24 + key kernel read 32 (x, y, z, m) / write 12 (key, index) + 32 ((x, y, z, m) record
+    # for the sorted gather); sort = 32 per radix pass (8 B
     # histogram read, 12 B pair read and written) + sorted gather (4 perm + 32 record + 32 out
     # + 8 eps + 4 inverse); walk = the 4-byte list entries written by the fill pass
     passes = 8 + (0 if ps.n_sys <= 1 else (int(np.ceil(np.log2(ps.n_sys))) + 7) // 8)
@@ -347,7 +348,7 @@ def main():
     # cell written; moments = 80 B per cell written + 80 B per child read; groups = 16 B per
     # particle + 1 B leaf level written and read
     ncell = int(st["n_cells"])
-    phase_gbs = {"keys": gbs(124 * ps.n, phase_ms["keys"]),
+    phase_gbs = {"keys": gbs(100 * ps.n, phase_ms["keys"]),
                  "sort": gbs((32 * passes + 80) * ps.n, phase_ms["sort"]),
                  "tree": gbs(30 * ps.n + 60 * ncell, phase_ms["tree"]),
                  "moments": gbs(160 * ncell, phase_ms["moments"]),
