@@ -118,6 +118,24 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
     x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false));
     return (uint32_t)__builtin_amdgcn_readlane((int)x, kWave - 1);
 }
+// Minimum / maximum over each 16-lane row, held by the row's last lane (lanes 15, 31, 47, 63;
+// the other lanes hold prefix results): the four row_shr moves of wave_min_u32 / wave_max_u32
+// without the broadcasts across rows.  All lanes must be active.
+__device__ __forceinline__ uint32_t row_min_u32(uint32_t x) {
+    constexpr int id = -1;
+    x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)x, 0x111, 0xf, 0xf, false));
+    x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)x, 0x112, 0xf, 0xf, false));
+    x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)x, 0x114, 0xf, 0xf, false));
+    x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)x, 0x118, 0xf, 0xf, false));
+    return x;
+}
+__device__ __forceinline__ uint32_t row_max_u32(uint32_t x) {
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false));
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false));
+    return x;
+}
 // one DPP lane move of a 64-bit value (both halves from the same lane; identity all ones)
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ uint64_t dpp_move_u64_max_id(uint64_t u) {
@@ -140,6 +158,15 @@ __device__ __forceinline__ double wave_min_nonneg_f64(double v) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, kWave - 1);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), kWave - 1);
     return __longlong_as_double((long long)((uint64_t)lo | ((uint64_t)hi << 32)));
+}
+// the same over each 16-lane row, held by the row's last lane
+__device__ __forceinline__ double row_min_nonneg_f64(double v) {
+    uint64_t u = (uint64_t)__double_as_longlong(v), o;
+    o = dpp_move_u64_max_id<0x111, 0xf>(u); u = o < u ? o : u;
+    o = dpp_move_u64_max_id<0x112, 0xf>(u); u = o < u ? o : u;
+    o = dpp_move_u64_max_id<0x114, 0xf>(u); u = o < u ? o : u;
+    o = dpp_move_u64_max_id<0x118, 0xf>(u); u = o < u ? o : u;
+    return __longlong_as_double((long long)u);
 }
 
 // Exclusive prefix sum over a block of NT threads (NT a multiple of 64, <= 1024); returns the

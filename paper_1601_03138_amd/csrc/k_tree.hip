@@ -101,24 +101,6 @@ __device__ __forceinline__ int shared_levels(uint64_t a, uint64_t b) {
     return x ? (__clzll((long long)x) - 1) / 3 : kLevels;
 }
 
-// the same search by a whole wave (every lane gets the result): a 64-way search, one round of
-// loads per factor of 64 in the system count
-__device__ __forceinline__ int wave_system_of(const int64_t *off, int nsys, size_t r) {
-    const int lane = lane_id();
-    int lo = 0, n = nsys;                 // off[lo] <= r < off[lo + n] (off[nsys] = N > r)
-    while (n > 1) {
-        const int step = (n + kWave - 1) / kWave;
-        const int k = lane * step;
-        const bool ok = k < n && (uint64_t)off[lo + k] <= r;
-        const uint64_t m = __ballot(ok);             // lane 0 always qualifies
-        const int last = 63 - __clzll((long long)m);
-        const int nlo = lo + last * step;
-        n = min(step, lo + n - nlo);
-        lo = nlo;
-    }
-    return lo;
-}
-
 // per position: lo(r) and c(r)
 __global__ void k_cells_prefix(size_t n, int nsys, const int64_t *off, const uint64_t *skey,
                                int n_leaf, uint8_t *lo8, int8_t *c8) {
@@ -431,6 +413,12 @@ __global__ void k_wide_list(const uint32_t *ngroups_c, Groups g, uint32_t *list,
         if (g.wide[gi]) list[atomicAdd(&st->wide_groups, 1u)] = (uint32_t)gi;
 }
 
+// Per group: the integer box of its members' keys, its deepest member leaf level, its smallest
+// softening, its system, the centre of its cell and the wide flag.  Four groups per wave, one
+// per 16-lane row: the members are read 16 at a time, the reductions are four DPP lane moves
+// within the row (the row's last lane ends up with the row's result), and the rows' last lanes
+// write the four groups in parallel.  Median groups hold a few tens of particles, so one group
+// per wave left most lanes idle and spent six reduction steps and a one-lane epilogue on each.
 __global__ void __launch_bounds__(kThreads)
 k_group_geom(const uint32_t *ngroups, int nsys, const int64_t *off, Cells c,
              const uint64_t *skey, const double *cube, const double *seps, const uint8_t *plev,
@@ -441,13 +429,18 @@ k_group_geom(const uint32_t *ngroups, int nsys, const int64_t *off, Cells c,
         if (*ngroups > g.cap) st->group_overflow = 1;
     }
     const int lane = lane_id();
+    const int row = lane >> 4, rl = lane & 15;
     const size_t wave0 = gtid() / kWave, nwaves = gstride() / kWave;
-    for (size_t gi = wave0; gi < G; gi += nwaves) {
-        const uint32_t b = g.begin[gi], e = b + g.count[gi];
+    // wave-uniform trip count: every lane reaches the row reductions below
+    for (size_t g0 = 4 * wave0; g0 < G; g0 += 4 * nwaves) {
+        const size_t gi = g0 + (size_t)row;
+        const bool valid = gi < G;
+        const uint32_t b = valid ? g.begin[gi] : 0u;
+        const uint32_t e = valid ? b + g.count[gi] : 0u;
         uint32_t lo[3] = {kNone, kNone, kNone}, hi[3] = {0, 0, 0};
         uint32_t deep = 0;
         double emin = INFINITY;
-        for (uint32_t r = b + lane; r < e; r += kWave) {
+        for (uint32_t r = b + (uint32_t)rl; r < e; r += 16) {
             const uint64_t k = skey[r];
             const uint32_t q[3] = {compact3(k >> 2), compact3(k >> 1), compact3(k)};
 #pragma unroll
@@ -456,11 +449,11 @@ k_group_geom(const uint32_t *ngroups, int nsys, const int64_t *off, Cells c,
             emin = fmin(emin, seps[r]);
         }
 #pragma unroll
-        for (int a = 0; a < 3; a++) { lo[a] = wave_min_u32(lo[a]); hi[a] = wave_max_u32(hi[a]); }
-        deep = wave_max_u32(deep);
-        emin = wave_min_nonneg_f64(emin);
-        const int slo = wave_system_of(off, nsys, b);   // last s with off[s] <= b
-        if (lane == 0) {
+        for (int a = 0; a < 3; a++) { lo[a] = row_min_u32(lo[a]); hi[a] = row_max_u32(hi[a]); }
+        deep = row_max_u32(deep);
+        emin = row_min_nonneg_f64(emin);
+        if (valid && rl == 15) {
+            const int slo = system_of(off, nsys, b);      // last s with off[s] <= b
             const uint32_t cell = g.cell[gi];
             const uint32_t l = c.level[cell];
             const uint64_t corner = c.prefix[cell] << (3 * (kLevels - l));
