@@ -180,6 +180,30 @@ def test_graph_steps_match_eager_steps_on_an_ensemble(ctx, fdx):
     assert all(np.array_equal(a, b) for a, b in zip(s0, s1))
 
 
+@pytest.mark.parametrize("shape", ["nt256_ipl2", "nt512_ipl2"])
+def test_graph_steps_match_eager_steps_in_two_per_lane_shapes(ctx, fdx, shape):
+    """The shapes the autotuner picks for the ensemble and the N = 2^24 benchmark (two
+    i-particles per lane) in captured steps: particles and forces equal the eager steps'."""
+    ens = I.ensemble(n_sys=24, seed=41, nmin=256, nmax=4096)
+    names = [ctx.shape_name(v) for v in range(ctx.lib.fdx_autotune_shapes())]
+    _say(f"[graph] shape {shape}, ensemble n={ens.n} systems={ens.n_sys}")
+    dt, steps = 1.0 / 256.0, 5
+    runs = {}
+    try:
+        ctx.set_shape(names.index(shape))
+        for graph in (False, True):
+            ctx.set_particles(ens)
+            ctx.calc_force(0.6, 8, 128, 0.0, quad=True, fp32=True, persistent=True)
+            assert ctx.stats()["shape"] == names.index(shape)
+            ctx.integrate(dt, steps, graph=graph)
+            runs[graph] = (ctx.particles(), ctx.forces())
+    finally:
+        ctx.set_shape(-1)
+    for a, b in zip(runs[False][0], runs[True][0]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(runs[False][1], runs[True][1])
+
+
 @pytest.mark.parametrize("percent", [0, 50])
 def test_graph_list_sizing_and_recovery(ctx, fdx, percent):
     """percent 0: a count walk sizes the lists in every captured step; 50: the first capture's
