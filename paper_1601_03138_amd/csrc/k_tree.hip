@@ -392,8 +392,6 @@ __global__ void k_group_emit(size_t n, int n_group, Cells c, const uint32_t *fla
     }
 }
 
-// One wave per group: integer box of the members' grid cells, centre of the group's cell,
-// and the group's system.
 // level of every particle's leaf (leaves partition the particles)
 __global__ void k_leaf_level(Cells c, uint8_t *plev) {
     const uint32_t nc = min(c.lvl[kLevels + 1], c.cap);
