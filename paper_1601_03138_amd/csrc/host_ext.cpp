@@ -14,9 +14,10 @@
 namespace fdx {
 
 int ext_force_variant(fdx_ctx *c) {
-    // defaults measured at N = 2^24: FP32 nt512_ipl1_pf_w8 for the direct launch and
+    // shapes used when none is set or tuned: FP32 nt512_ipl1_pf_w8 for the direct launch and
     // nt512_ipl1_w8 (no register prefetch: no spills in the persistent loop) for the
-    // persistent launch, FP64 nt256_ipl2 (no prefetch)
+    // persistent launch, FP64 nt256_ipl2 (no prefetch; also the shape of the wide-group
+    // hand-off).  At N = 2^24 the autotuner finds nt512_ipl2 about 1.3 % faster for FP32.
     const bool f32 = (c->flags & FDX_FP32REL) != 0;
     const int dflt = f32 ? ((c->flags & FDX_PERSISTENT) ? 9 : 8) : 5;
     int v = c->ext.variant[f32] >= 0 ? c->ext.variant[f32] : dflt;
